@@ -1,0 +1,368 @@
+"""Pins for the CPU oracle (runs without a GPU).
+
+The oracle is only trusted because these tests tie it to facts that do not
+come from the oracle itself: closed forms, identities stated in the paper,
+printed worked values (tests/golden), LAPACK on small inputs, calculus and
+finite differences.  test_mutants.py shows that plausible mistakes planted in
+a copy of the oracle fail at least one of these pins.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from conftest import golden
+
+U_D = 2.0 ** -53
+U_L = 2.0 ** -24
+
+
+# ----------------------------------------------------------------- rotation
+@pytest.mark.parametrize("a,b,d,expect", [
+    (2.0, 1.0, 2.0, (1.0, 3.0)),      # tau = 0 -> t = 1, theta = pi/4
+    (0.0, 1.0, 0.0, (-1.0, 1.0)),
+])
+def test_pair_closed_form_textbook(orc, a, b, d, expect):
+    """Section 3.1: J^T [[a,b],[b,d]] J is diagonal, eigenvalues from the
+    quadratic formula."""
+    c, s = orc.jacobi_pair(a, d, b)
+    J = np.array([[c, s], [-s, c]])
+    B = J.T @ np.array([[a, b], [b, d]]) @ J
+    assert abs(B[0, 1]) < 1e-15 and abs(B[1, 0]) < 1e-15
+    assert sorted([B[0, 0], B[1, 1]]) == pytest.approx(expect, abs=1e-15)
+    if (a, b, d) == (2.0, 1.0, 2.0):
+        # V = [1 1; -1 1]/sqrt(2): t = 1 exactly
+        assert c == pytest.approx(1 / math.sqrt(2), abs=1e-16)
+        assert s == pytest.approx(1 / math.sqrt(2), abs=1e-16)
+
+
+def test_pair_random_2x2(orc):
+    g = np.random.default_rng(11)
+    for _ in range(200):
+        a, b, d = g.standard_normal(3) * 10.0 ** g.integers(-3, 4, 3)
+        c, s = orc.jacobi_pair(a, d, b)
+        t = s / c
+        assert abs(t) <= 1.0 + 1e-15                       # smaller root
+        assert c * c + s * s == pytest.approx(1.0, abs=1e-15)
+        # t solves t^2 + 2 tau t - 1 = 0 with tau = (d - a)/(2 b)
+        # b_pp = a - t b, b_qq = d + t b (rotated diagonal)
+        disc = math.sqrt(((a - d) / 2) ** 2 + b * b)
+        lo, hi = (a + d) / 2 - disc, (a + d) / 2 + disc
+        got = sorted([a - t * b, d + t * b])
+        scale = max(abs(a), abs(b), abs(d))
+        assert got[0] == pytest.approx(lo, abs=8e-16 * scale)
+        assert got[1] == pytest.approx(hi, abs=8e-16 * scale)
+        # the pair is annihilated (the 2x2 subproblem of Section 3.1)
+        bpq = c * s * (a - d) + (c * c - s * s) * b
+        assert abs(bpq) <= 4e-16 * scale
+
+
+def test_pair_zero_coupling(orc):
+    assert orc.jacobi_pair(1.0, -3.0, 0.0) == (1.0, 0.0)
+
+
+def test_small_angle_appendix_a(orc):
+    """Appendix A: approach 2 keeps s != 0 for a_pq ~ 1e-14 where
+    approach 1 (t = -tau + sqrt(tau^2 + 1)) collapses to s = 0."""
+    app, aqq, apq = 1.0, 2.0, 1e-14
+    tau = (aqq - app) / (2 * apq)
+    t1 = -tau + math.sqrt(tau * tau + 1.0)
+    assert t1 == 0.0                                      # approach 1 fails
+    c, s = orc.jacobi_pair(app, aqq, apq)
+    assert s != 0.0
+    assert s == pytest.approx(apq / (aqq - app), rel=1e-12)
+    A = np.array([[app, apq], [apq, aqq]])
+    B, _ = orc.rotate(A, None, 0, 1, c, s)
+    assert abs(B[0, 1]) < 1e-28
+
+
+def test_rotation_off_identity(orc):
+    """Section 3.1: off(B)^2 = off(A)^2 - 2 a_pq^2; only rows/cols p, q move
+    (Section 2.2.1)."""
+    A = wl.random_symmetric(12, 5)
+    for (p, q) in [(0, 1), (3, 9), (10, 11), (2, 7)]:
+        c, s = orc.jacobi_pair(A[p, p], A[q, q], A[p, q])
+        V = np.eye(12)
+        B, V2 = orc.rotate(A, V, p, q, c, s)
+        lhs = orc.off(B) ** 2
+        rhs = orc.off(A) ** 2 - 2 * A[p, q] ** 2
+        assert lhs == pytest.approx(rhs, rel=1e-13)
+        assert abs(B[p, q]) < 1e-14 and abs(B[q, p]) < 1e-14
+        keep = [k for k in range(12) if k not in (p, q)]
+        assert np.array_equal(B[np.ix_(keep, keep)], A[np.ix_(keep, keep)])
+        assert np.allclose(V2.T @ V2, np.eye(12), atol=1e-15)
+        assert np.allclose(V2.T @ A @ V2, B, atol=1e-14)
+
+
+# ------------------------------------------------------------- whole solve
+def test_edge_sizes(orc):
+    W, V, sw, st, _ = orc.eigh(np.zeros((0, 0)))
+    assert W.shape == (0,) and st == 0
+    W, V, sw, st, _ = orc.eigh(np.array([[-2.5]]))
+    assert W[0] == -2.5 and V[0, 0] == 1.0 and sw == 0
+
+
+def test_diagonal_input(orc):
+    d = np.array([3.0, -1.0, 2.0, 0.5, -7.0])
+    W, V, sw, st, _ = orc.eigh(np.diag(d))
+    assert sw == 0 and st == 0
+    assert np.array_equal(W, np.sort(d))
+    P = np.zeros((5, 5))
+    for c, i in enumerate(np.argsort(d, kind="stable")):
+        P[i, c] = 1.0
+    assert np.array_equal(V, P)
+
+
+def test_known_spectrum(orc):
+    A, lam = wl.uniform_spectrum(64, 1)
+    W, V, sw, st, _ = orc.eigh(A)
+    n = 64
+    nrm2 = np.abs(lam).max()                   # ||A||_2 = max |lambda|
+    assert st == 0
+    assert np.abs(W - lam).max() <= 10 * n * U_D * nrm2
+    assert np.linalg.norm(A @ V - V * W) / np.linalg.norm(A) <= 10 * n * U_D
+    # orthogonality: the tolerance of the solver's contract, 1e-14 n
+    assert np.linalg.norm(V.T @ V - np.eye(n)) <= 1e-14 * n
+
+
+@pytest.mark.parametrize("n,seed", [(7, 1), (30, 2), (64, 3)])
+def test_invariants(orc, n, seed):
+    """Orthogonal invariance (Section 2.2): trace and Frobenius norm."""
+    A = wl.random_symmetric(n, seed)
+    W, V, *_ = orc.eigh(A)
+    assert W.sum() == pytest.approx(np.trace(A), abs=1e-13 * np.abs(A).sum())
+    assert (W ** 2).sum() == pytest.approx((A ** 2).sum(), rel=1e-13)
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8, 16, 33, 64])
+def test_brute_force_vs_lapack(orc, n):
+    A = wl.random_symmetric(n, 100 + n)
+    W, V, *_ = orc.eigh(A)
+    Wl, Vl = np.linalg.eigh(A)
+    nrm2 = np.abs(Wl).max()
+    assert np.abs(W - Wl).max() <= 1e-13 * nrm2
+    # eigenvectors agree up to sign where the gap is comfortable
+    gaps = np.diff(Wl)
+    for k in range(n):
+        gap = min(gaps[k - 1] if k > 0 else np.inf,
+                  gaps[k] if k < n - 1 else np.inf)
+        if gap > 1e-6 * nrm2:
+            assert abs(abs(V[:, k] @ Vl[:, k]) - 1.0) < 1e-9
+    # sign convention: largest |entry| of each column is positive
+    idx = np.argmax(np.abs(V), axis=0)
+    assert (V[idx, np.arange(n)] > 0).all()
+
+
+def test_residual_scale_paper_fixture(orc):
+    """Section 3.3 test: n=100, A = randn + randn', tol = 2^-53 (per pair).
+    The paper's residual sits at about twice n u_d ||A||_2; a correct solver
+    on the same family lands at that scale, not orders of magnitude away."""
+    fx = golden("cyclic_residual_n100.txt")
+    fc = golden("classical_residual_n100.txt")
+    ratio_paper = fx["residual"] / fx["reference"]
+    assert 1.0 < ratio_paper < 2.0 and fc["residual"] / fc["reference"] < 2.0
+    g = np.random.default_rng(1)
+    n = int(fx["n"])
+    for trial in range(3):
+        G = g.standard_normal((n, n))
+        A = G + G.T
+        A_fin, V, sw, st, _, _ = orc.jacobi_cyclic(A, tol_abs=0.0,
+                                                   rel_eps=U_D)
+        D = np.diag(np.diag(A_fin))
+        res = np.linalg.norm(A @ V - V @ D, 2)
+        ref = n * U_D * np.linalg.norm(A, 2)
+        assert st == 0
+        assert res / ref < 5 * ratio_paper
+
+
+def test_householder_fixture():
+    """Section 2.2.2 worked example: the generator's Householder QR maps x to
+    +-||x|| e_1 with ||x|| = 3.4748."""
+    fx = golden("householder_example.txt")
+    x = np.array(fx["x"]).reshape(5, 1)
+    Q, R = np.linalg.qr(x, mode="complete")
+    assert abs(R[0, 0]) == pytest.approx(fx["Px0"], abs=1e-4)  # inputs carry 5 digits
+    Px = Q.T @ x
+    assert np.abs(Px[1:]).max() < 1e-15
+
+
+def test_haar_generator_orthogonal():
+    Q = wl.haar(50, wl.rng(0))
+    assert np.linalg.norm(Q.T @ Q - np.eye(50)) < 1e-13
+
+
+# -------------------------------------------------------- convergence pins
+def test_quadratic_convergence(orc):
+    """Section 5.2.2 (Wilkinson's bound): once off < delta/8,
+    off after one more sweep <= off^2 / delta, delta = half the minimum gap."""
+    n = 24
+    lam = np.linspace(-1.0, 1.0, n)
+    A = wl.from_spectrum(lam, wl.haar(n, wl.rng(8)))
+    delta = 0.5 * np.diff(lam).min()
+    *_, hist = orc.eigh(A, tol=1e-300, max_sweeps=30)
+    floor = 20 * n * U_D * np.abs(lam).max()
+    seen = 0
+    for k in range(len(hist) - 1):
+        if hist[k] < delta / 8:
+            assert hist[k + 1] <= hist[k] ** 2 / delta + floor
+            seen += 1
+    assert seen >= 1
+
+
+def test_linear_phase_decreases(orc):
+    A = wl.random_symmetric(40, 9)
+    *_, hist = orc.eigh(A, tol=1e-300)
+    assert (np.diff(hist) < 0).all()
+
+
+def test_noconv_status(orc):
+    A = wl.random_symmetric(32, 4)
+    W, V, sw, st, _ = orc.eigh(A, max_sweeps=1)
+    assert st == 1 and sw == 1
+    assert np.linalg.norm(V.T @ V - np.eye(32)) < 1e-13
+
+
+# ------------------------------------------------------- Newton-Schulz pins
+def _ns_scalar(d, k):
+    for _ in range(k):
+        d = 0.5 * d * (3.0 - d * d)
+    return d
+
+
+def test_newton_schulz_scalar_map(orc):
+    """Section 4.3.4: with X_0 = P diag(sigma) Q^T, X_k = P diag(f^k(sigma)) Q^T,
+    f(d) = d(3 - d^2)/2, and f(d) - 1 = -(d - 1)^2 (d + 2)/2."""
+    n = 20
+    g = wl.rng(3)
+    P, Q = wl.haar(n, g), wl.haar(n, g)
+    sigma = np.concatenate([[0.3, 1.6, 1.0], 1.0 + 1e-3 * g.standard_normal(n - 3)])
+    X0 = (P * sigma) @ Q.T
+    for k in (1, 2, 3):
+        Xk = orc.newton_schulz(X0, k)
+        expect = (P * _ns_scalar(sigma, k)) @ Q.T
+        assert np.abs(Xk - expect).max() < 1e-14
+    for d in (0.2, 0.9, 1.3, 1.7):
+        got = orc.newton_schulz(np.array([[d]]), 1)[0, 0]
+        assert got - 1.0 == pytest.approx(-0.5 * (d - 1) ** 2 * (d + 2), abs=1e-15)
+
+
+def test_newton_schulz_polar_factor(orc):
+    """The limit is the orthogonal polar factor P Q^T (best approximation,
+    Section 4.3.1); two steps suffice from ||Q^T Q - I|| ~ n u_l."""
+    n = 40
+    g = wl.rng(4)
+    P, Q = wl.haar(n, g), wl.haar(n, g)
+    sigma = 1.0 + n * U_L * g.uniform(-1, 1, n)
+    X0 = (P * sigma) @ Q.T
+    X2 = orc.newton_schulz(X0, 2)
+    assert np.linalg.norm(X2.T @ X2 - np.eye(n)) <= n * U_D
+    assert np.abs(X2 - P @ Q.T).max() < 1e-14
+
+
+def test_ns_iteration_count_fixture():
+    """Section 4.3.4: (sqrt(1 + n u_l) - 1)^4 = n u_d crosses at n ~ 52071; the
+    figure's marker is n u_d at n = 52400."""
+    fx = golden("ns_iteration_count.txt")
+    f = lambda n: (math.sqrt(1 + n * U_L) - 1) ** 4 - n * U_D
+    lo, hi = 1e3, 1e6
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if f(mid) < 0 else (lo, mid)
+    assert abs(lo - fx["crossover_two"]) < 60
+    assert fx["marker_n"] * U_D == pytest.approx(fx["marker_value"], rel=1e-5)
+    # three iterations: (sqrt(1 + n u_l) - 1)^8 = n u_d
+    g3 = lambda n: (math.sqrt(1 + n * U_L) - 1) ** 8 - n * U_D
+    lo, hi = 1e5, 1e8
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if g3(mid) < 0 else (lo, mid)
+    assert abs(lo - fx["crossover_three"]) / fx["crossover_three"] < 1e-3
+
+
+def test_qtaq_vs_library(orc):
+    g = wl.rng(5)
+    Q = g.standard_normal((17, 17))
+    A = wl.random_symmetric(17, 6)
+    B = orc.qtaq(Q, A)
+    ref = Q.T @ A @ Q
+    ref = 0.5 * (ref + ref.T)
+    assert np.abs(B - ref).max() < 1e-12
+
+
+# ------------------------------------------------------- mixed pipeline pins
+@pytest.mark.parametrize("n,seed", [(50, 1), (120, 2)])
+def test_mixed_stage_bounds(orc, n, seed):
+    """Algorithm 9 with an FP32 Jacobi first stage.  Section 4.3.4:
+    ||Q_d^T Q_d - I|| <= n u_d; Section 5.2.1: off(A_cond) <~ n u_l ||A||;
+    Section 5.2.2: at most five FP64 sweeps; Section 5.1: the result is a
+    spectral decomposition at double precision."""
+    A, lam = wl.geo_spectrum(n, seed, kappa=1e3)
+    nrm2 = np.abs(lam).max()
+    W, Q, st, d = orc.eigh_mixed(A)
+    assert st == 0 and d["status32"] == 0
+    assert d["orth_ql"] <= 10 * n * U_L
+    assert d["orth_qd"] <= n * U_D
+    assert d["off_cond"] <= n * U_L * nrm2
+    assert 1 <= d["sweeps64"] <= 5
+    assert np.abs(W - lam).max() <= 1e-13 * nrm2
+    assert np.linalg.norm(A @ Q - Q * W) / np.linalg.norm(A) <= 1e-13 * n
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 1e-14 * n
+    # the same answer as the plain solver
+    W2, *_ = orc.eigh(A)
+    assert np.abs(W - W2).max() <= 1e-13 * nrm2
+
+
+# -------------------------------------------------------------- adjoint pins
+def _loss_parts(orc, A, w, C):
+    W, V, *_ = orc.eigh(A, tol=1e-300)
+    return float(w @ W + (C * V).sum())
+
+
+def test_backward_trace_identity(orc):
+    """d(sum lambda)/dA = d(tr A)/dA = I."""
+    A, lam = wl.uniform_spectrum(12, 9)
+    W, V, *_ = orc.eigh(A)
+    dA, st = orc.eigh_backward(W, V, dW=np.ones(12))
+    assert st == 0
+    assert np.abs(dA - np.eye(12)).max() < 1e-14
+
+
+def test_backward_frobenius_identity(orc):
+    """d(sum lambda^2)/dA = d(||A||_F^2)/dA = 2A."""
+    A, lam = wl.uniform_spectrum(12, 10)
+    W, V, *_ = orc.eigh(A)
+    dA, st = orc.eigh_backward(W, V, dW=2 * W)
+    assert np.abs(dA - 2 * A).max() < 1e-14
+
+
+def test_backward_central_fd(orc):
+    """loss = sum w_i lambda_i + <C, V> (sign-fixed V): the adjoint matches
+    central differences (h = 1e-6) along random symmetric directions."""
+    n = 8
+    lam = np.sort(wl.rng(1).uniform(-1, 1, n)) + np.arange(n) * 0.05
+    A = wl.from_spectrum(lam, wl.haar(n, wl.rng(2)))
+    g = wl.rng(3)
+    w = g.standard_normal(n)
+    C = g.standard_normal((n, n))
+    W, V, *_ = orc.eigh(A, tol=1e-300)
+    dA, st = orc.eigh_backward(W, V, dW=w, dV=C)
+    assert st == 0
+    # the gradient with respect to a symmetric A is itself symmetric
+    assert np.abs(dA - dA.T).max() < 1e-14
+    h = 1e-6
+    for k in range(4):
+        E = g.standard_normal((n, n))
+        E = 0.5 * (E + E.T)
+        fd = (_loss_parts(orc, A + h * E, w, C) -
+              _loss_parts(orc, A - h * E, w, C)) / (2 * h)
+        assert (dA * E).sum() == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+def test_backward_degenerate_status(orc):
+    W = np.array([1.0, 1.0, 2.0])
+    V = np.eye(3)
+    dV = np.ones((3, 3))
+    dA, st = orc.eigh_backward(W, V, dV=dV, gap_tol=1e-12)
+    assert st == 4
+    assert np.isfinite(dA).all()
