@@ -1,0 +1,175 @@
+/*
+ * libjacobi: mixed-precision Jacobi eigensolver for dense real symmetric
+ * matrices, A = V diag(W) V^T, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Z. Zhou, "A Mixed Precision Eigensolver Based on the Jacobi
+ * Algorithm" (arXiv 2509.00495).  Algorithm 4 (cyclic Jacobi, Section 3.3)
+ * is run as a parallel round-robin block Jacobi; Algorithm 9 (Section 5.1)
+ * replaces the single-precision eigensolver by the same Jacobi kernels in
+ * FP32, orthogonalises with Newton-Schulz (Algorithm 8, Section 4.3.4) and
+ * finishes with FP64 Jacobi sweeps on Q_d^T A Q_d.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are dense, ROW-MAJOR, FP64.  Row i of A starts at A + i*lda.
+ * - All array arguments are DEVICE pointers owned by the caller, unless the
+ *   argument says "host".  The library never frees or keeps them.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *   is enqueued on it in order; a call returns after its last readback
+ *   (convergence flags are read once per sweep), so outputs are ready on
+ *   `stream` when the call returns.
+ * - `work`/`work_bytes`: device scratch of at least jacobi_workspace_bytes()
+ *   bytes, 256-byte aligned.  work == NULL makes the call allocate and free
+ *   its own scratch (hipMalloc/hipFree, synchronising).
+ * - A is read, never written; it is symmetrised on ingest, B = (A + A^T)/2.
+ * - Outputs: W ascending; column k of V is the eigenvector of W[k], scaled by
+ *   +-1 so its entry of largest magnitude (lowest row on ties) is positive.
+ * - Errors: arguments are validated on the host before anything is launched;
+ *   argument i invalid -> return -i (LAPACK convention).  Positive codes are
+ *   listed below.
+ */
+#ifndef LIBJACOBI_H
+#define LIBJACOBI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes (return values; negative = invalid argument position). */
+#define JACOBI_OK 0
+#define JACOBI_NOCONV 1     /* max_sweeps reached; outputs hold the last iterate */
+#define JACOBI_NOTSYM 2     /* opts->check_symmetry and A != A^T exactly */
+#define JACOBI_NONFINITE 3  /* A holds NaN or Inf (or the iteration produced one) */
+#define JACOBI_DEGENERATE 4 /* backward: an eigenvalue gap < gap_tol with nonzero coupling */
+#define JACOBI_DEVICE 5     /* a HIP runtime call failed */
+#define JACOBI_WORKSPACE 6  /* work_bytes smaller than jacobi_workspace_bytes() */
+
+/* Tuning and stopping options.  Zero-initialise and set what you need; a zero
+ * field selects the default.  May be NULL. */
+typedef struct jacobi_opts {
+    int32_t max_sweeps;     /* per stage; default 30 */
+    int32_t block;          /* block size b of the block path: 16 or 32; default
+                               16 for n <= 256, else 32 */
+    int32_t inner_sweeps;   /* inner sweeps of each 2b x 2b pair solve; default 1 */
+    int32_t ns_iters;       /* Newton-Schulz iterations: 0 = the count of
+                               Algorithm 8 (2 for n < 52 000, else 3); -1 =
+                               adaptive as Algorithm 7 (stop once
+                               ||I - X^T X||_F <= n u_d, at most 3); > 0 fixed */
+    double c32;             /* FP32 stage stops at off <= c32 n u_l ||A||_F; default 1 */
+    int32_t check_symmetry; /* nonzero: return JACOBI_NOTSYM unless A == A^T exactly */
+    int32_t small_max_n;    /* n up to which one workgroup solves the whole matrix;
+                               default 128, 0 keeps the default, -1 forces the block path */
+    int32_t threads;        /* threads per workgroup of the one-workgroup solver:
+                               256 or 512; default by n */
+    int32_t reserved[5];
+} jacobi_opts;
+
+/* Diagnostics filled on return (host struct, may be NULL). */
+typedef struct jacobi_info {
+    int32_t sweeps;         /* FP64 sweeps (plain), or FP64-stage sweeps (mixed) */
+    int32_t sweeps32;       /* FP32-stage sweeps (mixed only) */
+    int32_t ns_iters;       /* Newton-Schulz iterations run (mixed only) */
+    int32_t path;           /* 0 = one-workgroup solver, 1 = block path */
+    int32_t block;          /* block size used by the block path */
+    int32_t reserved_i[3];
+    double norm_f;          /* ||A||_F of the symmetrised input */
+    double tol;             /* absolute threshold on off(B) actually used */
+    double off_final;       /* off(B) when the FP64 stage stopped */
+    double off32;           /* off(B32) when the FP32 stage stopped (mixed) */
+    double off_cond;        /* off(Q_d^T A Q_d) before the FP64 stage (mixed) */
+    double orth_ns;         /* ||I - Q_d^T Q_d||_F after the last NS step (mixed);
+                               the residual R of that step, computed in FP64 */
+    double reserved_d[4];
+} jacobi_info;
+
+/* Plain FP64 Jacobi eigendecomposition (Algorithm 4, Section 3.3, run as a
+ * round-robin block Jacobi; Alg. 2 angles with approach 2 of Appendix A).
+ *   A    [in]  n x n, leading dimension lda >= max(1, n)
+ *   n    [in]  order, n >= 0 (n = 0 is a no-op)
+ *   W    [out] n eigenvalues, ascending
+ *   V    [out] n x n eigenvectors (columns), leading dimension ldv >= max(1, n)
+ *   tol  [in]  stop when off(B) <= tol (absolute); tol <= 0 selects
+ *              1e-15 * n * ||A||_F.  NaN is an invalid argument.
+ * Returns JACOBI_OK, JACOBI_NOCONV (outputs still written), JACOBI_NOTSYM,
+ * JACOBI_NONFINITE (outputs not written), JACOBI_DEVICE, JACOBI_WORKSPACE or -i.
+ * Argument positions for -i: A 1, n 2, lda 3, W 4, V 5, ldv 6, tol 7, opts 8. */
+int jacobi_eigh(const double *A, int64_t n, int64_t lda, double *W, double *V,
+                int64_t ldv, double tol, const jacobi_opts *opts, void *work,
+                size_t work_bytes, void *stream, jacobi_info *info);
+
+/* Mixed-precision eigendecomposition (Algorithm 9, Section 5.1): FP32 Jacobi
+ * on fl32(A) gives Q_l (angles in FP64, updates on FP32 MFMA), Newton-Schulz in
+ * FP64 gives Q_d (Section 4.3.4), then FP64 Jacobi on B = Q_d^T A Q_d starting
+ * from V = Q_d until off(B) <= tol.  Same arguments and results as jacobi_eigh. */
+int jacobi_eigh_mixed(const double *A, int64_t n, int64_t lda, double *W,
+                      double *V, int64_t ldv, double tol,
+                      const jacobi_opts *opts, void *work, size_t work_bytes,
+                      void *stream, jacobi_info *info);
+
+/* Batched eigendecomposition of matrices of uneven order in one persistent
+ * launch (each workgroup pops matrices from a device work queue, largest
+ * first, and runs Algorithm 4 on the whole matrix in LDS).
+ *   A      [in]  packed: matrix i is n_i x n_i row-major at offset
+ *                sum_{j<i} n_j^2 doubles
+ *   n      [in, HOST] batch orders, 1 <= n_i <= 128
+ *   batch  [in]  number of matrices, >= 0
+ *   W      [out] packed: n_i eigenvalues at offset sum_{j<i} n_j
+ *   V      [out] packed like A
+ *   tol    [in]  absolute threshold on off for every matrix; <= 0 selects
+ *                1e-15 * n_i * ||A_i||_F per matrix
+ *   mixed  [in]  reserved, must be 0 (the batched path is plain FP64)
+ *   status [out] batch int32 per-matrix status codes (device), may be NULL
+ * Returns the largest per-matrix status, or -i, JACOBI_DEVICE, JACOBI_WORKSPACE. */
+int jacobi_eigh_batched(const double *A, const int64_t *n, int64_t batch,
+                        double *W, double *V, double tol, int mixed,
+                        const jacobi_opts *opts, void *work, size_t work_bytes,
+                        void *stream, int32_t *status);
+
+/* Adjoint of the eigendecomposition for a batch of equal-order matrices
+ * (first-order perturbation theory for distinct eigenvalues; the paper does
+ * not treat derivatives):
+ *   dA = sym(V (diag(dW) + F o (V^T dV)) V^T),  F_ij = 1/(W_j - W_i), F_ii = 0,
+ *   sym(G) = (G + G^T)/2.
+ *   W  [in]  batch x n eigenvalues as returned by jacobi_eigh
+ *   V  [in]  batch x n x n eigenvectors (row-major, ld = n)
+ *   dW [in]  batch x n, or NULL (zero)
+ *   dV [in]  batch x n x n, or NULL (zero)
+ *   dA [out] batch x n x n, symmetric
+ *   gap_tol [in] pairs with |W_j - W_i| < gap_tol get F_ij = 0; if such a
+ *           pair has nonzero (V^T dV)_ij the call returns JACOBI_DEGENERATE
+ *           (dA is still written).
+ * Returns JACOBI_OK, JACOBI_DEGENERATE, JACOBI_DEVICE, JACOBI_WORKSPACE or -i. */
+int jacobi_eigh_backward(const double *W, const double *V, const double *dW,
+                         const double *dV, int64_t n, int64_t batch,
+                         double *dA, double gap_tol, void *work,
+                         size_t work_bytes, void *stream);
+
+/* Workspace query (LAPACK style).  op: 0 = eigh, 1 = eigh_mixed,
+ * 2 = eigh_batched (n_max = largest order, batch = count),
+ * 3 = eigh_backward (n_max = n).  Returns bytes; 0 for invalid op. */
+size_t jacobi_workspace_bytes(int op, int64_t n_max, int64_t batch,
+                              const jacobi_opts *opts);
+
+/* Human-readable text for a status code (static storage). */
+const char *jacobi_status_string(int status);
+
+/* Library version string (static storage). */
+const char *jacobi_version(void);
+
+/* One line describing the current HIP device (name, arch, CU count, LDS per
+ * workgroup, clocks) written into buf (host, len bytes).  Returns
+ * JACOBI_OK or JACOBI_DEVICE. */
+int jacobi_device_summary(char *buf, size_t len);
+
+/* Text of the last HIP runtime error seen by a call of this thread that
+ * returned JACOBI_DEVICE (static storage). */
+const char *jacobi_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBJACOBI_H */

@@ -1,0 +1,818 @@
+// libjacobi host side: argument validation, workspace layout, stage
+// sequencing and the C ABI.  Every arithmetic step runs in the kernels of
+// kernels_*.hip; the host only launches, reads back one convergence scalar
+// per sweep and decides when to stop.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+using namespace lj;
+
+namespace {
+
+thread_local hipError_t g_last_error = hipSuccess;
+
+#define CK(x)                                                                  \
+    do {                                                                       \
+        hipError_t e_ = (x);                                                   \
+        if (e_ != hipSuccess) {                                                \
+            g_last_error = e_;                                                 \
+            return JACOBI_DEVICE;                                              \
+        }                                                                      \
+    } while (0)
+
+constexpr double U_D = 0x1p-53; // unit roundoff, double
+constexpr double U_L = 0x1p-24; // unit roundoff, single
+
+struct Opts {
+    int max_sweeps, block, inner, ns_iters, check_sym, small_max_n, threads;
+    double c32;
+};
+
+// returns 0 or the (positive) index of the offending field
+int resolve_opts(const jacobi_opts *o, Opts &r)
+{
+    r.max_sweeps = 30;
+    r.block = 0;
+    r.inner = 1;
+    r.ns_iters = 0;
+    r.check_sym = 0;
+    r.small_max_n = 128;
+    r.threads = 0;
+    r.c32 = 1.0;
+    if (!o)
+        return 0;
+    if (o->max_sweeps < 0 || o->max_sweeps > 1000)
+        return 1;
+    if (o->max_sweeps)
+        r.max_sweeps = o->max_sweeps;
+    if (o->block != 0 && o->block != 16 && o->block != 32)
+        return 1;
+    r.block = o->block;
+    if (o->inner_sweeps < 0 || o->inner_sweeps > 16)
+        return 1;
+    if (o->inner_sweeps)
+        r.inner = o->inner_sweeps;
+    if (o->ns_iters < -1 || o->ns_iters > 8)
+        return 1;
+    r.ns_iters = o->ns_iters;
+    if (std::isnan(o->c32) || o->c32 < 0.0)
+        return 1;
+    if (o->c32 > 0.0)
+        r.c32 = o->c32;
+    r.check_sym = o->check_symmetry != 0;
+    if (o->small_max_n < -1 || o->small_max_n > 128)
+        return 1;
+    if (o->small_max_n == -1)
+        r.small_max_n = 0;
+    else if (o->small_max_n > 0)
+        r.small_max_n = o->small_max_n;
+    if (o->threads != 0 && o->threads != 256 && o->threads != 512)
+        return 1;
+    r.threads = o->threads;
+    return 0;
+}
+
+struct DevInfo {
+    int cus = 0;
+    int lds_max = 0;
+};
+
+DevInfo dev_info()
+{
+    static DevInfo cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return DevInfo{};
+    DevInfo &d = cache[dev];
+    if (d.cus == 0) {
+        int v = 0;
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+        d.cus = v;
+        v = 0;
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        d.lds_max = v;
+    }
+    return d;
+}
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures.
+struct Bump {
+    char *base;
+    size_t off = 0;
+    explicit Bump(void *b) : base((char *)b) {}
+    template <typename T>
+    T *take(size_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+int default_block(int64_t n) { return n <= 256 ? 16 : 32; }
+
+struct Geometry {
+    int b, N, M, npairs, nbt;
+    int64_t npad;
+};
+
+Geometry geometry(int64_t n, int block)
+{
+    Geometry g;
+    g.b = block ? block : default_block(n);
+    int64_t N = (n + g.b - 1) / g.b;
+    if (N < 2)
+        N = 2;
+    N += N % 2;
+    g.N = (int)N;
+    g.M = 2 * g.b;
+    g.npairs = g.N / 2;
+    g.nbt = g.npairs * (g.npairs - 1) / 2;
+    g.npad = N * g.b;
+    return g;
+}
+
+// Buffers of one block-path solve (plain or mixed).
+struct BlockWs {
+    double *B64, *V64, *U64, *X2, *R;
+    float *B32, *V32, *U32;
+    double *partial, *scal, *wtmp, *sg;
+    int *flags, *perm;
+    int2 *pairs, *btiles;
+};
+
+size_t partial_count(const Geometry &g)
+{
+    size_t c = (size_t)g.npairs + g.nbt;
+    c = std::max(c, (size_t)INGEST_BLOCKS);
+    c = std::max(c, (size_t)OFF_BLOCKS);
+    return c;
+}
+
+BlockWs layout_block(Bump &bp, int64_t n, const Geometry &g, bool mixed)
+{
+    BlockWs w{};
+    const size_t nn = (size_t)g.npad * g.npad;
+    const size_t uu = (size_t)g.npairs * g.M * g.M;
+    w.B64 = bp.take<double>(nn);
+    w.V64 = bp.take<double>(nn);
+    w.U64 = bp.take<double>(uu);
+    if (mixed) {
+        w.X2 = bp.take<double>(nn);
+        w.R = bp.take<double>(nn);
+        w.B32 = bp.take<float>(nn);
+        w.V32 = bp.take<float>(nn);
+        w.U32 = bp.take<float>(uu);
+    }
+    w.partial = bp.take<double>(partial_count(g));
+    w.scal = bp.take<double>(8);
+    w.flags = bp.take<int>(8);
+    w.pairs = bp.take<int2>((size_t)(g.N - 1) * g.npairs);
+    w.btiles = bp.take<int2>((size_t)std::max(g.nbt, 1));
+    w.perm = bp.take<int>((size_t)std::max<int64_t>(n, 1));
+    w.wtmp = bp.take<double>((size_t)std::max<int64_t>(n, 1));
+    w.sg = bp.take<double>((size_t)std::max<int64_t>(n, 1));
+    return w;
+}
+
+struct SmallWs {
+    SmallDesc *desc;
+    int *queue;
+    double *vscratch, *info;
+    int32_t *status;
+};
+
+SmallWs layout_small(Bump &bp, int64_t count, int64_t n_max, int64_t slots)
+{
+    SmallWs w{};
+    const int64_t m = (n_max + 3) & ~3;
+    w.desc = bp.take<SmallDesc>((size_t)std::max<int64_t>(count, 1));
+    w.queue = bp.take<int>(4);
+    w.vscratch = bp.take<double>((size_t)slots * n_max * (m + 1));
+    w.info = bp.take<double>(8);
+    w.status = bp.take<int32_t>((size_t)std::max<int64_t>(count, 1));
+    return w;
+}
+
+int small_threads(int64_t n_max, int req) { return req ? req : (n_max > 64 ? 512 : 256); }
+
+// LDS pool (doubles) of the one-workgroup solver: S of the largest matrix,
+// plus its V when both fit the per-workgroup limit; otherwise as much as the
+// limit allows (smaller matrices of a batch then still keep V in LDS).
+// Returns 0 when S alone does not fit.
+int small_pool(int64_t n_max, int lds_max)
+{
+    const int m = (int)((n_max + 3) & ~3);
+    const int s = m * (m + 1);
+    const int want = s + (int)(n_max * (m + 1));
+    if (lds_max <= 0 || small_smem_bytes(m, want) <= (size_t)lds_max)
+        return want;
+    const size_t fixed = small_smem_bytes(m, 0);
+    if (fixed >= (size_t)lds_max)
+        return 0;
+    const int fit = (int)((lds_max - fixed) / sizeof(double));
+    return fit >= s ? fit : 0;
+}
+
+size_t small_slots(int64_t n_max, int count, int threads)
+{
+    DevInfo d = dev_info();
+    int cus = d.cus > 0 ? d.cus : 256;
+    const int m = (int)((n_max + 3) & ~3);
+    int per_cu = d.cus > 0 ? small_max_active(m, small_pool(n_max, d.lds_max), threads) : 1;
+    per_cu = std::max(per_cu, 1);
+    return (size_t)std::min<int64_t>((int64_t)cus * per_cu, std::max(count, 1));
+}
+
+size_t ws_small(int64_t count, int64_t n_max, int threads)
+{
+    Bump bp(nullptr);
+    layout_small(bp, count, n_max, (int64_t)small_slots(n_max, (int)count, threads));
+    return bp.off + 256;
+}
+
+size_t ws_block(int64_t n, const Opts &o, bool mixed)
+{
+    Bump bp(nullptr);
+    layout_block(bp, n, geometry(n, o.block), mixed);
+    return bp.off + 256;
+}
+
+void fill_tables(const Geometry &g, std::vector<int2> &pairs, std::vector<int2> &tiles)
+{
+    pairs.resize((size_t)(g.N - 1) * g.npairs);
+    for (int r = 0; r < g.N - 1; ++r)
+        for (int k = 0; k < g.npairs; ++k) {
+            int p, q;
+            rr_pair(k, r, g.N, p, q);
+            pairs[(size_t)r * g.npairs + k] = make_int2(p, q);
+        }
+    tiles.clear();
+    for (int k = 0; k < g.npairs; ++k)
+        for (int l = k + 1; l < g.npairs; ++l)
+            tiles.push_back(make_int2(k, l));
+    if (tiles.empty())
+        tiles.push_back(make_int2(0, 0));
+}
+
+struct Readback {
+    double scal[8];
+    int flags[8];
+};
+
+int read_scalars(const BlockWs &w, hipStream_t s, Readback &rb)
+{
+    CK(hipMemcpyAsync(rb.scal, w.scal, sizeof(rb.scal), hipMemcpyDeviceToHost, s));
+    CK(hipMemcpyAsync(rb.flags, w.flags, sizeof(rb.flags), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    return 0;
+}
+
+// Sweeps of the round-robin block Jacobi on (B, V) until off(B) <= tol.
+// fp32_stage: also stop when a sweep no longer decreases off (the FP32
+// rounding floor).  Returns a status; sweeps and final off through pointers.
+template <typename T>
+int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U, double tol,
+               double eps, int max_sweeps, int inner, bool fp32_stage, hipStream_t s,
+               int *sweeps_out, double *off_out, double *off0_out)
+{
+    Readback rb;
+    CK(launch_off2_partial<T>(B, g.npad, w.partial, s));
+    CK(launch_sum(w.partial, OFF_BLOCKS, w.scal + 1, s));
+    if (int e = read_scalars(w, s, rb))
+        return e;
+    double off = std::sqrt(rb.scal[1]);
+    if (off0_out)
+        *off0_out = off;
+    int sweeps = 0;
+    int status = JACOBI_OK;
+    const double thr = n > 0 ? tol / (double)n : 0.0;
+    while (off > tol) {
+        if (sweeps >= max_sweeps) {
+            status = JACOBI_NOCONV;
+            break;
+        }
+        CK(launch_fill_i32(w.flags + 2, 1, 0, s));
+        for (int r = 0; r < g.N - 1; ++r) {
+            const int2 *pr = w.pairs + (size_t)r * g.npairs;
+            CK(launch_pair_solve<T>(B, g.npad, g.b, g.npairs, pr, U, eps, thr, inner, w.partial,
+                                    w.flags + 2, s));
+            CK(launch_apply<T>(B, g.npad, V, g.npad, g.npad, g.b, g.npairs, pr, w.btiles, g.nbt,
+                               U, w.partial + g.npairs, r == g.N - 2, s));
+        }
+        CK(launch_sum(w.partial, (int64_t)g.npairs + g.nbt, w.scal + 1, s));
+        if (int e = read_scalars(w, s, rb))
+            return e;
+        ++sweeps;
+        const double prev = off;
+        off = std::sqrt(rb.scal[1]);
+        if (!std::isfinite(off)) {
+            status = JACOBI_NONFINITE;
+            break;
+        }
+        if (!rb.flags[2])
+            break; // no pair rotated: converged by the per-pair test
+        if (fp32_stage && off >= prev)
+            break;
+    }
+    *sweeps_out = sweeps;
+    *off_out = off;
+    return status;
+}
+
+int setup_block(const Geometry &g, const BlockWs &w, hipStream_t s)
+{
+    std::vector<int2> pairs, tiles;
+    fill_tables(g, pairs, tiles);
+    CK(hipMemcpyAsync(w.pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice,
+                      s));
+    CK(hipMemcpyAsync(w.btiles, tiles.data(), tiles.size() * sizeof(int2),
+                      hipMemcpyHostToDevice, s));
+    CK(launch_fill_i32(w.flags, 8, 0, s));
+    CK(hipStreamSynchronize(s)); // the host tables go out of scope
+    return 0;
+}
+
+int validate_common(const double *A, int64_t n, int64_t lda, double *W, double *V, int64_t ldv,
+                    double tol, const jacobi_opts *opts, Opts &o)
+{
+    if (n < 0)
+        return -2;
+    if (n > 0 && !A)
+        return -1;
+    if (lda < std::max<int64_t>(1, n))
+        return -3;
+    if (n > 0 && !W)
+        return -4;
+    if (n > 0 && !V)
+        return -5;
+    if (ldv < std::max<int64_t>(1, n))
+        return -6;
+    if (std::isnan(tol) || std::isinf(tol))
+        return -7;
+    if (resolve_opts(opts, o))
+        return -8;
+    if (n > (int64_t)1 << 20)
+        return -2;
+    return 0;
+}
+
+struct WsGuard {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    ~WsGuard()
+    {
+        if (p) {
+            hipStreamSynchronize(s);
+            hipFree(p);
+        }
+    }
+};
+
+void fill_info(jacobi_info *info, int sweeps, int sweeps32, int ns, int path, int block,
+               double normf, double tol, double off, double off32, double offc, double orth)
+{
+    if (!info)
+        return;
+    std::memset(info, 0, sizeof(*info));
+    info->sweeps = sweeps;
+    info->sweeps32 = sweeps32;
+    info->ns_iters = ns;
+    info->path = path;
+    info->block = block;
+    info->norm_f = normf;
+    info->tol = tol;
+    info->off_final = off;
+    info->off32 = off32;
+    info->off_cond = offc;
+    info->orth_ns = orth;
+}
+
+// ---- one matrix on the one-workgroup solver
+int eigh_small(const double *A, int64_t n, int64_t lda, double *W, double *V, int64_t ldv,
+               double tol, const Opts &o, void *work, hipStream_t s, jacobi_info *info)
+{
+    const int threads = small_threads(n, o.threads);
+    Bump bp(work);
+    SmallWs w = layout_small(bp, 1, n, 1);
+    SmallDesc d{};
+    d.a_off = 0;
+    d.w_off = 0;
+    d.v_off = 0;
+    d.n = (int)n;
+    d.lda = (int)lda;
+    d.ldv = (int)ldv;
+    d.orig = 0;
+    d.info = w.info;
+    CK(hipMemcpyAsync(w.desc, &d, sizeof(d), hipMemcpyHostToDevice, s));
+    CK(launch_fill_i32(w.queue, 1, 0, s));
+    const DevInfo dv = dev_info();
+    const int m = (int)((n + 3) & ~3);
+    const int pool = small_pool(n, dv.lds_max);
+    CK(launch_small(A, W, V, w.desc, 1, w.queue, tol, o.max_sweeps, w.vscratch,
+                    (int64_t)n * (m + 1), pool, m, threads, 1, w.status, s));
+    double hinfo[4] = {0, 0, 0, 0};
+    int32_t st = 0;
+    CK(hipMemcpyAsync(hinfo, w.info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+    CK(hipMemcpyAsync(&st, w.status, sizeof(st), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    fill_info(info, (int)hinfo[0], 0, 0, 0, 0, hinfo[1], hinfo[2], hinfo[3], 0, 0, 0);
+    return st;
+}
+
+int finalize_block(const Geometry &g, int64_t n, const BlockWs &w, const double *B,
+                   const double *Vin, double *W, double *V, int64_t ldv, hipStream_t s)
+{
+    CK(launch_fill_i32(w.perm, n, 0, s));
+    CK(launch_finalize(B, g.npad, Vin, g.npad, n, W, V, ldv, w.perm, w.wtmp, w.sg, s));
+    return 0;
+}
+
+int ingest_norm(const double *A, int64_t lda, int64_t n, const Geometry &g, const BlockWs &w,
+                double *B, int check_sym, hipStream_t s, double &normf)
+{
+    CK(launch_ingest<double>(A, lda, n, B, g.npad, w.partial, w.flags, check_sym, s));
+    CK(launch_sum(w.partial, INGEST_BLOCKS, w.scal, s));
+    Readback rb;
+    if (int e = read_scalars(w, s, rb))
+        return e;
+    if (rb.flags[0])
+        return JACOBI_NONFINITE;
+    if (check_sym && rb.flags[1])
+        return JACOBI_NOTSYM;
+    normf = std::sqrt(rb.scal[0]);
+    return 0;
+}
+
+int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, int64_t ldv,
+               double tol_in, const Opts &o, void *work, hipStream_t s, jacobi_info *info)
+{
+    const Geometry g = geometry(n, o.block);
+    Bump bp(work);
+    BlockWs w = layout_block(bp, n, g, false);
+    if (int e = setup_block(g, w, s))
+        return e;
+    double normf = 0.0;
+    if (int e = ingest_norm(A, lda, n, g, w, w.B64, o.check_sym, s, normf))
+        return e;
+    CK(launch_eye<double>(w.V64, g.npad, s));
+    const double tol = tol_in > 0.0 ? tol_in : 1e-15 * (double)n * normf;
+    int sweeps = 0;
+    double off = 0.0;
+    int st = run_sweeps<double>(g, n, w, w.B64, w.V64, w.U64, tol, U_D, o.max_sweeps, o.inner,
+                                false, s, &sweeps, &off, nullptr);
+    if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
+        return st;
+    if (int e = finalize_block(g, n, w, w.B64, w.V64, W, V, ldv, s))
+        return e;
+    CK(hipStreamSynchronize(s));
+    fill_info(info, sweeps, 0, 0, 1, g.b, normf, tol, off, 0, 0, 0);
+    return st;
+}
+
+int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double *V,
+                     int64_t ldv, double tol_in, const Opts &o, void *work, hipStream_t s,
+                     jacobi_info *info)
+{
+    const Geometry g = geometry(n, o.block);
+    Bump bp(work);
+    BlockWs w = layout_block(bp, n, g, true);
+    if (int e = setup_block(g, w, s))
+        return e;
+    const int64_t nn = g.npad * g.npad;
+    // ingest: A64 = sym(A) (kept for the preconditioning product), B32 = fl32(A64)
+    double *A64 = w.B64;
+    double normf = 0.0;
+    if (int e = ingest_norm(A, lda, n, g, w, A64, o.check_sym, s, normf))
+        return e;
+    CK(launch_cast_f32(A64, w.B32, nn, s));
+    CK(launch_eye<float>(w.V32, g.npad, s));
+    // stage 1: FP32 Jacobi -> Q_l
+    const double tol32 = o.c32 * (double)n * U_L * normf;
+    int sw32 = 0;
+    double off32 = 0.0;
+    int st32 = run_sweeps<float>(g, n, w, w.B32, w.V32, w.U32, tol32, U_L, o.max_sweeps,
+                                 o.inner, true, s, &sw32, &off32, nullptr);
+    if (st32 == JACOBI_DEVICE)
+        return st32;
+    // stage 2: Newton-Schulz, X <- X + X (I - X^T X) / 2  (= X (3I - X^T X) / 2)
+    double *X = w.V64, *X2 = w.X2, *R = w.R;
+    CK(launch_widen_f64(w.V32, X, nn, s));
+    const int fixed = o.ns_iters > 0 ? o.ns_iters : (n < 52000 ? 2 : 3);
+    const bool adaptive = o.ns_iters == -1;
+    const int max_it = adaptive ? 3 : fixed;
+    int ns = 0;
+    double orth = 0.0;
+    for (int it = 0; it < max_it; ++it) {
+        CK(launch_gemm64(1, 0, g.npad, g.npad, g.npad, -1.0, X, g.npad, 0, X, g.npad, 0, 0.0,
+                         nullptr, 0, 0, 1.0, R, g.npad, 0, 1, s));
+        if (adaptive || it == max_it - 1) {
+            CK(launch_sq_partial(R, nn, w.partial, s));
+            CK(launch_sum(w.partial, OFF_BLOCKS, w.scal + 2, s));
+            Readback rb;
+            if (int e = read_scalars(w, s, rb))
+                return e;
+            orth = std::sqrt(rb.scal[2]);
+            if (adaptive && orth <= (double)n * U_D)
+                break;
+        }
+        CK(launch_gemm64(0, 0, g.npad, g.npad, g.npad, 0.5, X, g.npad, 0, R, g.npad, 0, 1.0, X,
+                         g.npad, 0, 0.0, X2, g.npad, 0, 1, s));
+        std::swap(X, X2);
+        ++ns;
+    }
+    // stage 3: B = Q_d^T A Q_d (symmetrised), then FP64 Jacobi from V = Q_d
+    CK(launch_gemm64(0, 0, g.npad, g.npad, g.npad, 1.0, A64, g.npad, 0, X, g.npad, 0, 0.0,
+                     nullptr, 0, 0, 0.0, R, g.npad, 0, 1, s));
+    CK(launch_gemm64(1, 0, g.npad, g.npad, g.npad, 1.0, X, g.npad, 0, R, g.npad, 0, 0.0,
+                     nullptr, 0, 0, 0.0, A64, g.npad, 0, 1, s));
+    CK(launch_symmetrize(A64, g.npad, s));
+    const double tol = tol_in > 0.0 ? tol_in : 1e-15 * (double)n * normf;
+    int sw64 = 0;
+    double off = 0.0, offc = 0.0;
+    int st = run_sweeps<double>(g, n, w, A64, X, w.U64, tol, U_D, o.max_sweeps, o.inner, false,
+                                s, &sw64, &off, &offc);
+    if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
+        return st;
+    if (int e = finalize_block(g, n, w, A64, X, W, V, ldv, s))
+        return e;
+    CK(hipStreamSynchronize(s));
+    fill_info(info, sw64, sw32, ns, 1, g.b, normf, tol, off, off32, offc, orth);
+    return st;
+}
+
+} // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+const char *jacobi_version(void) { return "libjacobi 0.1 (gfx950)"; }
+
+const char *jacobi_status_string(int status)
+{
+    if (status < 0)
+        return "invalid argument";
+    switch (status) {
+    case JACOBI_OK:
+        return "ok";
+    case JACOBI_NOCONV:
+        return "not converged within max_sweeps";
+    case JACOBI_NOTSYM:
+        return "matrix is not symmetric";
+    case JACOBI_NONFINITE:
+        return "non-finite input";
+    case JACOBI_DEGENERATE:
+        return "degenerate eigenvalue gap in backward";
+    case JACOBI_DEVICE:
+        return "HIP runtime error";
+    case JACOBI_WORKSPACE:
+        return "workspace too small";
+    default:
+        return "unknown status";
+    }
+}
+
+size_t jacobi_workspace_bytes(int op, int64_t n_max, int64_t batch, const jacobi_opts *opts)
+{
+    Opts o;
+    if (resolve_opts(opts, o) || n_max < 0 || batch < 0)
+        return 0;
+    switch (op) {
+    case 0: {
+        size_t a = (n_max <= o.small_max_n) ? ws_small(1, std::max<int64_t>(n_max, 1),
+                                                       small_threads(n_max, o.threads))
+                                            : 0;
+        size_t b = ws_block(std::max<int64_t>(n_max, 1), o, false);
+        return std::max(a, b) + 256;
+    }
+    case 1:
+        return ws_block(std::max<int64_t>(n_max, 1), o, true) + 256;
+    case 2:
+        return ws_small(std::max<int64_t>(batch, 1), std::max<int64_t>(n_max, 1),
+                        small_threads(n_max, o.threads)) +
+               256;
+    case 3: {
+        size_t nn = (size_t)n_max * n_max * std::max<int64_t>(batch, 1);
+        return 2 * nn * sizeof(double) + 1024;
+    }
+    default:
+        return 0;
+    }
+}
+
+static int eigh_entry(bool mixed, const double *A, int64_t n, int64_t lda, double *W, double *V,
+                      int64_t ldv, double tol, const jacobi_opts *opts, void *work,
+                      size_t work_bytes, void *stream, jacobi_info *info)
+{
+    Opts o;
+    if (int e = validate_common(A, n, lda, W, V, ldv, tol, opts, o))
+        return e;
+    if (info)
+        std::memset(info, 0, sizeof(*info));
+    if (n == 0)
+        return JACOBI_OK;
+    hipStream_t s = (hipStream_t)stream;
+    bool small = !mixed && n <= o.small_max_n;
+    if (small && small_pool(n, dev_info().lds_max) == 0)
+        small = false; // the matrix does not fit one workgroup's LDS
+
+    const size_t need = jacobi_workspace_bytes(mixed ? 1 : 0, n, 1, opts);
+    WsGuard guard;
+    if (!work) {
+        CK(hipMalloc(&guard.p, need));
+        guard.s = s;
+        work = guard.p;
+    } else if (work_bytes < need) {
+        return JACOBI_WORKSPACE;
+    }
+    void *aligned = (void *)(((uintptr_t)work + 255) & ~(uintptr_t)255);
+    if (small)
+        return eigh_small(A, n, lda, W, V, ldv, tol, o, aligned, s, info);
+    if (mixed)
+        return eigh_mixed_block(A, n, lda, W, V, ldv, tol, o, aligned, s, info);
+    return eigh_block(A, n, lda, W, V, ldv, tol, o, aligned, s, info);
+}
+
+int jacobi_eigh(const double *A, int64_t n, int64_t lda, double *W, double *V, int64_t ldv,
+                double tol, const jacobi_opts *opts, void *work, size_t work_bytes,
+                void *stream, jacobi_info *info)
+{
+    return eigh_entry(false, A, n, lda, W, V, ldv, tol, opts, work, work_bytes, stream, info);
+}
+
+int jacobi_eigh_mixed(const double *A, int64_t n, int64_t lda, double *W, double *V,
+                      int64_t ldv, double tol, const jacobi_opts *opts, void *work,
+                      size_t work_bytes, void *stream, jacobi_info *info)
+{
+    return eigh_entry(true, A, n, lda, W, V, ldv, tol, opts, work, work_bytes, stream, info);
+}
+
+int jacobi_eigh_batched(const double *A, const int64_t *n, int64_t batch, double *W, double *V,
+                        double tol, int mixed, const jacobi_opts *opts, void *work,
+                        size_t work_bytes, void *stream, int32_t *status)
+{
+    if (batch < 0)
+        return -3;
+    if (batch > 0 && !n)
+        return -2;
+    int64_t n_max = 0;
+    for (int64_t i = 0; i < batch; ++i) {
+        if (n[i] < 1 || n[i] > 128)
+            return -2;
+        n_max = std::max(n_max, n[i]);
+    }
+    if (batch > 0 && !A)
+        return -1;
+    if (batch > 0 && !W)
+        return -4;
+    if (batch > 0 && !V)
+        return -5;
+    if (std::isnan(tol) || std::isinf(tol))
+        return -6;
+    if (mixed != 0)
+        return -7;
+    Opts o;
+    if (resolve_opts(opts, o))
+        return -8;
+    if (batch == 0)
+        return JACOBI_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t need = jacobi_workspace_bytes(2, n_max, batch, opts);
+    WsGuard guard;
+    if (!work) {
+        CK(hipMalloc(&guard.p, need));
+        guard.s = s;
+        work = guard.p;
+    } else if (work_bytes < need) {
+        return JACOBI_WORKSPACE;
+    }
+    void *aligned = (void *)(((uintptr_t)work + 255) & ~(uintptr_t)255);
+    const int threads = small_threads(n_max, o.threads);
+    const int64_t slots = (int64_t)small_slots(n_max, (int)batch, threads);
+    Bump bp(aligned);
+    SmallWs w = layout_small(bp, batch, n_max, slots);
+    // descriptors: packed offsets in input order, queue order = n descending
+    std::vector<SmallDesc> d((size_t)batch);
+    int64_t ao = 0, wo = 0;
+    for (int64_t i = 0; i < batch; ++i) {
+        SmallDesc &e = d[(size_t)i];
+        e.a_off = ao;
+        e.v_off = ao;
+        e.w_off = wo;
+        e.n = (int)n[i];
+        e.lda = (int)n[i];
+        e.ldv = (int)n[i];
+        e.orig = (int)i;
+        e.info = nullptr;
+        ao += n[i] * n[i];
+        wo += n[i];
+    }
+    std::stable_sort(d.begin(), d.end(),
+                     [](const SmallDesc &a, const SmallDesc &b) { return a.n > b.n; });
+    CK(hipMemcpyAsync(w.desc, d.data(), d.size() * sizeof(SmallDesc), hipMemcpyHostToDevice, s));
+    CK(launch_fill_i32(w.queue, 1, 0, s));
+    CK(launch_fill_i32(w.status, batch, 0, s));
+    const int m = (int)((n_max + 3) & ~3);
+    const DevInfo dv = dev_info();
+    const int pool = small_pool(n_max, dv.lds_max);
+    if (pool == 0) {
+        g_last_error = hipErrorInvalidConfiguration;
+        return JACOBI_DEVICE; // the largest matrix does not fit one workgroup's LDS
+    }
+    CK(launch_small(A, W, V, w.desc, (int)batch, w.queue, tol, o.max_sweeps, w.vscratch,
+                    n_max * (m + 1), pool, m, threads, (int)slots, w.status, s));
+    std::vector<int32_t> st((size_t)batch);
+    CK(hipMemcpyAsync(st.data(), w.status, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                      s));
+    if (status)
+        CK(hipMemcpyAsync(status, w.status, st.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, s));
+    CK(hipStreamSynchronize(s));
+    int worst = 0;
+    for (int32_t v : st)
+        worst = std::max(worst, (int)v);
+    return worst;
+}
+
+int jacobi_eigh_backward(const double *W, const double *V, const double *dW, const double *dV,
+                         int64_t n, int64_t batch, double *dA, double gap_tol, void *work,
+                         size_t work_bytes, void *stream)
+{
+    if (n < 0)
+        return -5;
+    if (batch < 0)
+        return -6;
+    if (n > 0 && batch > 0) {
+        if (!W)
+            return -1;
+        if (!V)
+            return -2;
+        if (!dA)
+            return -7;
+    }
+    if (std::isnan(gap_tol) || gap_tol < 0.0)
+        return -8;
+    if (n == 0 || batch == 0)
+        return JACOBI_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t need = jacobi_workspace_bytes(3, n, batch, nullptr);
+    WsGuard guard;
+    if (!work) {
+        CK(hipMalloc(&guard.p, need));
+        guard.s = s;
+        work = guard.p;
+    } else if (work_bytes < need) {
+        return JACOBI_WORKSPACE;
+    }
+    void *aligned = (void *)(((uintptr_t)work + 255) & ~(uintptr_t)255);
+    Bump bp(aligned);
+    const int64_t nn = n * n;
+    double *Mb = bp.take<double>((size_t)(nn * batch));
+    double *Tb = bp.take<double>((size_t)(nn * batch));
+    int *flag = bp.take<int>(4);
+    CK(launch_fill_i32(flag, 1, 0, s));
+    if (dV)
+        CK(launch_gemm64(1, 0, n, n, n, 1.0, V, n, nn, dV, n, nn, 0.0, nullptr, 0, 0, 0.0, Mb, n,
+                         nn, batch, s));
+    CK(launch_adjoint_mid(Mb, W, dW, n, batch, gap_tol, dV != nullptr, flag, s));
+    CK(launch_gemm64(0, 0, n, n, n, 1.0, V, n, nn, Mb, n, nn, 0.0, nullptr, 0, 0, 0.0, Tb, n, nn,
+                     batch, s));
+    CK(launch_gemm64(0, 1, n, n, n, 1.0, Tb, n, nn, V, n, nn, 0.0, nullptr, 0, 0, 0.0, Mb, n, nn,
+                     batch, s));
+    CK(launch_sym_out(Mb, dA, n, batch, s));
+    int hflag = 0;
+    CK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    return hflag ? JACOBI_DEGENERATE : JACOBI_OK;
+}
+
+int jacobi_device_summary(char *buf, size_t len)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return JACOBI_DEVICE;
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess)
+        return JACOBI_DEVICE;
+    int optin = 0;
+    hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev);
+    if (buf && len)
+        std::snprintf(buf, len,
+                      "%s arch=%s cus=%d lds_per_block=%zu lds_optin=%d clock_khz=%d "
+                      "mem_clock_khz=%d bus_bits=%d l2=%d",
+                      p.name, p.gcnArchName, p.multiProcessorCount, (size_t)p.sharedMemPerBlock,
+                      optin, p.clockRate, p.memoryClockRate, p.memoryBusWidth, p.l2CacheSize);
+    return 0;
+}
+
+const char *jacobi_last_hip_error(void) { return hipGetErrorString(g_last_error); }
+
+} // extern "C"

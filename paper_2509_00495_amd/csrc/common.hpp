@@ -1,0 +1,149 @@
+// Device-side building blocks shared by the libjacobi kernels (gfx950).
+//
+// Nothing here is shared with the CPU oracle: the oracle lives in its own
+// C file and is only used by the tests.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lj {
+
+constexpr int WAVE = 64;
+
+// Round-robin ("circle") schedule for m players, m even: in round r
+// (0 <= r < m-1) slot 0 holds player 0 and slot i >= 1 holds player
+// 1 + ((i - 1 + r) mod (m - 1)); slot k is paired with slot m-1-k.  Over
+// m-1 rounds every unordered pair of players meets exactly once, and the
+// m/2 pairs of one round are disjoint, so their rotations commute and can
+// be applied together (the parallel ordering that replaces the paper's
+// cyclic-by-row sequence of Section 3.3).
+__host__ __device__ inline int rr_player(int slot, int r, int m)
+{
+    return slot == 0 ? 0 : 1 + (slot - 1 + r) % (m - 1);
+}
+
+__host__ __device__ inline void rr_pair(int k, int r, int m, int &p, int &q)
+{
+    int a = rr_player(k, r, m);
+    int b = rr_player(m - 1 - k, r, m);
+    p = a < b ? a : b;
+    q = a < b ? b : a;
+}
+
+// Map idx in [0, h/2 * (h+1)) to (k, l), 0 <= k <= l < h, h even: row rho of
+// the folded rectangle holds the upper-triangle rows rho and h-1-rho.
+__device__ inline void tri_fold(int idx, int h, int &k, int &l)
+{
+    int w = h + 1;
+    int rho = idx / w;
+    int c = idx - rho * w;
+    if (c < h - rho) {
+        k = rho;
+        l = rho + c;
+    } else {
+        k = h - 1 - rho;
+        l = k + (c - (h - rho));
+    }
+}
+
+// Rotation that annihilates a_pq of a symmetric 2x2 problem (Algorithm 2,
+// Section 3.1.1), with t = 1/(tau +- sqrt(1 + tau^2)) (approach 2 of
+// Appendix A) so that |t| <= 1.  J = [c s; -s c]; after J^T A J the diagonal
+// is (a_pp - t a_pq, a_qq + t a_pq).  Computed in FP64 for both precisions.
+__device__ inline void jacobi_angle(double app, double aqq, double apq,
+                                    double &c, double &s, double &t)
+{
+    double tau = (aqq - app) / (2.0 * apq);
+    double root = sqrt(1.0 + tau * tau);
+    t = 1.0 / (tau >= 0.0 ? tau + root : tau - root);
+    c = 1.0 / sqrt(1.0 + t * t);
+    s = t * c;
+}
+
+// Per-pair test: rotate only when a_pq is not negligible relative to the
+// diagonal (the per-pair threshold of Algorithm 4 with tol = eps) and above
+// the absolute floor thr = tol_off / n (if every |a_pq| <= tol_off / n then
+// off(B) <= tol_off already).
+__device__ inline bool jacobi_should_rotate(double app, double aqq, double apq,
+                                            double eps, double thr)
+{
+    double a = fabs(apq);
+    return apq != 0.0 && a > thr && a > eps * sqrt(fabs(app * aqq));
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+// Block-wide sum; every thread gets the result.  `red` is LDS scratch of at
+// least NT/WAVE entries.  Deterministic: fixed shuffle tree, then waves in
+// order.
+template <int NT>
+__device__ inline double block_sum(double v, double *red)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    __syncthreads();
+    if (lane == 0)
+        red[w] = v;
+    __syncthreads();
+    double tot = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / WAVE; ++i)
+        tot += red[i];
+    __syncthreads();
+    return tot;
+}
+
+template <int NT>
+__device__ inline int block_or(int v, int *red)
+{
+    v = __any(v) ? 1 : 0;
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    __syncthreads();
+    if (lane == 0)
+        red[w] = v;
+    __syncthreads();
+    int tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / WAVE; ++i)
+        tot |= red[i];
+    __syncthreads();
+    return tot;
+}
+
+// ---------------------------------------------------------------- MFMA
+// 16x16x4 MFMA on one wavefront: D(16x16) += A(16x4) * B(4x16).
+// Operand layout: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// the accumulator holds D[4 * (l / 16) + v][l % 16] in element v (v = 0..3).
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline d4 mfma16(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ inline f4 mfma16(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+struct acc4;
+template <>
+struct acc4<double> {
+    typedef d4 type;
+};
+template <>
+struct acc4<float> {
+    typedef f4 type;
+};
+
+} // namespace lj

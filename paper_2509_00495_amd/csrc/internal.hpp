@@ -1,0 +1,74 @@
+// Internal declarations of libjacobi: kernel descriptors and launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/jacobi.h"
+
+namespace lj {
+
+// One matrix of the one-workgroup solver.  Offsets are in doubles from the
+// base pointers passed to the launch.
+struct SmallDesc {
+    int64_t a_off, w_off, v_off;
+    int32_t n, lda, ldv, orig;
+    double *info; // optional device output: sweeps, ||A||_F, tol, off
+};
+
+// ---- one-workgroup solver (kernels_small.hip)
+size_t small_smem_bytes(int m_max, int pool);
+hipError_t launch_small(const double *A, double *W, double *V, const SmallDesc *desc,
+                        int count, int *queue, double tol, int max_sweeps,
+                        double *vscratch, int64_t vscratch_stride, int pool,
+                        int m_max, int nthreads, int grid, int32_t *status,
+                        hipStream_t stream);
+int small_max_active(int m_max, int pool, int nthreads);
+
+// ---- block path (kernels_block.hip); T = double or float
+template <typename T>
+hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
+                             T *U, double eps, double thr, int inner, double *partial,
+                             int *rot_flag, hipStream_t s);
+template <typename T>
+hipError_t launch_apply(T *B, int64_t ldb, T *V, int64_t ldv, int64_t nrows, int b,
+                        int npairs, const int2 *pairs, const int2 *btiles, int nbt,
+                        const T *U, double *partial, int want_off, hipStream_t s);
+hipError_t launch_sum(const double *x, int64_t count, double *out, hipStream_t s);
+template <typename T>
+hipError_t launch_ingest(const double *A, int64_t lda, int64_t n, T *B, int64_t npad,
+                         double *norm_partial, int *flags, int check_sym, hipStream_t s);
+template <typename T>
+hipError_t launch_eye(T *V, int64_t npad, hipStream_t s);
+template <typename T>
+hipError_t launch_off2_partial(const T *B, int64_t npad, double *partial, hipStream_t s);
+hipError_t launch_fill_i32(int *p, int64_t count, int value, hipStream_t s);
+hipError_t launch_cast_f32(const double *src, float *dst, int64_t count, hipStream_t s);
+hipError_t launch_widen_f64(const float *src, double *dst, int64_t count, hipStream_t s);
+hipError_t launch_symmetrize(double *B, int64_t npad, hipStream_t s);
+hipError_t launch_finalize(const double *B, int64_t ldb, const double *V, int64_t ldv_in,
+                           int64_t n, double *W, double *Vout, int64_t ldv, int *perm,
+                           double *wtmp, double *sg, hipStream_t s);
+constexpr int INGEST_BLOCKS = 1024;
+constexpr int OFF_BLOCKS = 1024;
+
+// ---- FP64 GEMM (kernels_gemm.hip)
+// C = alpha * op(A) * op(B) + beta * C0 + gamma * I, all row-major FP64,
+// batched over `batch` with element strides sA, sB, sC, sC0.
+hipError_t launch_gemm64(int transA, int transB, int64_t M, int64_t N, int64_t K,
+                         double alpha, const double *A, int64_t lda, int64_t sA,
+                         const double *B, int64_t ldb, int64_t sB, double beta,
+                         const double *C0, int64_t ldc0, int64_t sC0, double gamma,
+                         double *C, int64_t ldc, int64_t sC, int64_t batch,
+                         hipStream_t s);
+hipError_t launch_sq_partial(const double *X, int64_t count, double *partial,
+                             hipStream_t s);
+// backward elementwise: M <- diag(dW) + F o M (F from gaps), flags DEGENERATE
+hipError_t launch_adjoint_mid(double *M, const double *W, const double *dW, int64_t n,
+                              int64_t batch, double gap_tol, int has_dv, int *flag,
+                              hipStream_t s);
+hipError_t launch_sym_out(const double *G, double *dA, int64_t n, int64_t batch,
+                          hipStream_t s);
+
+} // namespace lj

@@ -1,0 +1,219 @@
+// FP64 MFMA GEMM used by the Newton-Schulz step, the preconditioning product
+// Q_d^T A Q_d and the adjoint, plus the small elementwise kernels of the
+// adjoint.
+//
+//   C = alpha * op(A) * op(B) + beta * C0 + gamma * I      (row-major)
+//
+// Workgroup tile 64 x 64 (4 waves, each 32 x 32 = 2 x 2 MFMA 16x16x4 tiles),
+// K staged through LDS 16 at a time; batched over blockIdx.z.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace lj {
+
+constexpr int GT = 64;  // tile edge
+constexpr int GK = 16;  // k per stage
+constexpr int GLD = GT + 1;
+
+template <int TA, int TB>
+__global__ __launch_bounds__(256) void gemm64_kernel(int64_t M, int64_t N, int64_t K, double alpha,
+                                                     const double *__restrict__ A, int64_t lda,
+                                                     int64_t sA, const double *__restrict__ B,
+                                                     int64_t ldb, int64_t sB, double beta,
+                                                     const double *__restrict__ C0, int64_t ldc0,
+                                                     int64_t sC0, double gamma,
+                                                     double *__restrict__ C, int64_t ldc,
+                                                     int64_t sC)
+{
+    __shared__ double As[GK * GLD]; // As[kk][i]
+    __shared__ double Bs[GK * GLD]; // Bs[kk][j]
+    const int tid = threadIdx.x;
+    const int lane = tid % WAVE, w = tid / WAVE;
+    const int li = lane % 16, lk = lane / 16;
+    const int64_t z = blockIdx.z;
+    A += z * sA;
+    B += z * sB;
+    C += z * sC;
+    if (C0)
+        C0 += z * sC0;
+    const int64_t i0 = (int64_t)blockIdx.y * GT, j0 = (int64_t)blockIdx.x * GT;
+    const int row0 = (w / 2) * 32, col0 = (w % 2) * 32;
+    d4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                acc[a][b][v] = 0.0;
+    for (int64_t k0 = 0; k0 < K; k0 += GK) {
+#pragma unroll
+        for (int e = tid; e < GT * GK; e += 256) {
+            int i, kk;
+            double va;
+            if (!TA) { // A is M x K: read along k
+                i = e / GK;
+                kk = e % GK;
+                int64_t gi = i0 + i, gk = k0 + kk;
+                va = (gi < M && gk < K) ? A[gi * lda + gk] : 0.0;
+            } else { // A is K x M: read along i
+                kk = e / GT;
+                i = e % GT;
+                int64_t gi = i0 + i, gk = k0 + kk;
+                va = (gi < M && gk < K) ? A[gk * lda + gi] : 0.0;
+            }
+            As[kk * GLD + i] = va;
+            int j;
+            double vb;
+            if (!TB) { // B is K x N: read along j
+                kk = e / GT;
+                j = e % GT;
+                int64_t gj = j0 + j, gk = k0 + kk;
+                vb = (gj < N && gk < K) ? B[gk * ldb + gj] : 0.0;
+            } else { // B is N x K: read along k
+                j = e / GK;
+                kk = e % GK;
+                int64_t gj = j0 + j, gk = k0 + kk;
+                vb = (gj < N && gk < K) ? B[gj * ldb + gk] : 0.0;
+            }
+            Bs[kk * GLD + j] = vb;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < GK; kb += 4) {
+            const int kk = kb + lk;
+            double a0 = As[kk * GLD + row0 + li], a1 = As[kk * GLD + row0 + 16 + li];
+            double b0 = Bs[kk * GLD + col0 + li], b1 = Bs[kk * GLD + col0 + 16 + li];
+            acc[0][0] = mfma16(a0, b0, acc[0][0]);
+            acc[0][1] = mfma16(a0, b1, acc[0][1]);
+            acc[1][0] = mfma16(a1, b0, acc[1][0]);
+            acc[1][1] = mfma16(a1, b1, acc[1][1]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int64_t gi = i0 + row0 + a * 16 + 4 * lk + v;
+                int64_t gj = j0 + col0 + b * 16 + li;
+                if (gi < M && gj < N) {
+                    double r = alpha * acc[a][b][v];
+                    if (beta != 0.0)
+                        r += beta * C0[gi * ldc0 + gj];
+                    if (gi == gj)
+                        r += gamma;
+                    C[gi * ldc + gj] = r;
+                }
+            }
+}
+
+hipError_t launch_gemm64(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha,
+                         const double *A, int64_t lda, int64_t sA, const double *B, int64_t ldb,
+                         int64_t sB, double beta, const double *C0, int64_t ldc0, int64_t sC0,
+                         double gamma, double *C, int64_t ldc, int64_t sC, int64_t batch,
+                         hipStream_t s)
+{
+    if (M <= 0 || N <= 0 || batch <= 0)
+        return hipSuccess;
+    dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT), (unsigned)batch);
+    if (!transA && !transB)
+        hipLaunchKernelGGL((gemm64_kernel<0, 0>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
+                           sA, B, ldb, sB, beta, C0, ldc0, sC0, gamma, C, ldc, sC);
+    else if (transA && !transB)
+        hipLaunchKernelGGL((gemm64_kernel<1, 0>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
+                           sA, B, ldb, sB, beta, C0, ldc0, sC0, gamma, C, ldc, sC);
+    else if (!transA && transB)
+        hipLaunchKernelGGL((gemm64_kernel<0, 1>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
+                           sA, B, ldb, sB, beta, C0, ldc0, sC0, gamma, C, ldc, sC);
+    else
+        hipLaunchKernelGGL((gemm64_kernel<1, 1>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
+                           sA, B, ldb, sB, beta, C0, ldc0, sC0, gamma, C, ldc, sC);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void sq_partial_kernel(const double *__restrict__ X,
+                                                         int64_t count,
+                                                         double *__restrict__ partial)
+{
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256)
+        acc += X[e] * X[e];
+    acc = wave_sum(acc);
+    if (threadIdx.x % WAVE == 0)
+        red[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+hipError_t launch_sq_partial(const double *X, int64_t count, double *partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(sq_partial_kernel, dim3(OFF_BLOCKS), dim3(256), 0, s, X, count, partial);
+    return hipGetLastError();
+}
+
+// M <- diag(dW) + F o M with F_ij = 1/(W_j - W_i) (i != j), F_ii = 0; a pair
+// closer than gap_tol contributes 0 and raises the DEGENERATE flag when its
+// coupling is nonzero.
+__global__ __launch_bounds__(256) void adjoint_mid_kernel(double *__restrict__ Mm,
+                                                          const double *__restrict__ W,
+                                                          const double *__restrict__ dW,
+                                                          int64_t n, int64_t batch,
+                                                          double gap_tol, int has_dv, int *flag)
+{
+    const int64_t total = batch * n * n;
+    int degen = 0;
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        int64_t z = e / (n * n), r = e - z * n * n;
+        int64_t i = r / n, j = r - (r / n) * n;
+        double m;
+        if (i == j) {
+            m = dW ? dW[z * n + i] : 0.0;
+        } else {
+            double mv = has_dv ? Mm[e] : 0.0;
+            double gap = W[z * n + j] - W[z * n + i];
+            if (fabs(gap) < gap_tol) {
+                if (mv != 0.0)
+                    degen = 1;
+                m = 0.0;
+            } else {
+                m = mv / gap;
+            }
+        }
+        Mm[e] = m;
+    }
+    if (__any(degen) && threadIdx.x % WAVE == 0)
+        atomicOr(flag, 1);
+}
+
+hipError_t launch_adjoint_mid(double *M, const double *W, const double *dW, int64_t n,
+                              int64_t batch, double gap_tol, int has_dv, int *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(adjoint_mid_kernel, dim3(2048), dim3(256), 0, s, M, W, dW, n, batch,
+                       gap_tol, has_dv, flag);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void sym_out_kernel(const double *__restrict__ G,
+                                                      double *__restrict__ dA, int64_t n,
+                                                      int64_t batch)
+{
+    const int64_t total = batch * n * n;
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        int64_t z = e / (n * n), r = e - z * n * n;
+        int64_t i = r / n, j = r - (r / n) * n;
+        dA[e] = 0.5 * (G[e] + G[z * n * n + j * n + i]);
+    }
+}
+
+hipError_t launch_sym_out(const double *G, double *dA, int64_t n, int64_t batch, hipStream_t s)
+{
+    hipLaunchKernelGGL(sym_out_kernel, dim3(2048), dim3(256), 0, s, G, dA, n, batch);
+    return hipGetLastError();
+}
+
+} // namespace lj

@@ -1,0 +1,186 @@
+// One-workgroup Jacobi solver: the whole (symmetrised) matrix lives in LDS and
+// a workgroup runs complete sweeps of the parallel round-robin ordering until
+// off(B) <= tol (Algorithm 4, Section 3.3, with the parallel ordering of
+// lds_jacobi_round).  Persistent: each workgroup pops matrices from a device
+// work queue (descriptors sorted by n, largest first), so one launch solves a
+// whole batch of matrices of uneven order.
+#include "internal.hpp"
+#include "lds_jacobi.hpp"
+
+namespace lj {
+
+template <int NT>
+__global__ __launch_bounds__(NT) void small_jacobi_kernel(
+    const double *__restrict__ A, double *__restrict__ W, double *__restrict__ Vout,
+    const SmallDesc *__restrict__ desc, int count, int *queue, double tol_in,
+    int max_sweeps, double *__restrict__ vscratch, int64_t vscratch_stride,
+    int pool, int m_max, int32_t *status)
+{
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x;
+    double *S = smem;                                  // pool: S, then V if it fits
+    double *cs = smem + pool;                          // 3 * m_max / 2
+    double *wv = cs + 3 * (m_max / 2);                 // m_max
+    double *sg = wv + m_max;                           // m_max
+    double *red = sg + m_max;                          // 16
+    int *perm = (int *)(red + 16);                     // m_max
+    int *slot = perm + m_max;                          // 1
+    int *ired = slot + 1;                              // 16
+
+    for (;;) {
+        if (tid == 0)
+            *slot = atomicAdd(queue, 1);
+        __syncthreads();
+        const int it = *slot;
+        __syncthreads();
+        if (it >= count)
+            break;
+        const SmallDesc d = desc[it];
+        const int n = d.n;
+        const int m = (n + 3) & ~3;
+        const int ld = m + 1;
+        const double *Ai = A + d.a_off;
+
+        // ingest: S = (A + A^T)/2, zero padding to m
+        double nrm = 0.0;
+        int finite = 1;
+        for (int idx = tid; idx < m * m; idx += NT) {
+            int i = idx / m, j = idx - (idx / m) * m;
+            double v = 0.0;
+            if (i < n && j < n) {
+                double a = Ai[(int64_t)i * d.lda + j], b = Ai[(int64_t)j * d.lda + i];
+                v = 0.5 * (a + b);
+                if (!isfinite(a))
+                    finite = 0;
+            }
+            S[i * ld + j] = v;
+            nrm += v * v;
+        }
+        const double nrm2 = block_sum<NT>(nrm, red);
+        const int bad = block_or<NT>(!finite, ired);
+        if (bad) {
+            if (tid == 0 && status)
+                status[d.orig] = JACOBI_NONFINITE;
+            continue;
+        }
+        const bool v_lds = (int64_t)(m + n) * ld <= pool;
+        double *V = v_lds ? S + m * ld : vscratch + (int64_t)blockIdx.x * vscratch_stride;
+        const int ldv = ld;
+        for (int idx = tid; idx < n * ld; idx += NT) {
+            int i = idx / ld, j = idx - (idx / ld) * ld;
+            V[idx] = (i == j) ? 1.0 : 0.0;
+        }
+        const double tol = tol_in > 0.0 ? tol_in : 1e-15 * (double)n * sqrt(nrm2);
+        const double thr = n > 0 ? tol / (double)n : 0.0;
+        const double eps = 0x1p-53;
+        __syncthreads();
+        double off2 = lds_off2<double, NT>(S, ld, m, red);
+        int sweeps = 0, any = 1;
+        while (off2 > tol * tol && sweeps < max_sweeps && any) {
+            int rot = 0;
+            for (int r = 0; r < m - 1; ++r)
+                rot |= lds_jacobi_round<double, NT>(S, ld, m, r, eps, thr, V, ldv, n, cs);
+            any = block_or<NT>(rot, ired);
+            ++sweeps;
+            off2 = lds_off2<double, NT>(S, ld, m, red);
+        }
+        // output: W ascending (stable), columns permuted and sign-fixed
+        for (int i = tid; i < m; i += NT) {
+            perm[i] = i < n ? i : 0;
+            if (i < n)
+                wv[i] = S[i * ld + i];
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += NT) {
+            double wi = wv[i];
+            int rank = 0;
+            for (int j = 0; j < n; ++j) {
+                double wj = wv[j];
+                rank += (wj < wi) || (wj == wi && j < i);
+            }
+            perm[rank] = i;
+        }
+        __syncthreads();
+        for (int c = tid; c < n; c += NT) {
+            int col = perm[c];
+            double best = -1.0, val = 0.0;
+            for (int i = 0; i < n; ++i) {
+                double v = V[(int64_t)i * ldv + col];
+                if (fabs(v) > best) {
+                    best = fabs(v);
+                    val = v;
+                }
+            }
+            sg[c] = val < 0.0 ? -1.0 : 1.0;
+            W[d.w_off + c] = wv[col];
+        }
+        __syncthreads();
+        double *Vo = Vout + d.v_off;
+        for (int idx = tid; idx < n * n; idx += NT) {
+            int i = idx / n, c = idx - (idx / n) * n;
+            Vo[(int64_t)i * d.ldv + c] = sg[c] * V[(int64_t)i * ldv + perm[c]];
+        }
+        if (tid == 0) {
+            int st = (off2 <= tol * tol || !any) ? JACOBI_OK : JACOBI_NOCONV;
+            if (status)
+                status[d.orig] = st;
+            if (d.info) {
+                d.info[0] = (double)sweeps;
+                d.info[1] = sqrt(nrm2);
+                d.info[2] = tol;
+                d.info[3] = sqrt(off2);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+size_t small_smem_bytes(int m_max, int pool)
+{
+    size_t d = (size_t)pool + 3 * (m_max / 2) + 2 * m_max + 16;
+    return d * sizeof(double) + (size_t)(m_max + 1 + 16) * sizeof(int);
+}
+
+hipError_t launch_small(const double *A, double *W, double *V, const SmallDesc *desc,
+                        int count, int *queue, double tol, int max_sweeps,
+                        double *vscratch, int64_t vscratch_stride, int pool,
+                        int m_max, int nthreads, int grid, int32_t *status,
+                        hipStream_t stream)
+{
+    size_t smem = small_smem_bytes(m_max, pool);
+    if (nthreads == 512) {
+        auto k = small_jacobi_kernel<512>;
+        hipError_t e = hipFuncSetAttribute((const void *)k,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)smem);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(512), smem, stream, A, W, V, desc, count,
+                           queue, tol, max_sweeps, vscratch, vscratch_stride, pool, m_max,
+                           status);
+    } else {
+        auto k = small_jacobi_kernel<256>;
+        hipError_t e = hipFuncSetAttribute((const void *)k,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)smem);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(256), smem, stream, A, W, V, desc, count,
+                           queue, tol, max_sweeps, vscratch, vscratch_stride, pool, m_max,
+                           status);
+    }
+    return hipGetLastError();
+}
+
+int small_max_active(int m_max, int pool, int nthreads)
+{
+    size_t smem = small_smem_bytes(m_max, pool);
+    int nb = 0;
+    if (nthreads == 512)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, small_jacobi_kernel<512>, 512, smem);
+    else
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, small_jacobi_kernel<256>, 256, smem);
+    return nb;
+}
+
+} // namespace lj

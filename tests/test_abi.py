@@ -1,0 +1,136 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/jacobi.h, and rejects bad arguments on the host before
+anything is launched."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def pj():
+    import paper_2509_00495_amd as pj
+    if not os.path.exists(pj.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return pj
+
+
+@pytest.fixture(scope="module")
+def lib(pj):
+    return pj.jacobi._lib()
+
+
+def test_every_declared_symbol_is_exported(pj, lib):
+    names = pj.declared_functions()
+    assert set(names) >= {"jacobi_eigh", "jacobi_eigh_mixed", "jacobi_eigh_batched",
+                          "jacobi_eigh_backward", "jacobi_workspace_bytes",
+                          "jacobi_status_string", "jacobi_version"}
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_exports_match_header_exactly(pj):
+    """Every exported jacobi_* symbol is declared in the header."""
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", pj.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = sorted(set(re.findall(r"\bT (jacobi_[a-z_0-9]+)$", out, flags=re.M)))
+    assert exported == pj.declared_functions()
+
+
+def test_status_strings(lib):
+    for st in range(7):
+        assert lib.jacobi_status_string(st)
+    assert lib.jacobi_status_string(-3) == b"invalid argument"
+
+
+def _eigh(lib, fn, A, n, lda, W, V, ldv, tol, opts=None):
+    return getattr(lib, fn)(A, n, lda, W, V, ldv, tol,
+                            ctypes.byref(opts) if opts is not None else None,
+                            None, 0, None, None)
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("fn", ["jacobi_eigh", "jacobi_eigh_mixed"])
+def test_eigh_argument_validation(lib, pj, fn):
+    assert _eigh(lib, fn, FAKE, -1, 1, FAKE, FAKE, 1, 0.0) == -2
+    assert _eigh(lib, fn, None, 4, 4, FAKE, FAKE, 4, 0.0) == -1
+    assert _eigh(lib, fn, FAKE, 4, 3, FAKE, FAKE, 4, 0.0) == -3
+    assert _eigh(lib, fn, FAKE, 4, 4, None, FAKE, 4, 0.0) == -4
+    assert _eigh(lib, fn, FAKE, 4, 4, FAKE, None, 4, 0.0) == -5
+    assert _eigh(lib, fn, FAKE, 4, 4, FAKE, FAKE, 2, 0.0) == -6
+    assert _eigh(lib, fn, FAKE, 4, 4, FAKE, FAKE, 4, float("nan")) == -7
+    assert _eigh(lib, fn, FAKE, 4, 4, FAKE, FAKE, 4, float("inf")) == -7
+    for bad in (dict(block=48), dict(threads=100), dict(max_sweeps=-1), dict(c32=-1.0),
+                dict(ns_iters=-2), dict(inner_sweeps=-1), dict(small_max_n=500)):
+        assert _eigh(lib, fn, FAKE, 4, 4, FAKE, FAKE, 4, 0.0, pj.make_opts(**bad)) == -8, bad
+    # n = 0 is a no-op that touches nothing
+    assert _eigh(lib, fn, None, 0, 1, None, None, 1, 0.0) == 0
+
+
+def test_batched_argument_validation(lib):
+    n = (ctypes.c_int64 * 3)(4, 0, 5)
+    assert lib.jacobi_eigh_batched(FAKE, n, 3, FAKE, FAKE, 0.0, 0, None, None, 0, None,
+                                   None) == -2
+    n = (ctypes.c_int64 * 2)(4, 129)
+    assert lib.jacobi_eigh_batched(FAKE, n, 2, FAKE, FAKE, 0.0, 0, None, None, 0, None,
+                                   None) == -2
+    n = (ctypes.c_int64 * 2)(4, 5)
+    assert lib.jacobi_eigh_batched(FAKE, n, -1, FAKE, FAKE, 0.0, 0, None, None, 0, None,
+                                   None) == -3
+    assert lib.jacobi_eigh_batched(None, n, 2, FAKE, FAKE, 0.0, 0, None, None, 0, None,
+                                   None) == -1
+    assert lib.jacobi_eigh_batched(FAKE, n, 2, FAKE, FAKE, float("nan"), 0, None, None, 0,
+                                   None, None) == -6
+    assert lib.jacobi_eigh_batched(FAKE, n, 2, FAKE, FAKE, 0.0, 1, None, None, 0, None,
+                                   None) == -7
+    assert lib.jacobi_eigh_batched(None, n, 0, None, None, 0.0, 0, None, None, 0, None,
+                                   None) == 0
+
+
+def test_backward_argument_validation(lib):
+    f = lib.jacobi_eigh_backward
+    assert f(FAKE, FAKE, None, None, -1, 1, FAKE, 0.0, None, 0, None) == -5
+    assert f(FAKE, FAKE, None, None, 4, -1, FAKE, 0.0, None, 0, None) == -6
+    assert f(None, FAKE, None, None, 4, 1, FAKE, 0.0, None, 0, None) == -1
+    assert f(FAKE, None, None, None, 4, 1, FAKE, 0.0, None, 0, None) == -2
+    assert f(FAKE, FAKE, None, None, 4, 1, None, 0.0, None, 0, None) == -7
+    assert f(FAKE, FAKE, None, None, 4, 1, FAKE, -1.0, None, 0, None) == -8
+    assert f(None, None, None, None, 0, 5, None, 0.0, None, 0, None) == 0
+
+
+def test_workspace_query(pj):
+    assert pj.workspace_bytes(0, 64) > 0
+    big = pj.workspace_bytes(0, 4096)
+    assert big >= 2 * 4096 * 4096 * 8          # B and V in FP64
+    mixed = pj.workspace_bytes(1, 4096)
+    assert mixed >= 4 * 4096 * 4096 * 8 + 2 * 4096 * 4096 * 4
+    assert pj.workspace_bytes(3, 256, 256) >= 2 * 256 * 256 * 256 * 8
+    assert pj.workspace_bytes(9, 10) == 0
+    assert pj.workspace_bytes(0, 64, 1, pj.make_opts(block=48)) == 0
+
+
+def test_product_path_has_no_cpu_fallback():
+    """The binding never imports the oracle and raises without a GPU."""
+    import torch
+    if not torch.cuda.is_available():
+        import paper_2509_00495_amd as pj
+        with pytest.raises(RuntimeError):
+            pj.eigh(torch.eye(3, dtype=torch.float64))
+
+
+def test_library_sources_do_not_touch_oracle():
+    csrc = os.path.join(ROOT, "paper_2509_00495_amd", "csrc")
+    for f in os.listdir(csrc):
+        for line in open(os.path.join(csrc, f)):
+            if line.lstrip().startswith("#include"):
+                assert "oracle" not in line.lower(), (f, line)
+    for f in ("jacobi.py", "__init__.py", "build.py"):
+        text = open(os.path.join(ROOT, "paper_2509_00495_amd", f)).read()
+        assert not re.search(r"^\s*(import|from)\s+oracle", text, flags=re.M), f
