@@ -74,15 +74,19 @@ typedef struct jacobi_info {
     int32_t ns_iters;       /* Newton-Schulz iterations run (mixed only) */
     int32_t path;           /* 0 = one-workgroup solver, 1 = block path */
     int32_t block;          /* block size used by the block path */
-    int32_t reserved_i[3];
+    int32_t polished;       /* 1 if the final Newton-Schulz refresh of V ran */
+    int32_t reserved_i[2];
     double norm_f;          /* ||A||_F of the symmetrised input */
     double tol;             /* absolute threshold on off(B) actually used */
     double off_final;       /* off(B) when the FP64 stage stopped */
     double off32;           /* off(B32) when the FP32 stage stopped (mixed) */
     double off_cond;        /* off(Q_d^T A Q_d) before the FP64 stage (mixed) */
-    double orth_ns;         /* ||I - Q_d^T Q_d||_F after the last NS step (mixed);
-                               the residual R of that step, computed in FP64 */
-    double reserved_d[4];
+    double orth_ns;         /* ||I - X^T X||_F of the last Newton-Schulz step of
+                               the mixed pipeline (the residual it corrected) */
+    double orth_est;        /* block path: randomized estimate of ||V^T V - I||_F
+                               of the accumulated eigenvectors before the final
+                               refresh (4 Rademacher probes) */
+    double reserved_d[3];
 } jacobi_info;
 
 /* Plain FP64 Jacobi eigendecomposition (Algorithm 4, Section 3.3, run as a

@@ -119,6 +119,10 @@ struct Bump {
 
 int default_block(int64_t n) { return n <= 256 ? 16 : 32; }
 
+constexpr int NPROBE = 4;           // Rademacher probes of the orthogonality estimate
+constexpr double POLISH_FRAC = 0.2; // refresh V when the estimate exceeds this
+                                    // fraction of 1e-14 n
+
 struct Geometry {
     int b, N, M, npairs, nbt;
     int64_t npad;
@@ -142,7 +146,7 @@ Geometry geometry(int64_t n, int block)
 
 // Buffers of one block-path solve (plain or mixed).
 struct BlockWs {
-    double *B64, *V64, *U64, *X2, *R;
+    double *B64, *V64, *U64, *X2, *R, *Vt, *probe;
     float *B32, *V32, *U32;
     double *partial, *scal, *wtmp, *sg;
     int *flags, *perm;
@@ -165,6 +169,9 @@ BlockWs layout_block(Bump &bp, int64_t n, const Geometry &g, bool mixed)
     w.B64 = bp.take<double>(nn);
     w.V64 = bp.take<double>(nn);
     w.U64 = bp.take<double>(uu);
+    w.probe = bp.take<double>((size_t)g.npad * 3 * NPROBE);
+    if (!mixed)
+        w.Vt = bp.take<double>(nn);
     if (mixed) {
         w.X2 = bp.take<double>(nn);
         w.R = bp.take<double>(nn);
@@ -428,11 +435,46 @@ int eigh_small(const double *A, int64_t n, int64_t lda, double *W, double *V, in
     return st;
 }
 
+// Output stage of the block path.  W is read off the diagonal of B; then the
+// orthogonality of the accumulated V is estimated from NPROBE Rademacher
+// probes x (||V^T V x - x||, O(n^2) work) and, when the estimate exceeds
+// POLISH_FRAC * 1e-14 n, V gets one Newton-Schulz step
+// V <- V + V (I - V^T V) / 2 (the paper's orthogonaliser, Section 4.3.4),
+// which squares its departure from orthogonality.  Rbuf and Vbuf are free
+// npad x npad scratch buffers (Rbuf may alias B: the diagonal is extracted
+// first).
 int finalize_block(const Geometry &g, int64_t n, const BlockWs &w, const double *B,
-                   const double *Vin, double *W, double *V, int64_t ldv, hipStream_t s)
+                   const double *Vin, double *Rbuf, double *Vbuf, double *W, double *V,
+                   int64_t ldv, hipStream_t s, double *orth_est, int *polished)
 {
+    const int64_t np = g.npad;
+    CK(launch_diag(B, np, n, w.wtmp, s));
+    double *X = w.probe, *Y = w.probe + np * NPROBE, *Z = w.probe + 2 * np * NPROBE;
+    CK(launch_rademacher(X, np, n, NPROBE, 0x5eedull, s));
+    CK(launch_gemm64(0, 0, np, NPROBE, np, 1.0, Vin, np, 0, X, NPROBE, 0, 0.0, nullptr, 0, 0,
+                     0.0, Y, NPROBE, 0, 1, s));
+    // Z = V^T Y - X = (V^T V - I) X
+    CK(launch_gemm64(1, 0, np, NPROBE, np, 1.0, Vin, np, 0, Y, NPROBE, 0, -1.0, X, NPROBE, 0,
+                     0.0, Z, NPROBE, 0, 1, s));
+    CK(launch_sq_partial(Z, np * NPROBE, w.partial, s));
+    CK(launch_sum(w.partial, OFF_BLOCKS, w.scal + 3, s));
+    Readback rb;
+    if (int e = read_scalars(w, s, rb))
+        return e;
+    const double est = std::sqrt(rb.scal[3] / NPROBE);
+    *orth_est = est;
+    *polished = 0;
+    const double *Vf = Vin;
+    if (!(est <= POLISH_FRAC * 1e-14 * (double)n)) {
+        CK(launch_gemm64(1, 0, np, np, np, -1.0, Vin, np, 0, Vin, np, 0, 0.0, nullptr, 0, 0,
+                         1.0, Rbuf, np, 0, 1, s));
+        CK(launch_gemm64(0, 0, np, np, np, 0.5, Vin, np, 0, Rbuf, np, 0, 1.0, Vin, np, 0, 0.0,
+                         Vbuf, np, 0, 1, s));
+        Vf = Vbuf;
+        *polished = 1;
+    }
     CK(launch_fill_i32(w.perm, n, 0, s));
-    CK(launch_finalize(B, g.npad, Vin, g.npad, n, W, V, ldv, w.perm, w.wtmp, w.sg, s));
+    CK(launch_finalize(w.wtmp, Vf, np, n, W, V, ldv, w.perm, w.sg, s));
     return 0;
 }
 
@@ -471,10 +513,16 @@ int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, in
                                 false, s, &sweeps, &off, nullptr);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;
-    if (int e = finalize_block(g, n, w, w.B64, w.V64, W, V, ldv, s))
+    double est = 0.0;
+    int pol = 0;
+    if (int e = finalize_block(g, n, w, w.B64, w.V64, w.B64, w.Vt, W, V, ldv, s, &est, &pol))
         return e;
     CK(hipStreamSynchronize(s));
     fill_info(info, sweeps, 0, 0, 1, g.b, normf, tol, off, 0, 0, 0);
+    if (info) {
+        info->orth_est = est;
+        info->polished = pol;
+    }
     return st;
 }
 
@@ -542,10 +590,16 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
                                 s, &sw64, &off, &offc);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;
-    if (int e = finalize_block(g, n, w, A64, X, W, V, ldv, s))
+    double est = 0.0;
+    int pol = 0;
+    if (int e = finalize_block(g, n, w, A64, X, A64, w.R, W, V, ldv, s, &est, &pol))
         return e;
     CK(hipStreamSynchronize(s));
     fill_info(info, sw64, sw32, ns, 1, g.b, normf, tol, off, off32, offc, orth);
+    if (info) {
+        info->orth_est = est;
+        info->polished = pol;
+    }
     return st;
 }
 

@@ -120,8 +120,12 @@ __device__ inline int block_or(int v, int *red)
 
 // ---------------------------------------------------------------- MFMA
 // 16x16x4 MFMA on one wavefront: D(16x16) += A(16x4) * B(4x16).
-// Operand layout: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
-// the accumulator holds D[4 * (l / 16) + v][l % 16] in element v (v = 0..3).
+// Operand layout (both precisions): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16].  Accumulator element v (v = 0..3) of lane l holds
+// D[r][l % 16] with r = acc_row<T>(l / 16, v):
+//   f32 (v_mfma_f32_16x16x4f32): r = 4 (l / 16) + v
+//   f64 (v_mfma_f64_16x16x4f64): r = l / 16 + 4 v
+// (the f64 mapping was measured on gfx950 with a one-wave probe).
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -133,6 +137,19 @@ __device__ inline d4 mfma16(double a, double b, d4 c)
 __device__ inline f4 mfma16(float a, float b, f4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__device__ inline int acc_row(int lk, int v);
+template <>
+__device__ inline int acc_row<float>(int lk, int v)
+{
+    return 4 * lk + v;
+}
+template <>
+__device__ inline int acc_row<double>(int lk, int v)
+{
+    return lk + 4 * v;
 }
 
 template <typename T>

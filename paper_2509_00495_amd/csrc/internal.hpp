@@ -47,9 +47,12 @@ hipError_t launch_fill_i32(int *p, int64_t count, int value, hipStream_t s);
 hipError_t launch_cast_f32(const double *src, float *dst, int64_t count, hipStream_t s);
 hipError_t launch_widen_f64(const float *src, double *dst, int64_t count, hipStream_t s);
 hipError_t launch_symmetrize(double *B, int64_t npad, hipStream_t s);
-hipError_t launch_finalize(const double *B, int64_t ldb, const double *V, int64_t ldv_in,
-                           int64_t n, double *W, double *Vout, int64_t ldv, int *perm,
-                           double *wtmp, double *sg, hipStream_t s);
+hipError_t launch_diag(const double *B, int64_t ldb, int64_t n, double *w, hipStream_t s);
+hipError_t launch_finalize(const double *w, const double *V, int64_t ldv_in, int64_t n,
+                           double *W, double *Vout, int64_t ldv, int *perm, double *sg,
+                           hipStream_t s);
+hipError_t launch_rademacher(double *X, int64_t rows, int64_t n, int k, uint64_t seed,
+                             hipStream_t s);
 constexpr int INGEST_BLOCKS = 1024;
 constexpr int OFF_BLOCKS = 1024;
 

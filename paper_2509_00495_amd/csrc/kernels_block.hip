@@ -130,7 +130,8 @@ __device__ inline void wave_store(T *Cs, int ld, typename acc4<T>::type (&acc)[M
         for (int tj = 0; tj < TM; ++tj)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                Cs[(row0 + ti * 16 + 4 * lk + v) * ld + col0 + tj * 16 + li] = acc[ti][tj][v];
+                Cs[(row0 + ti * 16 + acc_row<T>(lk, v)) * ld + col0 + tj * 16 + li] =
+                    acc[ti][tj][v];
 }
 
 template <typename T, int M>
@@ -515,16 +516,47 @@ __global__ __launch_bounds__(256) void permute_out_kernel(const double *__restri
     }
 }
 
-hipError_t launch_finalize(const double *B, int64_t ldb, const double *V, int64_t ldv_in,
-                           int64_t n, double *W, double *Vout, int64_t ldv, int *perm,
-                           double *wtmp, double *sg, hipStream_t s)
+hipError_t launch_diag(const double *B, int64_t ldb, int64_t n, double *w, hipStream_t s)
 {
     int g = (int)((n + 255) / 256);
-    hipLaunchKernelGGL(diag_kernel, dim3(g), dim3(256), 0, s, B, ldb, n, wtmp);
-    hipLaunchKernelGGL(rank_kernel, dim3(g), dim3(256), 0, s, wtmp, n, perm);
+    hipLaunchKernelGGL(diag_kernel, dim3(g), dim3(256), 0, s, B, ldb, n, w);
+    return hipGetLastError();
+}
+
+// Output stage from the extracted diagonal w: stable ascending order, column
+// permutation and sign convention.
+hipError_t launch_finalize(const double *w, const double *V, int64_t ldv_in, int64_t n,
+                           double *W, double *Vout, int64_t ldv, int *perm, double *sg,
+                           hipStream_t s)
+{
+    int g = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(rank_kernel, dim3(g), dim3(256), 0, s, w, n, perm);
     hipLaunchKernelGGL(colsign_kernel, dim3(g), dim3(256), 0, s, V, ldv_in, n, perm, sg);
     hipLaunchKernelGGL(permute_out_kernel, dim3(2048), dim3(256), 0, s, V, ldv_in, n, perm, sg,
-                       wtmp, W, Vout, ldv);
+                       w, W, Vout, ldv);
+    return hipGetLastError();
+}
+
+// Rademacher probe vectors (+-1 in rows < n, 0 below) from a counter-based
+// hash (splitmix64 finaliser), for the randomized estimate
+// ||V^T V - I||_F^2 ~ mean_k ||(V^T V - I) x_k||^2.
+__global__ void rademacher_kernel(double *X, int64_t rows, int64_t n, int k, uint64_t seed)
+{
+    const int64_t total = rows * k;
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        int64_t i = e / k;
+        uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(e + 1);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        X[e] = i < n ? ((z & 1) ? 1.0 : -1.0) : 0.0;
+    }
+}
+
+hipError_t launch_rademacher(double *X, int64_t rows, int64_t n, int k, uint64_t seed,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(rademacher_kernel, dim3(64), dim3(256), 0, s, X, rows, n, k, seed);
     return hipGetLastError();
 }
 

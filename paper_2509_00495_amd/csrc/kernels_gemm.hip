@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void gemm64_kernel(int64_t M, int64_t N, int64
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int64_t gi = i0 + row0 + a * 16 + 4 * lk + v;
+                int64_t gi = i0 + row0 + a * 16 + acc_row<double>(lk, v);
                 int64_t gj = j0 + col0 + b * 16 + li;
                 if (gi < M && gj < N) {
                     double r = alpha * acc[a][b][v];

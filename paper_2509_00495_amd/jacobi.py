@@ -50,14 +50,16 @@ class Info(ctypes.Structure):
         ("ns_iters", ctypes.c_int32),
         ("path", ctypes.c_int32),
         ("block", ctypes.c_int32),
-        ("reserved_i", ctypes.c_int32 * 3),
+        ("polished", ctypes.c_int32),
+        ("reserved_i", ctypes.c_int32 * 2),
         ("norm_f", ctypes.c_double),
         ("tol", ctypes.c_double),
         ("off_final", ctypes.c_double),
         ("off32", ctypes.c_double),
         ("off_cond", ctypes.c_double),
         ("orth_ns", ctypes.c_double),
-        ("reserved_d", ctypes.c_double * 4),
+        ("orth_est", ctypes.c_double),
+        ("reserved_d", ctypes.c_double * 3),
     ]
 
     def as_dict(self):

@@ -57,6 +57,8 @@ def run(pj, fn, A, **kw):
     opts = pj.make_opts(**kw) if kw else None
     W, V, info = getattr(pj, fn)(gpu(A), opts=opts, return_info=True)
     torch.cuda.synchronize()
+    print(f"     sweeps={info['sweeps']} sweeps32={info['sweeps32']} "
+          f"orth_est={info['orth_est']:.2e} polished={info['polished']}", flush=True)
     return W.cpu().numpy(), V.cpu().numpy(), info
 
 
