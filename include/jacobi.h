@@ -64,7 +64,10 @@ typedef struct jacobi_opts {
                                default 128, 0 keeps the default, -1 forces the block path */
     int32_t threads;        /* threads per workgroup of the one-workgroup solver:
                                256 or 512; default by n */
-    int32_t reserved[5];
+    int32_t timing;         /* nonzero: time every pair-solve and apply launch of
+                               the block path with HIP events on `stream`
+                               (results in jacobi_info.t_*) */
+    int32_t reserved[4];
 } jacobi_opts;
 
 /* Diagnostics filled on return (host struct, may be NULL). */
@@ -86,6 +89,16 @@ typedef struct jacobi_info {
     double orth_est;        /* block path: randomized estimate of ||V^T V - I||_F
                                of the accumulated eigenvectors before the final
                                refresh (4 Rademacher probes) */
+    /* with opts->timing: summed kernel time (ms) and launch counts of the
+     * block path, index 0 = FP64 stage, 1 = FP32 stage; "apply" is the update
+     * of the off-diagonal tiles of B, "applyv" the update of V */
+    double t_pair_ms[2];
+    double t_apply_ms[2];
+    double t_applyv_ms[2];
+    int32_t n_pair[2];
+    int32_t n_apply[2];
+    int32_t n_applyv[2];
+    int32_t reserved_i2[2];
     double reserved_d[3];
 } jacobi_info;
 

@@ -61,6 +61,8 @@ def _load():
         lib.orc_qtaq.argtypes = [i64, P, P, P]
         lib.orc_eigh_mixed.argtypes = [i64, P, P, P, d, i32, i32, d, P]
         lib.orc_eigh_mixed.restype = i32
+        lib.orc_jacobi_rows.argtypes = [i64, P, P, i64, i64, d]
+        lib.orc_jacobi_rows.restype = i64
         lib.orc_eigh_backward.argtypes = [i64, P, P, P, P, d, P]
         lib.orc_eigh_backward.restype = i32
         _lib = lib
@@ -109,6 +111,14 @@ def jacobi_cyclic(A, tol_abs: float, rel_eps: float = U_D,
                                    max_sweeps, ctypes.byref(sw), _p(hist),
                                    ctypes.byref(rot))
     return A, V, sw.value, st, hist[: sw.value + 1].copy(), rot.value
+
+
+def jacobi_rows(A, V, p_begin: int, p_end: int, rel_eps: float = U_D) -> int:
+    """Pivot rows [p_begin, p_end) of one cyclic-by-row sweep, in place on
+    the float64 C-contiguous arrays A and V.  Returns the rotations made."""
+    assert A.dtype == np.float64 and A.flags.c_contiguous
+    assert V.dtype == np.float64 and V.flags.c_contiguous
+    return int(_load().orc_jacobi_rows(A.shape[0], _p(A), _p(V), p_begin, p_end, rel_eps))
 
 
 def jacobi_cyclic_f32(A, tol_abs: float, rel_eps: float = U_L,

@@ -176,6 +176,27 @@ DEFINE_ROTATE(orc_rotate_f32, float)
 DEFINE_CYCLIC(orc_jacobi_cyclic, double, orc_rotate, orc_off)
 DEFINE_CYCLIC(orc_jacobi_cyclic_f32, float, orc_rotate_f32, orc_off_f32)
 
+/* A bounded piece of one sweep of Algorithm 4: the cyclic-by-row visits of
+ * pivot rows p in [p_begin, p_end) (all q > p), with the same per-pair test
+ * and rotation as orc_jacobi_cyclic, no end-of-sweep step.  Used to time the
+ * oracle on a sample of a large workload.  Returns the rotations made. */
+int64_t orc_jacobi_rows(int64_t n, double *A, double *V, int64_t p_begin,
+                        int64_t p_end, double rel_eps)
+{
+    int64_t rotations = 0;
+    for (int64_t p = p_begin; p < p_end && p < n - 1; ++p)
+        for (int64_t q = p + 1; q < n; ++q) {
+            double apq = A[IDX(p, q, n)], app = A[IDX(p, p, n)], aqq = A[IDX(q, q, n)];
+            if (apq != 0.0 && fabs(apq) > rel_eps * sqrt(fabs(app * aqq))) {
+                double c, s;
+                orc_jacobi_pair(app, aqq, apq, &c, &s);
+                orc_rotate(n, A, V, p, q, c, s);
+                ++rotations;
+            }
+        }
+    return rotations;
+}
+
 /* Output convention (the paper leaves the order free, Section 3.2): W ascending,
  * ties kept in diagonal order; the columns of V are permuted alike and each is
  * scaled by +-1 so that its entry of largest magnitude (lowest row on ties) is

@@ -30,7 +30,7 @@ constexpr double U_D = 0x1p-53; // unit roundoff, double
 constexpr double U_L = 0x1p-24; // unit roundoff, single
 
 struct Opts {
-    int max_sweeps, block, inner, ns_iters, check_sym, small_max_n, threads;
+    int max_sweeps, block, inner, ns_iters, check_sym, small_max_n, threads, timing;
     double c32;
 };
 
@@ -44,9 +44,11 @@ int resolve_opts(const jacobi_opts *o, Opts &r)
     r.check_sym = 0;
     r.small_max_n = 128;
     r.threads = 0;
+    r.timing = 0;
     r.c32 = 1.0;
     if (!o)
         return 0;
+    r.timing = o->timing != 0;
     if (o->max_sweeps < 0 || o->max_sweeps > 1000)
         return 1;
     if (o->max_sweeps)
@@ -148,9 +150,9 @@ Geometry geometry(int64_t n, int block)
 struct BlockWs {
     double *B64, *V64, *U64, *X2, *R, *Vt, *probe;
     float *B32, *V32, *U32;
-    double *partial, *scal, *wtmp, *sg;
-    int *flags, *perm;
-    int2 *pairs, *btiles;
+    double *partial, *scal, *wtmp, *sg, *cmax;
+    int *flags, *perm, *cidx;
+    int2 *pairs, *btiles, *psmap;
 };
 
 size_t partial_count(const Geometry &g)
@@ -168,7 +170,7 @@ BlockWs layout_block(Bump &bp, int64_t n, const Geometry &g, bool mixed)
     const size_t uu = (size_t)g.npairs * g.M * g.M;
     w.B64 = bp.take<double>(nn);
     w.V64 = bp.take<double>(nn);
-    w.U64 = bp.take<double>(uu);
+    w.U64 = bp.take<double>(2 * uu); // double-buffered across rounds
     w.probe = bp.take<double>((size_t)g.npad * 3 * NPROBE);
     if (!mixed)
         w.Vt = bp.take<double>(nn);
@@ -177,16 +179,19 @@ BlockWs layout_block(Bump &bp, int64_t n, const Geometry &g, bool mixed)
         w.R = bp.take<double>(nn);
         w.B32 = bp.take<float>(nn);
         w.V32 = bp.take<float>(nn);
-        w.U32 = bp.take<float>(uu);
+        w.U32 = bp.take<float>(2 * uu);
     }
     w.partial = bp.take<double>(partial_count(g));
     w.scal = bp.take<double>(8);
     w.flags = bp.take<int>(8);
     w.pairs = bp.take<int2>((size_t)(g.N - 1) * g.npairs);
     w.btiles = bp.take<int2>((size_t)std::max(g.nbt, 1));
+    w.psmap = bp.take<int2>((size_t)g.b * (g.b + 1) / 2);
     w.perm = bp.take<int>((size_t)std::max<int64_t>(n, 1));
     w.wtmp = bp.take<double>((size_t)std::max<int64_t>(n, 1));
     w.sg = bp.take<double>((size_t)std::max<int64_t>(n, 1));
+    w.cmax = bp.take<double>((size_t)SIGN_CHUNKS_HOST * std::max<int64_t>(n, 1));
+    w.cidx = bp.take<int>((size_t)SIGN_CHUNKS_HOST * std::max<int64_t>(n, 1));
     return w;
 }
 
@@ -283,15 +288,100 @@ int read_scalars(const BlockWs &w, hipStream_t s, Readback &rb)
     return 0;
 }
 
-// Sweeps of the round-robin block Jacobi on (B, V) until off(B) <= tol.
-// fp32_stage: also stop when a sweep no longer decreases off (the FP32
-// rounding floor).  Returns a status; sweeps and final off through pointers.
+// Kernel timing of the block path with HIP events recorded around every
+// pair-solve and B-update launch on the caller's stream and around every
+// V-update launch on the side stream (opts->timing).  Events are read after
+// the per-sweep readback.
+struct RoundTimer {
+    bool on = false;
+    std::vector<hipEvent_t> ev; // 5 per round
+    double pair_ms = 0.0, apply_ms = 0.0, applyv_ms = 0.0;
+    int npair = 0, napply = 0, napplyv = 0;
+    int ensure(int rounds)
+    {
+        while ((int)ev.size() < 5 * rounds) {
+            hipEvent_t e;
+            CK(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+        return 0;
+    }
+    ~RoundTimer()
+    {
+        for (hipEvent_t e : ev)
+            hipEventDestroy(e);
+    }
+    int collect(int rounds)
+    {
+        for (int r = 0; r < rounds; ++r) {
+            float a = 0.f, b = 0.f, c = 0.f;
+            CK(hipEventElapsedTime(&a, ev[5 * r], ev[5 * r + 1]));
+            CK(hipEventElapsedTime(&b, ev[5 * r + 1], ev[5 * r + 2]));
+            CK(hipEventElapsedTime(&c, ev[5 * r + 3], ev[5 * r + 4]));
+            pair_ms += a;
+            apply_ms += b;
+            applyv_ms += c;
+        }
+        npair += rounds;
+        napply += rounds;
+        napplyv += rounds;
+        return 0;
+    }
+    void store(jacobi_info *info, int idx) const
+    {
+        if (!info)
+            return;
+        info->t_pair_ms[idx] = pair_ms;
+        info->t_apply_ms[idx] = apply_ms;
+        info->t_applyv_ms[idx] = applyv_ms;
+        info->n_pair[idx] = npair;
+        info->n_apply[idx] = napply;
+        info->n_applyv[idx] = napplyv;
+    }
+};
+
+// Side stream for the V updates.  The update of V in round r only needs U_r,
+// so it runs beside the B update of round r and the pair solve of round r+1;
+// U is double-buffered and the pair solve of round r+2 waits for the V update
+// of round r, which last read that buffer.  Non-blocking and default priority.
+struct SideStream {
+    hipStream_t s2 = nullptr;
+    hipEvent_t evU[2] = {nullptr, nullptr}, evV[2] = {nullptr, nullptr};
+    int64_t round = 0; // rounds issued so far (across stages)
+    int init()
+    {
+        CK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+        for (int j = 0; j < 2; ++j) {
+            CK(hipEventCreateWithFlags(&evU[j], hipEventDisableTiming));
+            CK(hipEventCreateWithFlags(&evV[j], hipEventDisableTiming));
+        }
+        return 0;
+    }
+    ~SideStream()
+    {
+        for (int j = 0; j < 2; ++j) {
+            if (evU[j])
+                hipEventDestroy(evU[j]);
+            if (evV[j])
+                hipEventDestroy(evV[j]);
+        }
+        if (s2) {
+            hipStreamSynchronize(s2);
+            hipStreamDestroy(s2);
+        }
+    }
+};
+
 template <typename T>
 int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U, double tol,
                double eps, int max_sweeps, int inner, bool fp32_stage, hipStream_t s,
-               int *sweeps_out, double *off_out, double *off0_out)
+               SideStream &ss, int *sweeps_out, double *off_out, double *off0_out,
+               RoundTimer *tm)
 {
     Readback rb;
+    if (tm && tm->on)
+        if (int e = tm->ensure(g.N - 1))
+            return e;
     CK(launch_off2_partial<T>(B, g.npad, w.partial, s));
     CK(launch_sum(w.partial, OFF_BLOCKS, w.scal + 1, s));
     if (int e = read_scalars(w, s, rb))
@@ -302,22 +392,48 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
     int sweeps = 0;
     int status = JACOBI_OK;
     const double thr = n > 0 ? tol / (double)n : 0.0;
+    const size_t ustride = (size_t)g.npairs * g.M * g.M;
     while (off > tol) {
         if (sweeps >= max_sweeps) {
             status = JACOBI_NOCONV;
             break;
         }
         CK(launch_fill_i32(w.flags + 2, 1, 0, s));
-        for (int r = 0; r < g.N - 1; ++r) {
+        const bool timed = tm && tm->on;
+        for (int r = 0; r < g.N - 1; ++r, ++ss.round) {
+            const int j = (int)(ss.round & 1);
+            T *Ub = U + j * ustride;
             const int2 *pr = w.pairs + (size_t)r * g.npairs;
-            CK(launch_pair_solve<T>(B, g.npad, g.b, g.npairs, pr, U, eps, thr, inner, w.partial,
-                                    w.flags + 2, s));
+            if (ss.round >= 2)
+                CK(hipStreamWaitEvent(s, ss.evV[j], 0));
+            if (timed)
+                CK(hipEventRecord(tm->ev[5 * r], s));
+            CK(launch_pair_solve<T>(B, g.npad, g.b, g.npairs, pr, w.psmap, Ub, eps, thr, inner,
+                                    w.partial, w.flags + 2, s));
+            CK(hipEventRecord(ss.evU[j], s));
+            if (timed)
+                CK(hipEventRecord(tm->ev[5 * r + 1], s));
             CK(launch_apply<T>(B, g.npad, V, g.npad, g.npad, g.b, g.npairs, pr, w.btiles, g.nbt,
-                               U, w.partial + g.npairs, r == g.N - 2, s));
+                               Ub, w.partial + g.npairs, r == g.N - 2, 1, s));
+            if (timed)
+                CK(hipEventRecord(tm->ev[5 * r + 2], s));
+            CK(hipStreamWaitEvent(ss.s2, ss.evU[j], 0));
+            if (timed)
+                CK(hipEventRecord(tm->ev[5 * r + 3], ss.s2));
+            CK(launch_apply<T>(B, g.npad, V, g.npad, g.npad, g.b, g.npairs, pr, w.btiles, g.nbt,
+                               Ub, nullptr, 0, 2, ss.s2));
+            if (timed)
+                CK(hipEventRecord(tm->ev[5 * r + 4], ss.s2));
+            CK(hipEventRecord(ss.evV[j], ss.s2));
         }
         CK(launch_sum(w.partial, (int64_t)g.npairs + g.nbt, w.scal + 1, s));
         if (int e = read_scalars(w, s, rb))
             return e;
+        if (timed) {
+            CK(hipStreamSynchronize(ss.s2));
+            if (int e = tm->collect(g.N - 1))
+                return e;
+        }
         ++sweeps;
         const double prev = off;
         off = std::sqrt(rb.scal[1]);
@@ -330,6 +446,9 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
         if (fp32_stage && off >= prev)
             break;
     }
+    // V is complete on the caller's stream from here on
+    if (ss.round > 0)
+        CK(hipStreamWaitEvent(s, ss.evV[(ss.round - 1) & 1], 0));
     *sweeps_out = sweeps;
     *off_out = off;
     return status;
@@ -343,6 +462,10 @@ int setup_block(const Geometry &g, const BlockWs &w, hipStream_t s)
                       s));
     CK(hipMemcpyAsync(w.btiles, tiles.data(), tiles.size() * sizeof(int2),
                       hipMemcpyHostToDevice, s));
+    std::vector<int2> psmap((size_t)g.b * (g.b + 1) / 2);
+    pair_solve_map(g.M, psmap.data());
+    CK(hipMemcpyAsync(w.psmap, psmap.data(), psmap.size() * sizeof(int2), hipMemcpyHostToDevice,
+                      s));
     CK(launch_fill_i32(w.flags, 8, 0, s));
     CK(hipStreamSynchronize(s)); // the host tables go out of scope
     return 0;
@@ -474,7 +597,7 @@ int finalize_block(const Geometry &g, int64_t n, const BlockWs &w, const double 
         *polished = 1;
     }
     CK(launch_fill_i32(w.perm, n, 0, s));
-    CK(launch_finalize(w.wtmp, Vf, np, n, W, V, ldv, w.perm, w.sg, s));
+    CK(launch_finalize(w.wtmp, Vf, np, n, W, V, ldv, w.perm, w.sg, w.cmax, w.cidx, s));
     return 0;
 }
 
@@ -509,8 +632,13 @@ int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, in
     const double tol = tol_in > 0.0 ? tol_in : 1e-15 * (double)n * normf;
     int sweeps = 0;
     double off = 0.0;
+    RoundTimer tm;
+    tm.on = o.timing;
+    SideStream ss;
+    if (int e = ss.init())
+        return e;
     int st = run_sweeps<double>(g, n, w, w.B64, w.V64, w.U64, tol, U_D, o.max_sweeps, o.inner,
-                                false, s, &sweeps, &off, nullptr);
+                                false, s, ss, &sweeps, &off, nullptr, &tm);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;
     double est = 0.0;
@@ -523,6 +651,7 @@ int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, in
         info->orth_est = est;
         info->polished = pol;
     }
+    tm.store(info, 0);
     return st;
 }
 
@@ -547,8 +676,13 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     const double tol32 = o.c32 * (double)n * U_L * normf;
     int sw32 = 0;
     double off32 = 0.0;
+    RoundTimer tm32, tm64;
+    tm32.on = tm64.on = o.timing;
+    SideStream ss;
+    if (int e = ss.init())
+        return e;
     int st32 = run_sweeps<float>(g, n, w, w.B32, w.V32, w.U32, tol32, U_L, o.max_sweeps,
-                                 o.inner, true, s, &sw32, &off32, nullptr);
+                                 o.inner, true, s, ss, &sw32, &off32, nullptr, &tm32);
     if (st32 == JACOBI_DEVICE)
         return st32;
     // stage 2: Newton-Schulz, X <- X + X (I - X^T X) / 2  (= X (3I - X^T X) / 2)
@@ -587,7 +721,7 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     int sw64 = 0;
     double off = 0.0, offc = 0.0;
     int st = run_sweeps<double>(g, n, w, A64, X, w.U64, tol, U_D, o.max_sweeps, o.inner, false,
-                                s, &sw64, &off, &offc);
+                                s, ss, &sw64, &off, &offc, &tm64);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;
     double est = 0.0;
@@ -600,6 +734,8 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
         info->orth_est = est;
         info->polished = pol;
     }
+    tm64.store(info, 0);
+    tm32.store(info, 1);
     return st;
 }
 

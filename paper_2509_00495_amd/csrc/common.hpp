@@ -31,6 +31,25 @@ __host__ __device__ inline void rr_pair(int k, int r, int m, int &p, int &q)
     q = a < b ? b : a;
 }
 
+// Physical layout of the round-robin schedule inside a 2b x 2b pair block
+// (M = 2b positions): slot s of the circle method is stored at position
+// pos(s) = 2s (s < M/2) or 2(M-1-s)+1, so the pairs of every round are the
+// adjacent positions (2k, 2k+1).  Between rounds the players move one slot
+// (slot s <- slot s+1, slot M-1 <- slot 1, slot 0 fixed), which in physical
+// positions is the fixed permutation sigma; after M-1 rounds every player is
+// back in its starting slot.
+__host__ __device__ inline int ps_pos(int slot, int M)
+{
+    return slot < M / 2 ? 2 * slot : 2 * (M - 1 - slot) + 1;
+}
+__host__ __device__ inline int ps_slot(int p, int M) { return (p & 1) ? M - 1 - (p >> 1) : (p >> 1); }
+__host__ __device__ inline int ps_sigma(int p, int M)
+{
+    int s = ps_slot(p, M);
+    int t = s == 0 ? 0 : (s == 1 ? M - 1 : s - 1);
+    return ps_pos(t, M);
+}
+
 // Map idx in [0, h/2 * (h+1)) to (k, l), 0 <= k <= l < h, h even: row rho of
 // the folded rectangle holds the upper-triangle rows rho and h-1-rho.
 __device__ inline void tri_fold(int idx, int h, int &k, int &l)

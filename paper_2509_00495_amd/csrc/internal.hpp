@@ -29,12 +29,15 @@ int small_max_active(int m_max, int pool, int nthreads);
 // ---- block path (kernels_block.hip); T = double or float
 template <typename T>
 hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
-                             T *U, double eps, double thr, int inner, double *partial,
-                             int *rot_flag, hipStream_t s);
+                             const int2 *psmap, T *U, double eps, double thr, int inner,
+                             double *partial, int *rot_flag, hipStream_t s);
+// thread -> block map of the pair solve (b(b+1)/2 entries for M = 2b)
+void pair_solve_map(int M, int2 *out);
+// which = 1: B tiles only, 2: V tiles only, 3: both
 template <typename T>
 hipError_t launch_apply(T *B, int64_t ldb, T *V, int64_t ldv, int64_t nrows, int b,
                         int npairs, const int2 *pairs, const int2 *btiles, int nbt,
-                        const T *U, double *partial, int want_off, hipStream_t s);
+                        const T *U, double *partial, int want_off, int which, hipStream_t s);
 hipError_t launch_sum(const double *x, int64_t count, double *out, hipStream_t s);
 template <typename T>
 hipError_t launch_ingest(const double *A, int64_t lda, int64_t n, T *B, int64_t npad,
@@ -50,7 +53,8 @@ hipError_t launch_symmetrize(double *B, int64_t npad, hipStream_t s);
 hipError_t launch_diag(const double *B, int64_t ldb, int64_t n, double *w, hipStream_t s);
 hipError_t launch_finalize(const double *w, const double *V, int64_t ldv_in, int64_t n,
                            double *W, double *Vout, int64_t ldv, int *perm, double *sg,
-                           hipStream_t s);
+                           double *cmax, int *cidx, hipStream_t s);
+constexpr int SIGN_CHUNKS_HOST = 16; // row chunks of the column-sign pass
 hipError_t launch_rademacher(double *X, int64_t rows, int64_t n, int k, uint64_t seed,
                              hipStream_t s);
 constexpr int INGEST_BLOCKS = 1024;

@@ -20,68 +20,228 @@ namespace lj {
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~(size_t)7; }
 
 // ------------------------------------------------------------- pair solve
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64_t ldb, int b,
+// Rotated diagonal entry of a pair after its rotation: a_pp - t a_pq for the
+// first position of the pair, a_qq + t a_pq for the second (Section 3.1).
+template <typename T>
+__device__ inline T rotated_diag(T a, double t, T apq, int second)
+{
+    double v = second ? (double)a + t * (double)apq : (double)a - t * (double)apq;
+    return (T)v;
+}
+
+// One workgroup per block pair (P, Q) of the round.  S (the 2b x 2b tile) and
+// U (its accumulated rotation, rows in logical order, columns in physical
+// order) are double-buffered in LDS; each round reads buffer a and writes the
+// rotated, permuted result to buffer b.  Each thread owns a fixed 2x2 block
+// (k <= l) of S and fixed (row, pair) items of U for the whole kernel.  The
+// angles of the next round are produced inside the same phase: every pair of
+// the next round joins one position of current pair k with one of current
+// pair l != k, so the owner of block (k, l) knows the new coupling (its own
+// result) and recomputes the two new diagonal entries from the current ones;
+// a round therefore costs one barrier.  Starting slot s holds tile index s.
+template <typename T, int M, int NT>
+__global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64_t ldb,
                                                         const int2 *__restrict__ pairs,
+                                                        const int2 *__restrict__ psmap,
                                                         T *__restrict__ U, double eps,
                                                         double thr, int inner,
                                                         double *__restrict__ partial,
                                                         int *rot_flag)
 {
+    constexpr int b = M / 2, h = M / 2, ld = M + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int M = 2 * b, ld = M + 1;
-    T *S = (T *)smem_raw;
-    T *Ul = S + M * ld;
-    double *cs = (double *)(smem_raw + align8(2 * sizeof(T) * M * ld));
-    double *red = cs + 3 * b;
+    T *S0 = (T *)smem_raw;
+    T *S1 = S0 + M * ld;
+    T *U0 = S1 + M * ld;
+    T *U1 = U0 + M * ld;
+    double *csA = (double *)(smem_raw + align8(4 * sizeof(T) * M * ld));
+    double *csB = csA + 3 * h;
+    double *red = csB + 3 * h;
     int *ired = (int *)(red + 16);
     const int tid = threadIdx.x;
-    const int k = blockIdx.x;
-    const int2 pq = pairs[k];
+    const int pk = blockIdx.x;
+    const int2 pq = pairs[pk];
     for (int idx = tid; idx < M * M; idx += NT) {
-        int i = idx / M, j = idx - (idx / M) * M;
+        int p = idx / M, q = idx % M;
+        int i = ps_slot(p, M), j = ps_slot(q, M);
         int64_t gi = i < b ? (int64_t)pq.x * b + i : (int64_t)pq.y * b + (i - b);
         int64_t gj = j < b ? (int64_t)pq.x * b + j : (int64_t)pq.y * b + (j - b);
-        S[i * ld + j] = B[gi * ldb + gj];
-        Ul[i * ld + j] = (T)(i == j ? 1 : 0);
+        S0[p * ld + q] = B[gi * ldb + gj];
+        U0[p * ld + q] = (T)(p == ps_slot(q, M) ? 1 : 0); // U[row i][phys col q]
     }
+    // fixed work assignment: block (bk, bl), bk <= bl, from the host-built
+    // map whose first h entries are the blocks hosting the next round's pairs
+    // (so their angle computations share one wavefront)
+    constexpr int NBLK = h * (h + 1) / 2;
+    int bk = -1, bl = -1;
+    if (tid < NBLK) {
+        const int2 e = psmap[tid];
+        bk = e.x;
+        bl = e.y;
+    }
+    const int dk0 = bk >= 0 ? ps_sigma(2 * bk, M) : 0, dk1 = bk >= 0 ? ps_sigma(2 * bk + 1, M) : 0;
+    const int dl0 = bk >= 0 ? ps_sigma(2 * bl, M) : 0, dl1 = bk >= 0 ? ps_sigma(2 * bl + 1, M) : 0;
+    // the next-round pair hosted by this block, if any: entry (ha, hc) =
+    // (2bk+ha, 2bl+hc) becomes next pair hk (a block hosts at most one; the
+    // host-built map puts the hosting blocks on threads 0 .. h-1).  Scalars,
+    // not arrays, so nothing lands in scratch memory.
+    int hosted = 0, ha = 0, hc = 0, hk = 0, hfirst = 0;
+    if (bk >= 0 && bk != bl) {
+        for (int a = 0; a < 2; ++a)
+            for (int c = 0; c < 2; ++c) {
+                int sp = ps_sigma(2 * bk + a, M), sq = ps_sigma(2 * bl + c, M);
+                if ((sp >> 1) == (sq >> 1)) {
+                    hosted = 1;
+                    ha = a;
+                    hc = c;
+                    hk = sp >> 1;
+                    hfirst = (sp & 1) == 0; // the row position lands first
+                }
+            }
+    }
+    constexpr int NU = M * h; // (row, pair) items of U
     __syncthreads();
     int rot = 0;
-    for (int sw = 0; sw < inner; ++sw)
-        for (int r = 0; r < M - 1; ++r)
-            rot |= lds_jacobi_round<T, NT>(S, ld, M, r, eps, thr, Ul, ld, M, cs);
-    T *Uk = U + (int64_t)k * M * M;
+    // angles of round 0
+    if (tid < h) {
+        const int p = 2 * tid, q = p + 1;
+        double app = (double)S0[p * ld + p], aqq = (double)S0[q * ld + q];
+        double apq = (double)S0[p * ld + q];
+        double c = 1.0, sn = 0.0, t = 0.0;
+        if (jacobi_should_rotate(app, aqq, apq, eps, thr)) {
+            jacobi_angle(app, aqq, apq, c, sn, t);
+            rot = 1;
+        }
+        csA[tid] = c;
+        csA[h + tid] = sn;
+        csA[2 * h + tid] = t;
+    }
+    __syncthreads();
+    T *Sa = S0, *Sb = S1, *Ua = U0, *Ub = U1;
+    double *ca = csA, *cb = csB;
+    const int rounds = inner * (M - 1);
+    for (int r = 0; r < rounds; ++r) {
+        if (bk >= 0) {
+            const int k = bk, l = bl;
+            const int pk0 = 2 * k, pk1 = pk0 + 1, pl0 = 2 * l, pl1 = pl0 + 1;
+            if (k == l) {
+                const double tk = ca[2 * h + k];
+                const T apq = Sa[pk0 * ld + pk1];
+                Sb[dk0 * ld + dk0] = rotated_diag<T>(Sa[pk0 * ld + pk0], tk, apq, 0);
+                Sb[dk1 * ld + dk1] = rotated_diag<T>(Sa[pk1 * ld + pk1], tk, apq, 1);
+                T z = ca[h + k] == 0.0 ? apq : (T)0;
+                Sb[dk0 * ld + dk1] = z;
+                Sb[dk1 * ld + dk0] = z;
+            } else {
+                const T ck = (T)ca[k], sk = (T)ca[h + k], cl = (T)ca[l], sl = (T)ca[h + l];
+                T x00 = Sa[pk0 * ld + pl0], x01 = Sa[pk0 * ld + pl1];
+                T x10 = Sa[pk1 * ld + pl0], x11 = Sa[pk1 * ld + pl1];
+                T y00 = ck * x00 - sk * x10, y01 = ck * x01 - sk * x11;
+                T y10 = sk * x00 + ck * x10, y11 = sk * x01 + ck * x11;
+                T z[2][2];
+                z[0][0] = cl * y00 - sl * y01;
+                z[0][1] = sl * y00 + cl * y01;
+                z[1][0] = cl * y10 - sl * y11;
+                z[1][1] = sl * y10 + cl * y11;
+                Sb[dk0 * ld + dl0] = z[0][0];
+                Sb[dk0 * ld + dl1] = z[0][1];
+                Sb[dk1 * ld + dl0] = z[1][0];
+                Sb[dk1 * ld + dl1] = z[1][1];
+                Sb[dl0 * ld + dk0] = z[0][0];
+                Sb[dl1 * ld + dk0] = z[0][1];
+                Sb[dl0 * ld + dk1] = z[1][0];
+                Sb[dl1 * ld + dk1] = z[1][1];
+                // angle of the next round for the hosted pair
+                if (hosted) {
+                    const int pe = pk0 + ha, qe = pl0 + hc;
+                    const T dpe = rotated_diag<T>(Sa[pe * ld + pe], ca[2 * h + k],
+                                                  Sa[pk0 * ld + pk1], ha);
+                    const T dqe = rotated_diag<T>(Sa[qe * ld + qe], ca[2 * h + l],
+                                                  Sa[pl0 * ld + pl1], hc);
+                    const double app = (double)(hfirst ? dpe : dqe);
+                    const double aqq = (double)(hfirst ? dqe : dpe);
+                    const T zz = ha ? (hc ? z[1][1] : z[1][0]) : (hc ? z[0][1] : z[0][0]);
+                    const double apq = (double)zz;
+                    double cc = 1.0, sn = 0.0, t = 0.0;
+                    if (jacobi_should_rotate(app, aqq, apq, eps, thr)) {
+                        jacobi_angle(app, aqq, apq, cc, sn, t);
+                        if (r + 1 < rounds)
+                            rot = 1;
+                    }
+                    cb[hk] = cc;
+                    cb[h + hk] = sn;
+                    cb[2 * h + hk] = t;
+                }
+            }
+        }
+        // U items go to the wavefronts after the first (which carries the
+        // angle computations)
+        for (int it = tid - WAVE; it >= 0 && it < NU; it += NT - WAVE) {
+            const int i = it / h, k = it % h;
+            const int p0 = 2 * k, p1 = p0 + 1;
+            const T c = (T)ca[k], sn = (T)ca[h + k];
+            T u0 = Ua[i * ld + p0], u1 = Ua[i * ld + p1];
+            Ub[i * ld + ps_sigma(p0, M)] = c * u0 - sn * u1;
+            Ub[i * ld + ps_sigma(p1, M)] = sn * u0 + c * u1;
+        }
+        __syncthreads();
+        T *tmp = Sa;
+        Sa = Sb;
+        Sb = tmp;
+        tmp = Ua;
+        Ua = Ub;
+        Ub = tmp;
+        double *tc = ca;
+        ca = cb;
+        cb = tc;
+    }
+    // back in the starting layout: position p holds tile index ps_slot(p)
+    T *Uk = U + (int64_t)pk * M * M;
     for (int idx = tid; idx < M * M; idx += NT) {
-        int i = idx / M, j = idx - (idx / M) * M;
+        int p = idx / M, q = idx % M;
+        int i = ps_slot(p, M), j = ps_slot(q, M);
         int64_t gi = i < b ? (int64_t)pq.x * b + i : (int64_t)pq.y * b + (i - b);
         int64_t gj = j < b ? (int64_t)pq.x * b + j : (int64_t)pq.y * b + (j - b);
-        B[gi * ldb + gj] = S[i * ld + j];
-        Uk[idx] = Ul[i * ld + j];
+        B[gi * ldb + gj] = Sa[p * ld + q];
+        Uk[p * M + j] = Ua[p * ld + q]; // U[row p][logical column j]
     }
-    double off2 = lds_off2<T, NT>(S, ld, M, red);
+    double off2 = lds_off2<T, NT>(Sa, ld, M, red);
     int any = block_or<NT>(rot, ired);
     if (tid == 0) {
-        partial[k] = off2;
+        partial[pk] = off2;
         if (any)
             atomicOr(rot_flag, 1);
     }
 }
 
 template <typename T>
-hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs, T *U,
-                             double eps, double thr, int inner, double *partial,
-                             int *rot_flag, hipStream_t s)
+hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
+                             const int2 *psmap, T *U, double eps, double thr, int inner,
+                             double *partial, int *rot_flag, hipStream_t s)
 {
     const int M = 2 * b;
-    size_t smem = align8(2 * sizeof(T) * M * (M + 1)) + (3 * b + 16) * sizeof(double) +
+    size_t smem = align8(4 * sizeof(T) * M * (M + 1)) + (6 * b + 16) * sizeof(double) +
                   16 * sizeof(int);
-    auto k = pair_solve_kernel<T, 256>;
-    hipError_t e = hipFuncSetAttribute((const void *)k,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k, dim3(npairs), dim3(256), smem, s, B, ldb, b, pairs, U, eps, thr,
-                       inner, partial, rot_flag);
+    hipError_t e;
+    if (M == 64) {
+        auto k = pair_solve_kernel<T, 64, 1024>;
+        e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)smem);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k, dim3(npairs), dim3(1024), smem, s, B, ldb, pairs, psmap, U, eps,
+                           thr, inner, partial, rot_flag);
+    } else if (M == 32) {
+        auto k = pair_solve_kernel<T, 32, 256>;
+        e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)smem);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k, dim3(npairs), dim3(256), smem, s, B, ldb, pairs, psmap, U, eps,
+                           thr, inner, partial, rot_flag);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -235,22 +395,24 @@ __global__ __launch_bounds__(256) void apply_kernel(T *__restrict__ B, int64_t l
     }
 }
 
+// which = 1: B tiles only, 2: V tiles only, 3: both in one launch.
 template <typename T>
 hipError_t launch_apply(T *B, int64_t ldb, T *V, int64_t ldv, int64_t nrows, int b, int npairs,
                         const int2 *pairs, const int2 *btiles, int nbt, const T *U,
-                        double *partial, int want_off, hipStream_t s)
+                        double *partial, int want_off, int which, hipStream_t s)
 {
     const int M = 2 * b;
-    const int64_t nvt = (nrows / M) * npairs;
-    const int64_t grid = nbt + nvt;
+    const int64_t nvt = (which & 2) ? (nrows / M) * npairs : 0;
+    const int nb = (which & 1) ? nbt : 0;
+    const int64_t grid = nb + nvt;
     if (grid == 0)
         return hipSuccess;
     if (M == 64)
         hipLaunchKernelGGL((apply_kernel<T, 64>), dim3((unsigned)grid), dim3(256), 0, s, B,
-                           ldb, V, ldv, pairs, btiles, nbt, npairs, U, partial, want_off);
+                           ldb, V, ldv, pairs, btiles, nb, npairs, U, partial, want_off);
     else if (M == 32)
         hipLaunchKernelGGL((apply_kernel<T, 32>), dim3((unsigned)grid), dim3(256), 0, s, B,
-                           ldb, V, ldv, pairs, btiles, nbt, npairs, U, partial, want_off);
+                           ldb, V, ldv, pairs, btiles, nb, npairs, U, partial, want_off);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -478,24 +640,54 @@ __global__ __launch_bounds__(256) void rank_kernel(const double *__restrict__ w,
 }
 
 // Sign of each output column: the entry of largest magnitude (lowest row on
-// ties) becomes positive.
+// ties) becomes positive.  Two passes so that V is read along rows: pass 1
+// scans row chunk z for every column j (threads over j), pass 2 reduces the
+// chunks in order for each output column.
+constexpr int SIGN_CHUNKS = 16;
+
+__global__ __launch_bounds__(256) void colmax_kernel(const double *__restrict__ V, int64_t ldv,
+                                                     int64_t n, double *__restrict__ cmax,
+                                                     int *__restrict__ cidx)
+{
+    const int64_t j = blockIdx.x * 256 + threadIdx.x;
+    const int z = blockIdx.y;
+    if (j >= n)
+        return;
+    const int64_t chunk = (n + SIGN_CHUNKS - 1) / SIGN_CHUNKS;
+    const int64_t i0 = z * chunk, i1 = (i0 + chunk < n) ? i0 + chunk : n;
+    double best = -1.0;
+    int64_t bi = i0 < n ? i0 : 0;
+    for (int64_t i = i0; i < i1; ++i) {
+        double a = fabs(V[i * ldv + j]);
+        if (a > best) {
+            best = a;
+            bi = i;
+        }
+    }
+    cmax[z * n + j] = best;
+    cidx[z * n + j] = (int)bi;
+}
+
 __global__ __launch_bounds__(256) void colsign_kernel(const double *__restrict__ V, int64_t ldv,
                                                       int64_t n, const int *__restrict__ perm,
+                                                      const double *__restrict__ cmax,
+                                                      const int *__restrict__ cidx,
                                                       double *__restrict__ sg)
 {
     const int64_t c = blockIdx.x * 256 + threadIdx.x;
     if (c >= n)
         return;
     const int col = perm[c];
-    double best = -1.0, val = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        double v = V[i * ldv + col];
-        if (fabs(v) > best) {
-            best = fabs(v);
-            val = v;
+    double best = -1.0;
+    int bi = 0;
+    for (int z = 0; z < SIGN_CHUNKS; ++z) {
+        double m = cmax[z * n + col];
+        if (m > best) {
+            best = m;
+            bi = cidx[z * n + col];
         }
     }
-    sg[c] = val < 0.0 ? -1.0 : 1.0;
+    sg[c] = V[(int64_t)bi * ldv + col] < 0.0 ? -1.0 : 1.0;
 }
 
 __global__ __launch_bounds__(256) void permute_out_kernel(const double *__restrict__ V,
@@ -527,11 +719,14 @@ hipError_t launch_diag(const double *B, int64_t ldb, int64_t n, double *w, hipSt
 // permutation and sign convention.
 hipError_t launch_finalize(const double *w, const double *V, int64_t ldv_in, int64_t n,
                            double *W, double *Vout, int64_t ldv, int *perm, double *sg,
-                           hipStream_t s)
+                           double *cmax, int *cidx, hipStream_t s)
 {
     int g = (int)((n + 255) / 256);
     hipLaunchKernelGGL(rank_kernel, dim3(g), dim3(256), 0, s, w, n, perm);
-    hipLaunchKernelGGL(colsign_kernel, dim3(g), dim3(256), 0, s, V, ldv_in, n, perm, sg);
+    hipLaunchKernelGGL(colmax_kernel, dim3(g, SIGN_CHUNKS), dim3(256), 0, s, V, ldv_in, n, cmax,
+                       cidx);
+    hipLaunchKernelGGL(colsign_kernel, dim3(g), dim3(256), 0, s, V, ldv_in, n, perm, cmax, cidx,
+                       sg);
     hipLaunchKernelGGL(permute_out_kernel, dim3(2048), dim3(256), 0, s, V, ldv_in, n, perm, sg,
                        w, W, Vout, ldv);
     return hipGetLastError();
@@ -562,16 +757,39 @@ hipError_t launch_rademacher(double *X, int64_t rows, int64_t n, int k, uint64_t
 
 // explicit instantiations
 template hipError_t launch_pair_solve<double>(double *, int64_t, int, int, const int2 *,
-                                              double *, double, double, int, double *, int *,
-                                              hipStream_t);
-template hipError_t launch_pair_solve<float>(float *, int64_t, int, int, const int2 *, float *,
-                                             double, double, int, double *, int *, hipStream_t);
+                                              const int2 *, double *, double, double, int,
+                                              double *, int *, hipStream_t);
+template hipError_t launch_pair_solve<float>(float *, int64_t, int, int, const int2 *,
+                                             const int2 *, float *, double, double, int,
+                                             double *, int *, hipStream_t);
+
+// Thread -> 2x2 block map of the pair solve for M = 2b positions: entry t < M/2
+// is the block hosting pair t of the next round, the rest follow in row order.
+void pair_solve_map(int M, int2 *out)
+{
+    const int h = M / 2;
+    int inv[128];
+    for (int p = 0; p < M; ++p)
+        inv[ps_sigma(p, M)] = p;
+    int cnt = 0;
+    bool used[64][64] = {};
+    for (int t = 0; t < h; ++t) {
+        int a = inv[2 * t] >> 1, c = inv[2 * t + 1] >> 1;
+        int k = a < c ? a : c, l = a < c ? c : a;
+        out[cnt++] = make_int2(k, l);
+        used[k][l] = true;
+    }
+    for (int k = 0; k < h; ++k)
+        for (int l = k; l < h; ++l)
+            if (!used[k][l])
+                out[cnt++] = make_int2(k, l);
+}
 template hipError_t launch_apply<double>(double *, int64_t, double *, int64_t, int64_t, int,
                                          int, const int2 *, const int2 *, int, const double *,
-                                         double *, int, hipStream_t);
+                                         double *, int, int, hipStream_t);
 template hipError_t launch_apply<float>(float *, int64_t, float *, int64_t, int64_t, int, int,
                                         const int2 *, const int2 *, int, const float *,
-                                        double *, int, hipStream_t);
+                                        double *, int, int, hipStream_t);
 template hipError_t launch_ingest<double>(const double *, int64_t, int64_t, double *, int64_t,
                                           double *, int *, int, hipStream_t);
 template hipError_t launch_ingest<float>(const double *, int64_t, int64_t, float *, int64_t,

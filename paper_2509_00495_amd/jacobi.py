@@ -39,7 +39,8 @@ class Opts(ctypes.Structure):
         ("check_symmetry", ctypes.c_int32),
         ("small_max_n", ctypes.c_int32),
         ("threads", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("timing", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -59,12 +60,24 @@ class Info(ctypes.Structure):
         ("off_cond", ctypes.c_double),
         ("orth_ns", ctypes.c_double),
         ("orth_est", ctypes.c_double),
+        ("t_pair_ms", ctypes.c_double * 2),
+        ("t_apply_ms", ctypes.c_double * 2),
+        ("t_applyv_ms", ctypes.c_double * 2),
+        ("n_pair", ctypes.c_int32 * 2),
+        ("n_apply", ctypes.c_int32 * 2),
+        ("n_applyv", ctypes.c_int32 * 2),
+        ("reserved_i2", ctypes.c_int32 * 2),
         ("reserved_d", ctypes.c_double * 3),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_
-                if not k.startswith("reserved")}
+        out = {}
+        for k, _ in self._fields_:
+            if k.startswith("reserved"):
+                continue
+            v = getattr(self, k)
+            out[k] = list(v) if isinstance(v, ctypes.Array) else v
+        return out
 
 
 _LIB = None
