@@ -80,6 +80,40 @@ __device__ inline void jacobi_angle(double app, double aqq, double apq,
     s = t * c;
 }
 
+// The same rotation from the hardware reciprocal and reciprocal square root
+// (v_rcp_f64, v_rsq_f64), each refined by one Newton step (r <- r (2 - x r);
+// y <- y (3 - x y^2) / 2).  c = 1/sqrt(1 + t^2) and s = t c then satisfy
+// c^2 + s^2 = 1 to a few ulp, which is what keeps the accumulated rotations
+// orthogonal; t itself only needs to annihilate a_pq to rounding level.
+// For |tau| > 2^500 (1 + tau^2 would overflow) t = 1/(2 tau).
+__device__ inline double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    return r * fma(-x, r, 2.0);
+}
+__device__ inline double rsq_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    return y * fma(-0.5 * x * y, y, 1.5);
+}
+__device__ inline void jacobi_angle_fast(double app, double aqq, double apq, double &c,
+                                         double &s, double &t)
+{
+    const double tau = (aqq - app) * rcp_nr(2.0 * apq);
+    const double at = fabs(tau);
+    double tt;
+    if (at > 0x1p500) {
+        tt = 0.5 * rcp_nr(at);
+    } else {
+        const double x = fma(at, at, 1.0);
+        const double root = x * rsq_nr(x); // sqrt(1 + tau^2)
+        tt = rcp_nr(at + root);
+    }
+    t = tau >= 0.0 ? tt : -tt;
+    c = rsq_nr(fma(t, t, 1.0));
+    s = t * c;
+}
+
 // Per-pair test: rotate only when a_pq is not negligible relative to the
 // diagonal (the per-pair threshold of Algorithm 4 with tol = eps) and above
 // the absolute floor thr = tol_off / n (if every |a_pq| <= tol_off / n then
@@ -89,6 +123,16 @@ __device__ inline bool jacobi_should_rotate(double app, double aqq, double apq,
 {
     double a = fabs(apq);
     return apq != 0.0 && a > thr && a > eps * sqrt(fabs(app * aqq));
+}
+
+// The same test without the square root: a^2 > eps^2 |a_pp a_qq| (the
+// operands are matrix entries of moderate size; a^2 underflows only below
+// 1e-154, far under any threshold used here).
+__device__ inline bool jacobi_should_rotate_sq(double app, double aqq, double apq, double eps,
+                                               double thr)
+{
+    double a = fabs(apq);
+    return apq != 0.0 && a > thr && a * a > eps * eps * fabs(app * aqq);
 }
 
 template <typename T>

@@ -29,16 +29,89 @@ __device__ inline T rotated_diag(T a, double t, T apq, int second)
     return (T)v;
 }
 
-// One workgroup per block pair (P, Q) of the round.  S (the 2b x 2b tile) and
-// U (its accumulated rotation, rows in logical order, columns in physical
-// order) are double-buffered in LDS; each round reads buffer a and writes the
-// rotated, permuted result to buffer b.  Each thread owns a fixed 2x2 block
-// (k <= l) of S and fixed (row, pair) items of U for the whole kernel.  The
-// angles of the next round are produced inside the same phase: every pair of
-// the next round joins one position of current pair k with one of current
-// pair l != k, so the owner of block (k, l) knows the new coupling (its own
-// result) and recomputes the two new diagonal entries from the current ones;
-// a round therefore costs one barrier.  Starting slot s holds tile index s.
+// Player of slot s in round r of the circle schedule on M players; the next
+// round moves every player of slot s >= 1 on by one (M-1 wraps to 1).
+__device__ inline int rr_next(int player, int M) { return player == 0 ? 0 : (player == M - 1 ? 1 : player + 1); }
+
+template <typename T>
+struct vec2;
+template <>
+struct vec2<float> {
+    typedef float2 type;
+};
+template <>
+struct vec2<double> {
+    typedef double2 type;
+};
+
+// 16-byte vector of T (4 floats or 2 doubles)
+template <typename T>
+struct vec16;
+template <>
+struct vec16<float> {
+    typedef float4 type;
+    static constexpr int n = 4;
+};
+template <>
+struct vec16<double> {
+    typedef double2 type;
+    static constexpr int n = 2;
+};
+
+// Per-pair record of a round in LDS: the rotation (c, s) packed for one
+// vector read, t, and the 2x2 problem it was computed from.
+template <typename T>
+struct PairRec {
+    typedef typename vec2<T>::type T2;
+    T2 *cs;
+    double *t;
+    T *app, *aqq, *apq;
+    __device__ PairRec(unsigned char *base, int h)
+    {
+        t = (double *)base;
+        cs = (T2 *)(t + h);
+        app = (T *)(cs + h);
+        aqq = app + h;
+        apq = aqq + h;
+    }
+    static constexpr size_t bytes(int h) { return ((size_t)h * (8 + 5 * sizeof(T)) + 15) & ~(size_t)15; }
+};
+
+template <typename T>
+__device__ inline int pair_record(PairRec<T> &R, int k, T app, T aqq, T apq, double eps,
+                                  double thr)
+{
+    double c = 1.0, sn = 0.0, t = 0.0;
+    int rot = 0;
+    if (jacobi_should_rotate_sq((double)app, (double)aqq, (double)apq, eps, thr)) {
+        jacobi_angle_fast((double)app, (double)aqq, (double)apq, c, sn, t);
+        rot = 1;
+    }
+    typename PairRec<T>::T2 v;
+    v.x = (T)c;
+    v.y = (T)sn;
+    R.cs[k] = v;
+    R.t[k] = t;
+    R.app[k] = app;
+    R.aqq[k] = aqq;
+    R.apq[k] = apq;
+    return rot;
+}
+
+// One workgroup per block pair (P, Q) of the round.  The 2b x 2b tile S (upper
+// triangle only, logical order) and its accumulated rotation U (stored
+// transposed, Ut[j][i] = U[i][j], so a column pair of U is two LDS rows that
+// are read and written 16 bytes at a time) are updated in place.  In inner
+// round r the M/2 disjoint pairs are those of the circle schedule on M = 2b
+// indices, (player(slot k), player(slot M-1-k)); every thread carries the
+// current players of the pairs it works on from round to round.  A thread
+// owns a fixed 2x2 block (k <= l) of S, or fixed (pair, 16-byte chunk) items
+// of U.  The next round's angles are computed in the same phase: each next
+// pair joins one index of current pair k with one of pair l != k, so the
+// owner of block (k, l) has the new coupling and recomputes the two new
+// diagonal entries from the pair records (never from S, which the diagonal
+// owners overwrite in the same phase).  One barrier per round, and about
+// 2 + 1/8 wavefront-level LDS instructions per element of S and U.
 template <typename T, int M, int NT>
 __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64_t ldb,
                                                         const int2 *__restrict__ pairs,
@@ -49,29 +122,30 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
                                                         int *rot_flag)
 {
     constexpr int b = M / 2, h = M / 2, ld = M + 1;
+    typedef typename vec16<T>::type TV;
+    constexpr int VN = vec16<T>::n;
+    constexpr int ldu = M + VN;             // 16-byte aligned rows of Ut
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *S0 = (T *)smem_raw;
-    T *S1 = S0 + M * ld;
-    T *U0 = S1 + M * ld;
-    T *U1 = U0 + M * ld;
-    double *csA = (double *)(smem_raw + align8(4 * sizeof(T) * M * ld));
-    double *csB = csA + 3 * h;
-    double *red = csB + 3 * h;
+    T *Ut = (T *)smem_raw;                  // M x ldu
+    T *S = Ut + M * ldu;                    // M x ld, entries i <= j
+    unsigned char *recbase = smem_raw + align8(sizeof(T) * (M * ldu + M * ld));
+    recbase = (unsigned char *)(((uintptr_t)recbase + 15) & ~(uintptr_t)15);
+    constexpr size_t RB = PairRec<T>::bytes(h);
+    double *red = (double *)(recbase + 2 * RB);
     int *ired = (int *)(red + 16);
     const int tid = threadIdx.x;
     const int pk = blockIdx.x;
     const int2 pq = pairs[pk];
+    auto sidx = [](int i, int j) { return i <= j ? i * ld + j : j * ld + i; };
     for (int idx = tid; idx < M * M; idx += NT) {
-        int p = idx / M, q = idx % M;
-        int i = ps_slot(p, M), j = ps_slot(q, M);
-        int64_t gi = i < b ? (int64_t)pq.x * b + i : (int64_t)pq.y * b + (i - b);
-        int64_t gj = j < b ? (int64_t)pq.x * b + j : (int64_t)pq.y * b + (j - b);
-        S0[p * ld + q] = B[gi * ldb + gj];
-        U0[p * ld + q] = (T)(p == ps_slot(q, M) ? 1 : 0); // U[row i][phys col q]
+        const int i = idx / M, j = idx % M;
+        if (i <= j) {
+            const int64_t gi = i < b ? (int64_t)pq.x * b + i : (int64_t)pq.y * b + (i - b);
+            const int64_t gj = j < b ? (int64_t)pq.x * b + j : (int64_t)pq.y * b + (j - b);
+            S[i * ld + j] = B[gi * ldb + gj];
+        }
+        Ut[i * ldu + j] = (T)(i == j ? 1 : 0);
     }
-    // fixed work assignment: block (bk, bl), bk <= bl, from the host-built
-    // map whose first h entries are the blocks hosting the next round's pairs
-    // (so their angle computations share one wavefront)
     constexpr int NBLK = h * (h + 1) / 2;
     int bk = -1, bl = -1;
     if (tid < NBLK) {
@@ -79,133 +153,131 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
         bk = e.x;
         bl = e.y;
     }
-    const int dk0 = bk >= 0 ? ps_sigma(2 * bk, M) : 0, dk1 = bk >= 0 ? ps_sigma(2 * bk + 1, M) : 0;
-    const int dl0 = bk >= 0 ? ps_sigma(2 * bl, M) : 0, dl1 = bk >= 0 ? ps_sigma(2 * bl + 1, M) : 0;
-    // the next-round pair hosted by this block, if any: entry (ha, hc) =
-    // (2bk+ha, 2bl+hc) becomes next pair hk (a block hosts at most one; the
-    // host-built map puts the hosting blocks on threads 0 .. h-1).  Scalars,
-    // not arrays, so nothing lands in scratch memory.
+    int pk0 = bk, pk1 = M - 1 - bk, pl0 = bl, pl1 = M - 1 - bl;
     int hosted = 0, ha = 0, hc = 0, hk = 0, hfirst = 0;
     if (bk >= 0 && bk != bl) {
         for (int a = 0; a < 2; ++a)
             for (int c = 0; c < 2; ++c) {
-                int sp = ps_sigma(2 * bk + a, M), sq = ps_sigma(2 * bl + c, M);
-                if ((sp >> 1) == (sq >> 1)) {
+                const int sa = a ? M - 1 - bk : bk, sc = c ? M - 1 - bl : bl;
+                const int na = sa == 0 ? 0 : (sa == 1 ? M - 1 : sa - 1);
+                const int nc = sc == 0 ? 0 : (sc == 1 ? M - 1 : sc - 1);
+                const int ka = na < h ? na : M - 1 - na, kc = nc < h ? nc : M - 1 - nc;
+                if (ka == kc) {
                     hosted = 1;
                     ha = a;
                     hc = c;
-                    hk = sp >> 1;
-                    hfirst = (sp & 1) == 0; // the row position lands first
+                    hk = ka;
+                    hfirst = na < h;
                 }
             }
     }
-    constexpr int NU = M * h; // (row, pair) items of U
+    // U items: (pair k, chunk of VN rows), on the wavefronts after the first
+    constexpr int CH = M / VN;
+    constexpr int NU = h * CH;
+    constexpr int UW = NT - WAVE;
+    constexpr int NIT = (NU + UW - 1) / UW;
+    int up0[NIT], up1[NIT];
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+        const int it = tid - WAVE + j * UW;
+        const int k = (tid >= WAVE && it < NU) ? it / CH : 0;
+        up0[j] = k;
+        up1[j] = M - 1 - k;
+    }
     __syncthreads();
     int rot = 0;
-    // angles of round 0
     if (tid < h) {
-        const int p = 2 * tid, q = p + 1;
-        double app = (double)S0[p * ld + p], aqq = (double)S0[q * ld + q];
-        double apq = (double)S0[p * ld + q];
-        double c = 1.0, sn = 0.0, t = 0.0;
-        if (jacobi_should_rotate(app, aqq, apq, eps, thr)) {
-            jacobi_angle(app, aqq, apq, c, sn, t);
-            rot = 1;
-        }
-        csA[tid] = c;
-        csA[h + tid] = sn;
-        csA[2 * h + tid] = t;
+        PairRec<T> R0(recbase, h);
+        rot |= pair_record<T>(R0, tid, S[tid * ld + tid], S[(M - 1 - tid) * ld + M - 1 - tid],
+                              S[tid * ld + M - 1 - tid], eps, thr);
     }
     __syncthreads();
-    T *Sa = S0, *Sb = S1, *Ua = U0, *Ub = U1;
-    double *ca = csA, *cb = csB;
     const int rounds = inner * (M - 1);
     for (int r = 0; r < rounds; ++r) {
+        const PairRec<T> A(recbase + (r & 1) * RB, h);
+        PairRec<T> Bn(recbase + ((r + 1) & 1) * RB, h);
         if (bk >= 0) {
             const int k = bk, l = bl;
-            const int pk0 = 2 * k, pk1 = pk0 + 1, pl0 = 2 * l, pl1 = pl0 + 1;
             if (k == l) {
-                const double tk = ca[2 * h + k];
-                const T apq = Sa[pk0 * ld + pk1];
-                Sb[dk0 * ld + dk0] = rotated_diag<T>(Sa[pk0 * ld + pk0], tk, apq, 0);
-                Sb[dk1 * ld + dk1] = rotated_diag<T>(Sa[pk1 * ld + pk1], tk, apq, 1);
-                T z = ca[h + k] == 0.0 ? apq : (T)0;
-                Sb[dk0 * ld + dk1] = z;
-                Sb[dk1 * ld + dk0] = z;
+                const double tk = A.t[k];
+                const T apq = A.apq[k];
+                S[pk0 * ld + pk0] = rotated_diag<T>(A.app[k], tk, apq, 0);
+                S[pk1 * ld + pk1] = rotated_diag<T>(A.aqq[k], tk, apq, 1);
+                S[sidx(pk0, pk1)] = A.cs[k].y == (T)0 ? apq : (T)0;
             } else {
-                const T ck = (T)ca[k], sk = (T)ca[h + k], cl = (T)ca[l], sl = (T)ca[h + l];
-                T x00 = Sa[pk0 * ld + pl0], x01 = Sa[pk0 * ld + pl1];
-                T x10 = Sa[pk1 * ld + pl0], x11 = Sa[pk1 * ld + pl1];
-                T y00 = ck * x00 - sk * x10, y01 = ck * x01 - sk * x11;
-                T y10 = sk * x00 + ck * x10, y11 = sk * x01 + ck * x11;
-                T z[2][2];
-                z[0][0] = cl * y00 - sl * y01;
-                z[0][1] = sl * y00 + cl * y01;
-                z[1][0] = cl * y10 - sl * y11;
-                z[1][1] = sl * y10 + cl * y11;
-                Sb[dk0 * ld + dl0] = z[0][0];
-                Sb[dk0 * ld + dl1] = z[0][1];
-                Sb[dk1 * ld + dl0] = z[1][0];
-                Sb[dk1 * ld + dl1] = z[1][1];
-                Sb[dl0 * ld + dk0] = z[0][0];
-                Sb[dl1 * ld + dk0] = z[0][1];
-                Sb[dl0 * ld + dk1] = z[1][0];
-                Sb[dl1 * ld + dk1] = z[1][1];
-                // angle of the next round for the hosted pair
+                const typename PairRec<T>::T2 csk = A.cs[k], csl = A.cs[l];
+                const T ck = csk.x, sk = csk.y, cl = csl.x, sl = csl.y;
+                const int a00 = sidx(pk0, pl0), a01 = sidx(pk0, pl1);
+                const int a10 = sidx(pk1, pl0), a11 = sidx(pk1, pl1);
+                const T x00 = S[a00], x01 = S[a01], x10 = S[a10], x11 = S[a11];
+                const T y00 = ck * x00 - sk * x10, y01 = ck * x01 - sk * x11;
+                const T y10 = sk * x00 + ck * x10, y11 = sk * x01 + ck * x11;
+                const T z00 = cl * y00 - sl * y01, z01 = sl * y00 + cl * y01;
+                const T z10 = cl * y10 - sl * y11, z11 = sl * y10 + cl * y11;
+                S[a00] = z00;
+                S[a01] = z01;
+                S[a10] = z10;
+                S[a11] = z11;
                 if (hosted) {
-                    const int pe = pk0 + ha, qe = pl0 + hc;
-                    const T dpe = rotated_diag<T>(Sa[pe * ld + pe], ca[2 * h + k],
-                                                  Sa[pk0 * ld + pk1], ha);
-                    const T dqe = rotated_diag<T>(Sa[qe * ld + qe], ca[2 * h + l],
-                                                  Sa[pl0 * ld + pl1], hc);
-                    const double app = (double)(hfirst ? dpe : dqe);
-                    const double aqq = (double)(hfirst ? dqe : dpe);
-                    const T zz = ha ? (hc ? z[1][1] : z[1][0]) : (hc ? z[0][1] : z[0][0]);
-                    const double apq = (double)zz;
-                    double cc = 1.0, sn = 0.0, t = 0.0;
-                    if (jacobi_should_rotate(app, aqq, apq, eps, thr)) {
-                        jacobi_angle(app, aqq, apq, cc, sn, t);
-                        if (r + 1 < rounds)
-                            rot = 1;
-                    }
-                    cb[hk] = cc;
-                    cb[h + hk] = sn;
-                    cb[2 * h + hk] = t;
+                    const T dpe = ha ? rotated_diag<T>(A.aqq[k], A.t[k], A.apq[k], 1)
+                                     : rotated_diag<T>(A.app[k], A.t[k], A.apq[k], 0);
+                    const T dqe = hc ? rotated_diag<T>(A.aqq[l], A.t[l], A.apq[l], 1)
+                                     : rotated_diag<T>(A.app[l], A.t[l], A.apq[l], 0);
+                    const T zz = ha ? (hc ? z11 : z10) : (hc ? z01 : z00);
+                    const int rr = pair_record<T>(Bn, hk, hfirst ? dpe : dqe,
+                                                  hfirst ? dqe : dpe, zz, eps, thr);
+                    if (r + 1 < rounds)
+                        rot |= rr;
                 }
             }
         }
-        // U items go to the wavefronts after the first (which carries the
-        // angle computations)
-        for (int it = tid - WAVE; it >= 0 && it < NU; it += NT - WAVE) {
-            const int i = it / h, k = it % h;
-            const int p0 = 2 * k, p1 = p0 + 1;
-            const T c = (T)ca[k], sn = (T)ca[h + k];
-            T u0 = Ua[i * ld + p0], u1 = Ua[i * ld + p1];
-            Ub[i * ld + ps_sigma(p0, M)] = c * u0 - sn * u1;
-            Ub[i * ld + ps_sigma(p1, M)] = sn * u0 + c * u1;
+#pragma unroll
+        for (int j = 0; j < NIT; ++j) {
+            const int it = tid - WAVE + j * UW;
+            if (tid >= WAVE && it < NU) {
+                const int k = it / CH, c = it % CH;
+                const typename PairRec<T>::T2 cs = A.cs[k];
+                if (cs.y != (T)0) {
+                    TV *r0 = (TV *)(Ut + up0[j] * ldu) + c;
+                    TV *r1 = (TV *)(Ut + up1[j] * ldu) + c;
+                    const TV u0 = *r0, u1 = *r1;
+                    TV n0, n1;
+                    n0.x = cs.x * u0.x - cs.y * u1.x;
+                    n1.x = cs.y * u0.x + cs.x * u1.x;
+                    n0.y = cs.x * u0.y - cs.y * u1.y;
+                    n1.y = cs.y * u0.y + cs.x * u1.y;
+                    if constexpr (VN == 4) {
+                        n0.z = cs.x * u0.z - cs.y * u1.z;
+                        n1.z = cs.y * u0.z + cs.x * u1.z;
+                        n0.w = cs.x * u0.w - cs.y * u1.w;
+                        n1.w = cs.y * u0.w + cs.x * u1.w;
+                    }
+                    *r0 = n0;
+                    *r1 = n1;
+                }
+                up0[j] = rr_next(up0[j], M);
+                up1[j] = rr_next(up1[j], M);
+            }
         }
+        pk0 = rr_next(pk0, M);
+        pk1 = rr_next(pk1, M);
+        pl0 = rr_next(pl0, M);
+        pl1 = rr_next(pl1, M);
         __syncthreads();
-        T *tmp = Sa;
-        Sa = Sb;
-        Sb = tmp;
-        tmp = Ua;
-        Ua = Ub;
-        Ub = tmp;
-        double *tc = ca;
-        ca = cb;
-        cb = tc;
     }
-    // back in the starting layout: position p holds tile index ps_slot(p)
     T *Uk = U + (int64_t)pk * M * M;
+    double acc = 0.0;
     for (int idx = tid; idx < M * M; idx += NT) {
-        int p = idx / M, q = idx % M;
-        int i = ps_slot(p, M), j = ps_slot(q, M);
-        int64_t gi = i < b ? (int64_t)pq.x * b + i : (int64_t)pq.y * b + (i - b);
-        int64_t gj = j < b ? (int64_t)pq.x * b + j : (int64_t)pq.y * b + (j - b);
-        B[gi * ldb + gj] = Sa[p * ld + q];
-        Uk[p * M + j] = Ua[p * ld + q]; // U[row p][logical column j]
+        const int i = idx / M, j = idx % M;
+        const int64_t gi = i < b ? (int64_t)pq.x * b + i : (int64_t)pq.y * b + (i - b);
+        const int64_t gj = j < b ? (int64_t)pq.x * b + j : (int64_t)pq.y * b + (j - b);
+        const T v = S[sidx(i, j)];
+        B[gi * ldb + gj] = v;
+        Uk[idx] = Ut[j * ldu + i];
+        if (i != j)
+            acc += (double)v * (double)v;
     }
-    double off2 = lds_off2<T, NT>(Sa, ld, M, red);
+    const double off2 = block_sum<NT>(acc, red);
     int any = block_or<NT>(rot, ired);
     if (tid == 0) {
         partial[pk] = off2;
@@ -220,8 +292,10 @@ hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *p
                              double *partial, int *rot_flag, hipStream_t s)
 {
     const int M = 2 * b;
-    size_t smem = align8(4 * sizeof(T) * M * (M + 1)) + (6 * b + 16) * sizeof(double) +
-                  16 * sizeof(int);
+    const int vn = 16 / (int)sizeof(T);
+    size_t smem = align8(sizeof(T) * ((size_t)M * (M + vn) + (size_t)M * (M + 1))) + 16 +
+                  2 * (((size_t)b * (8 + 5 * sizeof(T)) + 15) & ~(size_t)15) +
+                  16 * sizeof(double) + 16 * sizeof(int);
     hipError_t e;
     if (M == 64) {
         auto k = pair_solve_kernel<T, 64, 1024>;
@@ -395,24 +469,253 @@ __global__ __launch_bounds__(256) void apply_kernel(T *__restrict__ B, int64_t l
     }
 }
 
-// which = 1: B tiles only, 2: V tiles only, 3: both in one launch.
+// Persistent, software-pipelined update kernel.  A workgroup walks tiles
+// t = blockIdx.x, blockIdx.x + gridDim.x, ...; mode 1 = off-diagonal B tiles
+// (Z = U_k^T X U_l, result and transpose written), mode 2 = V row tiles
+// (Z = X U_l).  The U operands never touch LDS: every lane keeps the MFMA
+// fragments it needs in registers (B operand of X U_l: U_l[kk][j]; A operand
+// of U_k^T Y: U_k[kk][i]; both read along rows of the L2-resident U blocks).
+// Only X, then Y, then Z pass through one LDS tile.  While a tile computes,
+// the next tile's X and U fragments are already being loaded.
+template <typename T, int M>
+struct TileOps {
+    static constexpr int b = M / 2, ld = M + 1, TM = M / 32, KS = M / 4;
+    static constexpr int PER = M * M / 256; // X elements per thread
+    __device__ static inline int64_t gidx(int2 pq, int i)
+    {
+        return i < b ? (int64_t)pq.x * b + i : (int64_t)pq.y * b + (i - b);
+    }
+    // fragment f = ks * TM + t: row kk = 4 ks + lane/16, column 16 t + lane%16
+    // of the wave's half (offset off = row0 or col0)
+    __device__ static inline void load_frag(const T *Ublk, int off, T (&fr)[KS * TM])
+    {
+        const int lane = threadIdx.x % WAVE, li = lane % 16, lk = lane / 16;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int t = 0; t < TM; ++t)
+                fr[ks * TM + t] = Ublk[(4 * ks + lk) * M + off + t * 16 + li];
+    }
+};
+
+template <typename T, int M>
+__global__ __launch_bounds__(256) void apply2_kernel(T *__restrict__ B, int64_t ldb,
+                                                     T *__restrict__ V, int64_t ldv,
+                                                     const int2 *__restrict__ pairs,
+                                                     const int2 *__restrict__ btiles, int ntiles,
+                                                     int npairs, const T *__restrict__ U,
+                                                     double *__restrict__ partial, int want_off,
+                                                     int mode)
+{
+    using O = TileOps<T, M>;
+    constexpr int ld = O::ld, TM = O::TM, KS = O::KS, PER = O::PER;
+    // FP32 keeps the next tile's U fragments in flight too; FP64 loads them
+    // per tile (U_l before the first product, U_k after it), which keeps
+    // register use low enough for three waves per SIMD
+    constexpr bool PREF_U = sizeof(T) == 4;
+    __shared__ T Xs[M * ld];
+    __shared__ double red[4];
+    const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+    const int li = lane % 16, lk = lane / 16;
+    const int row0 = (w / 2) * (M / 2), col0 = (w % 2) * (M / 2);
+    typedef typename acc4<T>::type accT;
+    T xr[PER];
+    T ul[KS * TM], uk[KS * TM];
+
+    // tile descriptors
+    auto tile_info = [&](int tile, int2 &pk, int2 &pl, int &kx, int &lx, int64_t &r0) {
+        if (mode == 1) {
+            const int2 kl = btiles[tile];
+            kx = kl.x;
+            lx = kl.y;
+            pk = pairs[kx];
+            pl = pairs[lx];
+            r0 = 0;
+        } else {
+            lx = tile % npairs;
+            kx = 0;
+            r0 = (int64_t)(tile / npairs) * M;
+            pl = pairs[lx];
+            pk = pl;
+        }
+    };
+    auto load_x = [&](int2 pk, int2 pl, int64_t r0) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * 256, i = idx / M, j = idx % M;
+            const int64_t gj = O::gidx(pl, j);
+            xr[e] = mode == 1 ? B[O::gidx(pk, i) * ldb + gj] : V[(r0 + i) * ldv + gj];
+        }
+    };
+
+    int tile = blockIdx.x;
+    if (tile >= ntiles)
+        return;
+    int2 pk, pl;
+    int kx, lx;
+    int64_t r0;
+    tile_info(tile, pk, pl, kx, lx, r0);
+    load_x(pk, pl, r0);
+    if (PREF_U) {
+        O::load_frag(U + (int64_t)lx * M * M, col0, ul);
+        if (mode == 1)
+            O::load_frag(U + (int64_t)kx * M * M, row0, uk);
+    }
+
+    while (true) {
+        // X -> LDS
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * 256;
+            Xs[(idx / M) * ld + idx % M] = xr[e];
+        }
+        __syncthreads();
+        const int next = tile + gridDim.x;
+        int2 npk = pk, npl = pl;
+        int nkx = kx, nlx = lx;
+        int64_t nr0 = r0;
+        if (next < ntiles) {
+            tile_info(next, npk, npl, nkx, nlx, nr0);
+            load_x(npk, npl, nr0); // in flight during this tile's GEMMs
+        }
+        if (!PREF_U)
+            O::load_frag(U + (int64_t)lx * M * M, col0, ul);
+        // Y = X U_l
+        accT acc[TM][TM];
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int c = 0; c < TM; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    acc[a][c][v] = (T)0;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int kk = 4 * ks + lk;
+            T a[TM];
+#pragma unroll
+            for (int t = 0; t < TM; ++t)
+                a[t] = Xs[(row0 + t * 16 + li) * ld + kk];
+#pragma unroll
+            for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < TM; ++tj)
+                    acc[ti][tj] = mfma16(a[ti], ul[ks * TM + tj], acc[ti][tj]);
+        }
+        if (PREF_U && next < ntiles)
+            O::load_frag(U + (int64_t)nlx * M * M, col0, ul);
+        if (!PREF_U && mode == 1)
+            O::load_frag(U + (int64_t)kx * M * M, row0, uk);
+        __syncthreads();
+        if (mode == 1) {
+#pragma unroll
+            for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < TM; ++tj)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        Xs[(row0 + ti * 16 + acc_row<T>(lk, v)) * ld + col0 + tj * 16 + li] =
+                            acc[ti][tj][v];
+            __syncthreads();
+            // Z = U_k^T Y
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int c = 0; c < TM; ++c)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        acc[a][c][v] = (T)0;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int kk = 4 * ks + lk;
+                T bb[TM];
+#pragma unroll
+                for (int t = 0; t < TM; ++t)
+                    bb[t] = Xs[kk * ld + col0 + t * 16 + li];
+#pragma unroll
+                for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TM; ++tj)
+                        acc[ti][tj] = mfma16(uk[ks * TM + ti], bb[tj], acc[ti][tj]);
+            }
+            if (PREF_U && next < ntiles)
+                O::load_frag(U + (int64_t)nkx * M * M, row0, uk);
+            __syncthreads();
+        }
+        // Z -> LDS -> global (B tile and its mirror, or V tile)
+#pragma unroll
+        for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < TM; ++tj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    Xs[(row0 + ti * 16 + acc_row<T>(lk, v)) * ld + col0 + tj * 16 + li] =
+                        acc[ti][tj][v];
+        __syncthreads();
+        double sq = 0.0;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * 256, i = idx / M, j = idx % M;
+            const T z = Xs[i * ld + j];
+            if (mode == 1) {
+                B[O::gidx(pk, i) * ldb + O::gidx(pl, j)] = z;
+                sq += (double)z * (double)z;
+                // mirror, coalesced along its rows: element (i, j) of Z^T
+                B[O::gidx(pl, i) * ldb + O::gidx(pk, j)] = Xs[j * ld + i];
+            } else {
+                V[(r0 + i) * ldv + O::gidx(pl, j)] = z;
+            }
+        }
+        if (mode == 1 && want_off) {
+            sq = wave_sum(sq);
+            if (lane == 0)
+                red[w] = sq;
+            __syncthreads();
+            if (tid == 0)
+                partial[tile] = 2.0 * (red[0] + red[1] + red[2] + red[3]);
+        }
+        if (next >= ntiles)
+            break;
+        __syncthreads(); // Xs is rewritten by the next tile
+        tile = next;
+        pk = npk;
+        pl = npl;
+        kx = nkx;
+        lx = nlx;
+        r0 = nr0;
+    }
+}
+
+// which = 1: B tiles, 2: V tiles.  Persistent grid: at most `grid_cap`
+// workgroups (0 = one per tile).
 template <typename T>
 hipError_t launch_apply(T *B, int64_t ldb, T *V, int64_t ldv, int64_t nrows, int b, int npairs,
                         const int2 *pairs, const int2 *btiles, int nbt, const T *U,
                         double *partial, int want_off, int which, hipStream_t s)
 {
     const int M = 2 * b;
-    const int64_t nvt = (which & 2) ? (nrows / M) * npairs : 0;
-    const int nb = (which & 1) ? nbt : 0;
-    const int64_t grid = nb + nvt;
-    if (grid == 0)
+    const int64_t ntiles = which == 1 ? nbt : (nrows / M) * npairs;
+    if (ntiles == 0)
         return hipSuccess;
+    static int cap[2][2] = {{0, 0}, {0, 0}};
+    int &c = cap[sizeof(T) == 8][M == 64];
+    if (c == 0) {
+        int dev = 0, cus = 0, per = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (M == 64)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, apply2_kernel<T, 64>, 256, 0);
+        else
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, apply2_kernel<T, 32>, 256, 0);
+        c = (cus > 0 ? cus : 256) * (per > 0 ? per : 1);
+    }
+    const unsigned grid = (unsigned)(ntiles < c ? ntiles : c);
     if (M == 64)
-        hipLaunchKernelGGL((apply_kernel<T, 64>), dim3((unsigned)grid), dim3(256), 0, s, B,
-                           ldb, V, ldv, pairs, btiles, nb, npairs, U, partial, want_off);
+        hipLaunchKernelGGL((apply2_kernel<T, 64>), dim3(grid), dim3(256), 0, s, B, ldb, V, ldv,
+                           pairs, btiles, (int)ntiles, npairs, U, partial, want_off, which);
     else if (M == 32)
-        hipLaunchKernelGGL((apply_kernel<T, 32>), dim3((unsigned)grid), dim3(256), 0, s, B,
-                           ldb, V, ldv, pairs, btiles, nb, npairs, U, partial, want_off);
+        hipLaunchKernelGGL((apply2_kernel<T, 32>), dim3(grid), dim3(256), 0, s, B, ldb, V, ldv,
+                           pairs, btiles, (int)ntiles, npairs, U, partial, want_off, which);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
