@@ -67,7 +67,13 @@ typedef struct jacobi_opts {
     int32_t timing;         /* nonzero: time every pair-solve and apply launch of
                                the block path with HIP events on `stream`
                                (results in jacobi_info.t_*) */
-    int32_t reserved[4];
+    int32_t schedule;       /* order of the rotations in a block-path sweep:
+                               0 (default) = every index pair once per sweep:
+                               the first round of a sweep rotates all pairs of
+                               its 2b x 2b tiles, the others only pairs that
+                               join the two blocks of a tile; 1 = all pairs of
+                               every tile in every round */
+    int32_t reserved[3];
 } jacobi_opts;
 
 /* Diagnostics filled on return (host struct, may be NULL). */

@@ -30,7 +30,7 @@ constexpr double U_D = 0x1p-53; // unit roundoff, double
 constexpr double U_L = 0x1p-24; // unit roundoff, single
 
 struct Opts {
-    int max_sweeps, block, inner, ns_iters, check_sym, small_max_n, threads, timing;
+    int max_sweeps, block, inner, ns_iters, check_sym, small_max_n, threads, timing, schedule;
     double c32;
 };
 
@@ -45,10 +45,14 @@ int resolve_opts(const jacobi_opts *o, Opts &r)
     r.small_max_n = 128;
     r.threads = 0;
     r.timing = 0;
+    r.schedule = 0;
     r.c32 = 1.0;
     if (!o)
         return 0;
     r.timing = o->timing != 0;
+    if (o->schedule < 0 || o->schedule > 1)
+        return 1;
+    r.schedule = o->schedule;
     if (o->max_sweeps < 0 || o->max_sweeps > 1000)
         return 1;
     if (o->max_sweeps)
@@ -186,7 +190,7 @@ BlockWs layout_block(Bump &bp, int64_t n, const Geometry &g, bool mixed)
     w.flags = bp.take<int>(8);
     w.pairs = bp.take<int2>((size_t)(g.N - 1) * g.npairs);
     w.btiles = bp.take<int2>((size_t)std::max(g.nbt, 1));
-    w.psmap = bp.take<int2>((size_t)g.b * (g.b + 1) / 2);
+    w.psmap = bp.take<int2>((size_t)g.b * (g.b + 1)); // circle map, then cross map
     w.perm = bp.take<int>((size_t)std::max<int64_t>(n, 1));
     w.wtmp = bp.take<double>((size_t)std::max<int64_t>(n, 1));
     w.sg = bp.take<double>((size_t)std::max<int64_t>(n, 1));
@@ -374,7 +378,8 @@ struct SideStream {
 
 template <typename T>
 int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U, double tol,
-               double eps, int max_sweeps, int inner, bool fp32_stage, hipStream_t s,
+               double eps, int max_sweeps, int inner, int schedule, bool fp32_stage,
+               hipStream_t s,
                SideStream &ss, int *sweeps_out, double *off_out, double *off0_out,
                RoundTimer *tm)
 {
@@ -408,8 +413,10 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
                 CK(hipStreamWaitEvent(s, ss.evV[j], 0));
             if (timed)
                 CK(hipEventRecord(tm->ev[5 * r], s));
-            CK(launch_pair_solve<T>(B, g.npad, g.b, g.npairs, pr, w.psmap, Ub, eps, thr, inner,
-                                    w.partial, w.flags + 2, s));
+            const int cross = schedule == 0 && r > 0;
+            const int2 *map = w.psmap + (cross ? (size_t)g.b * (g.b + 1) / 2 : 0);
+            CK(launch_pair_solve<T>(B, g.npad, g.b, g.npairs, pr, map, Ub, eps, thr, inner,
+                                    cross, w.partial, w.flags + 2, s));
             CK(hipEventRecord(ss.evU[j], s));
             if (timed)
                 CK(hipEventRecord(tm->ev[5 * r + 1], s));
@@ -462,8 +469,10 @@ int setup_block(const Geometry &g, const BlockWs &w, hipStream_t s)
                       s));
     CK(hipMemcpyAsync(w.btiles, tiles.data(), tiles.size() * sizeof(int2),
                       hipMemcpyHostToDevice, s));
-    std::vector<int2> psmap((size_t)g.b * (g.b + 1) / 2);
-    pair_solve_map(g.M, psmap.data());
+    const size_t nblk = (size_t)g.b * (g.b + 1) / 2;
+    std::vector<int2> psmap(2 * nblk);
+    pair_solve_map(g.M, 0, psmap.data());
+    pair_solve_map(g.M, 1, psmap.data() + nblk);
     CK(hipMemcpyAsync(w.psmap, psmap.data(), psmap.size() * sizeof(int2), hipMemcpyHostToDevice,
                       s));
     CK(launch_fill_i32(w.flags, 8, 0, s));
@@ -638,7 +647,7 @@ int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, in
     if (int e = ss.init())
         return e;
     int st = run_sweeps<double>(g, n, w, w.B64, w.V64, w.U64, tol, U_D, o.max_sweeps, o.inner,
-                                false, s, ss, &sweeps, &off, nullptr, &tm);
+                                o.schedule, false, s, ss, &sweeps, &off, nullptr, &tm);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;
     double est = 0.0;
@@ -682,7 +691,7 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     if (int e = ss.init())
         return e;
     int st32 = run_sweeps<float>(g, n, w, w.B32, w.V32, w.U32, tol32, U_L, o.max_sweeps,
-                                 o.inner, true, s, ss, &sw32, &off32, nullptr, &tm32);
+                                 o.inner, o.schedule, true, s, ss, &sw32, &off32, nullptr, &tm32);
     if (st32 == JACOBI_DEVICE)
         return st32;
     // stage 2: Newton-Schulz, X <- X + X (I - X^T X) / 2  (= X (3I - X^T X) / 2)
@@ -720,8 +729,8 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     const double tol = tol_in > 0.0 ? tol_in : 1e-15 * (double)n * normf;
     int sw64 = 0;
     double off = 0.0, offc = 0.0;
-    int st = run_sweeps<double>(g, n, w, A64, X, w.U64, tol, U_D, o.max_sweeps, o.inner, false,
-                                s, ss, &sw64, &off, &offc, &tm64);
+    int st = run_sweeps<double>(g, n, w, A64, X, w.U64, tol, U_D, o.max_sweeps, o.inner,
+                                o.schedule, false, s, ss, &sw64, &off, &offc, &tm64);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;
     double est = 0.0;

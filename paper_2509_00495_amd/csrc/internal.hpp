@@ -30,9 +30,9 @@ int small_max_active(int m_max, int pool, int nthreads);
 template <typename T>
 hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                              const int2 *psmap, T *U, double eps, double thr, int inner,
-                             double *partial, int *rot_flag, hipStream_t s);
+                             int cross, double *partial, int *rot_flag, hipStream_t s);
 // thread -> block map of the pair solve (b(b+1)/2 entries for M = 2b)
-void pair_solve_map(int M, int2 *out);
+void pair_solve_map(int M, int cross, int2 *out);
 // which = 1: B tiles only, 2: V tiles only, 3: both
 template <typename T>
 hipError_t launch_apply(T *B, int64_t ldb, T *V, int64_t ldv, int64_t nrows, int b,

@@ -112,7 +112,17 @@ __device__ inline int pair_record(PairRec<T> &R, int k, T app, T aqq, T apq, dou
 // diagonal entries from the pair records (never from S, which the diagonal
 // owners overwrite in the same phase).  One barrier per round, and about
 // 2 + 1/8 wavefront-level LDS instructions per element of S and U.
-template <typename T, int M, int NT>
+//
+// CROSS selects the cross schedule instead: only pairs (i, j) with i in P and
+// j in Q are rotated, in b rounds; round r pairs position i with b + (i + r)
+// mod b.  A sweep that runs the circle schedule in its first round (every
+// block appears once there, so every pair inside a block is rotated) and the
+// cross schedule in the others rotates every index pair of the matrix exactly
+// once, as a cyclic sweep of Algorithm 4 does, in about n instead of 2n
+// rounds.  The next pair i joins position i of pair i with the second position
+// of pair i + 1 (mod b), so block (i, i + 1), or (0, b - 1) for i = b - 1,
+// hosts it.
+template <typename T, int M, int NT, bool CROSS>
 __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64_t ldb,
                                                         const int2 *__restrict__ pairs,
                                                         const int2 *__restrict__ psmap,
@@ -153,9 +163,22 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
         bk = e.x;
         bl = e.y;
     }
-    int pk0 = bk, pk1 = M - 1 - bk, pl0 = bl, pl1 = M - 1 - bl;
+    // second position of a pair in the next round of the cross schedule
+    auto cnext = [](int q) { return q == M - 1 ? b : q + 1; };
+    int pk0 = bk, pk1 = CROSS ? b + bk : M - 1 - bk, pl0 = bl, pl1 = CROSS ? b + bl : M - 1 - bl;
     int hosted = 0, ha = 0, hc = 0, hk = 0, hfirst = 0;
-    if (bk >= 0 && bk != bl) {
+    if (CROSS) {
+        if (bk >= 0 && bl == bk + 1) {
+            hosted = 1;
+            hk = bk;
+            hfirst = 1;
+            hc = 1;
+        } else if (bk == 0 && bl == b - 1) {
+            hosted = 1;
+            hk = b - 1;
+            ha = 1;
+        }
+    } else if (bk >= 0 && bk != bl) {
         for (int a = 0; a < 2; ++a)
             for (int c = 0; c < 2; ++c) {
                 const int sa = a ? M - 1 - bk : bk, sc = c ? M - 1 - bl : bl;
@@ -182,17 +205,18 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
         const int it = tid - WAVE + j * UW;
         const int k = (tid >= WAVE && it < NU) ? it / CH : 0;
         up0[j] = k;
-        up1[j] = M - 1 - k;
+        up1[j] = CROSS ? b + k : M - 1 - k;
     }
     __syncthreads();
     int rot = 0;
     if (tid < h) {
         PairRec<T> R0(recbase, h);
-        rot |= pair_record<T>(R0, tid, S[tid * ld + tid], S[(M - 1 - tid) * ld + M - 1 - tid],
-                              S[tid * ld + M - 1 - tid], eps, thr);
+        const int q = CROSS ? b + tid : M - 1 - tid;
+        rot |= pair_record<T>(R0, tid, S[tid * ld + tid], S[q * ld + q], S[tid * ld + q], eps,
+                              thr);
     }
     __syncthreads();
-    const int rounds = inner * (M - 1);
+    const int rounds = inner * (CROSS ? b : M - 1);
     for (int r = 0; r < rounds; ++r) {
         const PairRec<T> A(recbase + (r & 1) * RB, h);
         PairRec<T> Bn(recbase + ((r + 1) & 1) * RB, h);
@@ -255,14 +279,23 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
                     *r0 = n0;
                     *r1 = n1;
                 }
-                up0[j] = rr_next(up0[j], M);
-                up1[j] = rr_next(up1[j], M);
+                if (CROSS) {
+                    up1[j] = cnext(up1[j]);
+                } else {
+                    up0[j] = rr_next(up0[j], M);
+                    up1[j] = rr_next(up1[j], M);
+                }
             }
         }
-        pk0 = rr_next(pk0, M);
-        pk1 = rr_next(pk1, M);
-        pl0 = rr_next(pl0, M);
-        pl1 = rr_next(pl1, M);
+        if (CROSS) {
+            pk1 = cnext(pk1);
+            pl1 = cnext(pl1);
+        } else {
+            pk0 = rr_next(pk0, M);
+            pk1 = rr_next(pk1, M);
+            pl0 = rr_next(pl0, M);
+            pl1 = rr_next(pl1, M);
+        }
         __syncthreads();
     }
     T *Uk = U + (int64_t)pk * M * M;
@@ -286,37 +319,47 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
     }
 }
 
+template <typename T, int M, int NT, bool CROSS>
+static hipError_t launch_pair_solve_t(T *B, int64_t ldb, int npairs, const int2 *pairs,
+                                      const int2 *psmap, T *U, double eps, double thr,
+                                      int inner, double *partial, int *rot_flag, size_t smem,
+                                      hipStream_t s)
+{
+    auto k = pair_solve_kernel<T, M, NT, CROSS>;
+    hipError_t e = hipFuncSetAttribute((const void *)k,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k, dim3(npairs), dim3(NT), smem, s, B, ldb, pairs, psmap, U, eps, thr,
+                       inner, partial, rot_flag);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                              const int2 *psmap, T *U, double eps, double thr, int inner,
-                             double *partial, int *rot_flag, hipStream_t s)
+                             int cross, double *partial, int *rot_flag, hipStream_t s)
 {
     const int M = 2 * b;
     const int vn = 16 / (int)sizeof(T);
     size_t smem = align8(sizeof(T) * ((size_t)M * (M + vn) + (size_t)M * (M + 1))) + 16 +
                   2 * (((size_t)b * (8 + 5 * sizeof(T)) + 15) & ~(size_t)15) +
                   16 * sizeof(double) + 16 * sizeof(int);
-    hipError_t e;
-    if (M == 64) {
-        auto k = pair_solve_kernel<T, 64, 1024>;
-        e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)smem);
-        if (e != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(k, dim3(npairs), dim3(1024), smem, s, B, ldb, pairs, psmap, U, eps,
-                           thr, inner, partial, rot_flag);
-    } else if (M == 32) {
-        auto k = pair_solve_kernel<T, 32, 256>;
-        e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)smem);
-        if (e != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(k, dim3(npairs), dim3(256), smem, s, B, ldb, pairs, psmap, U, eps,
-                           thr, inner, partial, rot_flag);
-    } else {
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (M == 64)
+        return cross ? launch_pair_solve_t<T, 64, 1024, true>(B, ldb, npairs, pairs, psmap, U,
+                                                              eps, thr, inner, partial,
+                                                              rot_flag, smem, s)
+                     : launch_pair_solve_t<T, 64, 1024, false>(B, ldb, npairs, pairs, psmap,
+                                                               U, eps, thr, inner, partial,
+                                                               rot_flag, smem, s);
+    if (M == 32)
+        return cross ? launch_pair_solve_t<T, 32, 256, true>(B, ldb, npairs, pairs, psmap, U,
+                                                             eps, thr, inner, partial, rot_flag,
+                                                             smem, s)
+                     : launch_pair_solve_t<T, 32, 256, false>(B, ldb, npairs, pairs, psmap, U,
+                                                              eps, thr, inner, partial,
+                                                              rot_flag, smem, s);
+    return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------------ apply
@@ -1060,17 +1103,29 @@ hipError_t launch_rademacher(double *X, int64_t rows, int64_t n, int k, uint64_t
 
 // explicit instantiations
 template hipError_t launch_pair_solve<double>(double *, int64_t, int, int, const int2 *,
-                                              const int2 *, double *, double, double, int,
+                                              const int2 *, double *, double, double, int, int,
                                               double *, int *, hipStream_t);
 template hipError_t launch_pair_solve<float>(float *, int64_t, int, int, const int2 *,
-                                             const int2 *, float *, double, double, int,
+                                             const int2 *, float *, double, double, int, int,
                                              double *, int *, hipStream_t);
 
 // Thread -> 2x2 block map of the pair solve for M = 2b positions: entry t < M/2
 // is the block hosting pair t of the next round, the rest follow in row order.
-void pair_solve_map(int M, int2 *out)
+// cross != 0 gives the map of the cross schedule.
+void pair_solve_map(int M, int cross, int2 *out)
 {
     const int h = M / 2;
+    if (cross) {
+        int cnt = 0;
+        for (int t = 0; t + 1 < h; ++t)
+            out[cnt++] = make_int2(t, t + 1);
+        out[cnt++] = make_int2(0, h - 1);
+        for (int k = 0; k < h; ++k)
+            for (int l = k; l < h; ++l)
+                if (!(l == k + 1 || (k == 0 && l == h - 1)))
+                    out[cnt++] = make_int2(k, l);
+        return;
+    }
     int inv[128];
     for (int p = 0; p < M; ++p)
         inv[ps_sigma(p, M)] = p;

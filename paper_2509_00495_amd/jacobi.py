@@ -40,7 +40,8 @@ class Opts(ctypes.Structure):
         ("small_max_n", ctypes.c_int32),
         ("threads", ctypes.c_int32),
         ("timing", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("schedule", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 

@@ -91,6 +91,16 @@ def test_block_path_vs_oracle(pj, n, block):
     check(A, W, V, Wo, Vo, f"block b={block}")
 
 
+@pytest.mark.parametrize("n,block", [(130, 16), (300, 32)])
+def test_block_path_circle_schedule(pj, n, block):
+    """schedule=1: every pair of each 2b x 2b tile in every round."""
+    A = wl.random_symmetric(n, 2500 + n)
+    W, V, info = run(pj, "eigh", A, small_max_n=-1, block=block, schedule=1)
+    assert info["path"] == 1 and info["status"] == 0
+    Wo, Vo, *_ = oracle.eigh(A)
+    check(A, W, V, Wo, Vo, f"circle b={block}")
+
+
 @pytest.mark.parametrize("n,block,inner", [(128, 16, 2), (192, 32, 3)])
 def test_block_path_inner_sweeps(pj, n, block, inner):
     A = wl.random_symmetric(n, 3000 + n)
