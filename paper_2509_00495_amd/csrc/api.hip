@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -28,6 +29,13 @@ thread_local hipError_t g_last_error = hipSuccess;
 
 constexpr double U_D = 0x1p-53; // unit roundoff, double
 constexpr double U_L = 0x1p-24; // unit roundoff, single
+
+// JACOBI_TRACE set in the environment: one line per block-path sweep on stderr
+bool trace_on()
+{
+    static const bool on = std::getenv("JACOBI_TRACE") != nullptr;
+    return on;
+}
 
 struct Opts {
     int max_sweeps, block, inner, ns_iters, check_sym, small_max_n, threads, timing, schedule;
@@ -161,7 +169,7 @@ struct BlockWs {
 
 size_t partial_count(const Geometry &g)
 {
-    size_t c = (size_t)g.npairs + g.nbt;
+    size_t c = (size_t)g.npairs + (size_t)g.nbt * (g.M / 16); // pair solve + update of B
     c = std::max(c, (size_t)INGEST_BLOCKS);
     c = std::max(c, (size_t)OFF_BLOCKS);
     return c;
@@ -271,10 +279,7 @@ void fill_tables(const Geometry &g, std::vector<int2> &pairs, std::vector<int2> 
             rr_pair(k, r, g.N, p, q);
             pairs[(size_t)r * g.npairs + k] = make_int2(p, q);
         }
-    tiles.clear();
-    for (int k = 0; k < g.npairs; ++k)
-        for (int l = k + 1; l < g.npairs; ++l)
-            tiles.push_back(make_int2(k, l));
+    update_b_tiles(g.npairs, tiles); // off-diagonal tiles k < l, by l then k
     if (tiles.empty())
         tiles.push_back(make_int2(0, 0));
 }
@@ -420,20 +425,27 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
             CK(hipEventRecord(ss.evU[j], s));
             if (timed)
                 CK(hipEventRecord(tm->ev[5 * r + 1], s));
-            CK(launch_apply<T>(B, g.npad, V, g.npad, g.npad, g.b, g.npairs, pr, w.btiles, g.nbt,
-                               Ub, w.partial + g.npairs, r == g.N - 2, 1, s));
+            if (sizeof(T) == 4)
+                CK(launch_update_b<T>(B, g.npad, g.b, pr, Ub, w.btiles, g.nbt,
+                                      w.partial + g.npairs, r == g.N - 2, s));
+            else
+                CK(launch_apply<T>(B, g.npad, V, g.npad, g.npad, g.b, g.npairs, pr, w.btiles,
+                                   g.nbt, Ub, w.partial + g.npairs, r == g.N - 2, 1, s));
             if (timed)
                 CK(hipEventRecord(tm->ev[5 * r + 2], s));
             CK(hipStreamWaitEvent(ss.s2, ss.evU[j], 0));
             if (timed)
                 CK(hipEventRecord(tm->ev[5 * r + 3], ss.s2));
-            CK(launch_apply<T>(B, g.npad, V, g.npad, g.npad, g.b, g.npairs, pr, w.btiles, g.nbt,
-                               Ub, nullptr, 0, 2, ss.s2));
+            CK(launch_update_v<T>(V, g.npad, g.npad, g.b, g.npairs, pr, Ub, ss.s2));
             if (timed)
                 CK(hipEventRecord(tm->ev[5 * r + 4], ss.s2));
             CK(hipEventRecord(ss.evV[j], ss.s2));
         }
-        CK(launch_sum(w.partial, (int64_t)g.npairs + g.nbt, w.scal + 1, s));
+        // partials: one per pair, then per B tile (one per wavefront of the FP32
+        // update, one per tile of the FP64 one)
+        CK(launch_sum(w.partial,
+                      (int64_t)g.npairs + (int64_t)g.nbt * (sizeof(T) == 4 ? g.M / 16 : 1),
+                      w.scal + 1, s));
         if (int e = read_scalars(w, s, rb))
             return e;
         if (timed) {
@@ -444,6 +456,9 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
         ++sweeps;
         const double prev = off;
         off = std::sqrt(rb.scal[1]);
+        if (trace_on())
+            std::fprintf(stderr, "jacobi: %s sweep %d off %.3e rotated %d\n",
+                         fp32_stage ? "fp32" : "fp64", sweeps, off, rb.flags[2]);
         if (!std::isfinite(off)) {
             status = JACOBI_NONFINITE;
             break;

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/jacobi.h"
 
 namespace lj {
@@ -34,6 +36,23 @@ hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *p
 // thread -> block map of the pair solve (b(b+1)/2 entries for M = 2b)
 void pair_solve_map(int M, int cross, int2 *out);
 // which = 1: B tiles only, 2: V tiles only, 3: both
+// B_kl <- U_k^T B_kl U_l (and mirror) for the tiles of update_b_tiles (pairs
+// k < l ordered by l, then k); partial[t (2b / 16) + w] gets twice the squared
+// sum of wavefront w's part of tile t when want_off (kernels_update.hip)
+template <typename T>
+hipError_t launch_update_b(T *B, int64_t ldb, int b, const int2 *pairs, const T *U,
+                           const int2 *tiles, int ntiles, double *partial, int want_off,
+                           hipStream_t s);
+template <typename T>
+int update_b_blocks_per_cu(int b);
+void update_b_tiles(int npairs, std::vector<int2> &out);
+// grid sizing of the V update: total resident wavefronts (0 = from occupancy)
+void tune_update_v(int total_waves);
+
+// V[:, cols(pair)] <- V[:, cols(pair)] U_pair for all pairs (kernels_update.hip)
+template <typename T>
+hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
+                           const int2 *pairs, const T *U, hipStream_t s);
 template <typename T>
 hipError_t launch_apply(T *B, int64_t ldb, T *V, int64_t ldv, int64_t nrows, int b,
                         int npairs, const int2 *pairs, const int2 *btiles, int nbt,

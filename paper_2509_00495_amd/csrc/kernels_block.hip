@@ -736,6 +736,8 @@ hipError_t launch_apply(T *B, int64_t ldb, T *V, int64_t ldv, int64_t nrows, int
                         const int2 *pairs, const int2 *btiles, int nbt, const T *U,
                         double *partial, int want_off, int which, hipStream_t s)
 {
+    if (which == 2)
+        return launch_update_v<T>(V, ldv, nrows, b, npairs, pairs, U, s);
     const int M = 2 * b;
     const int64_t ntiles = which == 1 ? nbt : (nrows / M) * npairs;
     if (ntiles == 0)

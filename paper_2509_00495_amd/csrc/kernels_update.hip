@@ -1,0 +1,481 @@
+// Update kernels of the block path (the round's block rotation, Section 3.3
+// applied blockwise): the eigenvectors V[:, cols(P, Q)] <- V[:, cols(P, Q)] U_PQ
+// for every block pair (P, Q) of the round, and the off-diagonal tiles
+// B_kl <- U_k^T B_kl U_l of every two pairs k < l (with its mirror).
+//
+// V update:
+// Each wavefront owns one pair l and a contiguous run of 16-row tiles of V.
+// It computes Z^T = U_l^T X^T on the 16x16x4 MFMA with no LDS and no barrier:
+//   * the B operand is X^T, so lane (li, lk) needs X[row li][k] for the k of
+//     its MFMA step.  The k order inside a step is free, so step (g, j) gives
+//     lane lk the k = g*4*VK + lk*VK + j: one 16-byte load of VK consecutive
+//     columns of row li feeds VK steps;
+//   * the A operand, U_l^T, is loaded once per wavefront into registers;
+//   * the accumulator of a 16-column tile holds, per lane, the four entries
+//     D[r][li] with r = acc_row(lk, v).  Column 16 tc + m of the MFMA output
+//     is mapped to output column 16 tc + out_perm(m), chosen so that the four
+//     values of a lane are four consecutive columns of row li: one 16-byte
+//     store (f32) or two (f64).
+// The next tile's X is in flight while the current one computes (two register
+// buffers).  Tiles of different wavefronts are disjoint, so the update is in
+// place.
+#include "internal.hpp"
+#include "common.hpp"
+
+#include <vector>
+
+namespace lj {
+
+namespace {
+
+// 16-byte vectors as plain clang vector types (they stay in registers)
+typedef float fv4 __attribute__((ext_vector_type(4)));
+typedef double dv2 __attribute__((ext_vector_type(2)));
+template <typename T>
+struct V16;
+template <>
+struct V16<float> {
+    typedef fv4 type;
+};
+template <>
+struct V16<double> {
+    typedef dv2 type;
+};
+
+// MFMA output row m of a 16-column tile -> column offset inside the tile
+template <typename T>
+__device__ inline int out_perm(int m);
+template <>
+__device__ inline int out_perm<float>(int m)
+{
+    return m; // acc row 4 lk + v is already column-contiguous per lane
+}
+template <>
+__device__ inline int out_perm<double>(int m)
+{
+    return 4 * (m & 3) + (m >> 2); // acc row lk + 4 v -> column 4 lk + v
+}
+
+// column c (0 <= c < 2b) of the pair's slice -> global column
+__device__ inline int pair_col(int2 pq, int c, int b)
+{
+    return c < b ? pq.x * b + c : pq.y * b + (c - b);
+}
+
+template <typename T>
+__device__ inline T vlane(const typename V16<T>::type &x, int j)
+{
+    return x[j];
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(256) void update_v_kernel(T *__restrict__ V, int64_t ldv,
+                                                       int64_t ntile, const int2 *__restrict__ pairs,
+                                                       int npairs, const T *__restrict__ U,
+                                                       int chunks)
+{
+    constexpr int b = M / 2;
+    constexpr int VK = 16 / (int)sizeof(T); // elements per 16-byte vector
+    constexpr int TC = M / 16;              // 16-column output tiles
+    constexpr int KG = M / (4 * VK);        // vectors per lane per tile row
+    typedef typename V16<T>::type TV;
+    typedef typename acc4<T>::type accT;
+    const int lane = threadIdx.x % WAVE, li = lane % 16, lk = lane / 16;
+    const int gw = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int l = gw % npairs, ch = gw / npairs;
+    if (ch >= chunks)
+        return;
+    const int64_t t0 = (int64_t)ch * ntile / chunks, t1 = (int64_t)(ch + 1) * ntile / chunks;
+    if (t0 >= t1)
+        return;
+    const int2 pl = pairs[l];
+    const T *Ul = U + (int64_t)l * M * M;
+    T uf[TC][KG][VK];
+#pragma unroll
+    for (int tc = 0; tc < TC; ++tc)
+#pragma unroll
+        for (int g = 0; g < KG; ++g)
+#pragma unroll
+            for (int j = 0; j < VK; ++j)
+                uf[tc][g][j] = Ul[(g * 4 * VK + lk * VK + j) * M + 16 * tc + out_perm<T>(li)];
+    int kc[KG], oc[TC];
+#pragma unroll
+    for (int g = 0; g < KG; ++g)
+        kc[g] = pair_col(pl, g * 4 * VK + lk * VK, b);
+#pragma unroll
+    for (int tc = 0; tc < TC; ++tc)
+        oc[tc] = pair_col(pl, 16 * tc + 4 * lk, b);
+
+    auto load = [&](TV(&x)[KG], int64_t t) __attribute__((always_inline)) {
+        const T *row = V + (t * 16 + li) * ldv;
+#pragma unroll
+        for (int g = 0; g < KG; ++g)
+            x[g] = *reinterpret_cast<const TV *>(row + kc[g]);
+    };
+    auto work = [&](const TV(&x)[KG], int64_t t) __attribute__((always_inline)) {
+        accT acc[TC];
+#pragma unroll
+        for (int tc = 0; tc < TC; ++tc)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                acc[tc][v] = (T)0;
+#pragma unroll
+        for (int g = 0; g < KG; ++g)
+#pragma unroll
+            for (int j = 0; j < VK; ++j) {
+                const T bv = vlane<T>(x[g], j);
+#pragma unroll
+                for (int tc = 0; tc < TC; ++tc)
+                    acc[tc] = mfma16(uf[tc][g][j], bv, acc[tc]);
+            }
+        T *row = V + (t * 16 + li) * ldv;
+#pragma unroll
+        for (int tc = 0; tc < TC; ++tc) {
+            if constexpr (sizeof(T) == 4) {
+                const fv4 z = {acc[tc][0], acc[tc][1], acc[tc][2], acc[tc][3]};
+                *reinterpret_cast<fv4 *>(row + oc[tc]) = z;
+            } else {
+                const dv2 z0 = {acc[tc][0], acc[tc][1]}, z1 = {acc[tc][2], acc[tc][3]};
+                *reinterpret_cast<dv2 *>(row + oc[tc]) = z0;
+                *reinterpret_cast<dv2 *>(row + oc[tc] + 2) = z1;
+            }
+        }
+    };
+
+    // Every path into the loop issues the same sequence of memory operations
+    // (prefetch indices are clamped to the last tile instead of skipped, the
+    // first step is peeled), so the wait for a buffer's loads never has to
+    // wait for the stores issued after them.
+    TV xa[KG], xb[KG];
+    auto step = [&](TV(&x)[KG], int64_t t) __attribute__((always_inline)) {
+        work(x, t);
+        load(x, t + 2 < t1 ? t + 2 : t1 - 1);
+        // keep the two buffers' steps apart, or the scheduler merges them and
+        // the second buffer's loads are waited for right after being issued
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    load(xa, t0);
+    load(xb, t0 + 1 < t1 ? t0 + 1 : t1 - 1);
+    step(xa, t0);
+    int64_t t = t0 + 1;
+    for (; t + 1 < t1; t += 2) {
+        step(xb, t);
+        step(xa, t + 1);
+    }
+    if (t < t1)
+        work(xb, t);
+}
+
+// B update.  The tiles (k, l), k < l, are listed by column pair l, then k;
+// workgroup g of G takes the run [g T / G, (g + 1) T / G) of the T tiles (the
+// same share for every workgroup).  Its M/16 wavefronts produce rows
+// 16w .. 16w + 15 of Z = U_k^T X U_l as two chained MFMA products:
+//   C1 = X^T U_k (M-index c, N-index i, K-index r): the A operand X^T is read
+//        from the mirror tile B[rows(l), cols(k)] (= X^T, B is kept exactly
+//        symmetric), staged through LDS with 16-byte rows; the B operand U_k
+//        is per-lane registers;
+//   Z^T = U_l^T C1 (M-index j, K-index c): the accumulator of C1 already has
+//        the B-operand layout (element v of a lane is C1[16 tc + acc_row][li]),
+//        so C1 never leaves registers; the A operand U_l^T sits in LDS in
+//        per-lane fragment order (16-byte reads at consecutive addresses),
+//        refilled when the run reaches a new l.
+// Z is stored along its rows with 16-byte stores (out_perm again), its
+// transpose into the mirror tile with one element per lane (16 consecutive
+// lanes write consecutive columns).  The next tile's X^T and U_k are loaded
+// while the current one computes.
+template <typename T, int M>
+__global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int64_t ldb,
+                                                         const int2 *__restrict__ pairs,
+                                                         const T *__restrict__ U,
+                                                         const int2 *__restrict__ tiles,
+                                                         int ntiles, double *__restrict__ partial,
+                                                         int want_off)
+{
+    constexpr int b = M / 2, NW = M / 16, NT = NW * WAVE;
+    constexpr int VK = 16 / (int)sizeof(T);
+    constexpr int TC = M / 16, TJ = M / 16, KG = M / (4 * VK);
+    constexpr int LDX = M + VK;       // padded LDS row of the X^T tile
+    constexpr int RV = M / VK;        // 16-byte vectors per tile row
+    constexpr int PERV = M * RV / NT; // vectors per thread per tile
+    constexpr int HV = 4 / VK;        // 16-byte reads per lane per U_l fragment
+    typedef typename V16<T>::type TV;
+    typedef typename acc4<T>::type accT;
+    __shared__ __align__(16) T xs[M * LDX];
+    __shared__ __align__(16) T ufl[M * M];
+    const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+    const int li = lane % 16, lk = lane / 16;
+    const int t0 = (int)((int64_t)blockIdx.x * ntiles / gridDim.x);
+    const int t1 = (int)((int64_t)(blockIdx.x + 1) * ntiles / gridDim.x);
+    if (t0 >= t1)
+        return;
+    // ufl[((f HV + h) 64 + lane) VK + j] = U_l[16 tc + acc_row(lk, v)][16 tj + out_perm(li)]
+    // with f = tj TC + tc and v = h VK + j: fragment v of lane for step (tc, v)
+    auto fill_ufl = [&](int l) __attribute__((always_inline)) {
+        const T *Ul = U + (int64_t)l * M * M;
+        for (int e = tid; e < M * M; e += NT) {
+            const int j = e % VK, ln = (e / VK) % WAVE, r = e / (VK * WAVE);
+            const int v = (r % HV) * VK + j, f = r / HV, tc = f % TC, tj = f / TC;
+            ufl[e] = Ul[(16 * tc + acc_row<T>(ln / 16, v)) * M + 16 * tj + out_perm<T>(ln % 16)];
+        }
+    };
+    TV xr[PERV];
+    T uk[KG * VK], ukn[KG * VK];
+    auto load_tile = [&](int t) __attribute__((always_inline)) {
+        const int2 kl = tiles[t];
+        const int2 pk = pairs[kl.x], pl = pairs[kl.y];
+#pragma unroll
+        for (int e = 0; e < PERV; ++e) {
+            const int idx = tid + e * NT, c = idx / RV, q = idx % RV;
+            xr[e] = *reinterpret_cast<const TV *>(B + (int64_t)pair_col(pl, c, b) * ldb +
+                                                  pair_col(pk, q * VK, b));
+        }
+        const T *Uk = U + (int64_t)kl.x * M * M;
+#pragma unroll
+        for (int g = 0; g < KG; ++g)
+#pragma unroll
+            for (int j = 0; j < VK; ++j)
+                ukn[g * VK + j] = Uk[(g * 4 * VK + lk * VK + j) * M + 16 * w + li];
+    };
+    int cur_l = -1;
+    auto body = [&](int t) __attribute__((always_inline)) {
+        __syncthreads(); // xs and ufl free again
+        const int2 kl = tiles[t];
+        if (kl.y != cur_l) {
+            fill_ufl(kl.y);
+            cur_l = kl.y;
+        }
+#pragma unroll
+        for (int e = 0; e < PERV; ++e) {
+            const int idx = tid + e * NT, c = idx / RV, q = idx % RV;
+            *reinterpret_cast<TV *>(xs + c * LDX + q * VK) = xr[e];
+        }
+#pragma unroll
+        for (int e = 0; e < KG * VK; ++e)
+            uk[e] = ukn[e];
+        __syncthreads();
+        // unconditional (clamped) prefetch: the same memory-operation sequence
+        // on every path into the next step, so its wait skips the stores below
+        load_tile(t + 1 < t1 ? t + 1 : t1 - 1);
+        const int2 pk = pairs[kl.x], pl = pairs[kl.y];
+        accT c1[TC];
+#pragma unroll
+        for (int tc = 0; tc < TC; ++tc)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                c1[tc][v] = (T)0;
+        // LDS operands are read one group ahead of the MFMAs that use them
+        auto xs_read = [&](TV(&a)[TC], int g) __attribute__((always_inline)) {
+#pragma unroll
+            for (int tc = 0; tc < TC; ++tc)
+                a[tc] = *reinterpret_cast<const TV *>(xs + (16 * tc + li) * LDX + g * 4 * VK +
+                                                      lk * VK);
+        };
+        TV xa[TC], xb[TC];
+        xs_read(xa, 0);
+#pragma unroll
+        for (int g = 0; g < KG; g += 2) {
+            if (g + 1 < KG)
+                xs_read(xb, g + 1);
+#pragma unroll
+            for (int tc = 0; tc < TC; ++tc)
+#pragma unroll
+                for (int j = 0; j < VK; ++j)
+                    c1[tc] = mfma16(vlane<T>(xa[tc], j), uk[g * VK + j], c1[tc]);
+            if (g + 1 < KG) {
+                if (g + 2 < KG)
+                    xs_read(xa, g + 2);
+#pragma unroll
+                for (int tc = 0; tc < TC; ++tc)
+#pragma unroll
+                    for (int j = 0; j < VK; ++j)
+                        c1[tc] = mfma16(vlane<T>(xb[tc], j), uk[(g + 1) * VK + j], c1[tc]);
+            }
+        }
+        // second product: the four accumulators interleave, U_l fragments of the
+        // next tc are read while the current tc multiplies
+        accT zt[TJ];
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                zt[tj][v] = (T)0;
+        auto uf_read = [&](TV(&u)[TJ][HV], int tc) __attribute__((always_inline)) {
+#pragma unroll
+            for (int tj = 0; tj < TJ; ++tj)
+#pragma unroll
+                for (int h = 0; h < HV; ++h)
+                    u[tj][h] = *reinterpret_cast<const TV *>(
+                        ufl + (((tj * TC + tc) * HV + h) * WAVE + lane) * VK);
+        };
+        TV ua[TJ][HV], ub[TJ][HV];
+        uf_read(ua, 0);
+#pragma unroll
+        for (int tc = 0; tc < TC; tc += 2) {
+            if (tc + 1 < TC)
+                uf_read(ub, tc + 1);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int tj = 0; tj < TJ; ++tj)
+                    zt[tj] = mfma16(vlane<T>(ua[tj][v / VK], v % VK), c1[tc][v], zt[tj]);
+            if (tc + 1 < TC) {
+                if (tc + 2 < TC)
+                    uf_read(ua, tc + 2);
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int tj = 0; tj < TJ; ++tj)
+                        zt[tj] = mfma16(vlane<T>(ub[tj][v / VK], v % VK), c1[tc + 1][v], zt[tj]);
+            }
+        }
+        const int i = 16 * w + li;
+        const int gi = pair_col(pk, i, b);
+        T *zrow = B + (int64_t)gi * ldb;
+        double sq = 0.0;
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj) {
+            const int gj0 = pair_col(pl, 16 * tj + 4 * lk, b);
+            if constexpr (sizeof(T) == 4) {
+                const fv4 z = {zt[tj][0], zt[tj][1], zt[tj][2], zt[tj][3]};
+                *reinterpret_cast<fv4 *>(zrow + gj0) = z;
+            } else {
+                const dv2 z0 = {zt[tj][0], zt[tj][1]}, z1 = {zt[tj][2], zt[tj][3]};
+                *reinterpret_cast<dv2 *>(zrow + gj0) = z0;
+                *reinterpret_cast<dv2 *>(zrow + gj0 + 2) = z1;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                B[(int64_t)(gj0 + v) * ldb + gi] = zt[tj][v];
+                sq += (double)zt[tj][v] * (double)zt[tj][v];
+            }
+        }
+        if (want_off) {
+            sq = wave_sum(sq);
+            if (lane == 0)
+                partial[(int64_t)t * NW + w] = 2.0 * sq;
+        }
+    };
+    load_tile(t0);
+    body(t0);
+    for (int t = t0 + 1; t < t1; ++t)
+        body(t);
+}
+
+int g_update_v_waves = 0; // total resident wavefronts to size the V-update grid; 0 = occupancy
+
+template <typename T, int M>
+hipError_t launch_update_v_t(T *V, int64_t ldv, int64_t nrows, int npairs, const int2 *pairs,
+                             const T *U, hipStream_t s)
+{
+    static int occ_waves = 0;
+    if (occ_waves == 0) {
+        int dev = 0, cus = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        // one wavefront per SIMD: long runs of tiles per wavefront amortise the
+        // U_l load and keep two tiles in flight (measured faster than filling
+        // the occupancy at n = 4096)
+        occ_waves = (cus > 0 ? cus : 256) * 4;
+    }
+    const int64_t ntile = nrows / 16;
+    const int waves_total = g_update_v_waves > 0 ? g_update_v_waves : occ_waves;
+    int64_t chunks = waves_total / npairs;
+    if (chunks < 1)
+        chunks = 1;
+    if (chunks > ntile)
+        chunks = ntile;
+    const int64_t waves = chunks * npairs;
+    const unsigned grid = (unsigned)((waves + 3) / 4);
+    hipLaunchKernelGGL((update_v_kernel<T, M>), dim3(grid), dim3(256), 0, s, V, ldv, ntile, pairs,
+                       npairs, U, (int)chunks);
+    return hipGetLastError();
+}
+
+template <typename T, int M>
+int update_b_blocks_per_cu_t()
+{
+    static int per = -1;
+    if (per < 0) {
+        int p = 0;
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, update_b_kernel<T, M>, M * 4, 0);
+        per = p > 0 ? p : 1;
+    }
+    return per;
+}
+
+} // namespace
+
+template <typename T>
+int update_b_blocks_per_cu(int b)
+{
+    return b == 32 ? update_b_blocks_per_cu_t<T, 64>() : update_b_blocks_per_cu_t<T, 32>();
+}
+
+void tune_update_v(int total_waves) { g_update_v_waves = total_waves; }
+
+void update_b_tiles(int npairs, std::vector<int2> &out)
+{
+    out.clear();
+    for (int l = 1; l < npairs; ++l)
+        for (int k = 0; k < l; ++k)
+            out.push_back(make_int2(k, l));
+}
+
+template <typename T>
+hipError_t launch_update_b(T *B, int64_t ldb, int b, const int2 *pairs, const T *U,
+                           const int2 *tiles, int ntiles, double *partial, int want_off,
+                           hipStream_t s)
+{
+    if (ldb % (16 / (int64_t)sizeof(T)) != 0 || ((uintptr_t)B % 16) != 0)
+        return hipErrorInvalidValue;
+    if (ntiles == 0)
+        return hipSuccess;
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (cus <= 0)
+            cus = 256;
+    }
+    const int slots = cus * update_b_blocks_per_cu<T>(b);
+    const unsigned grid = (unsigned)(ntiles < slots ? ntiles : slots);
+    if (b == 32)
+        hipLaunchKernelGGL((update_b_kernel<T, 64>), dim3(grid), dim3(256), 0, s, B, ldb, pairs,
+                           U, tiles, ntiles, partial, want_off);
+    else if (b == 16)
+        hipLaunchKernelGGL((update_b_kernel<T, 32>), dim3(grid), dim3(128), 0, s, B, ldb, pairs,
+                           U, tiles, ntiles, partial, want_off);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
+                           const int2 *pairs, const T *U, hipStream_t s)
+{
+    if (nrows % 16 != 0 || ldv % (16 / (int64_t)sizeof(T)) != 0 ||
+        ((uintptr_t)V % 16) != 0)
+        return hipErrorInvalidValue;
+    if (nrows == 0 || npairs == 0)
+        return hipSuccess;
+    if (b == 32)
+        return launch_update_v_t<T, 64>(V, ldv, nrows, npairs, pairs, U, s);
+    if (b == 16)
+        return launch_update_v_t<T, 32>(V, ldv, nrows, npairs, pairs, U, s);
+    return hipErrorInvalidValue;
+}
+
+template int update_b_blocks_per_cu<double>(int);
+template int update_b_blocks_per_cu<float>(int);
+template hipError_t launch_update_b<double>(double *, int64_t, int, const int2 *, const double *,
+                                            const int2 *, int, double *, int, hipStream_t);
+template hipError_t launch_update_b<float>(float *, int64_t, int, const int2 *, const float *,
+                                           const int2 *, int, double *, int, hipStream_t);
+template hipError_t launch_update_v<double>(double *, int64_t, int64_t, int, int, const int2 *,
+                                            const double *, hipStream_t);
+template hipError_t launch_update_v<float>(float *, int64_t, int64_t, int, int, const int2 *,
+                                           const float *, hipStream_t);
+
+} // namespace lj

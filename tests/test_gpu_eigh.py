@@ -181,3 +181,44 @@ def test_strided_input(pj):
         W, V = pj.eigh(At, opts=kw)
         Wo, Vo, *_ = oracle.eigh(A)
         check(A, W.cpu().numpy(), V.cpu().numpy(), Wo, Vo, "strided")
+
+
+@pytest.mark.parametrize("fn", ["eigh", "eigh_mixed"])
+def test_goe4096_properties(pj, fn):
+    """The n = 4096 workload, in the launch configuration the benchmark times.
+    The oracle cannot solve it in test time, so the checks are size-independent.
+    Eigenvalues: with r_k = A v_k - rho_k v_k and rho_k = v_k^T A v_k, the
+    Kato-Temple bound puts an eigenvalue within |r_k|^2 / delta_k of rho_k,
+    delta_k being the distance from rho_k to the rest of the spectrum (taken
+    from the computed neighbours less the residual norms); w_k must lie within
+    1e-13 ||A||_2 of that certified interval wherever delta_k > 1e-6 ||A||_2.
+    Plus the residual and orthogonality bars and the trace and Frobenius
+    invariants."""
+    A = wl.goe(4096, 3)
+    n = A.shape[0]
+    W, V, info = run(pj, fn, A)
+    assert info["status"] == 0 and info["path"] == 1
+    nrm2 = np.abs(W).max()
+    AV = A @ V
+    rho = np.einsum("ij,ij->j", V, AV) / np.einsum("ij,ij->j", V, V)
+    rk = np.linalg.norm(AV - V * rho, axis=0)
+    R = AV - V * W
+    res = np.linalg.norm(R) / np.linalg.norm(A)
+    orth = np.linalg.norm(V.T @ V - np.eye(n))
+    gap = np.minimum(np.r_[np.inf, np.diff(W)], np.r_[np.diff(W), np.inf])
+    delta = gap - 2 * rk.max()
+    sep = delta > 1e-6 * nrm2
+    kt = np.where(sep, rk ** 2 / np.where(sep, delta, 1.0), np.inf)
+    err = np.abs(W - rho) + kt
+    print(f"  {fn} n={n}: res={res:.2e} orth={orth:.2e} max|r_k|/|A|_2={rk.max() / nrm2:.2e} "
+          f"separated={sep.sum()} max certified |dW|/|A|_2={err[sep].max() / nrm2:.2e}",
+          flush=True)
+    assert sep.sum() >= 0.99 * n
+    assert err[sep].max() <= 1e-13 * nrm2
+    assert res <= 1e-13 * n
+    assert orth <= 1e-14 * n
+    assert abs(W.sum() - np.trace(A)) <= 1e-13 * n * nrm2
+    assert abs(np.sqrt((W * W).sum()) - np.linalg.norm(A)) <= 1e-13 * np.linalg.norm(A)
+    assert (np.diff(W) >= 0).all()
+    idx = np.argmax(np.abs(V), axis=0)
+    assert (V[idx, np.arange(n)] > 0).all()
