@@ -136,10 +136,13 @@ def main():
     ap.add_argument("--workload", default="goe4096", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 256 MiB device-to-device copy three times (the "
+                         "reference kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no "
-              "multi-GPU path in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver is a "
+              "single-GPU library", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -148,16 +151,25 @@ def main():
         raise SystemExit("libjacobi.so is not built: run python -c 'import __graft_entry__ as g; g.build()'")
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
+    if args.copy_probe:
+        x = torch.ones(1 << 25, dtype=torch.float64, device="cuda")  # 256 MiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel() * 8, "launches": 3}), flush=True)
+        return
 
     wl_name = args.workload
     A, lam = make_input(wl_name)
     n = A.shape[0]
     At = torch.tensor(A, device="cuda")
-    opts = pj.make_opts(timing=1)
+    opts = pj.make_opts()
+    topts = pj.make_opts(timing=1)  # per-kernel HIP events: separate, untimed pass
     ws = pj.Workspace()
 
-    def run_mixed():
-        return pj.eigh_mixed(At, opts=opts, ws=ws, return_info=True)
+    def run_mixed(o=opts):
+        return pj.eigh_mixed(At, opts=o, ws=ws, return_info=True)
 
     def run_plain():
         return pj.eigh(At, opts=opts, ws=ws, return_info=True)
@@ -215,7 +227,10 @@ def main():
         gate = gate and acc["eig_err_vs_oracle"] <= 1e-13
     acc["gate_passed"] = bool(gate)
 
-    # roofline of the dominant update kernel, from the in-library HIP events
+    # roofline of the dominant update kernel, from the in-library HIP events of
+    # one instrumented (untimed) solve: events around every launch on its stream
+    infos = [run_mixed(topts)[2]]
+    torch.cuda.synchronize()
     last = infos[-1]
     b = last["block"]
 
@@ -228,27 +243,38 @@ def main():
         "apply_B_f64": (tot("t_apply_ms", 0), tot("n_apply", 0), "B", "f64"),
         "apply_V_f64": (tot("t_applyv_ms", 0), tot("n_applyv", 0), "V", "f64"),
     }
-    kern_ms = {k: round(v[0] / args.steps, 2) for k, v in cands.items()}
-    kern_ms["pair_solve_f32"] = round(tot("t_pair_ms", 1) / args.steps, 2)
-    kern_ms["pair_solve_f64"] = round(tot("t_pair_ms", 0) / args.steps, 2)
+    kern_ms = {k: round(v[0], 2) for k, v in cands.items()}
+    kern_ms["pair_solve_f32"] = round(tot("t_pair_ms", 1), 2)
+    kern_ms["pair_solve_f64"] = round(tot("t_pair_ms", 0), 2)
     dom = max(cands, key=lambda k: cands[k][0])
     t_ms, cnt, part, dtype = cands[dom]
     avg_s = t_ms / max(cnt, 1) / 1e3
+    elem = 4 if dtype == "f32" else 8
     flops = apply_flops(n, b, part)
-    achieved = flops / avg_s / 1e12
+    nbytes = apply_bytes(n, b, elem, part)
+    # the bound is whichever floor is higher for this launch's algorithmic work
+    mfma_bound = flops / (PEAK[dtype] * 1e12) >= nbytes / (HBM_PEAK * 1e9)
+    names = {("B", "f32"): "lj::update_b_kernel<float, 64>",
+             ("V", "f32"): "lj::update_v_kernel<float, 64>",
+             ("B", "f64"): "lj::apply2_kernel<double, 64>",
+             ("V", "f64"): "lj::update_v_kernel<double, 64>"}
+    achieved = flops / avg_s / 1e12 if mfma_bound else nbytes / avg_s / 1e9
+    peak = PEAK[dtype] if mfma_bound else HBM_PEAK
     roofline = {
-        "kernel": f"lj::apply_kernel<{'float' if dtype == 'f32' else 'double'}, {2 * b}> "
-                  f"({'off-diagonal B tiles' if part == 'B' else 'V row tiles'})",
-        "bound": "mfma",
+        "kernel": names[(part, dtype)] + (" (off-diagonal B tiles)" if part == "B"
+                                           else " (V row tiles)"),
+        "bound": "mfma" if mfma_bound else "hbm",
         "achieved": round(achieved, 2),
-        "peak": PEAK[dtype],
-        "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK[dtype], 4),
+        "peak": peak,
+        "unit": "TFLOP/s" if mfma_bound else "GB/s",
+        "frac": round(achieved / peak, 4),
         "traffic": None,
         "avg_launch_us": round(avg_s * 1e6, 2),
         "launches": cnt,
         "flops_per_launch": flops,
-        "algorithmic_GBps": round(apply_bytes(n, b, 4 if dtype == "f32" else 8, part) / avg_s / 1e9, 1),
+        "bytes_per_launch": nbytes,
+        "achieved_TFLOPs": round(flops / avg_s / 1e12, 2),
+        "achieved_GBps": round(nbytes / avg_s / 1e9, 1),
         "kernel_ms_per_step": kern_ms,
     }
 

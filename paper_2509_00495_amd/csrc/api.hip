@@ -37,6 +37,14 @@ bool trace_on()
     return on;
 }
 
+// JACOBI_OVERLAP_V set: the eigenvector update of a round runs on a second
+// stream beside the next round's pair solve instead of after the B update
+bool overlap_v_on()
+{
+    static const bool on = std::getenv("JACOBI_OVERLAP_V") != nullptr;
+    return on;
+}
+
 struct Opts {
     int max_sweeps, block, inner, ns_iters, check_sym, small_max_n, threads, timing, schedule;
     double c32;
@@ -403,6 +411,7 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
     int status = JACOBI_OK;
     const double thr = n > 0 ? tol / (double)n : 0.0;
     const size_t ustride = (size_t)g.npairs * g.M * g.M;
+    const bool side = overlap_v_on();
     while (off > tol) {
         if (sweeps >= max_sweeps) {
             status = JACOBI_NOCONV;
@@ -414,7 +423,7 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
             const int j = (int)(ss.round & 1);
             T *Ub = U + j * ustride;
             const int2 *pr = w.pairs + (size_t)r * g.npairs;
-            if (ss.round >= 2)
+            if (side && ss.round >= 2)
                 CK(hipStreamWaitEvent(s, ss.evV[j], 0));
             if (timed)
                 CK(hipEventRecord(tm->ev[5 * r], s));
@@ -422,7 +431,8 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
             const int2 *map = w.psmap + (cross ? (size_t)g.b * (g.b + 1) / 2 : 0);
             CK(launch_pair_solve<T>(B, g.npad, g.b, g.npairs, pr, map, Ub, eps, thr, inner,
                                     cross, w.partial, w.flags + 2, s));
-            CK(hipEventRecord(ss.evU[j], s));
+            if (side)
+                CK(hipEventRecord(ss.evU[j], s));
             if (timed)
                 CK(hipEventRecord(tm->ev[5 * r + 1], s));
             if (sizeof(T) == 4)
@@ -433,13 +443,16 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
                                    g.nbt, Ub, w.partial + g.npairs, r == g.N - 2, 1, s));
             if (timed)
                 CK(hipEventRecord(tm->ev[5 * r + 2], s));
-            CK(hipStreamWaitEvent(ss.s2, ss.evU[j], 0));
+            hipStream_t sv = side ? ss.s2 : s;
+            if (side)
+                CK(hipStreamWaitEvent(ss.s2, ss.evU[j], 0));
             if (timed)
-                CK(hipEventRecord(tm->ev[5 * r + 3], ss.s2));
-            CK(launch_update_v<T>(V, g.npad, g.npad, g.b, g.npairs, pr, Ub, ss.s2));
+                CK(hipEventRecord(tm->ev[5 * r + 3], sv));
+            CK(launch_update_v<T>(V, g.npad, g.npad, g.b, g.npairs, pr, Ub, sv));
             if (timed)
-                CK(hipEventRecord(tm->ev[5 * r + 4], ss.s2));
-            CK(hipEventRecord(ss.evV[j], ss.s2));
+                CK(hipEventRecord(tm->ev[5 * r + 4], sv));
+            if (side)
+                CK(hipEventRecord(ss.evV[j], sv));
         }
         // partials: one per pair, then per B tile (one per wavefront of the FP32
         // update, one per tile of the FP64 one)
@@ -469,7 +482,7 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
             break;
     }
     // V is complete on the caller's stream from here on
-    if (ss.round > 0)
+    if (side && ss.round > 0)
         CK(hipStreamWaitEvent(s, ss.evV[(ss.round - 1) & 1], 0));
     *sweeps_out = sweeps;
     *off_out = off;

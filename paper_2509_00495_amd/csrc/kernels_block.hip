@@ -326,10 +326,14 @@ static hipError_t launch_pair_solve_t(T *B, int64_t ldb, int npairs, const int2 
                                       hipStream_t s)
 {
     auto k = pair_solve_kernel<T, M, NT, CROSS>;
-    hipError_t e = hipFuncSetAttribute((const void *)k,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    if (e != hipSuccess)
-        return e;
+    static size_t smem_set = 0; // the attribute is set once per size (host-side cost)
+    if (smem_set != smem) {
+        hipError_t e = hipFuncSetAttribute((const void *)k,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess)
+            return e;
+        smem_set = smem;
+    }
     hipLaunchKernelGGL(k, dim3(npairs), dim3(NT), smem, s, B, ldb, pairs, psmap, U, eps, thr,
                        inner, partial, rot_flag);
     return hipGetLastError();
