@@ -70,6 +70,31 @@ def apply_bytes(n, b, elem, part):
     return tile * (3 * nbt if part == "B" else 2 * nvt)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "update_kernels_goe4096_traffic.md")
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary (already scaled by the copy-probe factors), or
+    None when there is none for this workload or a kernel source has changed
+    since the counters were taken (the summary records the source hashes)."""
+    import hashlib
+    import re
+    if workload != "goe4096" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    for path, h in re.findall(r"- `([^`]+)`: `([0-9a-f]+)`", text):
+        full = os.path.join(ROOT, path)
+        if not os.path.exists(full) or \
+                hashlib.sha256(open(full, "rb").read()).hexdigest()[:len(h)] != h:
+            return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 7 and cells[0] == kernel:
+            return int(float(cells[4]))
+    return None
+
+
 def oracle_sweeps_estimate(name, n):
     """The oracle's sweep count for this workload: read from the fixture when
     the oracle was run at this size, else extrapolated linearly in log2(n) from
@@ -254,21 +279,22 @@ def main():
     nbytes = apply_bytes(n, b, elem, part)
     # the bound is whichever floor is higher for this launch's algorithmic work
     mfma_bound = flops / (PEAK[dtype] * 1e12) >= nbytes / (HBM_PEAK * 1e9)
-    names = {("B", "f32"): "lj::update_b_kernel<float, 64>",
-             ("V", "f32"): "lj::update_v_kernel<float, 64>",
-             ("B", "f64"): "lj::apply2_kernel<double, 64>",
-             ("V", "f64"): "lj::update_v_kernel<double, 64>"}
+    names = {("B", "f32"): "update_b_kernel<float, 64>",
+             ("V", "f32"): "update_v_kernel<float, 64>",
+             ("B", "f64"): "apply2_kernel<double, 64>",
+             ("V", "f64"): "update_v_kernel<double, 64>"}
     achieved = flops / avg_s / 1e12 if mfma_bound else nbytes / avg_s / 1e9
     peak = PEAK[dtype] if mfma_bound else HBM_PEAK
     roofline = {
-        "kernel": names[(part, dtype)] + (" (off-diagonal B tiles)" if part == "B"
-                                           else " (V row tiles)"),
+        "kernel": "lj::" + names[(part, dtype)] + (" (off-diagonal B tiles)" if part == "B"
+                                                   else " (V row tiles)"),
         "bound": "mfma" if mfma_bound else "hbm",
         "achieved": round(achieved, 2),
         "peak": peak,
         "unit": "TFLOP/s" if mfma_bound else "GB/s",
         "frac": round(achieved / peak, 4),
-        "traffic": None,
+        "traffic": measured_traffic(names[(part, dtype)], wl_name),
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-probe scaled)",
         "avg_launch_us": round(avg_s * 1e6, 2),
         "launches": cnt,
         "flops_per_launch": flops,

@@ -73,7 +73,10 @@ typedef struct jacobi_opts {
                                its 2b x 2b tiles, the others only pairs that
                                join the two blocks of a tile; 1 = all pairs of
                                every tile in every round */
-    int32_t reserved[3];
+    int32_t serial_v;       /* nonzero: update the eigenvectors of a round on `stream`
+                               after its B update; default (0): on a second,
+                               library-owned stream beside the next round */
+    int32_t reserved[2];
 } jacobi_opts;
 
 /* Diagnostics filled on return (host struct, may be NULL). */

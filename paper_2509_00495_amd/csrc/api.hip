@@ -37,16 +37,9 @@ bool trace_on()
     return on;
 }
 
-// JACOBI_OVERLAP_V set: the eigenvector update of a round runs on a second
-// stream beside the next round's pair solve instead of after the B update
-bool overlap_v_on()
-{
-    static const bool on = std::getenv("JACOBI_OVERLAP_V") != nullptr;
-    return on;
-}
-
 struct Opts {
-    int max_sweeps, block, inner, ns_iters, check_sym, small_max_n, threads, timing, schedule;
+    int max_sweeps, block, inner, ns_iters, check_sym, small_max_n, threads, timing, schedule,
+        serial_v;
     double c32;
 };
 
@@ -62,6 +55,7 @@ int resolve_opts(const jacobi_opts *o, Opts &r)
     r.threads = 0;
     r.timing = 0;
     r.schedule = 0;
+    r.serial_v = 0;
     r.c32 = 1.0;
     if (!o)
         return 0;
@@ -69,6 +63,7 @@ int resolve_opts(const jacobi_opts *o, Opts &r)
     if (o->schedule < 0 || o->schedule > 1)
         return 1;
     r.schedule = o->schedule;
+    r.serial_v = o->serial_v != 0;
     if (o->max_sweeps < 0 || o->max_sweeps > 1000)
         return 1;
     if (o->max_sweeps)
@@ -391,7 +386,8 @@ struct SideStream {
 
 template <typename T>
 int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U, double tol,
-               double eps, int max_sweeps, int inner, int schedule, bool fp32_stage,
+               double eps, int max_sweeps, int inner, int schedule, int serial_v,
+               bool fp32_stage,
                hipStream_t s,
                SideStream &ss, int *sweeps_out, double *off_out, double *off0_out,
                RoundTimer *tm)
@@ -411,7 +407,7 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
     int status = JACOBI_OK;
     const double thr = n > 0 ? tol / (double)n : 0.0;
     const size_t ustride = (size_t)g.npairs * g.M * g.M;
-    const bool side = overlap_v_on();
+    const bool side = !serial_v;
     while (off > tol) {
         if (sweeps >= max_sweeps) {
             status = JACOBI_NOCONV;
@@ -675,7 +671,7 @@ int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, in
     if (int e = ss.init())
         return e;
     int st = run_sweeps<double>(g, n, w, w.B64, w.V64, w.U64, tol, U_D, o.max_sweeps, o.inner,
-                                o.schedule, false, s, ss, &sweeps, &off, nullptr, &tm);
+                                o.schedule, o.serial_v, false, s, ss, &sweeps, &off, nullptr, &tm);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;
     double est = 0.0;
@@ -719,7 +715,7 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     if (int e = ss.init())
         return e;
     int st32 = run_sweeps<float>(g, n, w, w.B32, w.V32, w.U32, tol32, U_L, o.max_sweeps,
-                                 o.inner, o.schedule, true, s, ss, &sw32, &off32, nullptr, &tm32);
+                                 o.inner, o.schedule, o.serial_v, true, s, ss, &sw32, &off32, nullptr, &tm32);
     if (st32 == JACOBI_DEVICE)
         return st32;
     // stage 2: Newton-Schulz, X <- X + X (I - X^T X) / 2  (= X (3I - X^T X) / 2)
@@ -758,7 +754,7 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     int sw64 = 0;
     double off = 0.0, offc = 0.0;
     int st = run_sweeps<double>(g, n, w, A64, X, w.U64, tol, U_D, o.max_sweeps, o.inner,
-                                o.schedule, false, s, ss, &sw64, &off, &offc, &tm64);
+                                o.schedule, o.serial_v, false, s, ss, &sw64, &off, &offc, &tm64);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;
     double est = 0.0;

@@ -41,7 +41,8 @@ class Opts(ctypes.Structure):
         ("threads", ctypes.c_int32),
         ("timing", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("serial_v", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 

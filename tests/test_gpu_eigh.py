@@ -101,6 +101,16 @@ def test_block_path_circle_schedule(pj, n, block):
     check(A, W, V, Wo, Vo, f"circle b={block}")
 
 
+@pytest.mark.parametrize("fn", ["eigh", "eigh_mixed"])
+def test_block_path_serial_v(pj, fn):
+    """serial_v=1: the eigenvector update on the caller's stream."""
+    A = wl.random_symmetric(260, 2600)
+    W, V, info = run(pj, fn, A, small_max_n=-1, block=32, serial_v=1)
+    assert info["path"] == 1 and info["status"] == 0
+    Wo, Vo, *_ = oracle.eigh(A)
+    check(A, W, V, Wo, Vo, f"serial_v {fn}")
+
+
 @pytest.mark.parametrize("n,block,inner", [(128, 16, 2), (192, 32, 3)])
 def test_block_path_inner_sweeps(pj, n, block, inner):
     A = wl.random_symmetric(n, 3000 + n)
