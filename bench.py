@@ -224,7 +224,8 @@ def main():
         torch.cuda.synchronize()
         dtp = time.perf_counter() - t1
         plain = {"value": args.steps / dtp, "ms_per_step": 1e3 * dtp / args.steps,
-                 "sweeps": pinfos[-1]["sweeps"]}
+                 "sweeps": pinfos[-1]["sweeps"], "orth_est": pinfos[-1]["orth_est"],
+                 "orth_refresh": pinfos[-1]["polished"]}
 
     # accuracy of the timed output (properties that hold at any size)
     Wn, Vn = W.cpu().numpy(), V.cpu().numpy()
@@ -330,6 +331,8 @@ def main():
             "sweeps32": last["sweeps32"],
             "sweeps64": last["sweeps"],
             "ns_iters": last["ns_iters"],
+            "orth_est": last["orth_est"],
+            "orth_refresh": last["polished"],
         },
         "plain_fp64": plain,
         "speedup_vs_plain": None if plain is None else round(value / plain["value"], 3),

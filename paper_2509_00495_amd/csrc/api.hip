@@ -599,9 +599,15 @@ int eigh_small(const double *A, int64_t n, int64_t lda, double *W, double *V, in
 // which squares its departure from orthogonality.  Rbuf and Vbuf are free
 // npad x npad scratch buffers (Rbuf may alias B: the diagonal is extracted
 // first).
+// A_rq != nullptr: the eigenvalues are the Rayleigh quotients v_k^T A v_k of
+// the final eigenvectors against the input (T = A V is formed in Rbuf) instead
+// of the diagonal of B.  The plain FP64 path uses this: after its many sweeps
+// of blockwise updates the rounding accumulated in the diagonal of B exceeds
+// what the eigenvectors themselves allow.
 int finalize_block(const Geometry &g, int64_t n, const BlockWs &w, const double *B,
                    const double *Vin, double *Rbuf, double *Vbuf, double *W, double *V,
-                   int64_t ldv, hipStream_t s, double *orth_est, int *polished)
+                   int64_t ldv, hipStream_t s, double *orth_est, int *polished,
+                   const double *A_rq = nullptr, int64_t lda = 0)
 {
     const int64_t np = g.npad;
     CK(launch_diag(B, np, n, w.wtmp, s));
@@ -628,6 +634,11 @@ int finalize_block(const Geometry &g, int64_t n, const BlockWs &w, const double 
                          Vbuf, np, 0, 1, s));
         Vf = Vbuf;
         *polished = 1;
+    }
+    if (A_rq) {
+        CK(launch_gemm64(0, 0, n, n, n, 1.0, A_rq, lda, 0, Vf, np, 0, 0.0, nullptr, 0, 0, 0.0,
+                         Rbuf, np, 0, 1, s));
+        CK(launch_rayleigh(Vf, np, Rbuf, np, n, w.cmax, w.wtmp, s));
     }
     CK(launch_fill_i32(w.perm, n, 0, s));
     CK(launch_finalize(w.wtmp, Vf, np, n, W, V, ldv, w.perm, w.sg, w.cmax, w.cidx, s));
@@ -676,7 +687,8 @@ int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, in
         return st;
     double est = 0.0;
     int pol = 0;
-    if (int e = finalize_block(g, n, w, w.B64, w.V64, w.B64, w.Vt, W, V, ldv, s, &est, &pol))
+    if (int e = finalize_block(g, n, w, w.B64, w.V64, w.B64, w.Vt, W, V, ldv, s, &est, &pol, A,
+                               lda))
         return e;
     CK(hipStreamSynchronize(s));
     fill_info(info, sweeps, 0, 0, 1, g.b, normf, tol, off, 0, 0, 0);

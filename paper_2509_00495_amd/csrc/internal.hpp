@@ -70,6 +70,10 @@ hipError_t launch_cast_f32(const double *src, float *dst, int64_t count, hipStre
 hipError_t launch_widen_f64(const float *src, double *dst, int64_t count, hipStream_t s);
 hipError_t launch_symmetrize(double *B, int64_t npad, hipStream_t s);
 hipError_t launch_diag(const double *B, int64_t ldb, int64_t n, double *w, hipStream_t s);
+// w_k = sum_i V[i][k] T[i][k] (Rayleigh quotients when T = A V); part holds
+// 16 n doubles
+hipError_t launch_rayleigh(const double *V, int64_t ldv, const double *T, int64_t ldt,
+                           int64_t n, double *part, double *w, hipStream_t s);
 hipError_t launch_finalize(const double *w, const double *V, int64_t ldv_in, int64_t n,
                            double *W, double *Vout, int64_t ldv, int *perm, double *sg,
                            double *cmax, int *cidx, hipStream_t s);

@@ -966,6 +966,36 @@ __global__ void diag_kernel(const double *__restrict__ B, int64_t ldb, int64_t n
         w[i] = B[i * ldb + i];
 }
 
+// Rayleigh quotients w_k = v_k^T (A v_k) from T = A V: column dots over row
+// chunk blockIdx.y (partial sums), then a sum over the chunks.
+constexpr int RQ_CHUNKS = 16;
+__global__ __launch_bounds__(256) void rq_partial_kernel(const double *__restrict__ V,
+                                                         int64_t ldv,
+                                                         const double *__restrict__ T,
+                                                         int64_t ldt, int64_t n,
+                                                         double *__restrict__ part)
+{
+    const int64_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n)
+        return;
+    const int64_t r0 = blockIdx.y * n / RQ_CHUNKS, r1 = (blockIdx.y + 1) * n / RQ_CHUNKS;
+    double acc = 0.0;
+    for (int64_t i = r0; i < r1; ++i)
+        acc = fma(V[i * ldv + k], T[i * ldt + k], acc);
+    part[blockIdx.y * n + k] = acc;
+}
+
+__global__ void rq_sum_kernel(const double *__restrict__ part, int64_t n, double *__restrict__ w)
+{
+    const int64_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n)
+        return;
+    double acc = 0.0;
+    for (int c = 0; c < RQ_CHUNKS; ++c)
+        acc += part[c * n + k];
+    w[k] = acc;
+}
+
 // Stable ascending rank of each eigenvalue: ties keep diagonal order.
 __global__ __launch_bounds__(256) void rank_kernel(const double *__restrict__ w, int64_t n,
                                                    int *__restrict__ perm)
@@ -1064,6 +1094,16 @@ hipError_t launch_diag(const double *B, int64_t ldb, int64_t n, double *w, hipSt
 {
     int g = (int)((n + 255) / 256);
     hipLaunchKernelGGL(diag_kernel, dim3(g), dim3(256), 0, s, B, ldb, n, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_rayleigh(const double *V, int64_t ldv, const double *T, int64_t ldt,
+                           int64_t n, double *part, double *w, hipStream_t s)
+{
+    int g = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(rq_partial_kernel, dim3(g, RQ_CHUNKS), dim3(256), 0, s, V, ldv, T, ldt,
+                       n, part);
+    hipLaunchKernelGGL(rq_sum_kernel, dim3(g), dim3(256), 0, s, part, n, w);
     return hipGetLastError();
 }
 

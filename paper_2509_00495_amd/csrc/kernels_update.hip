@@ -253,9 +253,10 @@ __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int6
         for (int e = 0; e < KG * VK; ++e)
             uk[e] = ukn[e];
         __syncthreads();
-        // unconditional (clamped) prefetch: the same memory-operation sequence
-        // on every path into the next step, so its wait skips the stores below
-        load_tile(t + 1 < t1 ? t + 1 : t1 - 1);
+        // unconditional prefetch: the same memory-operation sequence on every
+        // path into the next step, so its wait skips the stores below (after
+        // the last tile it re-reads the run's first tile, still in L2)
+        load_tile(t + 1 < t1 ? t + 1 : t0);
         const int2 pk = pairs[kl.x], pl = pairs[kl.y];
         accT c1[TC];
 #pragma unroll
