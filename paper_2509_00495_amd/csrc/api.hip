@@ -306,12 +306,12 @@ int read_scalars(const BlockWs &w, hipStream_t s, Readback &rb)
 // the per-sweep readback.
 struct RoundTimer {
     bool on = false;
-    std::vector<hipEvent_t> ev; // 5 per round
+    std::vector<hipEvent_t> ev; // 6 per round: pair solve, B update, V update
     double pair_ms = 0.0, apply_ms = 0.0, applyv_ms = 0.0;
     int npair = 0, napply = 0, napplyv = 0;
     int ensure(int rounds)
     {
-        while ((int)ev.size() < 5 * rounds) {
+        while ((int)ev.size() < 6 * rounds) {
             hipEvent_t e;
             CK(hipEventCreate(&e));
             ev.push_back(e);
@@ -327,9 +327,9 @@ struct RoundTimer {
     {
         for (int r = 0; r < rounds; ++r) {
             float a = 0.f, b = 0.f, c = 0.f;
-            CK(hipEventElapsedTime(&a, ev[5 * r], ev[5 * r + 1]));
-            CK(hipEventElapsedTime(&b, ev[5 * r + 1], ev[5 * r + 2]));
-            CK(hipEventElapsedTime(&c, ev[5 * r + 3], ev[5 * r + 4]));
+            CK(hipEventElapsedTime(&a, ev[6 * r], ev[6 * r + 1]));
+            CK(hipEventElapsedTime(&b, ev[6 * r + 2], ev[6 * r + 3]));
+            CK(hipEventElapsedTime(&c, ev[6 * r + 4], ev[6 * r + 5]));
             pair_ms += a;
             apply_ms += b;
             applyv_ms += c;
@@ -352,10 +352,8 @@ struct RoundTimer {
     }
 };
 
-// Side stream for the V updates.  The update of V in round r only needs U_r,
-// so it runs beside the B update of round r and the pair solve of round r+1;
-// U is double-buffered and the pair solve of round r+2 waits for the V update
-// of round r, which last read that buffer.  Non-blocking and default priority.
+// Side stream for the V updates of the block path (overlapped mode, see
+// run_sweeps).  Non-blocking and default priority.
 struct SideStream {
     hipStream_t s2 = nullptr;
     hipEvent_t evU[2] = {nullptr, nullptr}, evV[2] = {nullptr, nullptr};
@@ -407,6 +405,10 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
     int status = JACOBI_OK;
     const double thr = n > 0 ? tol / (double)n : 0.0;
     const size_t ustride = (size_t)g.npairs * g.M * g.M;
+    // Overlapped mode: the V update of round r runs on the side stream beside
+    // round r + 1's pair solve and B update (it needs only U_r).  U is
+    // double-buffered, and the pair solve of round r + 2, which overwrites
+    // U_r's buffer, waits for that V update.
     const bool side = !serial_v;
     while (off > tol) {
         if (sweeps >= max_sweeps) {
@@ -422,39 +424,36 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
             if (side && ss.round >= 2)
                 CK(hipStreamWaitEvent(s, ss.evV[j], 0));
             if (timed)
-                CK(hipEventRecord(tm->ev[5 * r], s));
+                CK(hipEventRecord(tm->ev[6 * r], s));
             const int cross = schedule == 0 && r > 0;
             const int2 *map = w.psmap + (cross ? (size_t)g.b * (g.b + 1) / 2 : 0);
             CK(launch_pair_solve<T>(B, g.npad, g.b, g.npairs, pr, map, Ub, eps, thr, inner,
                                     cross, w.partial, w.flags + 2, s));
+            if (timed)
+                CK(hipEventRecord(tm->ev[6 * r + 1], s));
             if (side)
                 CK(hipEventRecord(ss.evU[j], s));
             if (timed)
-                CK(hipEventRecord(tm->ev[5 * r + 1], s));
-            if (sizeof(T) == 4)
-                CK(launch_update_b<T>(B, g.npad, g.b, pr, Ub, w.btiles, g.nbt,
-                                      w.partial + g.npairs, r == g.N - 2, s));
-            else
-                CK(launch_apply<T>(B, g.npad, V, g.npad, g.npad, g.b, g.npairs, pr, w.btiles,
-                                   g.nbt, Ub, w.partial + g.npairs, r == g.N - 2, 1, s));
+                CK(hipEventRecord(tm->ev[6 * r + 2], s));
+            CK(launch_update_b<T>(B, g.npad, g.b, pr, Ub, w.btiles, g.nbt, w.partial + g.npairs,
+                                  r == g.N - 2, s));
             if (timed)
-                CK(hipEventRecord(tm->ev[5 * r + 2], s));
+                CK(hipEventRecord(tm->ev[6 * r + 3], s));
             hipStream_t sv = side ? ss.s2 : s;
             if (side)
                 CK(hipStreamWaitEvent(ss.s2, ss.evU[j], 0));
             if (timed)
-                CK(hipEventRecord(tm->ev[5 * r + 3], sv));
+                CK(hipEventRecord(tm->ev[6 * r + 4], sv));
             CK(launch_update_v<T>(V, g.npad, g.npad, g.b, g.npairs, pr, Ub, sv));
             if (timed)
-                CK(hipEventRecord(tm->ev[5 * r + 4], sv));
+                CK(hipEventRecord(tm->ev[6 * r + 5], sv));
             if (side)
-                CK(hipEventRecord(ss.evV[j], sv));
+                CK(hipEventRecord(ss.evV[j], ss.s2));
         }
         // partials: one per pair, then per B tile (one per wavefront of the FP32
         // update, one per tile of the FP64 one)
-        CK(launch_sum(w.partial,
-                      (int64_t)g.npairs + (int64_t)g.nbt * (sizeof(T) == 4 ? g.M / 16 : 1),
-                      w.scal + 1, s));
+        CK(launch_sum(w.partial, (int64_t)g.npairs + (int64_t)g.nbt * (g.M / 16), w.scal + 1,
+                      s));
         if (int e = read_scalars(w, s, rb))
             return e;
         if (timed) {

@@ -36,9 +36,9 @@ hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *p
 // thread -> block map of the pair solve (b(b+1)/2 entries for M = 2b)
 void pair_solve_map(int M, int cross, int2 *out);
 // which = 1: B tiles only, 2: V tiles only, 3: both
-// B_kl <- U_k^T B_kl U_l (and mirror) for the tiles of update_b_tiles (pairs
-// k < l ordered by l, then k); partial[t (2b / 16) + w] gets twice the squared
-// sum of wavefront w's part of tile t when want_off (kernels_update.hip)
+// B_kl <- U_k^T B_kl U_l (and mirror) for the ntiles tiles (k, l), k < l, of
+// the list; partial[(l (l - 1) / 2 + k) (2b / 16) + w] gets twice the squared
+// sum of wavefront w's part of tile (k, l) when want_off (kernels_update.hip)
 template <typename T>
 hipError_t launch_update_b(T *B, int64_t ldb, int b, const int2 *pairs, const T *U,
                            const int2 *tiles, int ntiles, double *partial, int want_off,

@@ -9,7 +9,8 @@
 //      rotation U_PQ and writes the rotated tile back;
 //   2. apply: every off-diagonal tile pair (k < l) becomes U_k^T B_kl U_l
 //      (two MFMA GEMMs, the result and its transpose are written), and every
-//      row tile of V becomes V_rows,l U_l (one MFMA GEMM).
+//      row tile of V becomes V_rows,l U_l (one MFMA GEMM); the update kernels
+//      are in kernels_update.hip.
 // Entries of B coupling a padding index are zero and stay exactly zero, so
 // padding never mixes with the matrix.
 #include "internal.hpp"
@@ -367,374 +368,8 @@ hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *p
 }
 
 // ------------------------------------------------------------------ apply
-// Wave-level GEMM on LDS operands: acc += op(A) * Bm over the full inner
-// dimension M.  Wave w owns rows [ (w/2) M/2, +M/2 ) and columns
-// [ (w%2) M/2, +M/2 ) of the M x M product, as TM x TM MFMA 16x16 tiles.
-template <typename T, int M, bool TA>
-__device__ inline void wave_gemm(const T *As, int lda, const T *Bs, int ldbs,
-                                 typename acc4<T>::type (&acc)[M / 32][M / 32])
-{
-    constexpr int TM = M / 32;
-    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-    const int row0 = (w / 2) * (M / 2), col0 = (w % 2) * (M / 2);
-    const int li = lane % 16, lk = lane / 16;
-#pragma unroll 4
-    for (int kb = 0; kb < M; kb += 4) {
-        const int kk = kb + lk;
-        T a[TM], bb[TM];
-#pragma unroll
-        for (int t = 0; t < TM; ++t) {
-            const int i = row0 + t * 16 + li;
-            a[t] = TA ? As[kk * lda + i] : As[i * lda + kk];
-            const int j = col0 + t * 16 + li;
-            bb[t] = Bs[kk * ldbs + j];
-        }
-#pragma unroll
-        for (int ti = 0; ti < TM; ++ti)
-#pragma unroll
-            for (int tj = 0; tj < TM; ++tj)
-                acc[ti][tj] = mfma16(a[ti], bb[tj], acc[ti][tj]);
-    }
-}
-
-// Store the wave's accumulators into an LDS matrix (row stride ld).
-template <typename T, int M>
-__device__ inline void wave_store(T *Cs, int ld, typename acc4<T>::type (&acc)[M / 32][M / 32])
-{
-    constexpr int TM = M / 32;
-    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-    const int row0 = (w / 2) * (M / 2), col0 = (w % 2) * (M / 2);
-    const int li = lane % 16, lk = lane / 16;
-#pragma unroll
-    for (int ti = 0; ti < TM; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < TM; ++tj)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                Cs[(row0 + ti * 16 + acc_row<T>(lk, v)) * ld + col0 + tj * 16 + li] =
-                    acc[ti][tj][v];
-}
-
-template <typename T, int M>
-__device__ inline void zero_acc(typename acc4<T>::type (&acc)[M / 32][M / 32])
-{
-#pragma unroll
-    for (int ti = 0; ti < M / 32; ++ti)
-#pragma unroll
-        for (int tj = 0; tj < M / 32; ++tj)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                acc[ti][tj][v] = (T)0;
-}
-
-template <typename T, int M>
-__global__ __launch_bounds__(256) void apply_kernel(T *__restrict__ B, int64_t ldb,
-                                                    T *__restrict__ V, int64_t ldv,
-                                                    const int2 *__restrict__ pairs,
-                                                    const int2 *__restrict__ btiles, int nbt,
-                                                    int npairs, const T *__restrict__ U,
-                                                    double *__restrict__ partial, int want_off)
-{
-    constexpr int b = M / 2, ld = M + 1;
-    __shared__ T Xs[M * ld];
-    __shared__ T Us[M * ld];
-    __shared__ double red[4];
-    const int tid = threadIdx.x;
-    typename acc4<T>::type acc[M / 32][M / 32];
-    zero_acc<T, M>(acc);
-    const int tile = blockIdx.x;
-    if (tile < nbt) {
-        const int2 kl = btiles[tile];
-        const int2 pk = pairs[kl.x], pl = pairs[kl.y];
-        const T *Ukp = U + (int64_t)kl.x * M * M;
-        const T *Ulp = U + (int64_t)kl.y * M * M;
-        for (int idx = tid; idx < M * M; idx += 256) {
-            int i = idx / M, j = idx % M;
-            int64_t gi = i < b ? (int64_t)pk.x * b + i : (int64_t)pk.y * b + (i - b);
-            int64_t gj = j < b ? (int64_t)pl.x * b + j : (int64_t)pl.y * b + (j - b);
-            Xs[i * ld + j] = B[gi * ldb + gj];
-            Us[i * ld + j] = Ulp[idx];
-        }
-        __syncthreads();
-        wave_gemm<T, M, false>(Xs, ld, Us, ld, acc); // Y = X U_l
-        __syncthreads();
-        wave_store<T, M>(Xs, ld, acc);
-        for (int idx = tid; idx < M * M; idx += 256) {
-            int i = idx / M, j = idx % M;
-            Us[i * ld + j] = Ukp[idx];
-        }
-        __syncthreads();
-        zero_acc<T, M>(acc);
-        wave_gemm<T, M, true>(Us, ld, Xs, ld, acc); // Z = U_k^T Y
-        __syncthreads();
-        wave_store<T, M>(Xs, ld, acc);
-        __syncthreads();
-        double sq = 0.0;
-        for (int idx = tid; idx < M * M; idx += 256) {
-            int i = idx / M, j = idx % M;
-            int64_t gi = i < b ? (int64_t)pk.x * b + i : (int64_t)pk.y * b + (i - b);
-            int64_t gj = j < b ? (int64_t)pl.x * b + j : (int64_t)pl.y * b + (j - b);
-            T z = Xs[i * ld + j];
-            B[gi * ldb + gj] = z;
-            sq += (double)z * (double)z;
-            // mirror: row gj' of the transposed tile, coalesced along i'
-            int i2 = idx / M, j2 = idx % M; // i2 indexes columns of Z, j2 rows
-            int64_t mi = i2 < b ? (int64_t)pl.x * b + i2 : (int64_t)pl.y * b + (i2 - b);
-            int64_t mj = j2 < b ? (int64_t)pk.x * b + j2 : (int64_t)pk.y * b + (j2 - b);
-            B[mi * ldb + mj] = Xs[j2 * ld + i2];
-        }
-        if (want_off) {
-            sq = wave_sum(sq);
-            if (tid % WAVE == 0)
-                red[tid / WAVE] = sq;
-            __syncthreads();
-            if (tid == 0)
-                partial[tile] = 2.0 * (red[0] + red[1] + red[2] + red[3]);
-        }
-    } else {
-        const int vt = tile - nbt;
-        const int l = vt % npairs;
-        const int64_t r0 = (int64_t)(vt / npairs) * M;
-        const int2 pl = pairs[l];
-        const T *Ulp = U + (int64_t)l * M * M;
-        for (int idx = tid; idx < M * M; idx += 256) {
-            int i = idx / M, j = idx % M;
-            int64_t gj = j < b ? (int64_t)pl.x * b + j : (int64_t)pl.y * b + (j - b);
-            Xs[i * ld + j] = V[(r0 + i) * ldv + gj];
-            Us[i * ld + j] = Ulp[idx];
-        }
-        __syncthreads();
-        wave_gemm<T, M, false>(Xs, ld, Us, ld, acc); // V_rows,l U_l
-        __syncthreads();
-        wave_store<T, M>(Xs, ld, acc);
-        __syncthreads();
-        for (int idx = tid; idx < M * M; idx += 256) {
-            int i = idx / M, j = idx % M;
-            int64_t gj = j < b ? (int64_t)pl.x * b + j : (int64_t)pl.y * b + (j - b);
-            V[(r0 + i) * ldv + gj] = Xs[i * ld + j];
-        }
-    }
-}
-
-// Persistent, software-pipelined update kernel.  A workgroup walks tiles
-// t = blockIdx.x, blockIdx.x + gridDim.x, ...; mode 1 = off-diagonal B tiles
-// (Z = U_k^T X U_l, result and transpose written), mode 2 = V row tiles
-// (Z = X U_l).  The U operands never touch LDS: every lane keeps the MFMA
-// fragments it needs in registers (B operand of X U_l: U_l[kk][j]; A operand
-// of U_k^T Y: U_k[kk][i]; both read along rows of the L2-resident U blocks).
-// Only X, then Y, then Z pass through one LDS tile.  While a tile computes,
-// the next tile's X and U fragments are already being loaded.
-template <typename T, int M>
-struct TileOps {
-    static constexpr int b = M / 2, ld = M + 1, TM = M / 32, KS = M / 4;
-    static constexpr int PER = M * M / 256; // X elements per thread
-    __device__ static inline int64_t gidx(int2 pq, int i)
-    {
-        return i < b ? (int64_t)pq.x * b + i : (int64_t)pq.y * b + (i - b);
-    }
-    // fragment f = ks * TM + t: row kk = 4 ks + lane/16, column 16 t + lane%16
-    // of the wave's half (offset off = row0 or col0)
-    __device__ static inline void load_frag(const T *Ublk, int off, T (&fr)[KS * TM])
-    {
-        const int lane = threadIdx.x % WAVE, li = lane % 16, lk = lane / 16;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-            for (int t = 0; t < TM; ++t)
-                fr[ks * TM + t] = Ublk[(4 * ks + lk) * M + off + t * 16 + li];
-    }
-};
-
-template <typename T, int M>
-__global__ __launch_bounds__(256) void apply2_kernel(T *__restrict__ B, int64_t ldb,
-                                                     T *__restrict__ V, int64_t ldv,
-                                                     const int2 *__restrict__ pairs,
-                                                     const int2 *__restrict__ btiles, int ntiles,
-                                                     int npairs, const T *__restrict__ U,
-                                                     double *__restrict__ partial, int want_off,
-                                                     int mode)
-{
-    using O = TileOps<T, M>;
-    constexpr int ld = O::ld, TM = O::TM, KS = O::KS, PER = O::PER;
-    // FP32 keeps the next tile's U fragments in flight too; FP64 loads them
-    // per tile (U_l before the first product, U_k after it), which keeps
-    // register use low enough for three waves per SIMD
-    constexpr bool PREF_U = sizeof(T) == 4;
-    __shared__ T Xs[M * ld];
-    __shared__ double red[4];
-    const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
-    const int li = lane % 16, lk = lane / 16;
-    const int row0 = (w / 2) * (M / 2), col0 = (w % 2) * (M / 2);
-    typedef typename acc4<T>::type accT;
-    T xr[PER];
-    T ul[KS * TM], uk[KS * TM];
-
-    // tile descriptors
-    auto tile_info = [&](int tile, int2 &pk, int2 &pl, int &kx, int &lx, int64_t &r0) {
-        if (mode == 1) {
-            const int2 kl = btiles[tile];
-            kx = kl.x;
-            lx = kl.y;
-            pk = pairs[kx];
-            pl = pairs[lx];
-            r0 = 0;
-        } else {
-            lx = tile % npairs;
-            kx = 0;
-            r0 = (int64_t)(tile / npairs) * M;
-            pl = pairs[lx];
-            pk = pl;
-        }
-    };
-    auto load_x = [&](int2 pk, int2 pl, int64_t r0) {
-#pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int idx = tid + e * 256, i = idx / M, j = idx % M;
-            const int64_t gj = O::gidx(pl, j);
-            xr[e] = mode == 1 ? B[O::gidx(pk, i) * ldb + gj] : V[(r0 + i) * ldv + gj];
-        }
-    };
-
-    int tile = blockIdx.x;
-    if (tile >= ntiles)
-        return;
-    int2 pk, pl;
-    int kx, lx;
-    int64_t r0;
-    tile_info(tile, pk, pl, kx, lx, r0);
-    load_x(pk, pl, r0);
-    if (PREF_U) {
-        O::load_frag(U + (int64_t)lx * M * M, col0, ul);
-        if (mode == 1)
-            O::load_frag(U + (int64_t)kx * M * M, row0, uk);
-    }
-
-    while (true) {
-        // X -> LDS
-#pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int idx = tid + e * 256;
-            Xs[(idx / M) * ld + idx % M] = xr[e];
-        }
-        __syncthreads();
-        const int next = tile + gridDim.x;
-        int2 npk = pk, npl = pl;
-        int nkx = kx, nlx = lx;
-        int64_t nr0 = r0;
-        if (next < ntiles) {
-            tile_info(next, npk, npl, nkx, nlx, nr0);
-            load_x(npk, npl, nr0); // in flight during this tile's GEMMs
-        }
-        if (!PREF_U)
-            O::load_frag(U + (int64_t)lx * M * M, col0, ul);
-        // Y = X U_l
-        accT acc[TM][TM];
-#pragma unroll
-        for (int a = 0; a < TM; ++a)
-#pragma unroll
-            for (int c = 0; c < TM; ++c)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    acc[a][c][v] = (T)0;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int kk = 4 * ks + lk;
-            T a[TM];
-#pragma unroll
-            for (int t = 0; t < TM; ++t)
-                a[t] = Xs[(row0 + t * 16 + li) * ld + kk];
-#pragma unroll
-            for (int ti = 0; ti < TM; ++ti)
-#pragma unroll
-                for (int tj = 0; tj < TM; ++tj)
-                    acc[ti][tj] = mfma16(a[ti], ul[ks * TM + tj], acc[ti][tj]);
-        }
-        if (PREF_U && next < ntiles)
-            O::load_frag(U + (int64_t)nlx * M * M, col0, ul);
-        if (!PREF_U && mode == 1)
-            O::load_frag(U + (int64_t)kx * M * M, row0, uk);
-        __syncthreads();
-        if (mode == 1) {
-#pragma unroll
-            for (int ti = 0; ti < TM; ++ti)
-#pragma unroll
-                for (int tj = 0; tj < TM; ++tj)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        Xs[(row0 + ti * 16 + acc_row<T>(lk, v)) * ld + col0 + tj * 16 + li] =
-                            acc[ti][tj][v];
-            __syncthreads();
-            // Z = U_k^T Y
-#pragma unroll
-            for (int a = 0; a < TM; ++a)
-#pragma unroll
-                for (int c = 0; c < TM; ++c)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        acc[a][c][v] = (T)0;
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const int kk = 4 * ks + lk;
-                T bb[TM];
-#pragma unroll
-                for (int t = 0; t < TM; ++t)
-                    bb[t] = Xs[kk * ld + col0 + t * 16 + li];
-#pragma unroll
-                for (int ti = 0; ti < TM; ++ti)
-#pragma unroll
-                    for (int tj = 0; tj < TM; ++tj)
-                        acc[ti][tj] = mfma16(uk[ks * TM + ti], bb[tj], acc[ti][tj]);
-            }
-            if (PREF_U && next < ntiles)
-                O::load_frag(U + (int64_t)nkx * M * M, row0, uk);
-            __syncthreads();
-        }
-        // Z -> LDS -> global (B tile and its mirror, or V tile)
-#pragma unroll
-        for (int ti = 0; ti < TM; ++ti)
-#pragma unroll
-            for (int tj = 0; tj < TM; ++tj)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    Xs[(row0 + ti * 16 + acc_row<T>(lk, v)) * ld + col0 + tj * 16 + li] =
-                        acc[ti][tj][v];
-        __syncthreads();
-        double sq = 0.0;
-#pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int idx = tid + e * 256, i = idx / M, j = idx % M;
-            const T z = Xs[i * ld + j];
-            if (mode == 1) {
-                B[O::gidx(pk, i) * ldb + O::gidx(pl, j)] = z;
-                sq += (double)z * (double)z;
-                // mirror, coalesced along its rows: element (i, j) of Z^T
-                B[O::gidx(pl, i) * ldb + O::gidx(pk, j)] = Xs[j * ld + i];
-            } else {
-                V[(r0 + i) * ldv + O::gidx(pl, j)] = z;
-            }
-        }
-        if (mode == 1 && want_off) {
-            sq = wave_sum(sq);
-            if (lane == 0)
-                red[w] = sq;
-            __syncthreads();
-            if (tid == 0)
-                partial[tile] = 2.0 * (red[0] + red[1] + red[2] + red[3]);
-        }
-        if (next >= ntiles)
-            break;
-        __syncthreads(); // Xs is rewritten by the next tile
-        tile = next;
-        pk = npk;
-        pl = npl;
-        kx = nkx;
-        lx = nlx;
-        r0 = nr0;
-    }
-}
-
-// which = 1: B tiles, 2: V tiles.  Persistent grid: at most `grid_cap`
-// workgroups (0 = one per tile).
+// which = 1: the off-diagonal B tiles listed in btiles (nbt of them); 2: the V
+// row tiles.  Both run on the update kernels of kernels_update.hip.
 template <typename T>
 hipError_t launch_apply(T *B, int64_t ldb, T *V, int64_t ldv, int64_t nrows, int b, int npairs,
                         const int2 *pairs, const int2 *btiles, int nbt, const T *U,
@@ -742,32 +377,7 @@ hipError_t launch_apply(T *B, int64_t ldb, T *V, int64_t ldv, int64_t nrows, int
 {
     if (which == 2)
         return launch_update_v<T>(V, ldv, nrows, b, npairs, pairs, U, s);
-    const int M = 2 * b;
-    const int64_t ntiles = which == 1 ? nbt : (nrows / M) * npairs;
-    if (ntiles == 0)
-        return hipSuccess;
-    static int cap[2][2] = {{0, 0}, {0, 0}};
-    int &c = cap[sizeof(T) == 8][M == 64];
-    if (c == 0) {
-        int dev = 0, cus = 0, per = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (M == 64)
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, apply2_kernel<T, 64>, 256, 0);
-        else
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, apply2_kernel<T, 32>, 256, 0);
-        c = (cus > 0 ? cus : 256) * (per > 0 ? per : 1);
-    }
-    const unsigned grid = (unsigned)(ntiles < c ? ntiles : c);
-    if (M == 64)
-        hipLaunchKernelGGL((apply2_kernel<T, 64>), dim3(grid), dim3(256), 0, s, B, ldb, V, ldv,
-                           pairs, btiles, (int)ntiles, npairs, U, partial, want_off, which);
-    else if (M == 32)
-        hipLaunchKernelGGL((apply2_kernel<T, 32>), dim3(grid), dim3(256), 0, s, B, ldb, V, ldv,
-                           pairs, btiles, (int)ntiles, npairs, U, partial, want_off, which);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    return launch_update_b<T>(B, ldb, b, pairs, U, btiles, nbt, partial, want_off, s);
 }
 
 // ------------------------------------------------------- reductions, etc.

@@ -166,9 +166,10 @@ __global__ __launch_bounds__(256) void update_v_kernel(T *__restrict__ V, int64_
         work(xb, t);
 }
 
-// B update.  The tiles (k, l), k < l, are listed by column pair l, then k;
-// workgroup g of G takes the run [g T / G, (g + 1) T / G) of the T tiles (the
-// same share for every workgroup).  Its M/16 wavefronts produce rows
+// B update.  The kernel takes a list of T tiles (k, l), k < l (all of them,
+// or a subset); workgroup g of G takes the run [g T / G, (g + 1) T / G) of
+// the list (the same share for every workgroup), so a list sorted by l keeps
+// the column pair of a run mostly fixed.  Its M/16 wavefronts produce rows
 // 16w .. 16w + 15 of Z = U_k^T X U_l as two chained MFMA products:
 //   C1 = X^T U_k (M-index c, N-index i, K-index r): the A operand X^T is read
 //        from the mirror tile B[rows(l), cols(k)] (= X^T, B is kept exactly
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int6
         if (want_off) {
             sq = wave_sum(sq);
             if (lane == 0)
-                partial[(int64_t)t * NW + w] = 2.0 * sq;
+                partial[((int64_t)kl.y * (kl.y - 1) / 2 + kl.x) * NW + w] = 2.0 * sq;
         }
     };
     load_tile(t0);
