@@ -68,7 +68,6 @@ hipError_t launch_off2_partial(const T *B, int64_t npad, double *partial, hipStr
 hipError_t launch_fill_i32(int *p, int64_t count, int value, hipStream_t s);
 hipError_t launch_cast_f32(const double *src, float *dst, int64_t count, hipStream_t s);
 hipError_t launch_widen_f64(const float *src, double *dst, int64_t count, hipStream_t s);
-hipError_t launch_symmetrize(double *B, int64_t npad, hipStream_t s);
 hipError_t launch_diag(const double *B, int64_t ldb, int64_t n, double *w, hipStream_t s);
 // w_k = sum_i V[i][k] T[i][k] (Rayleigh quotients when T = A V); part holds
 // 16 n doubles
@@ -92,6 +91,12 @@ hipError_t launch_gemm64(int transA, int transB, int64_t M, int64_t N, int64_t K
                          const double *C0, int64_t ldc0, int64_t sC0, double gamma,
                          double *C, int64_t ldc, int64_t sC, int64_t batch,
                          hipStream_t s);
+// The same for a square N x N result known to be symmetric (alpha op(A) op(B)
+// symmetric and C0 symmetric): upper tiles computed, mirrored below.
+hipError_t launch_gemm64_sym(int transA, int transB, int64_t N, int64_t K, double alpha,
+                             const double *A, int64_t lda, const double *B, int64_t ldb,
+                             double beta, const double *C0, int64_t ldc0, double gamma, double *C,
+                             int64_t ldc, hipStream_t s);
 hipError_t launch_sq_partial(const double *X, int64_t count, double *partial,
                              hipStream_t s);
 // backward elementwise: M <- diag(dW) + F o M (F from gaps), flags DEGENERATE

@@ -350,11 +350,16 @@ hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *p
     size_t smem = align8(sizeof(T) * ((size_t)M * (M + vn) + (size_t)M * (M + 1))) + 16 +
                   2 * (((size_t)b * (8 + 5 * sizeof(T)) + 15) & ~(size_t)15) +
                   16 * sizeof(double) + 16 * sizeof(int);
+    // M = 64: 528 threads own the 2x2 blocks of S; the U items (32 pairs x
+    // 64 / VN chunks) go to the threads after the first wavefront.  16
+    // wavefronts for both types (10 would cover the FP32 items, but measured
+    // slower: the extra wavefronts hide LDS latency).
+    constexpr int NT64 = 1024;
     if (M == 64)
-        return cross ? launch_pair_solve_t<T, 64, 1024, true>(B, ldb, npairs, pairs, psmap, U,
+        return cross ? launch_pair_solve_t<T, 64, NT64, true>(B, ldb, npairs, pairs, psmap, U,
                                                               eps, thr, inner, partial,
                                                               rot_flag, smem, s)
-                     : launch_pair_solve_t<T, 64, 1024, false>(B, ldb, npairs, pairs, psmap,
+                     : launch_pair_solve_t<T, 64, NT64, false>(B, ldb, npairs, pairs, psmap,
                                                                U, eps, thr, inner, partial,
                                                                rot_flag, smem, s);
     if (M == 32)
@@ -545,26 +550,6 @@ __global__ void widen_f64_kernel(const float *__restrict__ src, double *__restri
 hipError_t launch_widen_f64(const float *src, double *dst, int64_t count, hipStream_t s)
 {
     hipLaunchKernelGGL(widen_f64_kernel, dim3(2048), dim3(256), 0, s, src, dst, count);
-    return hipGetLastError();
-}
-
-// B <- (B + B^T)/2 in place; each unordered pair (i < j) has one owner.
-__global__ __launch_bounds__(256) void symmetrize_kernel(double *B, int64_t npad)
-{
-    const int64_t total = npad * npad;
-    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-        int64_t i = e / npad, j = e - (e / npad) * npad;
-        if (i < j) {
-            double m = 0.5 * (B[i * npad + j] + B[j * npad + i]);
-            B[i * npad + j] = m;
-            B[j * npad + i] = m;
-        }
-    }
-}
-
-hipError_t launch_symmetrize(double *B, int64_t npad, hipStream_t s)
-{
-    hipLaunchKernelGGL(symmetrize_kernel, dim3(2048), dim3(256), 0, s, B, npad);
     return hipGetLastError();
 }
 

@@ -5,7 +5,10 @@
 //   C = alpha * op(A) * op(B) + beta * C0 + gamma * I      (row-major)
 //
 // Workgroup tile 64 x 64 (4 waves, each 32 x 32 = 2 x 2 MFMA 16x16x4 tiles),
-// K staged through LDS 16 at a time; batched over blockIdx.z.
+// K staged through LDS 16 at a time; batched over blockIdx.z.  SYM (square C
+// whose product is symmetric, e.g. X^T X): only tiles on or above the
+// diagonal are computed, and off-diagonal tiles also write their transpose,
+// so C comes out exactly symmetric for half the work.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -15,7 +18,7 @@ constexpr int GT = 64;  // tile edge
 constexpr int GK = 16;  // k per stage
 constexpr int GLD = GT + 1;
 
-template <int TA, int TB>
+template <int TA, int TB, bool SYM>
 __global__ __launch_bounds__(256) void gemm64_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                      const double *__restrict__ A, int64_t lda,
                                                      int64_t sA, const double *__restrict__ B,
@@ -36,6 +39,8 @@ __global__ __launch_bounds__(256) void gemm64_kernel(int64_t M, int64_t N, int64
     C += z * sC;
     if (C0)
         C0 += z * sC0;
+    if (SYM && blockIdx.x < blockIdx.y)
+        return;
     const int64_t i0 = (int64_t)blockIdx.y * GT, j0 = (int64_t)blockIdx.x * GT;
     const int row0 = (w / 2) * 32, col0 = (w % 2) * 32;
     d4 acc[2][2];
@@ -106,8 +111,35 @@ __global__ __launch_bounds__(256) void gemm64_kernel(int64_t M, int64_t N, int64
                     if (gi == gj)
                         r += gamma;
                     C[gi * ldc + gj] = r;
+                    if (SYM && blockIdx.x != blockIdx.y)
+                        C[gj * ldc + gi] = r;
                 }
             }
+}
+
+template <bool SYM>
+static hipError_t launch_gemm64_t(int transA, int transB, int64_t M, int64_t N, int64_t K,
+                                  double alpha, const double *A, int64_t lda, int64_t sA,
+                                  const double *B, int64_t ldb, int64_t sB, double beta,
+                                  const double *C0, int64_t ldc0, int64_t sC0, double gamma,
+                                  double *C, int64_t ldc, int64_t sC, int64_t batch, hipStream_t s)
+{
+    if (M <= 0 || N <= 0 || batch <= 0)
+        return hipSuccess;
+    dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT), (unsigned)batch);
+    if (!transA && !transB)
+        hipLaunchKernelGGL((gemm64_kernel<0, 0, SYM>), grid, dim3(256), 0, s, M, N, K, alpha, A,
+                           lda, sA, B, ldb, sB, beta, C0, ldc0, sC0, gamma, C, ldc, sC);
+    else if (transA && !transB)
+        hipLaunchKernelGGL((gemm64_kernel<1, 0, SYM>), grid, dim3(256), 0, s, M, N, K, alpha, A,
+                           lda, sA, B, ldb, sB, beta, C0, ldc0, sC0, gamma, C, ldc, sC);
+    else if (!transA && transB)
+        hipLaunchKernelGGL((gemm64_kernel<0, 1, SYM>), grid, dim3(256), 0, s, M, N, K, alpha, A,
+                           lda, sA, B, ldb, sB, beta, C0, ldc0, sC0, gamma, C, ldc, sC);
+    else
+        hipLaunchKernelGGL((gemm64_kernel<1, 1, SYM>), grid, dim3(256), 0, s, M, N, K, alpha, A,
+                           lda, sA, B, ldb, sB, beta, C0, ldc0, sC0, gamma, C, ldc, sC);
+    return hipGetLastError();
 }
 
 hipError_t launch_gemm64(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha,
@@ -116,22 +148,17 @@ hipError_t launch_gemm64(int transA, int transB, int64_t M, int64_t N, int64_t K
                          double gamma, double *C, int64_t ldc, int64_t sC, int64_t batch,
                          hipStream_t s)
 {
-    if (M <= 0 || N <= 0 || batch <= 0)
-        return hipSuccess;
-    dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT), (unsigned)batch);
-    if (!transA && !transB)
-        hipLaunchKernelGGL((gemm64_kernel<0, 0>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
-                           sA, B, ldb, sB, beta, C0, ldc0, sC0, gamma, C, ldc, sC);
-    else if (transA && !transB)
-        hipLaunchKernelGGL((gemm64_kernel<1, 0>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
-                           sA, B, ldb, sB, beta, C0, ldc0, sC0, gamma, C, ldc, sC);
-    else if (!transA && transB)
-        hipLaunchKernelGGL((gemm64_kernel<0, 1>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
-                           sA, B, ldb, sB, beta, C0, ldc0, sC0, gamma, C, ldc, sC);
-    else
-        hipLaunchKernelGGL((gemm64_kernel<1, 1>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
-                           sA, B, ldb, sB, beta, C0, ldc0, sC0, gamma, C, ldc, sC);
-    return hipGetLastError();
+    return launch_gemm64_t<false>(transA, transB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta,
+                                  C0, ldc0, sC0, gamma, C, ldc, sC, batch, s);
+}
+
+hipError_t launch_gemm64_sym(int transA, int transB, int64_t N, int64_t K, double alpha,
+                             const double *A, int64_t lda, const double *B, int64_t ldb,
+                             double beta, const double *C0, int64_t ldc0, double gamma, double *C,
+                             int64_t ldc, hipStream_t s)
+{
+    return launch_gemm64_t<true>(transA, transB, N, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C0,
+                                 ldc0, 0, gamma, C, ldc, 0, 1, s);
 }
 
 __global__ __launch_bounds__(256) void sq_partial_kernel(const double *__restrict__ X,
