@@ -117,6 +117,219 @@ __global__ __launch_bounds__(256) void gemm64_kernel(int64_t M, int64_t N, int64
             }
 }
 
+// Large-matrix variant: workgroup tile 128 x 128 (4 waves, each 64 x 64 =
+// 4 x 4 MFMA tiles), K staged 16 at a time through two LDS buffers (the next
+// stage's operands are loaded into registers while the current one
+// multiplies: one barrier per stage), 16-byte global loads.  LDS rows hold
+// 128 + 16 doubles: the four k rows a wavefront reads at once then start
+// 128 bytes apart and fall in different banks.  Requires even leading
+// dimensions and 16-byte aligned bases; edges are zero-filled and masked.
+constexpr int BT = 128, BK = 16, BLD = BT + 16;
+typedef double dv2g __attribute__((ext_vector_type(2)));
+
+template <int TA, int TB, bool SYM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void gemm128_kernel(int64_t M, int64_t N, int64_t K,
+                                                      double alpha,
+                                                      const double *__restrict__ A, int64_t lda,
+                                                      const double *__restrict__ B, int64_t ldb,
+                                                      double beta,
+                                                      const double *__restrict__ C0,
+                                                      int64_t ldc0, double gamma,
+                                                      double *__restrict__ C, int64_t ldc,
+                                                      int tiles_n)
+{
+    __shared__ __align__(16) double sm[2][2][BK * BLD]; // [buffer][A or B][k][i or j]
+    const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+    const int li = lane % 16, lk = lane / 16;
+    int by, bx;
+    if (SYM) { // linear index -> upper-triangular tile (by <= bx)
+        int t = blockIdx.x, r = 0;
+        while (t >= tiles_n - r) {
+            t -= tiles_n - r;
+            ++r;
+        }
+        by = r;
+        bx = r + t;
+    } else {
+        by = blockIdx.y;
+        bx = blockIdx.x;
+    }
+    const int64_t i0 = (int64_t)by * BT, j0 = (int64_t)bx * BT;
+    const int row0 = (w / 2) * 64, col0 = (w % 2) * 64;
+    // operand staging: 2048 doubles per matrix and stage = 8 per thread as
+    // four 16-byte pieces
+    // source [row][k] (A, or B^T when TB): thread -> row t/2, k 8 (t&1) .. +7
+    // source [k][col] (A^T when TA, or B): thread -> k t/16, col 8 (t%16) .. +7
+    dv2g ra[4], rb[4];
+    auto load = [&](int64_t k0) __attribute__((always_inline)) {
+        if (!TA) {
+            const int64_t gi = i0 + tid / 2, gk = k0 + 8 * (tid & 1);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t k = gk + 2 * e;
+                dv2g v = {0.0, 0.0};
+                if (gi < M && k + 1 < K)
+                    v = *reinterpret_cast<const dv2g *>(A + gi * lda + k);
+                else if (gi < M && k < K)
+                    v[0] = A[gi * lda + k];
+                ra[e] = v;
+            }
+        } else {
+            const int64_t gk = k0 + tid / 16, gi = i0 + 8 * (tid % 16);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t i = gi + 2 * e;
+                dv2g v = {0.0, 0.0};
+                if (gk < K && i + 1 < M)
+                    v = *reinterpret_cast<const dv2g *>(A + gk * lda + i);
+                else if (gk < K && i < M)
+                    v[0] = A[gk * lda + i];
+                ra[e] = v;
+            }
+        }
+        if (TB) {
+            const int64_t gj = j0 + tid / 2, gk = k0 + 8 * (tid & 1);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t k = gk + 2 * e;
+                dv2g v = {0.0, 0.0};
+                if (gj < N && k + 1 < K)
+                    v = *reinterpret_cast<const dv2g *>(B + gj * ldb + k);
+                else if (gj < N && k < K)
+                    v[0] = B[gj * ldb + k];
+                rb[e] = v;
+            }
+        } else {
+            const int64_t gk = k0 + tid / 16, gj = j0 + 8 * (tid % 16);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t j = gj + 2 * e;
+                dv2g v = {0.0, 0.0};
+                if (gk < K && j + 1 < N)
+                    v = *reinterpret_cast<const dv2g *>(B + gk * ldb + j);
+                else if (gk < K && j < N)
+                    v[0] = B[gk * ldb + j];
+                rb[e] = v;
+            }
+        }
+    };
+    auto store = [&](int buf) __attribute__((always_inline)) {
+        double *As = sm[buf][0], *Bs = sm[buf][1];
+        if (!TA) {
+            const int i = tid / 2, kk = 8 * (tid & 1);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                As[(kk + 2 * e) * BLD + i] = ra[e][0];
+                As[(kk + 2 * e + 1) * BLD + i] = ra[e][1];
+            }
+        } else {
+            const int kk = tid / 16, i = 8 * (tid % 16);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                *reinterpret_cast<dv2g *>(As + kk * BLD + i + 2 * e) = ra[e];
+        }
+        if (TB) {
+            const int j = tid / 2, kk = 8 * (tid & 1);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                Bs[(kk + 2 * e) * BLD + j] = rb[e][0];
+                Bs[(kk + 2 * e + 1) * BLD + j] = rb[e][1];
+            }
+        } else {
+            const int kk = tid / 16, j = 8 * (tid % 16);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                *reinterpret_cast<dv2g *>(Bs + kk * BLD + j + 2 * e) = rb[e];
+        }
+    };
+    d4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                acc[a][b][v] = 0.0;
+    const int nst = (int)((K + BK - 1) / BK);
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nst)
+            load((int64_t)(st + 1) * BK);
+        const double *As = sm[buf][0], *Bs = sm[buf][1];
+#pragma unroll
+        for (int kb = 0; kb < BK; kb += 4) {
+            const int kk = kb + lk;
+            double fa[4], fb[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                fa[t] = As[kk * BLD + row0 + 16 * t + li];
+                fb[t] = Bs[kk * BLD + col0 + 16 * t + li];
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = mfma16(fa[a], fb[b], acc[a][b]);
+        }
+        if (st + 1 < nst)
+            store(buf ^ 1); // the other buffer was last read before the previous barrier
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t gi = i0 + row0 + a * 16 + acc_row<double>(lk, v);
+                const int64_t gj = j0 + col0 + b * 16 + li;
+                if (gi < M && gj < N) {
+                    double r = alpha * acc[a][b][v];
+                    if (beta != 0.0)
+                        r += beta * C0[gi * ldc0 + gj];
+                    if (gi == gj)
+                        r += gamma;
+                    C[gi * ldc + gj] = r;
+                    if (SYM && bx != by)
+                        C[gj * ldc + gi] = r;
+                }
+            }
+}
+
+template <bool SYM>
+static bool gemm128_fits(int64_t M, int64_t N, const double *A, int64_t lda, const double *B,
+                         int64_t ldb)
+{
+    return M >= BT && N >= BT && lda % 2 == 0 && ldb % 2 == 0 &&
+           (reinterpret_cast<uintptr_t>(A) % 16) == 0 && (reinterpret_cast<uintptr_t>(B) % 16) == 0;
+}
+
+template <bool SYM>
+static hipError_t launch_gemm128(int transA, int transB, int64_t M, int64_t N, int64_t K,
+                                 double alpha, const double *A, int64_t lda, const double *B,
+                                 int64_t ldb, double beta, const double *C0, int64_t ldc0,
+                                 double gamma, double *C, int64_t ldc, hipStream_t s)
+{
+    const int tn = (int)((N + BT - 1) / BT), tm = (int)((M + BT - 1) / BT);
+    dim3 grid = SYM ? dim3((unsigned)(tn * (tn + 1) / 2)) : dim3((unsigned)tn, (unsigned)tm);
+#define LJ_G128(TA_, TB_)                                                                          \
+    hipLaunchKernelGGL((gemm128_kernel<TA_, TB_, SYM>), grid, dim3(256), 0, s, M, N, K, alpha, A,  \
+                       lda, B, ldb, beta, C0, ldc0, gamma, C, ldc, tn)
+    if (!transA && !transB)
+        LJ_G128(0, 0);
+    else if (transA && !transB)
+        LJ_G128(1, 0);
+    else if (!transA && transB)
+        LJ_G128(0, 1);
+    else
+        LJ_G128(1, 1);
+#undef LJ_G128
+    return hipGetLastError();
+}
+
 template <bool SYM>
 static hipError_t launch_gemm64_t(int transA, int transB, int64_t M, int64_t N, int64_t K,
                                   double alpha, const double *A, int64_t lda, int64_t sA,
@@ -126,6 +339,9 @@ static hipError_t launch_gemm64_t(int transA, int transB, int64_t M, int64_t N, 
 {
     if (M <= 0 || N <= 0 || batch <= 0)
         return hipSuccess;
+    if (batch == 1 && gemm128_fits<SYM>(M, N, A, lda, B, ldb))
+        return launch_gemm128<SYM>(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C0,
+                                   ldc0, gamma, C, ldc, s);
     dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT), (unsigned)batch);
     if (!transA && !transB)
         hipLaunchKernelGGL((gemm64_kernel<0, 0, SYM>), grid, dim3(256), 0, s, M, N, K, alpha, A,
