@@ -58,7 +58,8 @@ typedef struct jacobi_opts {
                                Algorithm 8 (2 for n < 52 000, else 3); -1 =
                                adaptive as Algorithm 7 (stop once
                                ||I - X^T X||_F <= n u_d, at most 3); > 0 fixed */
-    double c32;             /* FP32 stage stops at off <= c32 n u_l ||A||_F; default 1 */
+    double c32;             /* FP32 stage stops at off <= c32 n u_l ||A||_F (or when a
+                               sweep no longer lowers off); default 0.1 */
     int32_t check_symmetry; /* nonzero: return JACOBI_NOTSYM unless A == A^T exactly */
     int32_t small_max_n;    /* n up to which one workgroup solves the whole matrix;
                                default 128, 0 keeps the default, -1 forces the block path */
