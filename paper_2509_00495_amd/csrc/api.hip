@@ -176,7 +176,8 @@ struct BlockWs {
 
 size_t partial_count(const Geometry &g)
 {
-    size_t c = (size_t)g.npairs + (size_t)g.nbt * (g.M / 16); // pair solve + update of B
+    // pair solve (one per wavefront) + update of B (one per wavefront and tile)
+    size_t c = (size_t)g.npairs * pair_solve_waves(g.M) + (size_t)g.nbt * (g.M / 16);
     c = std::max(c, (size_t)INGEST_BLOCKS);
     c = std::max(c, (size_t)OFF_BLOCKS);
     return c;
@@ -439,7 +440,8 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
                 CK(hipEventRecord(ss.evU[j], s));
             if (timed)
                 CK(hipEventRecord(tm->ev[6 * r + 2], s));
-            CK(launch_update_b<T>(B, g.npad, g.b, pr, Ub, w.btiles, g.nbt, w.partial + g.npairs,
+            CK(launch_update_b<T>(B, g.npad, g.b, pr, Ub, w.btiles, g.nbt,
+                                  w.partial + (size_t)g.npairs * pair_solve_waves(g.M),
                                   r == g.N - 2, s));
             if (timed)
                 CK(hipEventRecord(tm->ev[6 * r + 3], s));
@@ -454,10 +456,11 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
             if (side)
                 CK(hipEventRecord(ss.evV[j], ss.s2));
         }
-        // partials: one per pair, then per B tile (one per wavefront of the FP32
-        // update, one per tile of the FP64 one)
-        CK(launch_sum(w.partial, (int64_t)g.npairs + (int64_t)g.nbt * (g.M / 16), w.scal + 1,
-                      s));
+        // partials: one per wavefront of each pair solve, then one per
+        // wavefront of each B tile
+        CK(launch_sum(w.partial,
+                      (int64_t)g.npairs * pair_solve_waves(g.M) + (int64_t)g.nbt * (g.M / 16),
+                      w.scal + 1, s));
         if (int e = read_scalars(w, s, rb))
             return e;
         if (timed) {

@@ -33,6 +33,8 @@ template <typename T>
 hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                              const int2 *psmap, T *U, double eps, double thr, int inner,
                              int cross, double *partial, int *rot_flag, hipStream_t s);
+// wavefronts of the pair-solve workgroup for 2b = M (one off^2 partial each)
+constexpr int pair_solve_waves(int M) { return M == 64 ? 16 : 4; }
 // thread -> block map of the pair solve (b(b+1)/2 entries for M = 2b)
 void pair_solve_map(int M, int cross, int2 *out);
 // which = 1: B tiles only, 2: V tiles only, 3: both

@@ -102,7 +102,8 @@ __device__ inline int pair_record(PairRec<T> &R, int k, T app, T aqq, T apq, dou
 // One workgroup per block pair (P, Q) of the round.  The 2b x 2b tile S (upper
 // triangle only, logical order) and its accumulated rotation U (stored
 // transposed, Ut[j][i] = U[i][j], so a column pair of U is two LDS rows that
-// are read and written 16 bytes at a time) are updated in place.  In inner
+// are read and written 16 bytes at a time) are updated in place.  U leaves
+// the kernel transposed as well: U_out[pair][j][i] = U[i][j].  In inner
 // round r the M/2 disjoint pairs are those of the circle schedule on M = 2b
 // indices, (player(slot k), player(slot M-1-k)); every thread carries the
 // current players of the pairs it works on from round to round.  A thread
@@ -142,20 +143,36 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
     unsigned char *recbase = smem_raw + align8(sizeof(T) * (M * ldu + M * ld));
     recbase = (unsigned char *)(((uintptr_t)recbase + 15) & ~(uintptr_t)15);
     constexpr size_t RB = PairRec<T>::bytes(h);
-    double *red = (double *)(recbase + 2 * RB);
-    int *ired = (int *)(red + 16);
     const int tid = threadIdx.x;
     const int pk = blockIdx.x;
     const int2 pq = pairs[pk];
     auto sidx = [](int i, int j) { return i <= j ? i * ld + j : j * ld + i; };
-    for (int idx = tid; idx < M * M; idx += NT) {
-        const int i = idx / M, j = idx % M;
-        if (i <= j) {
-            const int64_t gi = i < b ? (int64_t)pq.x * b + i : (int64_t)pq.y * b + (i - b);
-            const int64_t gj = j < b ? (int64_t)pq.x * b + j : (int64_t)pq.y * b + (j - b);
-            S[i * ld + j] = B[gi * ldb + gj];
+    auto gpos = [&](int i) { return i < b ? (int64_t)pq.x * b + i : (int64_t)pq.y * b + (i - b); };
+    // the tile as 16-byte row pieces (all loads issued before the LDS writes);
+    // S gets full rows (only its upper triangle is read), Ut the identity
+    constexpr int RV = M / VN, PV = (M * RV + NT - 1) / NT;
+    TV xin[PV];
+#pragma unroll
+    for (int e = 0; e < PV; ++e) {
+        const int v = tid + e * NT;
+        if (v < M * RV)
+            xin[e] = *reinterpret_cast<const TV *>(B + gpos(v / RV) * ldb + gpos((v % RV) * VN));
+    }
+#pragma unroll
+    for (int e = 0; e < PV; ++e) {
+        const int v = tid + e * NT;
+        if (v < M * RV) {
+            const int i = v / RV, j = (v % RV) * VN;
+            const T *xe = reinterpret_cast<const T *>(&xin[e]);
+            TV id;
+            T *ie = reinterpret_cast<T *>(&id);
+#pragma unroll
+            for (int q = 0; q < VN; ++q) {
+                S[i * ld + j + q] = xe[q];
+                ie[q] = (T)(i == j + q ? 1 : 0);
+            }
+            *reinterpret_cast<TV *>(Ut + i * ldu + j) = id;
         }
-        Ut[i * ldu + j] = (T)(i == j ? 1 : 0);
     }
     constexpr int NBLK = h * (h + 1) / 2;
     int bk = -1, bl = -1;
@@ -262,24 +279,23 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
             if (tid >= WAVE && it < NU) {
                 const int k = it / CH, c = it % CH;
                 const typename PairRec<T>::T2 cs = A.cs[k];
-                if (cs.y != (T)0) {
-                    TV *r0 = (TV *)(Ut + up0[j] * ldu) + c;
-                    TV *r1 = (TV *)(Ut + up1[j] * ldu) + c;
-                    const TV u0 = *r0, u1 = *r1;
-                    TV n0, n1;
-                    n0.x = cs.x * u0.x - cs.y * u1.x;
-                    n1.x = cs.y * u0.x + cs.x * u1.x;
-                    n0.y = cs.x * u0.y - cs.y * u1.y;
-                    n1.y = cs.y * u0.y + cs.x * u1.y;
-                    if constexpr (VN == 4) {
-                        n0.z = cs.x * u0.z - cs.y * u1.z;
-                        n1.z = cs.y * u0.z + cs.x * u1.z;
-                        n0.w = cs.x * u0.w - cs.y * u1.w;
-                        n1.w = cs.y * u0.w + cs.x * u1.w;
-                    }
-                    *r0 = n0;
-                    *r1 = n1;
+                // no skip for s = 0: a uniform path (the update is then exact)
+                TV *r0 = (TV *)(Ut + up0[j] * ldu) + c;
+                TV *r1 = (TV *)(Ut + up1[j] * ldu) + c;
+                const TV u0 = *r0, u1 = *r1;
+                TV n0, n1;
+                n0.x = cs.x * u0.x - cs.y * u1.x;
+                n1.x = cs.y * u0.x + cs.x * u1.x;
+                n0.y = cs.x * u0.y - cs.y * u1.y;
+                n1.y = cs.y * u0.y + cs.x * u1.y;
+                if constexpr (VN == 4) {
+                    n0.z = cs.x * u0.z - cs.y * u1.z;
+                    n1.z = cs.y * u0.z + cs.x * u1.z;
+                    n0.w = cs.x * u0.w - cs.y * u1.w;
+                    n1.w = cs.y * u0.w + cs.x * u1.w;
                 }
+                *r0 = n0;
+                *r1 = n1;
                 if (CROSS) {
                     up1[j] = cnext(up1[j]);
                 } else {
@@ -299,25 +315,34 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
         }
         __syncthreads();
     }
+    // write-back in 16-byte pieces: the tile (both triangles from the upper
+    // one) and U^T (Ut as it is, row i = column i of U), plus the squared
+    // off-diagonal sum per wavefront and the rotation flag
     T *Uk = U + (int64_t)pk * M * M;
     double acc = 0.0;
-    for (int idx = tid; idx < M * M; idx += NT) {
-        const int i = idx / M, j = idx % M;
-        const int64_t gi = i < b ? (int64_t)pq.x * b + i : (int64_t)pq.y * b + (i - b);
-        const int64_t gj = j < b ? (int64_t)pq.x * b + j : (int64_t)pq.y * b + (j - b);
-        const T v = S[sidx(i, j)];
-        B[gi * ldb + gj] = v;
-        Uk[idx] = Ut[j * ldu + i];
-        if (i != j)
-            acc += (double)v * (double)v;
+#pragma unroll
+    for (int e = 0; e < PV; ++e) {
+        const int v = tid + e * NT;
+        if (v < M * RV) {
+            const int i = v / RV, j = (v % RV) * VN;
+            TV x;
+            T *xe = reinterpret_cast<T *>(&x);
+#pragma unroll
+            for (int q = 0; q < VN; ++q) {
+                xe[q] = S[sidx(i, j + q)];
+                if (i != j + q)
+                    acc += (double)xe[q] * (double)xe[q];
+            }
+            *reinterpret_cast<TV *>(B + gpos(i) * ldb + gpos(j)) = x;
+            *reinterpret_cast<TV *>(Uk + i * M + j) = *reinterpret_cast<const TV *>(Ut + i * ldu + j);
+        }
     }
-    const double off2 = block_sum<NT>(acc, red);
-    int any = block_or<NT>(rot, ired);
-    if (tid == 0) {
-        partial[pk] = off2;
-        if (any)
-            atomicOr(rot_flag, 1);
-    }
+    acc = wave_sum(acc);
+    const int lane = tid % WAVE;
+    if (lane == 0)
+        partial[(int64_t)pk * (NT / WAVE) + tid / WAVE] = acc;
+    if (__any(rot) && lane == 0)
+        atomicOr(rot_flag, 1);
 }
 
 template <typename T, int M, int NT, bool CROSS>
@@ -751,8 +776,10 @@ template hipError_t launch_pair_solve<float>(float *, int64_t, int, int, const i
                                              double *, int *, hipStream_t);
 
 // Thread -> 2x2 block map of the pair solve for M = 2b positions: entry t < M/2
-// is the block hosting pair t of the next round, the rest follow in row order.
-// cross != 0 gives the map of the cross schedule.
+// is the block hosting pair t of the next round, then the M/2 diagonal blocks
+// (k, k) (so that their different code path stays inside the first
+// wavefronts), then the rest in row order.  cross != 0 gives the map of the
+// cross schedule.
 void pair_solve_map(int M, int cross, int2 *out)
 {
     const int h = M / 2;
@@ -762,7 +789,9 @@ void pair_solve_map(int M, int cross, int2 *out)
             out[cnt++] = make_int2(t, t + 1);
         out[cnt++] = make_int2(0, h - 1);
         for (int k = 0; k < h; ++k)
-            for (int l = k; l < h; ++l)
+            out[cnt++] = make_int2(k, k);
+        for (int k = 0; k < h; ++k)
+            for (int l = k + 1; l < h; ++l)
                 if (!(l == k + 1 || (k == 0 && l == h - 1)))
                     out[cnt++] = make_int2(k, l);
         return;
@@ -779,7 +808,9 @@ void pair_solve_map(int M, int cross, int2 *out)
         used[k][l] = true;
     }
     for (int k = 0; k < h; ++k)
-        for (int l = k; l < h; ++l)
+        out[cnt++] = make_int2(k, k);
+    for (int k = 0; k < h; ++k)
+        for (int l = k + 1; l < h; ++l)
             if (!used[k][l])
                 out[cnt++] = make_int2(k, l);
 }

@@ -10,7 +10,8 @@
 //     its MFMA step.  The k order inside a step is free, so step (g, j) gives
 //     lane lk the k = g*4*VK + lk*VK + j: one 16-byte load of VK consecutive
 //     columns of row li feeds VK steps;
-//   * the A operand, U_l^T, is loaded once per wavefront into registers;
+//   * the A operand, U_l^T, is loaded once per wavefront into registers (the
+//     U blocks are stored transposed, so these are 16-byte loads);
 //   * the accumulator of a 16-column tile holds, per lane, the four entries
 //     D[r][li] with r = acc_row(lk, v).  Column 16 tc + m of the MFMA output
 //     is mapped to output column 16 tc + out_perm(m), chosen so that the four
@@ -89,15 +90,20 @@ __global__ __launch_bounds__(256) void update_v_kernel(T *__restrict__ V, int64_
     if (t0 >= t1)
         return;
     const int2 pl = pairs[l];
-    const T *Ul = U + (int64_t)l * M * M;
+    // U blocks are stored transposed (Ut[j][i] = U[i][j]): the VK fragments of
+    // a step group are consecutive, one 16-byte load
+    const T *Ult = U + (int64_t)l * M * M;
     T uf[TC][KG][VK];
 #pragma unroll
     for (int tc = 0; tc < TC; ++tc)
 #pragma unroll
-        for (int g = 0; g < KG; ++g)
+        for (int g = 0; g < KG; ++g) {
+            const TV u = *reinterpret_cast<const TV *>(Ult + (16 * tc + out_perm<T>(li)) * M +
+                                                       g * 4 * VK + lk * VK);
 #pragma unroll
             for (int j = 0; j < VK; ++j)
-                uf[tc][g][j] = Ul[(g * 4 * VK + lk * VK + j) * M + 16 * tc + out_perm<T>(li)];
+                uf[tc][g][j] = vlane<T>(u, j);
+        }
     int kc[KG], oc[TC];
 #pragma unroll
     for (int g = 0; g < KG; ++g)
@@ -212,11 +218,11 @@ __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int6
     // ufl[((f HV + h) 64 + lane) VK + j] = U_l[16 tc + acc_row(lk, v)][16 tj + out_perm(li)]
     // with f = tj TC + tc and v = h VK + j: fragment v of lane for step (tc, v)
     auto fill_ufl = [&](int l) __attribute__((always_inline)) {
-        const T *Ul = U + (int64_t)l * M * M;
+        const T *Ult = U + (int64_t)l * M * M; // transposed: Ult[j][i] = U_l[i][j]
         for (int e = tid; e < M * M; e += NT) {
             const int j = e % VK, ln = (e / VK) % WAVE, r = e / (VK * WAVE);
             const int v = (r % HV) * VK + j, f = r / HV, tc = f % TC, tj = f / TC;
-            ufl[e] = Ul[(16 * tc + acc_row<T>(ln / 16, v)) * M + 16 * tj + out_perm<T>(ln % 16)];
+            ufl[e] = Ult[(16 * tj + out_perm<T>(ln % 16)) * M + 16 * tc + acc_row<T>(ln / 16, v)];
         }
     };
     TV xr[PERV];
@@ -230,12 +236,15 @@ __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int6
             xr[e] = *reinterpret_cast<const TV *>(B + (int64_t)pair_col(pl, c, b) * ldb +
                                                   pair_col(pk, q * VK, b));
         }
-        const T *Uk = U + (int64_t)kl.x * M * M;
+        const T *Ukt = U + (int64_t)kl.x * M * M; // transposed: Ukt[j][i] = U_k[i][j]
 #pragma unroll
-        for (int g = 0; g < KG; ++g)
+        for (int g = 0; g < KG; ++g) {
+            const TV u = *reinterpret_cast<const TV *>(Ukt + (16 * w + li) * M + g * 4 * VK +
+                                                       lk * VK);
 #pragma unroll
             for (int j = 0; j < VK; ++j)
-                ukn[g * VK + j] = Uk[(g * 4 * VK + lk * VK + j) * M + 16 * w + li];
+                ukn[g * VK + j] = vlane<T>(u, j);
+        }
     };
     int cur_l = -1;
     auto body = [&](int t) __attribute__((always_inline)) {
