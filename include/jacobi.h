@@ -74,9 +74,12 @@ typedef struct jacobi_opts {
                                its 2b x 2b tiles, the others only pairs that
                                join the two blocks of a tile; 1 = all pairs of
                                every tile in every round */
-    int32_t serial_v;       /* nonzero: update the eigenvectors of a round on `stream`
-                               after its B update; default (0): on a second,
-                               library-owned stream beside the next round */
+    int32_t serial_v;       /* where the eigenvector update of a round runs:
+                               0 (default) = by precision: FP32 rounds on
+                               `stream` after their B update, FP64 rounds on a
+                               second, library-owned stream beside the next
+                               round; 1 = always on `stream`; 2 = always on
+                               the second stream; other values are rejected */
     int32_t reserved[2];
 } jacobi_opts;
 

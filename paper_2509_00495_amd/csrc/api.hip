@@ -67,7 +67,9 @@ int resolve_opts(const jacobi_opts *o, Opts &r)
     if (o->schedule < 0 || o->schedule > 1)
         return 1;
     r.schedule = o->schedule;
-    r.serial_v = o->serial_v != 0;
+    if (o->serial_v < 0 || o->serial_v > 2)
+        return 1;
+    r.serial_v = o->serial_v;
     if (o->max_sweeps < 0 || o->max_sweeps > 1000)
         return 1;
     if (o->max_sweeps)
@@ -362,7 +364,9 @@ struct RoundTimer {
 struct SideStream {
     hipStream_t s2 = nullptr;
     hipEvent_t evU[2] = {nullptr, nullptr}, evV[2] = {nullptr, nullptr};
-    int64_t round = 0; // rounds issued so far (across stages)
+    bool recV[2] = {false, false}; // evV[j] recorded at least once (a stage on
+                                   // one stream records none)
+    int64_t round = 0;             // rounds issued so far (across stages)
     int init()
     {
         CK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
@@ -413,8 +417,12 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
     // Overlapped mode: the V update of round r runs on the side stream beside
     // round r + 1's pair solve and B update (it needs only U_r).  U is
     // double-buffered, and the pair solve of round r + 2, which overwrites
-    // U_r's buffer, waits for that V update.
-    const bool side = !serial_v;
+    // U_r's buffer, waits for that V update.  Each cross-stream event adds a
+    // gap of several microseconds between the kernels around it, and the FP32
+    // pair solve runs slower beside an FP32 V update, so by default the FP32
+    // stage keeps everything on one stream and only the FP64 stage (whose
+    // V update is twice as long) overlaps.
+    const bool side = serial_v == 2 || (serial_v == 0 && !fp32_stage);
     while (off > tol) {
         if (sweeps >= max_sweeps) {
             status = JACOBI_NOCONV;
@@ -426,7 +434,7 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
             const int j = (int)(ss.round & 1);
             T *Ub = U + j * ustride;
             const int2 *pr = w.pairs + (size_t)r * g.npairs;
-            if (side && ss.round >= 2)
+            if (side && ss.recV[j])
                 CK(hipStreamWaitEvent(s, ss.evV[j], 0));
             if (timed)
                 CK(hipEventRecord(tm->ev[6 * r], s));
@@ -453,8 +461,10 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
             CK(launch_update_v<T>(V, g.npad, g.npad, g.b, g.npairs, pr, Ub, sv));
             if (timed)
                 CK(hipEventRecord(tm->ev[6 * r + 5], sv));
-            if (side)
+            if (side) {
                 CK(hipEventRecord(ss.evV[j], ss.s2));
+                ss.recV[j] = true;
+            }
         }
         // partials: one per wavefront of each pair solve, then one per
         // wavefront of each B tile
@@ -484,7 +494,7 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
             break;
     }
     // V is complete on the caller's stream from here on
-    if (side && ss.round > 0)
+    if (side && ss.round > 0 && ss.recV[(ss.round - 1) & 1])
         CK(hipStreamWaitEvent(s, ss.evV[(ss.round - 1) & 1], 0));
     *sweeps_out = sweeps;
     *off_out = off;

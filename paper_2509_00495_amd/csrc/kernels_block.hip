@@ -140,8 +140,10 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *Ut = (T *)smem_raw;                  // M x ldu
     T *S = Ut + M * ldu;                    // M x ld, entries i <= j
-    unsigned char *recbase = smem_raw + align8(sizeof(T) * (M * ldu + M * ld));
-    recbase = (unsigned char *)(((uintptr_t)recbase + 15) & ~(uintptr_t)15);
+    // a constant offset keeps the records in the LDS address space (an
+    // integer round trip of the pointer would turn every access into a flat one)
+    constexpr size_t REC_OFF = (sizeof(T) * (M * ldu + M * ld) + 15) & ~(size_t)15;
+    unsigned char *recbase = smem_raw + REC_OFF;
     constexpr size_t RB = PairRec<T>::bytes(h);
     const int tid = threadIdx.x;
     const int pk = blockIdx.x;

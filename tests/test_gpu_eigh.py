@@ -101,14 +101,16 @@ def test_block_path_circle_schedule(pj, n, block):
     check(A, W, V, Wo, Vo, f"circle b={block}")
 
 
+@pytest.mark.parametrize("serial_v", [1, 2])
 @pytest.mark.parametrize("fn", ["eigh", "eigh_mixed"])
-def test_block_path_serial_v(pj, fn):
-    """serial_v=1: the eigenvector update on the caller's stream."""
+def test_block_path_serial_v(pj, fn, serial_v):
+    """serial_v=1: every eigenvector update on the caller's stream; 2: every
+    one on the second stream (the default splits by precision)."""
     A = wl.random_symmetric(260, 2600)
-    W, V, info = run(pj, fn, A, small_max_n=-1, block=32, serial_v=1)
+    W, V, info = run(pj, fn, A, small_max_n=-1, block=32, serial_v=serial_v)
     assert info["path"] == 1 and info["status"] == 0
     Wo, Vo, *_ = oracle.eigh(A)
-    check(A, W, V, Wo, Vo, f"serial_v {fn}")
+    check(A, W, V, Wo, Vo, f"serial_v={serial_v} {fn}")
 
 
 @pytest.mark.parametrize("n,block,inner", [(128, 16, 2), (192, 32, 3)])
