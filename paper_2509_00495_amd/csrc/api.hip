@@ -423,6 +423,14 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
     // stage keeps everything on one stream and only the FP64 stage (whose
     // V update is twice as long) overlaps.
     const bool side = serial_v == 2 || (serial_v == 0 && !fp32_stage);
+    // One-stream FP32 default: the V update of round r rides in the launch of
+    // round r + 1's pair solves, on the compute units they leave free (the
+    // pair solves are latency-bound and use one unit per block pair).  The
+    // last round's V update is launched on its own after the sweeps.  Not
+    // with per-launch timing, which times the kernels one by one.
+    const bool fuse = !side && serial_v == 0 && !(tm && tm->on);
+    const int2 *vpend_pairs = nullptr; // V update waiting for the next launch
+    const T *vpend_U = nullptr;
     while (off > tol) {
         if (sweeps >= max_sweeps) {
             status = JACOBI_NOCONV;
@@ -440,8 +448,15 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
                 CK(hipEventRecord(tm->ev[6 * r], s));
             const int cross = schedule == 0 && r > 0;
             const int2 *map = w.psmap + (cross ? (size_t)g.b * (g.b + 1) / 2 : 0);
-            CK(launch_pair_solve<T>(B, g.npad, g.b, g.npairs, pr, map, Ub, eps, thr, inner,
-                                    cross, w.partial, w.flags + 2, s));
+            if (vpend_pairs) {
+                CK(launch_pair_solve_v<T>(B, g.npad, g.b, g.npairs, pr, map, Ub, eps, thr, inner,
+                                          cross, w.partial, w.flags + 2, V, g.npad, g.npad,
+                                          vpend_pairs, vpend_U, s));
+                vpend_pairs = nullptr;
+            } else {
+                CK(launch_pair_solve<T>(B, g.npad, g.b, g.npairs, pr, map, Ub, eps, thr, inner,
+                                        cross, w.partial, w.flags + 2, s));
+            }
             if (timed)
                 CK(hipEventRecord(tm->ev[6 * r + 1], s));
             if (side)
@@ -453,6 +468,11 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
                                   r == g.N - 2, s));
             if (timed)
                 CK(hipEventRecord(tm->ev[6 * r + 3], s));
+            if (fuse) {
+                vpend_pairs = pr;
+                vpend_U = Ub;
+                continue;
+            }
             hipStream_t sv = side ? ss.s2 : s;
             if (side)
                 CK(hipStreamWaitEvent(ss.s2, ss.evU[j], 0));
@@ -493,6 +513,8 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
         if (fp32_stage && off >= prev)
             break;
     }
+    if (vpend_pairs)
+        CK(launch_update_v<T>(V, g.npad, g.npad, g.b, g.npairs, vpend_pairs, vpend_U, s));
     // V is complete on the caller's stream from here on
     if (side && ss.round > 0 && ss.recV[(ss.round - 1) & 1])
         CK(hipStreamWaitEvent(s, ss.evV[(ss.round - 1) & 1], 0));

@@ -33,12 +33,23 @@ template <typename T>
 hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                              const int2 *psmap, T *U, double eps, double thr, int inner,
                              int cross, double *partial, int *rot_flag, hipStream_t s);
+// the same pair solves, plus the V update V[:, cols] <- V[:, cols] vU of the
+// previous round (pairs vpairs, rotations vU) on further workgroups of the
+// same launch
+template <typename T>
+hipError_t launch_pair_solve_v(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
+                               const int2 *psmap, T *U, double eps, double thr, int inner,
+                               int cross, double *partial, int *rot_flag, T *V, int64_t ldv,
+                               int64_t nrows, const int2 *vpairs, const T *vU, hipStream_t s);
+// experiments: V workgroups of the shared launch (0 = default) and a minimum
+// dynamic LDS per workgroup (larger keeps one workgroup per compute unit)
+void tune_pair_v(int wgs, size_t lds);
 // wavefronts of the pair-solve workgroup for 2b = M (one off^2 partial each)
 constexpr int pair_solve_waves(int M) { return M == 64 ? 16 : 4; }
 // thread -> block map of the pair solve (b(b+1)/2 entries for M = 2b)
 void pair_solve_map(int M, int cross, int2 *out);
 // which = 1: B tiles only, 2: V tiles only, 3: both
-// B_kl <- U_k^T B_kl U_l (and mirror) for the ntiles tiles (k, l), k < l, of
+// B_kl <- U_k^T B_kl U_l (into B's upper blocks) for the ntiles tiles (k, l), k < l, of
 // the list; partial[(l (l - 1) / 2 + k) (2b / 16) + w] gets twice the squared
 // sum of wavefront w's part of tile (k, l) when want_off (kernels_update.hip)
 template <typename T>

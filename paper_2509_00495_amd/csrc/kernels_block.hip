@@ -15,6 +15,7 @@
 // padding never mixes with the matrix.
 #include "internal.hpp"
 #include "lds_jacobi.hpp"
+#include "update_v.hpp"
 
 namespace lj {
 
@@ -125,13 +126,11 @@ __device__ inline int pair_record(PairRec<T> &R, int k, T app, T aqq, T apq, dou
 // of pair i + 1 (mod b), so block (i, i + 1), or (0, b - 1) for i = b - 1,
 // hosts it.
 template <typename T, int M, int NT, bool CROSS>
-__global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64_t ldb,
-                                                        const int2 *__restrict__ pairs,
-                                                        const int2 *__restrict__ psmap,
-                                                        T *__restrict__ U, double eps,
-                                                        double thr, int inner,
-                                                        double *__restrict__ partial,
-                                                        int *rot_flag)
+__device__ inline void pair_solve_body(T *__restrict__ B, int64_t ldb,
+                                       const int2 *__restrict__ pairs,
+                                       const int2 *__restrict__ psmap, T *__restrict__ U,
+                                       double eps, double thr, int inner,
+                                       double *__restrict__ partial, int *rot_flag, int pk)
 {
     constexpr int b = M / 2, h = M / 2, ld = M + 1;
     typedef typename vec16<T>::type TV;
@@ -146,35 +145,64 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
     unsigned char *recbase = smem_raw + REC_OFF;
     constexpr size_t RB = PairRec<T>::bytes(h);
     const int tid = threadIdx.x;
-    const int pk = blockIdx.x;
     const int2 pq = pairs[pk];
     auto sidx = [](int i, int j) { return i <= j ? i * ld + j : j * ld + i; };
-    auto gpos = [&](int i) { return i < b ? (int64_t)pq.x * b + i : (int64_t)pq.y * b + (i - b); };
-    // the tile as 16-byte row pieces (all loads issued before the LDS writes);
-    // S gets full rows (only its upper triangle is read), Ut the identity
-    constexpr int RV = M / VN, PV = (M * RV + NT - 1) / NT;
+    // B holds only its upper b x b blocks (block row <= block column) during
+    // the sweeps.  The tile is read as three stored blocks: P's and Q's
+    // diagonal blocks and the off-diagonal block in its stored orientation
+    // (rows of min(P, Q), columns of max(P, Q)), each in 16-byte row pieces,
+    // all loads issued before the LDS writes.  S gets the diagonal blocks as
+    // full rows (only their upper triangles are read) and the off-diagonal
+    // block at logical (i < b, j >= b), transposed when P > Q.
+    constexpr int RV = M / VN;            // 16-byte vectors per row of Ut
+    constexpr int BV = b / VN;            // 16-byte vectors per block row
+    constexpr int VPB = b * BV;           // vectors per b x b block
+    constexpr int PV = (3 * VPB + NT - 1) / NT;
+    const bool swapo = pq.x > pq.y;       // off-diagonal block stored as (Q, P)
+    const int64_t orow = (int64_t)(swapo ? pq.y : pq.x) * b, ocol = (int64_t)(swapo ? pq.x : pq.y) * b;
+    // global (row, column) of vector v of stored block s (0: P P, 1: Q Q, 2: off)
+    auto blk_row = [&](int s, int a) {
+        return s == 0 ? (int64_t)pq.x * b + a : (s == 1 ? (int64_t)pq.y * b + a : orow + a);
+    };
+    auto blk_col = [&](int s, int c) {
+        return s == 0 ? (int64_t)pq.x * b + c : (s == 1 ? (int64_t)pq.y * b + c : ocol + c);
+    };
     TV xin[PV];
 #pragma unroll
     for (int e = 0; e < PV; ++e) {
         const int v = tid + e * NT;
-        if (v < M * RV)
-            xin[e] = *reinterpret_cast<const TV *>(B + gpos(v / RV) * ldb + gpos((v % RV) * VN));
+        if (v < 3 * VPB) {
+            const int s = v / VPB, a = (v % VPB) / BV, c = (v % BV) * VN;
+            xin[e] = *reinterpret_cast<const TV *>(B + blk_row(s, a) * ldb + blk_col(s, c));
+        }
     }
 #pragma unroll
     for (int e = 0; e < PV; ++e) {
         const int v = tid + e * NT;
-        if (v < M * RV) {
-            const int i = v / RV, j = (v % RV) * VN;
+        if (v < 3 * VPB) {
+            const int s = v / VPB, a = (v % VPB) / BV, c = (v % BV) * VN;
             const T *xe = reinterpret_cast<const T *>(&xin[e]);
-            TV id;
-            T *ie = reinterpret_cast<T *>(&id);
 #pragma unroll
             for (int q = 0; q < VN; ++q) {
-                S[i * ld + j + q] = xe[q];
-                ie[q] = (T)(i == j + q ? 1 : 0);
+                if (s == 0)
+                    S[a * ld + c + q] = xe[q];
+                else if (s == 1)
+                    S[(b + a) * ld + b + c + q] = xe[q];
+                else if (!swapo)
+                    S[a * ld + b + c + q] = xe[q];
+                else
+                    S[(c + q) * ld + b + a] = xe[q];
             }
-            *reinterpret_cast<TV *>(Ut + i * ldu + j) = id;
         }
+    }
+    for (int v = tid; v < M * RV; v += NT) {
+        const int i = v / RV, j = (v % RV) * VN;
+        TV id;
+        T *ie = reinterpret_cast<T *>(&id);
+#pragma unroll
+        for (int q = 0; q < VN; ++q)
+            ie[q] = (T)(i == j + q ? 1 : 0);
+        *reinterpret_cast<TV *>(Ut + i * ldu + j) = id;
     }
     constexpr int NBLK = h * (h + 1) / 2;
     int bk = -1, bl = -1;
@@ -317,27 +345,41 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
         }
         __syncthreads();
     }
-    // write-back in 16-byte pieces: the tile (both triangles from the upper
-    // one) and U^T (Ut as it is, row i = column i of U), plus the squared
-    // off-diagonal sum per wavefront and the rotation flag
+    // write-back in 16-byte pieces: the three stored blocks of the tile (the
+    // off-diagonal one in its stored orientation) and U^T (Ut as it is, row i
+    // = column i of U), plus the squared off-diagonal sum of the whole tile
+    // (the off-diagonal block counts twice) per wavefront and the rotation flag
     T *Uk = U + (int64_t)pk * M * M;
     double acc = 0.0;
 #pragma unroll
     for (int e = 0; e < PV; ++e) {
         const int v = tid + e * NT;
-        if (v < M * RV) {
-            const int i = v / RV, j = (v % RV) * VN;
+        if (v < 3 * VPB) {
+            const int s = v / VPB, a = (v % VPB) / BV, c = (v % BV) * VN;
             TV x;
             T *xe = reinterpret_cast<T *>(&x);
 #pragma unroll
             for (int q = 0; q < VN; ++q) {
-                xe[q] = S[sidx(i, j + q)];
-                if (i != j + q)
-                    acc += (double)xe[q] * (double)xe[q];
+                if (s == 0)
+                    xe[q] = S[sidx(a, c + q)];
+                else if (s == 1)
+                    xe[q] = S[sidx(b + a, b + c + q)];
+                else if (!swapo)
+                    xe[q] = S[a * ld + b + c + q];
+                else
+                    xe[q] = S[(c + q) * ld + b + a];
+                const double sq = (double)xe[q] * (double)xe[q];
+                if (s == 2)
+                    acc += 2.0 * sq;
+                else if (a != c + q)
+                    acc += sq;
             }
-            *reinterpret_cast<TV *>(B + gpos(i) * ldb + gpos(j)) = x;
-            *reinterpret_cast<TV *>(Uk + i * M + j) = *reinterpret_cast<const TV *>(Ut + i * ldu + j);
+            *reinterpret_cast<TV *>(B + blk_row(s, a) * ldb + blk_col(s, c)) = x;
         }
+    }
+    for (int v = tid; v < M * RV; v += NT) {
+        const int i = v / RV, j = (v % RV) * VN;
+        *reinterpret_cast<TV *>(Uk + i * M + j) = *reinterpret_cast<const TV *>(Ut + i * ldu + j);
     }
     acc = wave_sum(acc);
     const int lane = tid % WAVE;
@@ -345,6 +387,40 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
         partial[(int64_t)pk * (NT / WAVE) + tid / WAVE] = acc;
     if (__any(rot) && lane == 0)
         atomicOr(rot_flag, 1);
+}
+
+template <typename T, int M, int NT, bool CROSS>
+__global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64_t ldb,
+                                                        const int2 *__restrict__ pairs,
+                                                        const int2 *__restrict__ psmap,
+                                                        T *__restrict__ U, double eps,
+                                                        double thr, int inner,
+                                                        double *__restrict__ partial,
+                                                        int *rot_flag)
+{
+    pair_solve_body<T, M, NT, CROSS>(B, ldb, pairs, psmap, U, eps, thr, inner, partial,
+                                     rot_flag, blockIdx.x);
+}
+
+// The pair solves of a round on workgroups 0 .. npairs-1 and, on the
+// workgroups after them, the V update of the previous round (its pairs vpairs
+// and rotations vU, vranges row ranges per pair).  The two parts touch
+// disjoint data: B and U versus V (vU is the other U buffer).
+template <typename T, int M, int NT, bool CROSS>
+__global__ __launch_bounds__(NT) void pair_solve_v_kernel(
+    T *__restrict__ B, int64_t ldb, const int2 *__restrict__ pairs,
+    const int2 *__restrict__ psmap, T *__restrict__ U, double eps, double thr, int inner,
+    double *__restrict__ partial, int *rot_flag, int npairs, T *__restrict__ V, int64_t ldv,
+    int64_t ntile, const int2 *__restrict__ vpairs, const T *__restrict__ vU, int vranges)
+{
+    if ((int)blockIdx.x < npairs) {
+        pair_solve_body<T, M, NT, CROSS>(B, ldb, pairs, psmap, U, eps, thr, inner, partial,
+                                         rot_flag, blockIdx.x);
+        return;
+    }
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    vupd::v_update_wg<T, M, NT>(V, ldv, ntile, vpairs, npairs, vU, vranges,
+                                (int)blockIdx.x - npairs, reinterpret_cast<T *>(smem_raw));
 }
 
 template <typename T, int M, int NT, bool CROSS>
@@ -367,16 +443,24 @@ static hipError_t launch_pair_solve_t(T *B, int64_t ldb, int npairs, const int2 
     return hipGetLastError();
 }
 
+// dynamic LDS of a pair-solve workgroup: Ut, S, two rotation records
+template <typename T>
+static size_t pair_solve_smem(int b)
+{
+    const int M = 2 * b;
+    const int vn = 16 / (int)sizeof(T);
+    return align8(sizeof(T) * ((size_t)M * (M + vn) + (size_t)M * (M + 1))) + 16 +
+           2 * (((size_t)b * (8 + 5 * sizeof(T)) + 15) & ~(size_t)15) + 16 * sizeof(double) +
+           16 * sizeof(int);
+}
+
 template <typename T>
 hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                              const int2 *psmap, T *U, double eps, double thr, int inner,
                              int cross, double *partial, int *rot_flag, hipStream_t s)
 {
     const int M = 2 * b;
-    const int vn = 16 / (int)sizeof(T);
-    size_t smem = align8(sizeof(T) * ((size_t)M * (M + vn) + (size_t)M * (M + 1))) + 16 +
-                  2 * (((size_t)b * (8 + 5 * sizeof(T)) + 15) & ~(size_t)15) +
-                  16 * sizeof(double) + 16 * sizeof(int);
+    const size_t smem = pair_solve_smem<T>(b);
     // M = 64: 528 threads own the 2x2 blocks of S; the U items (32 pairs x
     // 64 / VN chunks) go to the threads after the first wavefront.  16
     // wavefronts for both types (10 would cover the FP32 items, but measured
@@ -396,6 +480,87 @@ hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *p
                      : launch_pair_solve_t<T, 32, 256, false>(B, ldb, npairs, pairs, psmap, U,
                                                               eps, thr, inner, partial,
                                                               rot_flag, smem, s);
+    return hipErrorInvalidValue;
+}
+
+int g_pair_v_wgs = 0;    // V workgroups of the shared launch; 0 = free compute units
+size_t g_pair_v_lds = 0; // minimum dynamic LDS per workgroup of the shared launch
+void tune_pair_v(int wgs, size_t lds)
+{
+    g_pair_v_wgs = wgs;
+    g_pair_v_lds = lds;
+}
+
+template <typename T, int M, int NT, bool CROSS>
+static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int2 *pairs,
+                                        const int2 *psmap, T *U, double eps, double thr,
+                                        int inner, double *partial, int *rot_flag, size_t smem,
+                                        T *V, int64_t ldv, int64_t nrows, const int2 *vpairs,
+                                        const T *vU, hipStream_t s)
+{
+    auto k = pair_solve_v_kernel<T, M, NT, CROSS>;
+    static size_t smem_set = 0;
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (cus <= 0)
+            cus = 256;
+    }
+    const int64_t ntile = nrows / 16;
+    // V workgroups: about one per compute unit the pair solves leave free (at
+    // least a quarter of the units), a whole number of row ranges per pair
+    const int vwg = g_pair_v_wgs > 0 ? g_pair_v_wgs
+                                     : (cus - npairs > cus / 4 ? cus - npairs : cus / 4);
+    int64_t ranges = vwg / npairs;
+    if (ranges < 1)
+        ranges = 1;
+    if (ranges > ntile)
+        ranges = ntile;
+    const unsigned grid = (unsigned)(npairs + ranges * npairs);
+    const size_t lds = smem > g_pair_v_lds ? smem : g_pair_v_lds;
+    if (lds != smem_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+        smem_set = lds;
+    }
+    hipLaunchKernelGGL(k, dim3(grid), dim3(NT), lds, s, B, ldb, pairs, psmap, U, eps, thr,
+                       inner, partial, rot_flag, npairs, V, ldv, ntile, vpairs, vU,
+                       (int)ranges);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pair_solve_v(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
+                               const int2 *psmap, T *U, double eps, double thr, int inner,
+                               int cross, double *partial, int *rot_flag, T *V, int64_t ldv,
+                               int64_t nrows, const int2 *vpairs, const T *vU, hipStream_t s)
+{
+    if (nrows % 16 != 0 || ldv % (16 / (int64_t)sizeof(T)) != 0 || ((uintptr_t)V % 16) != 0)
+        return hipErrorInvalidValue;
+    const int M = 2 * b;
+    const size_t smem = pair_solve_smem<T>(b);
+    if (M == 64)
+        return cross ? launch_pair_solve_v_t<T, 64, 1024, true>(B, ldb, npairs, pairs, psmap, U,
+                                                                eps, thr, inner, partial,
+                                                                rot_flag, smem, V, ldv, nrows,
+                                                                vpairs, vU, s)
+                     : launch_pair_solve_v_t<T, 64, 1024, false>(B, ldb, npairs, pairs, psmap,
+                                                                 U, eps, thr, inner, partial,
+                                                                 rot_flag, smem, V, ldv, nrows,
+                                                                 vpairs, vU, s);
+    if (M == 32)
+        return cross ? launch_pair_solve_v_t<T, 32, 256, true>(B, ldb, npairs, pairs, psmap, U,
+                                                               eps, thr, inner, partial,
+                                                               rot_flag, smem, V, ldv, nrows,
+                                                               vpairs, vU, s)
+                     : launch_pair_solve_v_t<T, 32, 256, false>(B, ldb, npairs, pairs, psmap, U,
+                                                                eps, thr, inner, partial,
+                                                                rot_flag, smem, V, ldv, nrows,
+                                                                vpairs, vU, s);
     return hipErrorInvalidValue;
 }
 
@@ -770,6 +935,14 @@ hipError_t launch_rademacher(double *X, int64_t rows, int64_t n, int k, uint64_t
 }
 
 // explicit instantiations
+template hipError_t launch_pair_solve_v<double>(double *, int64_t, int, int, const int2 *,
+                                               const int2 *, double *, double, double, int, int,
+                                               double *, int *, double *, int64_t, int64_t,
+                                               const int2 *, const double *, hipStream_t);
+template hipError_t launch_pair_solve_v<float>(float *, int64_t, int, int, const int2 *,
+                                              const int2 *, float *, double, double, int, int,
+                                              double *, int *, float *, int64_t, int64_t,
+                                              const int2 *, const float *, hipStream_t);
 template hipError_t launch_pair_solve<double>(double *, int64_t, int, int, const int2 *,
                                               const int2 *, double *, double, double, int, int,
                                               double *, int *, hipStream_t);

@@ -1,27 +1,11 @@
 // Update kernels of the block path (the round's block rotation, Section 3.3
 // applied blockwise): the eigenvectors V[:, cols(P, Q)] <- V[:, cols(P, Q)] U_PQ
-// for every block pair (P, Q) of the round, and the off-diagonal tiles
-// B_kl <- U_k^T B_kl U_l of every two pairs k < l (with its mirror).
-//
-// V update:
-// Each wavefront owns one pair l and a contiguous run of 16-row tiles of V.
-// It computes Z^T = U_l^T X^T on the 16x16x4 MFMA with no LDS and no barrier:
-//   * the B operand is X^T, so lane (li, lk) needs X[row li][k] for the k of
-//     its MFMA step.  The k order inside a step is free, so step (g, j) gives
-//     lane lk the k = g*4*VK + lk*VK + j: one 16-byte load of VK consecutive
-//     columns of row li feeds VK steps;
-//   * the A operand, U_l^T, is loaded once per wavefront into registers (the
-//     U blocks are stored transposed, so these are 16-byte loads);
-//   * the accumulator of a 16-column tile holds, per lane, the four entries
-//     D[r][li] with r = acc_row(lk, v).  Column 16 tc + m of the MFMA output
-//     is mapped to output column 16 tc + out_perm(m), chosen so that the four
-//     values of a lane are four consecutive columns of row li: one 16-byte
-//     store (f32) or two (f64).
-// The next tile's X is in flight while the current one computes (two register
-// buffers).  Tiles of different wavefronts are disjoint, so the update is in
-// place.
+// for every block pair (P, Q) of the round (the per-wavefront body is in
+// update_v.hpp), and the off-diagonal tiles B_kl <- U_k^T B_kl U_l of every two
+// pairs k < l (B's upper blocks).
 #include "internal.hpp"
 #include "common.hpp"
+#include "update_v.hpp"
 
 #include <vector>
 
@@ -29,45 +13,7 @@ namespace lj {
 
 namespace {
 
-// 16-byte vectors as plain clang vector types (they stay in registers)
-typedef float fv4 __attribute__((ext_vector_type(4)));
-typedef double dv2 __attribute__((ext_vector_type(2)));
-template <typename T>
-struct V16;
-template <>
-struct V16<float> {
-    typedef fv4 type;
-};
-template <>
-struct V16<double> {
-    typedef dv2 type;
-};
-
-// MFMA output row m of a 16-column tile -> column offset inside the tile
-template <typename T>
-__device__ inline int out_perm(int m);
-template <>
-__device__ inline int out_perm<float>(int m)
-{
-    return m; // acc row 4 lk + v is already column-contiguous per lane
-}
-template <>
-__device__ inline int out_perm<double>(int m)
-{
-    return 4 * (m & 3) + (m >> 2); // acc row lk + 4 v -> column 4 lk + v
-}
-
-// column c (0 <= c < 2b) of the pair's slice -> global column
-__device__ inline int pair_col(int2 pq, int c, int b)
-{
-    return c < b ? pq.x * b + c : pq.y * b + (c - b);
-}
-
-template <typename T>
-__device__ inline T vlane(const typename V16<T>::type &x, int j)
-{
-    return x[j];
-}
+using namespace vupd;
 
 template <typename T, int M>
 __global__ __launch_bounds__(256) void update_v_kernel(T *__restrict__ V, int64_t ldv,
@@ -75,101 +21,8 @@ __global__ __launch_bounds__(256) void update_v_kernel(T *__restrict__ V, int64_
                                                        int npairs, const T *__restrict__ U,
                                                        int chunks)
 {
-    constexpr int b = M / 2;
-    constexpr int VK = 16 / (int)sizeof(T); // elements per 16-byte vector
-    constexpr int TC = M / 16;              // 16-column output tiles
-    constexpr int KG = M / (4 * VK);        // vectors per lane per tile row
-    typedef typename V16<T>::type TV;
-    typedef typename acc4<T>::type accT;
-    const int lane = threadIdx.x % WAVE, li = lane % 16, lk = lane / 16;
-    const int gw = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    const int l = gw % npairs, ch = gw / npairs;
-    if (ch >= chunks)
-        return;
-    const int64_t t0 = (int64_t)ch * ntile / chunks, t1 = (int64_t)(ch + 1) * ntile / chunks;
-    if (t0 >= t1)
-        return;
-    const int2 pl = pairs[l];
-    // U blocks are stored transposed (Ut[j][i] = U[i][j]): the VK fragments of
-    // a step group are consecutive, one 16-byte load
-    const T *Ult = U + (int64_t)l * M * M;
-    T uf[TC][KG][VK];
-#pragma unroll
-    for (int tc = 0; tc < TC; ++tc)
-#pragma unroll
-        for (int g = 0; g < KG; ++g) {
-            const TV u = *reinterpret_cast<const TV *>(Ult + (16 * tc + out_perm<T>(li)) * M +
-                                                       g * 4 * VK + lk * VK);
-#pragma unroll
-            for (int j = 0; j < VK; ++j)
-                uf[tc][g][j] = vlane<T>(u, j);
-        }
-    int kc[KG], oc[TC];
-#pragma unroll
-    for (int g = 0; g < KG; ++g)
-        kc[g] = pair_col(pl, g * 4 * VK + lk * VK, b);
-#pragma unroll
-    for (int tc = 0; tc < TC; ++tc)
-        oc[tc] = pair_col(pl, 16 * tc + 4 * lk, b);
-
-    auto load = [&](TV(&x)[KG], int64_t t) __attribute__((always_inline)) {
-        const T *row = V + (t * 16 + li) * ldv;
-#pragma unroll
-        for (int g = 0; g < KG; ++g)
-            x[g] = *reinterpret_cast<const TV *>(row + kc[g]);
-    };
-    auto work = [&](const TV(&x)[KG], int64_t t) __attribute__((always_inline)) {
-        accT acc[TC];
-#pragma unroll
-        for (int tc = 0; tc < TC; ++tc)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                acc[tc][v] = (T)0;
-#pragma unroll
-        for (int g = 0; g < KG; ++g)
-#pragma unroll
-            for (int j = 0; j < VK; ++j) {
-                const T bv = vlane<T>(x[g], j);
-#pragma unroll
-                for (int tc = 0; tc < TC; ++tc)
-                    acc[tc] = mfma16(uf[tc][g][j], bv, acc[tc]);
-            }
-        T *row = V + (t * 16 + li) * ldv;
-#pragma unroll
-        for (int tc = 0; tc < TC; ++tc) {
-            if constexpr (sizeof(T) == 4) {
-                const fv4 z = {acc[tc][0], acc[tc][1], acc[tc][2], acc[tc][3]};
-                *reinterpret_cast<fv4 *>(row + oc[tc]) = z;
-            } else {
-                const dv2 z0 = {acc[tc][0], acc[tc][1]}, z1 = {acc[tc][2], acc[tc][3]};
-                *reinterpret_cast<dv2 *>(row + oc[tc]) = z0;
-                *reinterpret_cast<dv2 *>(row + oc[tc] + 2) = z1;
-            }
-        }
-    };
-
-    // Every path into the loop issues the same sequence of memory operations
-    // (prefetch indices are clamped to the last tile instead of skipped, the
-    // first step is peeled), so the wait for a buffer's loads never has to
-    // wait for the stores issued after them.
-    TV xa[KG], xb[KG];
-    auto step = [&](TV(&x)[KG], int64_t t) __attribute__((always_inline)) {
-        work(x, t);
-        load(x, t + 2 < t1 ? t + 2 : t1 - 1);
-        // keep the two buffers' steps apart, or the scheduler merges them and
-        // the second buffer's loads are waited for right after being issued
-        __builtin_amdgcn_sched_barrier(0);
-    };
-    load(xa, t0);
-    load(xb, t0 + 1 < t1 ? t0 + 1 : t1 - 1);
-    step(xa, t0);
-    int64_t t = t0 + 1;
-    for (; t + 1 < t1; t += 2) {
-        step(xb, t);
-        step(xa, t + 1);
-    }
-    if (t < t1)
-        work(xb, t);
+    vupd::v_update_wave<T, M>(V, ldv, ntile, pairs, npairs, U, chunks,
+                              blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE);
 }
 
 // B update.  The kernel takes a list of T tiles (k, l), k < l (all of them,
@@ -177,19 +30,20 @@ __global__ __launch_bounds__(256) void update_v_kernel(T *__restrict__ V, int64_
 // the list (the same share for every workgroup), so a list sorted by l keeps
 // the column pair of a run mostly fixed.  Its M/16 wavefronts produce rows
 // 16w .. 16w + 15 of Z = U_k^T X U_l as two chained MFMA products:
-//   C1 = X^T U_k (M-index c, N-index i, K-index r): the A operand X^T is read
-//        from the mirror tile B[rows(l), cols(k)] (= X^T, B is kept exactly
-//        symmetric), staged through LDS with 16-byte rows; the B operand U_k
-//        is per-lane registers;
+//   C1 = X^T U_k (M-index c, N-index i, K-index r): the A operand X^T is
+//        staged through LDS from the four stored b x b blocks of the tile (B
+//        keeps only its upper blocks during the sweeps; a block stored in X
+//        orientation is transposed on the way into LDS); the B operand U_k is
+//        per-lane registers;
 //   Z^T = U_l^T C1 (M-index j, K-index c): the accumulator of C1 already has
 //        the B-operand layout (element v of a lane is C1[16 tc + acc_row][li]),
 //        so C1 never leaves registers; the A operand U_l^T sits in LDS in
 //        per-lane fragment order (16-byte reads at consecutive addresses),
 //        refilled when the run reaches a new l.
-// Z is stored along its rows with 16-byte stores (out_perm again), its
-// transpose into the mirror tile with one element per lane (16 consecutive
-// lanes write consecutive columns).  The next tile's X^T and U_k are loaded
-// while the current one computes.
+// Each b x b block of Z is stored once, into B's upper block: along its rows
+// with 16-byte stores (out_perm again), or transposed with one element per
+// lane.  The next tile's X^T and U_k are loaded while the current one
+// computes.
 template <typename T, int M>
 __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int64_t ldb,
                                                          const int2 *__restrict__ pairs,
@@ -202,8 +56,9 @@ __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int6
     constexpr int VK = 16 / (int)sizeof(T);
     constexpr int TC = M / 16, TJ = M / 16, KG = M / (4 * VK);
     constexpr int LDX = M + VK;       // padded LDS row of the X^T tile
-    constexpr int RV = M / VK;        // 16-byte vectors per tile row
-    constexpr int PERV = M * RV / NT; // vectors per thread per tile
+    constexpr int BV = b / VK;        // 16-byte vectors per sub-block row
+    constexpr int VPB = b * BV;       // vectors per b x b sub-block
+    constexpr int PERV = 4 * VPB / NT; // vectors per thread per tile
     constexpr int HV = 4 / VK;        // 16-byte reads per lane per U_l fragment
     typedef typename V16<T>::type TV;
     typedef typename acc4<T>::type accT;
@@ -227,14 +82,23 @@ __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int6
     };
     TV xr[PERV];
     T uk[KG * VK], ukn[KG * VK];
+    // X^T consists of four b x b sub-blocks s = 2 ci + ri: rows of block
+    // C = (ci ? pl.y : pl.x) of the column pair, columns of block R = (ri ?
+    // pk.y : pk.x) of the row pair.  B keeps only blocks (I, J) with I <= J, so
+    // a sub-block with C < R is read in X^T orientation, one with C > R as its
+    // stored transpose (the decision is uniform per sub-block, and a
+    // sub-block covers whole wavefronts).
     auto load_tile = [&](int t) __attribute__((always_inline)) {
         const int2 kl = tiles[t];
         const int2 pk = pairs[kl.x], pl = pairs[kl.y];
 #pragma unroll
         for (int e = 0; e < PERV; ++e) {
-            const int idx = tid + e * NT, c = idx / RV, q = idx % RV;
-            xr[e] = *reinterpret_cast<const TV *>(B + (int64_t)pair_col(pl, c, b) * ldb +
-                                                  pair_col(pk, q * VK, b));
+            const int idx = tid + e * NT, sb = idx / VPB, a = (idx % VPB) / BV,
+                      col = (idx % BV) * VK;
+            const int C = (sb >> 1) ? pl.y : pl.x, R = (sb & 1) ? pk.y : pk.x;
+            const int64_t row = (int64_t)(C < R ? C : R) * b + a;
+            const int64_t cl = (int64_t)(C < R ? R : C) * b + col;
+            xr[e] = *reinterpret_cast<const TV *>(B + row * ldb + cl);
         }
         const T *Ukt = U + (int64_t)kl.x * M * M; // transposed: Ukt[j][i] = U_k[i][j]
 #pragma unroll
@@ -254,10 +118,20 @@ __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int6
             fill_ufl(kl.y);
             cur_l = kl.y;
         }
+        const int2 pk = pairs[kl.x], pl = pairs[kl.y];
 #pragma unroll
         for (int e = 0; e < PERV; ++e) {
-            const int idx = tid + e * NT, c = idx / RV, q = idx % RV;
-            *reinterpret_cast<TV *>(xs + c * LDX + q * VK) = xr[e];
+            const int idx = tid + e * NT, sb = idx / VPB, a = (idx % VPB) / BV,
+                      col = (idx % BV) * VK;
+            const int ci = sb >> 1, ri = sb & 1;
+            const int C = ci ? pl.y : pl.x, R = ri ? pk.y : pk.x;
+            if (C < R) {
+                *reinterpret_cast<TV *>(xs + (ci * b + a) * LDX + ri * b + col) = xr[e];
+            } else {
+#pragma unroll
+                for (int j = 0; j < VK; ++j)
+                    xs[(ci * b + col + j) * LDX + ri * b + a] = vlane<T>(xr[e], j);
+            }
         }
 #pragma unroll
         for (int e = 0; e < KG * VK; ++e)
@@ -265,9 +139,9 @@ __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int6
         __syncthreads();
         // unconditional prefetch: the same memory-operation sequence on every
         // path into the next step, so its wait skips the stores below (after
-        // the last tile it re-reads the run's first tile, still in L2)
-        load_tile(t + 1 < t1 ? t + 1 : t0);
-        const int2 pk = pairs[kl.x], pl = pairs[kl.y];
+        // the last tile it reads the list's first tile, which every workgroup
+        // reads, so it comes from L2)
+        load_tile(t + 1 < t1 ? t + 1 : 0);
         accT c1[TC];
 #pragma unroll
         for (int tc = 0; tc < TC; ++tc)
@@ -339,26 +213,37 @@ __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int6
                         zt[tj] = mfma16(vlane<T>(ub[tj][v / VK], v % VK), c1[tc + 1][v], zt[tj]);
             }
         }
+        // Z goes to the stored block of each (row block, column block): rows
+        // along rows with 16-byte stores when the row block is the smaller
+        // one, else into the transpose, one element per lane (16 consecutive
+        // lanes write consecutive columns).  A wavefront's 16 rows and a
+        // 16-column group each lie in one block, so the choice is uniform.
         const int i = 16 * w + li;
         const int gi = pair_col(pk, i, b);
+        const int rblk = 16 * w < b ? pk.x : pk.y;
         T *zrow = B + (int64_t)gi * ldb;
         double sq = 0.0;
 #pragma unroll
         for (int tj = 0; tj < TJ; ++tj) {
             const int gj0 = pair_col(pl, 16 * tj + 4 * lk, b);
-            if constexpr (sizeof(T) == 4) {
-                const fv4 z = {zt[tj][0], zt[tj][1], zt[tj][2], zt[tj][3]};
-                *reinterpret_cast<fv4 *>(zrow + gj0) = z;
+            const int cblk = 16 * tj < b ? pl.x : pl.y;
+            if (rblk < cblk) {
+                if constexpr (sizeof(T) == 4) {
+                    const fv4 z = {zt[tj][0], zt[tj][1], zt[tj][2], zt[tj][3]};
+                    *reinterpret_cast<fv4 *>(zrow + gj0) = z;
+                } else {
+                    const dv2 z0 = {zt[tj][0], zt[tj][1]}, z1 = {zt[tj][2], zt[tj][3]};
+                    *reinterpret_cast<dv2 *>(zrow + gj0) = z0;
+                    *reinterpret_cast<dv2 *>(zrow + gj0 + 2) = z1;
+                }
             } else {
-                const dv2 z0 = {zt[tj][0], zt[tj][1]}, z1 = {zt[tj][2], zt[tj][3]};
-                *reinterpret_cast<dv2 *>(zrow + gj0) = z0;
-                *reinterpret_cast<dv2 *>(zrow + gj0 + 2) = z1;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    B[(int64_t)(gj0 + v) * ldb + gi] = zt[tj][v];
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                B[(int64_t)(gj0 + v) * ldb + gi] = zt[tj][v];
+            for (int v = 0; v < 4; ++v)
                 sq += (double)zt[tj][v] * (double)zt[tj][v];
-            }
         }
         if (want_off) {
             sq = wave_sum(sq);
