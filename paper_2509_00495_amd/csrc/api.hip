@@ -173,7 +173,7 @@ struct BlockWs {
     float *B32, *V32, *U32;
     double *partial, *scal, *wtmp, *sg, *cmax;
     int *flags, *perm, *cidx;
-    int2 *pairs, *btiles, *psmap;
+    int2 *pairs, *psmap;
 };
 
 size_t partial_count(const Geometry &g)
@@ -207,7 +207,6 @@ BlockWs layout_block(Bump &bp, int64_t n, const Geometry &g, bool mixed)
     w.scal = bp.take<double>(8);
     w.flags = bp.take<int>(8);
     w.pairs = bp.take<int2>((size_t)(g.N - 1) * g.npairs);
-    w.btiles = bp.take<int2>((size_t)std::max(g.nbt, 1));
     w.psmap = bp.take<int2>((size_t)g.b * (g.b + 1)); // circle map, then cross map
     w.perm = bp.take<int>((size_t)std::max<int64_t>(n, 1));
     w.wtmp = bp.take<double>((size_t)std::max<int64_t>(n, 1));
@@ -280,7 +279,7 @@ size_t ws_block(int64_t n, const Opts &o, bool mixed)
     return bp.off + 256;
 }
 
-void fill_tables(const Geometry &g, std::vector<int2> &pairs, std::vector<int2> &tiles)
+void fill_tables(const Geometry &g, std::vector<int2> &pairs)
 {
     pairs.resize((size_t)(g.N - 1) * g.npairs);
     for (int r = 0; r < g.N - 1; ++r)
@@ -289,9 +288,6 @@ void fill_tables(const Geometry &g, std::vector<int2> &pairs, std::vector<int2> 
             rr_pair(k, r, g.N, p, q);
             pairs[(size_t)r * g.npairs + k] = make_int2(p, q);
         }
-    update_b_tiles(g.npairs, tiles); // off-diagonal tiles k < l, by l then k
-    if (tiles.empty())
-        tiles.push_back(make_int2(0, 0));
 }
 
 struct Readback {
@@ -463,7 +459,7 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
                 CK(hipEventRecord(ss.evU[j], s));
             if (timed)
                 CK(hipEventRecord(tm->ev[6 * r + 2], s));
-            CK(launch_update_b<T>(B, g.npad, g.b, pr, Ub, w.btiles, g.nbt,
+            CK(launch_update_b<T>(B, g.npad, g.b, g.npairs, pr, Ub,
                                   w.partial + (size_t)g.npairs * pair_solve_waves(g.M),
                                   r == g.N - 2, s));
             if (timed)
@@ -525,12 +521,10 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
 
 int setup_block(const Geometry &g, const BlockWs &w, hipStream_t s)
 {
-    std::vector<int2> pairs, tiles;
-    fill_tables(g, pairs, tiles);
+    std::vector<int2> pairs;
+    fill_tables(g, pairs);
     CK(hipMemcpyAsync(w.pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice,
                       s));
-    CK(hipMemcpyAsync(w.btiles, tiles.data(), tiles.size() * sizeof(int2),
-                      hipMemcpyHostToDevice, s));
     const size_t nblk = (size_t)g.b * (g.b + 1) / 2;
     std::vector<int2> psmap(2 * nblk);
     pair_solve_map(g.M, 0, psmap.data());

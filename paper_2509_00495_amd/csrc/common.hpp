@@ -143,6 +143,17 @@ __device__ inline bool jacobi_should_rotate_sq(double app, double aqq, double ap
     return apq != 0.0 && a > thr && a * a > eps * eps * fabs(app * aqq);
 }
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// makes every wavefront wait for all of its outstanding global stores and
+// loads; phases that share data only through LDS use this one, so stores and
+// prefetches stay in flight across it.
+__device__ inline void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <typename T>
 __device__ inline T wave_sum(T v)
 {

@@ -48,17 +48,15 @@ void tune_pair_v(int wgs, size_t lds);
 constexpr int pair_solve_waves(int M) { return M == 64 ? 16 : 4; }
 // thread -> block map of the pair solve (b(b+1)/2 entries for M = 2b)
 void pair_solve_map(int M, int cross, int2 *out);
-// which = 1: B tiles only, 2: V tiles only, 3: both
-// B_kl <- U_k^T B_kl U_l (into B's upper blocks) for the ntiles tiles (k, l), k < l, of
-// the list; partial[(l (l - 1) / 2 + k) (2b / 16) + w] gets twice the squared
-// sum of wavefront w's part of tile (k, l) when want_off (kernels_update.hip)
+// B_kl <- U_k^T B_kl U_l (into B's upper blocks) for every two pairs k < l of
+// the round; tile t = l (l - 1) / 2 + k; partial[t (2b / 16) + w] gets twice
+// the squared sum of wavefront w's part of tile t when want_off
+// (kernels_update.hip)
 template <typename T>
-hipError_t launch_update_b(T *B, int64_t ldb, int b, const int2 *pairs, const T *U,
-                           const int2 *tiles, int ntiles, double *partial, int want_off,
-                           hipStream_t s);
+hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pairs, const T *U,
+                           double *partial, int want_off, hipStream_t s);
 template <typename T>
 int update_b_blocks_per_cu(int b);
-void update_b_tiles(int npairs, std::vector<int2> &out);
 // grid sizing of the V update: total resident wavefronts (0 = from occupancy)
 void tune_update_v(int total_waves);
 
@@ -66,10 +64,6 @@ void tune_update_v(int total_waves);
 template <typename T>
 hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
                            const int2 *pairs, const T *U, hipStream_t s);
-template <typename T>
-hipError_t launch_apply(T *B, int64_t ldb, T *V, int64_t ldv, int64_t nrows, int b,
-                        int npairs, const int2 *pairs, const int2 *btiles, int nbt,
-                        const T *U, double *partial, int want_off, int which, hipStream_t s);
 hipError_t launch_sum(const double *x, int64_t count, double *out, hipStream_t s);
 template <typename T>
 hipError_t launch_ingest(const double *A, int64_t lda, int64_t n, T *B, int64_t npad,

@@ -564,18 +564,6 @@ hipError_t launch_pair_solve_v(T *B, int64_t ldb, int b, int npairs, const int2 
     return hipErrorInvalidValue;
 }
 
-// ------------------------------------------------------------------ apply
-// which = 1: the off-diagonal B tiles listed in btiles (nbt of them); 2: the V
-// row tiles.  Both run on the update kernels of kernels_update.hip.
-template <typename T>
-hipError_t launch_apply(T *B, int64_t ldb, T *V, int64_t ldv, int64_t nrows, int b, int npairs,
-                        const int2 *pairs, const int2 *btiles, int nbt, const T *U,
-                        double *partial, int want_off, int which, hipStream_t s)
-{
-    if (which == 2)
-        return launch_update_v<T>(V, ldv, nrows, b, npairs, pairs, U, s);
-    return launch_update_b<T>(B, ldb, b, pairs, U, btiles, nbt, partial, want_off, s);
-}
 
 // ------------------------------------------------------- reductions, etc.
 __global__ __launch_bounds__(256) void sum_kernel(const double *__restrict__ x, int64_t count,
@@ -989,12 +977,6 @@ void pair_solve_map(int M, int cross, int2 *out)
             if (!used[k][l])
                 out[cnt++] = make_int2(k, l);
 }
-template hipError_t launch_apply<double>(double *, int64_t, double *, int64_t, int64_t, int,
-                                         int, const int2 *, const int2 *, int, const double *,
-                                         double *, int, int, hipStream_t);
-template hipError_t launch_apply<float>(float *, int64_t, float *, int64_t, int64_t, int, int,
-                                        const int2 *, const int2 *, int, const float *,
-                                        double *, int, int, hipStream_t);
 template hipError_t launch_ingest<double>(const double *, int64_t, int64_t, double *, int64_t,
                                           double *, int *, int, hipStream_t);
 template hipError_t launch_ingest<float>(const double *, int64_t, int64_t, float *, int64_t,

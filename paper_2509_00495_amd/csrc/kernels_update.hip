@@ -45,11 +45,10 @@ __global__ __launch_bounds__(256) void update_v_kernel(T *__restrict__ V, int64_
 // lane.  The next tile's X^T and U_k are loaded while the current one
 // computes.
 template <typename T, int M>
-__global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int64_t ldb,
-                                                         const int2 *__restrict__ pairs,
-                                                         const T *__restrict__ U,
-                                                         const int2 *__restrict__ tiles,
-                                                         int ntiles, double *__restrict__ partial,
+__global__ __launch_bounds__(M * 4, sizeof(T) == 4 ? 4 : 2) void update_b_kernel(T *__restrict__ B, int64_t ldb,
+                                                         const int2 *__restrict__ pairs_g,
+                                                         int npairs, const T *__restrict__ U,
+                                                         double *__restrict__ partial,
                                                          int want_off)
 {
     constexpr int b = M / 2, NW = M / 16, NT = NW * WAVE;
@@ -62,34 +61,65 @@ __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int6
     constexpr int HV = 4 / VK;        // 16-byte reads per lane per U_l fragment
     typedef typename V16<T>::type TV;
     typedef typename acc4<T>::type accT;
+    constexpr int ZLD = 16 + VK; // padded row of a wavefront's transpose scratch
     __shared__ __align__(16) T xs[M * LDX];
     __shared__ __align__(16) T ufl[M * M];
+    __shared__ __align__(16) T zsc[NW * 16 * ZLD];
     const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
     const int li = lane % 16, lk = lane / 16;
+    T *zw = zsc + w * 16 * ZLD;
+    const int ntiles = npairs * (npairs - 1) / 2;
     const int t0 = (int)((int64_t)blockIdx.x * ntiles / gridDim.x);
     const int t1 = (int)((int64_t)(blockIdx.x + 1) * ntiles / gridDim.x);
     if (t0 >= t1)
         return;
+    // tile t of the list (k < l, by l then k) is (t - l (l - 1) / 2, l), and
+    // the pair entries are read with scalar loads (the indices are uniform):
+    // the loop has no vector loads whose values it waits for, as such a wait
+    // would also wait for the stores of the previous tile
+    auto tile_kl = [](int t) __attribute__((always_inline)) {
+        int l = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
+        while ((int64_t)l * (l - 1) / 2 > t)
+            --l;
+        while ((int64_t)(l + 1) * l / 2 <= t)
+            ++l;
+        return make_int2(__builtin_amdgcn_readfirstlane(t - (int)((int64_t)l * (l - 1) / 2)),
+                         __builtin_amdgcn_readfirstlane(l));
+    };
+    const int2 *__restrict__ pairs = pairs_g;
     // ufl[((f HV + h) 64 + lane) VK + j] = U_l[16 tc + acc_row(lk, v)][16 tj + out_perm(li)]
     // with f = tj TC + tc and v = h VK + j: fragment v of lane for step (tc, v)
+    // all M*M/NT gathers of a thread are issued before the first LDS write,
+    // so the fill costs one memory latency
     auto fill_ufl = [&](int l) __attribute__((always_inline)) {
         const T *Ult = U + (int64_t)l * M * M; // transposed: Ult[j][i] = U_l[i][j]
-        for (int e = tid; e < M * M; e += NT) {
+        constexpr int PF = M * M / NT;
+        T u[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int e = tid + q * NT;
             const int j = e % VK, ln = (e / VK) % WAVE, r = e / (VK * WAVE);
             const int v = (r % HV) * VK + j, f = r / HV, tc = f % TC, tj = f / TC;
-            ufl[e] = Ult[(16 * tj + out_perm<T>(ln % 16)) * M + 16 * tc + acc_row<T>(ln / 16, v)];
+            u[q] = Ult[(16 * tj + out_perm<T>(ln % 16)) * M + 16 * tc + acc_row<T>(ln / 16, v)];
         }
+#pragma unroll
+        for (int q = 0; q < PF; ++q)
+            ufl[tid + q * NT] = u[q];
     };
-    TV xr[PERV];
-    T uk[KG * VK], ukn[KG * VK];
+    // one tile's X^T pieces and U_k fragments; two of them alternate (the
+    // next tile's loads fly while the current one computes)
+    struct Buf {
+        TV xr[PERV];
+        T uk[KG * VK];
+    };
     // X^T consists of four b x b sub-blocks s = 2 ci + ri: rows of block
     // C = (ci ? pl.y : pl.x) of the column pair, columns of block R = (ri ?
     // pk.y : pk.x) of the row pair.  B keeps only blocks (I, J) with I <= J, so
     // a sub-block with C < R is read in X^T orientation, one with C > R as its
     // stored transpose (the decision is uniform per sub-block, and a
     // sub-block covers whole wavefronts).
-    auto load_tile = [&](int t) __attribute__((always_inline)) {
-        const int2 kl = tiles[t];
+    auto load_tile = [&](Buf &nb, int t) __attribute__((always_inline)) {
+        const int2 kl = tile_kl(t);
         const int2 pk = pairs[kl.x], pl = pairs[kl.y];
 #pragma unroll
         for (int e = 0; e < PERV; ++e) {
@@ -98,7 +128,7 @@ __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int6
             const int C = (sb >> 1) ? pl.y : pl.x, R = (sb & 1) ? pk.y : pk.x;
             const int64_t row = (int64_t)(C < R ? C : R) * b + a;
             const int64_t cl = (int64_t)(C < R ? R : C) * b + col;
-            xr[e] = *reinterpret_cast<const TV *>(B + row * ldb + cl);
+            nb.xr[e] = *reinterpret_cast<const TV *>(B + row * ldb + cl);
         }
         const T *Ukt = U + (int64_t)kl.x * M * M; // transposed: Ukt[j][i] = U_k[i][j]
 #pragma unroll
@@ -107,13 +137,13 @@ __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int6
                                                        lk * VK);
 #pragma unroll
             for (int j = 0; j < VK; ++j)
-                ukn[g * VK + j] = vlane<T>(u, j);
+                nb.uk[g * VK + j] = vlane<T>(u, j);
         }
     };
     int cur_l = -1;
-    auto body = [&](int t) __attribute__((always_inline)) {
-        __syncthreads(); // xs and ufl free again
-        const int2 kl = tiles[t];
+    auto body = [&](int t, const Buf &cb, Buf &nb, int tn) __attribute__((always_inline)) {
+        lds_barrier(); // xs and ufl free again
+        const int2 kl = tile_kl(t);
         if (kl.y != cur_l) {
             fill_ufl(kl.y);
             cur_l = kl.y;
@@ -126,22 +156,18 @@ __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int6
             const int ci = sb >> 1, ri = sb & 1;
             const int C = ci ? pl.y : pl.x, R = ri ? pk.y : pk.x;
             if (C < R) {
-                *reinterpret_cast<TV *>(xs + (ci * b + a) * LDX + ri * b + col) = xr[e];
+                *reinterpret_cast<TV *>(xs + (ci * b + a) * LDX + ri * b + col) = cb.xr[e];
             } else {
 #pragma unroll
                 for (int j = 0; j < VK; ++j)
-                    xs[(ci * b + col + j) * LDX + ri * b + a] = vlane<T>(xr[e], j);
+                    xs[(ci * b + col + j) * LDX + ri * b + a] = vlane<T>(cb.xr[e], j);
             }
         }
-#pragma unroll
-        for (int e = 0; e < KG * VK; ++e)
-            uk[e] = ukn[e];
-        __syncthreads();
-        // unconditional prefetch: the same memory-operation sequence on every
-        // path into the next step, so its wait skips the stores below (after
-        // the last tile it reads the list's first tile, which every workgroup
-        // reads, so it comes from L2)
-        load_tile(t + 1 < t1 ? t + 1 : 0);
+        lds_barrier();
+        // the next tile's loads go out now; their wait in the next step
+        // skips this step's stores, which are as many on every path
+        load_tile(nb, tn);
+        const T *uk = cb.uk;
         accT c1[TC];
 #pragma unroll
         for (int tc = 0; tc < TC; ++tc)
@@ -227,19 +253,31 @@ __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int6
         for (int tj = 0; tj < TJ; ++tj) {
             const int gj0 = pair_col(pl, 16 * tj + 4 * lk, b);
             const int cblk = 16 * tj < b ? pl.x : pl.y;
+            T *dst;
+            T zv[4];
             if (rblk < cblk) {
-                if constexpr (sizeof(T) == 4) {
-                    const fv4 z = {zt[tj][0], zt[tj][1], zt[tj][2], zt[tj][3]};
-                    *reinterpret_cast<fv4 *>(zrow + gj0) = z;
-                } else {
-                    const dv2 z0 = {zt[tj][0], zt[tj][1]}, z1 = {zt[tj][2], zt[tj][3]};
-                    *reinterpret_cast<dv2 *>(zrow + gj0) = z0;
-                    *reinterpret_cast<dv2 *>(zrow + gj0 + 2) = z1;
-                }
-            } else {
+                dst = zrow + gj0;
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    B[(int64_t)(gj0 + v) * ldb + gi] = zt[tj][v];
+                    zv[v] = zt[tj][v];
+            } else {
+                // through the wavefront's LDS scratch: lane (li, lk) then holds
+                // four consecutive rows 16 w + 4 lk .. of Z's column 16 tj + li
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    zw[(4 * lk + v) * ZLD + li] = zt[tj][v];
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    zv[v] = zw[li * ZLD + 4 * lk + v];
+                dst = B + (int64_t)pair_col(pl, 16 * tj + li, b) * ldb + pair_col(pk, 16 * w + 4 * lk, b);
+            }
+            if constexpr (sizeof(T) == 4) {
+                const fv4 z = {zv[0], zv[1], zv[2], zv[3]};
+                *reinterpret_cast<fv4 *>(dst) = z;
+            } else {
+                const dv2 z0 = {zv[0], zv[1]}, z1 = {zv[2], zv[3]};
+                *reinterpret_cast<dv2 *>(dst) = z0;
+                *reinterpret_cast<dv2 *>(dst + 2) = z1;
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v)
@@ -248,13 +286,22 @@ __global__ __launch_bounds__(M * 4) void update_b_kernel(T *__restrict__ B, int6
         if (want_off) {
             sq = wave_sum(sq);
             if (lane == 0)
-                partial[((int64_t)kl.y * (kl.y - 1) / 2 + kl.x) * NW + w] = 2.0 * sq;
+                partial[(int64_t)t * NW + w] = 2.0 * sq;
         }
     };
-    load_tile(t0);
-    body(t0);
-    for (int t = t0 + 1; t < t1; ++t)
-        body(t);
+    // peeled first step, then pairs of steps, so the two buffers alternate
+    // without copies and every path issues the same memory operations (the
+    // prefetch after the last tile reads tile 0, which every workgroup reads)
+    Buf ba, bb;
+    load_tile(ba, t0);
+    body(t0, ba, bb, t0 + 1 < t1 ? t0 + 1 : 0);
+    int t = t0 + 1;
+    for (; t + 1 < t1; t += 2) {
+        body(t, bb, ba, t + 1);
+        body(t + 1, ba, bb, t + 2 < t1 ? t + 2 : 0);
+    }
+    if (t < t1)
+        body(t, bb, ba, 0);
 }
 
 int g_update_v_waves = 0; // total resident wavefronts to size the V-update grid; 0 = occupancy
@@ -309,21 +356,13 @@ int update_b_blocks_per_cu(int b)
 
 void tune_update_v(int total_waves) { g_update_v_waves = total_waves; }
 
-void update_b_tiles(int npairs, std::vector<int2> &out)
-{
-    out.clear();
-    for (int l = 1; l < npairs; ++l)
-        for (int k = 0; k < l; ++k)
-            out.push_back(make_int2(k, l));
-}
-
 template <typename T>
-hipError_t launch_update_b(T *B, int64_t ldb, int b, const int2 *pairs, const T *U,
-                           const int2 *tiles, int ntiles, double *partial, int want_off,
-                           hipStream_t s)
+hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pairs, const T *U,
+                           double *partial, int want_off, hipStream_t s)
 {
     if (ldb % (16 / (int64_t)sizeof(T)) != 0 || ((uintptr_t)B % 16) != 0)
         return hipErrorInvalidValue;
+    const int ntiles = npairs * (npairs - 1) / 2;
     if (ntiles == 0)
         return hipSuccess;
     static int cus = 0;
@@ -338,10 +377,10 @@ hipError_t launch_update_b(T *B, int64_t ldb, int b, const int2 *pairs, const T 
     const unsigned grid = (unsigned)(ntiles < slots ? ntiles : slots);
     if (b == 32)
         hipLaunchKernelGGL((update_b_kernel<T, 64>), dim3(grid), dim3(256), 0, s, B, ldb, pairs,
-                           U, tiles, ntiles, partial, want_off);
+                           npairs, U, partial, want_off);
     else if (b == 16)
         hipLaunchKernelGGL((update_b_kernel<T, 32>), dim3(grid), dim3(128), 0, s, B, ldb, pairs,
-                           U, tiles, ntiles, partial, want_off);
+                           npairs, U, partial, want_off);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -365,10 +404,10 @@ hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
 
 template int update_b_blocks_per_cu<double>(int);
 template int update_b_blocks_per_cu<float>(int);
-template hipError_t launch_update_b<double>(double *, int64_t, int, const int2 *, const double *,
-                                            const int2 *, int, double *, int, hipStream_t);
-template hipError_t launch_update_b<float>(float *, int64_t, int, const int2 *, const float *,
-                                           const int2 *, int, double *, int, hipStream_t);
+template hipError_t launch_update_b<double>(double *, int64_t, int, int, const int2 *,
+                                            const double *, double *, int, hipStream_t);
+template hipError_t launch_update_b<float>(float *, int64_t, int, int, const int2 *,
+                                           const float *, double *, int, hipStream_t);
 template hipError_t launch_update_v<double>(double *, int64_t, int64_t, int, int, const int2 *,
                                             const double *, hipStream_t);
 template hipError_t launch_update_v<float>(float *, int64_t, int64_t, int, int, const int2 *,
