@@ -41,9 +41,10 @@ hipError_t launch_pair_solve_v(T *B, int64_t ldb, int b, int npairs, const int2 
                                const int2 *psmap, T *U, double eps, double thr, int inner,
                                int cross, double *partial, int *rot_flag, T *V, int64_t ldv,
                                int64_t nrows, const int2 *vpairs, const T *vU, hipStream_t s);
-// experiments: V workgroups of the shared launch (0 = default) and a minimum
-// dynamic LDS per workgroup (larger keeps one workgroup per compute unit)
-void tune_pair_v(int wgs, size_t lds);
+// experiments: V workgroups of the shared launch (0 = default), a minimum
+// dynamic LDS per workgroup (larger keeps one workgroup per compute unit) and
+// the working wavefronts per V workgroup (0 = all)
+void tune_pair_v(int wgs, size_t lds, int waves);
 // wavefronts of the pair-solve workgroup for 2b = M (one off^2 partial each)
 constexpr int pair_solve_waves(int M) { return M == 64 ? 16 : 4; }
 // thread -> block map of the pair solve (b(b+1)/2 entries for M = 2b)

@@ -411,7 +411,8 @@ __global__ __launch_bounds__(NT) void pair_solve_v_kernel(
     T *__restrict__ B, int64_t ldb, const int2 *__restrict__ pairs,
     const int2 *__restrict__ psmap, T *__restrict__ U, double eps, double thr, int inner,
     double *__restrict__ partial, int *rot_flag, int npairs, T *__restrict__ V, int64_t ldv,
-    int64_t ntile, const int2 *__restrict__ vpairs, const T *__restrict__ vU, int vranges)
+    int64_t ntile, const int2 *__restrict__ vpairs, const T *__restrict__ vU, int vranges,
+    int vwaves)
 {
     if ((int)blockIdx.x < npairs) {
         pair_solve_body<T, M, NT, CROSS>(B, ldb, pairs, psmap, U, eps, thr, inner, partial,
@@ -419,7 +420,7 @@ __global__ __launch_bounds__(NT) void pair_solve_v_kernel(
         return;
     }
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    vupd::v_update_wg<T, M, NT>(V, ldv, ntile, vpairs, npairs, vU, vranges,
+    vupd::v_update_wg<T, M, NT>(V, ldv, ntile, vpairs, npairs, vU, vranges, vwaves,
                                 (int)blockIdx.x - npairs, reinterpret_cast<T *>(smem_raw));
 }
 
@@ -485,10 +486,12 @@ hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *p
 
 int g_pair_v_wgs = 0;    // V workgroups of the shared launch; 0 = free compute units
 size_t g_pair_v_lds = 0; // minimum dynamic LDS per workgroup of the shared launch
-void tune_pair_v(int wgs, size_t lds)
+int g_pair_v_waves = 0;  // working wavefronts per V workgroup; 0 = default
+void tune_pair_v(int wgs, size_t lds, int waves)
 {
     g_pair_v_wgs = wgs;
     g_pair_v_lds = lds;
+    g_pair_v_waves = waves;
 }
 
 template <typename T, int M, int NT, bool CROSS>
@@ -519,6 +522,10 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
     if (ranges > ntile)
         ranges = ntile;
     const unsigned grid = (unsigned)(npairs + ranges * npairs);
+    // working wavefronts per V workgroup: one per SIMD in FP32, two in FP64
+    // (long runs of tiles per wavefront; measured at n = 4096)
+    const int vdef = (sizeof(T) == 4 ? 4 : 8) < NT / WAVE ? (sizeof(T) == 4 ? 4 : 8) : NT / WAVE;
+    const int vwaves = g_pair_v_waves > 0 && g_pair_v_waves <= NT / WAVE ? g_pair_v_waves : vdef;
     const size_t lds = smem > g_pair_v_lds ? smem : g_pair_v_lds;
     if (lds != smem_set) {
         hipError_t e = hipFuncSetAttribute((const void *)k,
@@ -529,7 +536,7 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
     }
     hipLaunchKernelGGL(k, dim3(grid), dim3(NT), lds, s, B, ldb, pairs, psmap, U, eps, thr,
                        inner, partial, rot_flag, npairs, V, ldv, ntile, vpairs, vU,
-                       (int)ranges);
+                       (int)ranges, vwaves);
     return hipGetLastError();
 }
 

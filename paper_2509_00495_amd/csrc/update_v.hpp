@@ -173,20 +173,19 @@ __device__ inline void v_update_wave(T *__restrict__ V, int64_t ldv, int64_t nti
 // Workgroup variant for the launch shared with the pair solves: workgroup wg
 // takes pair l = wg % npairs and part wg / npairs of `ranges` equal row ranges
 // of V.  U_l^T is staged once into LDS (ufl, M*M entries) in per-lane fragment
-// order, so every wavefront of the workgroup reads it with 16-byte LDS loads
-// at consecutive addresses instead of holding it in registers; the NT / 64
-// wavefronts take the range's 16-row tiles in turn (tile t0 + w + i NW), each
-// with two X buffers in flight as above.  Every thread reaches the barrier.
+// order, and every wavefront reads it from there with 16-byte LDS loads at
+// consecutive addresses; the first nw wavefronts take the range's 16-row tiles
+// in turn (tile t0 + w + i nw), each with two X buffers in flight as above.
+// Every thread reaches the barrier.
 template <typename T, int M, int NT>
 __device__ inline void v_update_wg(T *__restrict__ V, int64_t ldv, int64_t ntile,
                                    const int2 *__restrict__ pairs, int npairs,
-                                   const T *__restrict__ U, int ranges, int wg, T *ufl)
+                                   const T *__restrict__ U, int ranges, int nw, int wg, T *ufl)
 {
     constexpr int b = M / 2;
     constexpr int VK = 16 / (int)sizeof(T);
     constexpr int TC = M / 16;
     constexpr int KG = M / (4 * VK);
-    constexpr int NW = NT / WAVE;
     typedef typename V16<T>::type TV;
     typedef typename acc4<T>::type accT;
     const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
@@ -201,7 +200,7 @@ __device__ inline void v_update_wg(T *__restrict__ V, int64_t ldv, int64_t ntile
             Ult + (16 * tc + out_perm<T>(ln % 16)) * M + g * 4 * VK + (ln / 16) * VK);
     }
     __syncthreads();
-    const int64_t cnt = t1 - t0 > w ? (t1 - t0 - w + NW - 1) / NW : 0;
+    const int64_t cnt = w < nw && t1 - t0 > w ? (t1 - t0 - w + nw - 1) / nw : 0;
     if (cnt == 0)
         return;
     int kc[KG], oc[TC];
@@ -211,7 +210,7 @@ __device__ inline void v_update_wg(T *__restrict__ V, int64_t ldv, int64_t ntile
 #pragma unroll
     for (int tc = 0; tc < TC; ++tc)
         oc[tc] = pair_col(pl, 16 * tc + 4 * lk, b);
-    auto tile = [&](int64_t i) { return t0 + w + i * NW; };
+    auto tile = [&](int64_t i) { return t0 + w + i * nw; };
     auto load = [&](TV(&x)[KG], int64_t i) __attribute__((always_inline)) {
         const T *row = V + (tile(i) * 16 + li) * ldv;
 #pragma unroll
