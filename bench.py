@@ -62,12 +62,14 @@ def apply_flops(n, b, part):
 
 
 def apply_bytes(n, b, elem, part):
-    """Algorithmic HBM bytes of one update launch: B tiles read once and
-    written twice (tile + mirror); V tiles read and written once.  The small
-    U blocks are cache resident and not counted."""
+    """Algorithmic HBM bytes of one update launch: each off-diagonal pair tile
+    of B read and written once (B keeps only its upper b x b blocks during the
+    sweeps, so a tile is four stored blocks in either orientation); V tiles
+    read and written once.  The small U blocks are cache resident and not
+    counted."""
     M, nbt, nvt = _tiles(n, b)
     tile = M * M * elem
-    return tile * (3 * nbt if part == "B" else 2 * nvt)
+    return tile * (2 * nbt if part == "B" else 2 * nvt)
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "update_kernels_goe4096_traffic.md")
@@ -272,7 +274,10 @@ def main():
     kern_ms = {k: round(v[0], 2) for k, v in cands.items()}
     kern_ms["pair_solve_f32"] = round(tot("t_pair_ms", 1), 2)
     kern_ms["pair_solve_f64"] = round(tot("t_pair_ms", 0), 2)
-    dom = max(cands, key=lambda k: cands[k][0])
+    # the FP32 V update runs inside the pair-solve launch in the timed solves
+    # (the instrumented solve times it as its own kernel), so the dominant
+    # kernel is taken among the update kernels the timed solves launch as such
+    dom = max((k for k in cands if k != "apply_V_f32"), key=lambda k: cands[k][0])
     t_ms, cnt, part, dtype = cands[dom]
     avg_s = t_ms / max(cnt, 1) / 1e3
     elem = 4 if dtype == "f32" else 8
@@ -282,7 +287,7 @@ def main():
     mfma_bound = flops / (PEAK[dtype] * 1e12) >= nbytes / (HBM_PEAK * 1e9)
     names = {("B", "f32"): "update_b_kernel<float, 64>",
              ("V", "f32"): "update_v_kernel<float, 64>",
-             ("B", "f64"): "apply2_kernel<double, 64>",
+             ("B", "f64"): "update_b_kernel<double, 64>",
              ("V", "f64"): "update_v_kernel<double, 64>"}
     achieved = flops / avg_s / 1e12 if mfma_bound else nbytes / avg_s / 1e9
     peak = PEAK[dtype] if mfma_bound else HBM_PEAK
