@@ -75,11 +75,12 @@ typedef struct jacobi_opts {
                                join the two blocks of a tile; 1 = all pairs of
                                every tile in every round */
     int32_t serial_v;       /* where the eigenvector update of a round runs:
-                               0 (default) = by precision: FP32 rounds on
-                               `stream` after their B update, FP64 rounds on a
-                               second, library-owned stream beside the next
-                               round; 1 = always on `stream`; 2 = always on
-                               the second stream; other values are rejected */
+                               0 (default) = inside the next round's
+                               pair-solve launch, on the compute units the
+                               pair solves leave free; 1 = on `stream` after
+                               the round's B update; 2 = on a second,
+                               library-owned stream beside the next round;
+                               other values are rejected */
     int32_t reserved[2];
 } jacobi_opts;
 

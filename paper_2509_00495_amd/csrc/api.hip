@@ -410,21 +410,19 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
     int status = JACOBI_OK;
     const double thr = n > 0 ? tol / (double)n : 0.0;
     const size_t ustride = (size_t)g.npairs * g.M * g.M;
-    // Overlapped mode: the V update of round r runs on the side stream beside
-    // round r + 1's pair solve and B update (it needs only U_r).  U is
-    // double-buffered, and the pair solve of round r + 2, which overwrites
-    // U_r's buffer, waits for that V update.  Each cross-stream event adds a
-    // gap of several microseconds between the kernels around it, and the FP32
-    // pair solve runs slower beside an FP32 V update, so by default the FP32
-    // stage keeps everything on one stream and only the FP64 stage (whose
-    // V update is twice as long) overlaps.
-    const bool side = serial_v == 2 || (serial_v == 0 && !fp32_stage);
-    // One-stream FP32 default: the V update of round r rides in the launch of
-    // round r + 1's pair solves, on the compute units they leave free (the
-    // pair solves are latency-bound and use one unit per block pair).  The
-    // last round's V update is launched on its own after the sweeps.  Not
-    // with per-launch timing, which times the kernels one by one.
-    const bool fuse = !side && serial_v == 0 && !(tm && tm->on);
+    // The V update of round r needs only U_r.  Default: it rides in the launch
+    // of round r + 1's pair solves, on the compute units they leave free (the
+    // pair solves are latency-bound and take one unit per block pair); the
+    // last round's update is launched on its own after the sweeps.  Without
+    // it (and with per-launch timing, which times the kernels one by one) the
+    // update runs after the B update on the same stream (serial_v = 1) or on a
+    // side stream beside round r + 1 (serial_v = 2; U is double-buffered and
+    // the pair solve of round r + 2, which overwrites U_r's buffer, waits for
+    // it).  Measured at n = 4096: the shared launch is fastest in both
+    // precisions; each cross-stream event adds a gap of several microseconds,
+    // and a pair solve beside a running V update slows down.
+    const bool side = serial_v == 2;
+    const bool fuse = serial_v == 0 && !(tm && tm->on);
     const int2 *vpend_pairs = nullptr; // V update waiting for the next launch
     const T *vpend_U = nullptr;
     while (off > tol) {

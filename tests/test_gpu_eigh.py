@@ -104,8 +104,9 @@ def test_block_path_circle_schedule(pj, n, block):
 @pytest.mark.parametrize("serial_v", [1, 2])
 @pytest.mark.parametrize("fn", ["eigh", "eigh_mixed"])
 def test_block_path_serial_v(pj, fn, serial_v):
-    """serial_v=1: every eigenvector update on the caller's stream; 2: every
-    one on the second stream (the default splits by precision)."""
+    """serial_v=1: every eigenvector update on the caller's stream after the
+    B update; 2: on the second stream (the default runs it inside the next
+    round's pair-solve launch)."""
     A = wl.random_symmetric(260, 2600)
     W, V, info = run(pj, fn, A, small_max_n=-1, block=32, serial_v=serial_v)
     assert info["path"] == 1 and info["status"] == 0
