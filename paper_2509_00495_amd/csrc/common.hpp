@@ -122,27 +122,6 @@ __device__ inline void jacobi_angle_fast(double app, double aqq, double apq, dou
     s = t * c;
 }
 
-// The same angle in single precision, for the FP32 stage, whose rotations are
-// single-precision ones: hardware reciprocal, square root and reciprocal
-// square root (about 1 ulp each), the last refined by one Newton step so that
-// c^2 + s^2 - 1 carries no systematic sign (a bias would build up over the
-// ~n rotations a column takes per sweep).  |tau| > 2^30 takes t = 1/(2 tau),
-// where sqrt(1 + tau^2) = |tau| in single precision.
-__device__ inline void jacobi_angle_f32(float app, float aqq, float apq, float &c, float &s,
-                                        float &t)
-{
-    const float tau = (aqq - app) * __builtin_amdgcn_rcpf(2.0f * apq);
-    const float at = fabsf(tau);
-    const float tt = at > 0x1p30f
-                         ? 0.5f * __builtin_amdgcn_rcpf(at)
-                         : __builtin_amdgcn_rcpf(at + __builtin_amdgcn_sqrtf(fmaf(at, at, 1.0f)));
-    t = tau >= 0.0f ? tt : -tt;
-    const float x = fmaf(t, t, 1.0f);
-    const float y = __builtin_amdgcn_rsqf(x);
-    c = y * fmaf(-0.5f * x * y, y, 1.5f);
-    s = t * c;
-}
-
 // Per-pair test: rotate only when a_pq is not negligible relative to the
 // diagonal (the per-pair threshold of Algorithm 4 with tol = eps) and above
 // the absolute floor thr = tol_off / n (if every |a_pq| <= tol_off / n then
@@ -162,16 +141,6 @@ __device__ inline bool jacobi_should_rotate_sq(double app, double aqq, double ap
 {
     double a = fabs(apq);
     return apq != 0.0 && a > thr && a * a > eps * eps * fabs(app * aqq);
-}
-
-// The per-pair test in single precision (as a product of square roots, which
-// neither overflows nor underflows for single-precision entries).
-__device__ inline bool jacobi_should_rotate_f32(float app, float aqq, float apq, float eps,
-                                                float thr)
-{
-    const float a = fabsf(apq);
-    return apq != 0.0f && a > thr &&
-           a > eps * (__builtin_amdgcn_sqrtf(fabsf(app)) * __builtin_amdgcn_sqrtf(fabsf(aqq)));
 }
 
 // Workgroup barrier that orders LDS accesses only.  __syncthreads() also

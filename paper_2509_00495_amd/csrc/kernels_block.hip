@@ -23,17 +23,13 @@ __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~(size_t)7
 
 // ------------------------------------------------------------- pair solve
 // Rotated diagonal entry of a pair after its rotation: a_pp - t a_pq for the
-// first position of the pair, a_qq + t a_pq for the second (Section 3.1), in
-// the stage's precision.
+// first position of the pair, a_qq + t a_pq for the second (Section 3.1),
+// formed in FP64 and rounded to the stage's precision.
 template <typename T>
 __device__ inline T rotated_diag(T a, double t, T apq, int second)
 {
-    if constexpr (sizeof(T) == 4) {
-        const float tf = (float)t;
-        return second ? fmaf(tf, apq, a) : fmaf(-tf, apq, a);
-    } else {
-        return second ? a + t * apq : a - t * apq;
-    }
+    double v = second ? (double)a + t * (double)apq : (double)a - t * (double)apq;
+    return (T)v;
 }
 
 // Player of slot s in round r of the circle schedule on M players; the next
@@ -88,20 +84,11 @@ template <typename T>
 __device__ inline int pair_record(PairRec<T> &R, int k, T app, T aqq, T apq, double eps,
                                   double thr)
 {
+    // the angle in FP64 in both stages (FP32 data are widened)
     double c = 1.0, sn = 0.0, t = 0.0;
     int rot = 0;
-    if constexpr (sizeof(T) == 4) {
-        // FP32 stage: the angle in single precision
-        if (jacobi_should_rotate_f32(app, aqq, apq, (float)eps, (float)thr)) {
-            float cf, sf, tf;
-            jacobi_angle_f32(app, aqq, apq, cf, sf, tf);
-            c = cf;
-            sn = sf;
-            t = tf;
-            rot = 1;
-        }
-    } else if (jacobi_should_rotate_sq(app, aqq, apq, eps, thr)) {
-        jacobi_angle_fast(app, aqq, apq, c, sn, t);
+    if (jacobi_should_rotate_sq((double)app, (double)aqq, (double)apq, eps, thr)) {
+        jacobi_angle_fast((double)app, (double)aqq, (double)apq, c, sn, t);
         rot = 1;
     }
     typename PairRec<T>::T2 v;
