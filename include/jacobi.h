@@ -81,7 +81,20 @@ typedef struct jacobi_opts {
                                the round's B update; 2 = on a second,
                                library-owned stream beside the next round;
                                other values are rejected */
-    int32_t reserved[2];
+    int32_t tune;           /* batched path, when `threads` is 0: 0 (default) = the
+                               workgroup size (256 or 512 threads) and the place
+                               of V (LDS beside S, or global scratch) are
+                               chosen by measurement: the first call for a
+                               (device, n_max, batch size class) times every
+                               candidate on its own input and keeps the
+                               fastest for later calls; 1 = fixed choice by
+                               n_max, without measuring */
+    int32_t graph;          /* batched path: nonzero = issue the call's launches
+                               as a hipGraph, captured on the first call with
+                               a given set of arguments, workspace and tuned
+                               configuration and replayed by later identical
+                               calls (needs a caller workspace; ignored
+                               without one); 0 (default) = direct launches */
 } jacobi_opts;
 
 /* Diagnostics filled on return (host struct, may be NULL). */

@@ -7,6 +7,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "common.hpp"
@@ -39,7 +42,7 @@ bool trace_on()
 
 struct Opts {
     int max_sweeps, block, inner, ns_iters, check_sym, small_max_n, threads, timing, schedule,
-        serial_v;
+        serial_v, tune, graph;
     double c32;
 };
 
@@ -56,6 +59,8 @@ int resolve_opts(const jacobi_opts *o, Opts &r)
     r.timing = 0;
     r.schedule = 0;
     r.serial_v = 0;
+    r.tune = 0;
+    r.graph = 0;
     // 0.1: the FP32 stage runs into its quadratic phase, to a few times its
     // rounding floor (off(Q_d^T A Q_d) settles near 0.05 n u_l ||A||_F), which
     // saves FP64 sweeps that cost more than the FP32 ones (measured on GOE and
@@ -70,6 +75,10 @@ int resolve_opts(const jacobi_opts *o, Opts &r)
     if (o->serial_v < 0 || o->serial_v > 2)
         return 1;
     r.serial_v = o->serial_v;
+    if (o->tune < 0 || o->tune > 1)
+        return 1;
+    r.tune = o->tune;
+    r.graph = o->graph != 0;
     if (o->max_sweeps < 0 || o->max_sweeps > 1000)
         return 1;
     if (o->max_sweeps)
@@ -255,21 +264,154 @@ int small_pool(int64_t n_max, int lds_max)
     return fit >= s ? fit : 0;
 }
 
-size_t small_slots(int64_t n_max, int count, int threads)
+// Launch configuration of the one-workgroup solver: workgroup size, LDS pool
+// (doubles) and persistent grid (resident workgroups, at most one per matrix).
+struct SmallCfg {
+    int threads, pool;
+    int64_t slots;
+};
+
+size_t small_slots(int64_t n_max, int count, int threads, int pool)
 {
     DevInfo d = dev_info();
     int cus = d.cus > 0 ? d.cus : 256;
     const int m = (int)((n_max + 3) & ~3);
-    int per_cu = d.cus > 0 ? small_max_active(m, small_pool(n_max, d.lds_max), threads) : 1;
+    int per_cu = d.cus > 0 ? small_max_active(m, pool, threads) : 1;
     per_cu = std::max(per_cu, 1);
     return (size_t)std::min<int64_t>((int64_t)cus * per_cu, std::max(count, 1));
 }
 
-size_t ws_small(int64_t count, int64_t n_max, int threads)
+// The configurations the batched autotuner measures: 256 and 512 threads,
+// each with V beside S in LDS (when it fits) and with only S in LDS (V in the
+// global scratch, which leaves room for more resident workgroups).  With a
+// fixed workgroup size (opts.threads) only that size; without tuning, the
+// first candidate is the choice by n_max.
+void small_candidates(int64_t n_max, int count, int req_threads, int tune,
+                      std::vector<SmallCfg> &out)
 {
+    out.clear();
+    const int lds = dev_info().lds_max;
+    const int full = small_pool(n_max, lds);
+    if (full == 0)
+        return;
+    const int m = (int)((n_max + 3) & ~3);
+    const int s_only = m * (m + 1);
+    const int first = small_threads(n_max, req_threads);
+    int sizes[2] = {first, first == 512 ? 256 : 512};
+    const int nsz = (req_threads || tune == 1) ? 1 : 2;
+    for (int k = 0; k < nsz; ++k) {
+        out.push_back({sizes[k], full, (int64_t)small_slots(n_max, count, sizes[k], full)});
+        if (tune == 0 && s_only < full)
+            out.push_back({sizes[k], s_only, (int64_t)small_slots(n_max, count, sizes[k], s_only)});
+    }
+    if (tune == 1)
+        out.resize(1);
+}
+
+size_t ws_small(int64_t count, int64_t n_max, int req_threads, int tune)
+{
+    std::vector<SmallCfg> c;
+    small_candidates(n_max, (int)count, req_threads, tune, c);
+    int64_t slots = 1;
+    for (const SmallCfg &e : c)
+        slots = std::max(slots, e.slots);
     Bump bp(nullptr);
-    layout_small(bp, count, n_max, (int64_t)small_slots(n_max, (int)count, threads));
+    layout_small(bp, count, n_max, slots);
     return bp.off + 256;
+}
+
+// Autotuner cache of the batched path: the configuration measured fastest
+// for a (device, largest order, batch size class = bit length of the count,
+// requested workgroup size).  Only the workgroup size and the LDS pool are
+// kept; the grid is recomputed for each call's count.
+struct SmallKey {
+    int dev, n_max, bclass, req_threads;
+    bool operator<(const SmallKey &o) const
+    {
+        return std::tie(dev, n_max, bclass, req_threads) <
+               std::tie(o.dev, o.n_max, o.bclass, o.req_threads);
+    }
+};
+
+std::mutex g_small_mu;
+std::map<SmallKey, SmallCfg> g_small_tuned;
+
+bool small_tuned(const SmallKey &k, SmallCfg &out)
+{
+    std::lock_guard<std::mutex> lk(g_small_mu);
+    auto it = g_small_tuned.find(k);
+    if (it == g_small_tuned.end())
+        return false;
+    out = it->second;
+    return true;
+}
+
+void small_tune_store(const SmallKey &k, const SmallCfg &c)
+{
+    std::lock_guard<std::mutex> lk(g_small_mu);
+    g_small_tuned[k] = c;
+}
+
+// Graph cache of the batched path: one instantiated graph per distinct set of
+// arguments, workspace and configuration.  A graph holds the queue and status
+// resets (fill kernels, no memset nodes) and the persistent launch; the
+// descriptor upload and the status read-back stay outside it.
+struct SmallGraphKey {
+    const void *A, *W, *V, *work;
+    int64_t batch, layout; // layout: scratch slots the workspace was laid out for
+    uint64_t nhash;
+    double tol;
+    int max_sweeps, threads, pool, slots, dev;
+    bool operator<(const SmallGraphKey &o) const
+    {
+        return std::tie(A, W, V, work, batch, layout, nhash, tol, max_sweeps, threads, pool, slots, dev) <
+               std::tie(o.A, o.W, o.V, o.work, o.batch, o.layout, o.nhash, o.tol, o.max_sweeps,
+                        o.threads, o.pool, o.slots, o.dev);
+    }
+};
+
+std::map<SmallGraphKey, hipGraphExec_t> g_small_graphs;
+
+// Replays the graph cached under `k` on `s`, capturing it first from
+// `issue(capture_stream)` when the key is new.
+template <typename F> int small_graph_run(const SmallGraphKey &k, hipStream_t s, F issue)
+{
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_small_mu);
+        auto it = g_small_graphs.find(k);
+        if (it != g_small_graphs.end())
+            exec = it->second;
+    }
+    if (!exec) {
+        hipStream_t cs = nullptr;
+        CK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+        int bad = e != hipSuccess;
+        if (!bad) {
+            bad = issue(cs) != 0;
+            e = hipStreamEndCapture(cs, &graph);
+            bad = bad || e != hipSuccess;
+        }
+        if (!bad)
+            bad = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess;
+        if (graph)
+            hipGraphDestroy(graph);
+        hipStreamDestroy(cs);
+        if (bad) {
+            g_last_error = e != hipSuccess ? e : hipErrorUnknown;
+            return JACOBI_DEVICE;
+        }
+        std::lock_guard<std::mutex> lk(g_small_mu);
+        auto ins = g_small_graphs.emplace(k, exec);
+        if (!ins.second) { // another thread stored the same graph meanwhile
+            hipGraphExecDestroy(exec);
+            exec = ins.first->second;
+        }
+    }
+    CK(hipGraphLaunch(exec, s));
+    return 0;
 }
 
 size_t ws_block(int64_t n, const Opts &o, bool mixed)
@@ -853,7 +995,7 @@ size_t jacobi_workspace_bytes(int op, int64_t n_max, int64_t batch, const jacobi
     switch (op) {
     case 0: {
         size_t a = (n_max <= o.small_max_n) ? ws_small(1, std::max<int64_t>(n_max, 1),
-                                                       small_threads(n_max, o.threads))
+                                                       o.threads, 1)
                                             : 0;
         size_t b = ws_block(std::max<int64_t>(n_max, 1), o, false);
         return std::max(a, b) + 256;
@@ -861,8 +1003,8 @@ size_t jacobi_workspace_bytes(int op, int64_t n_max, int64_t batch, const jacobi
     case 1:
         return ws_block(std::max<int64_t>(n_max, 1), o, true) + 256;
     case 2:
-        return ws_small(std::max<int64_t>(batch, 1), std::max<int64_t>(n_max, 1),
-                        small_threads(n_max, o.threads)) +
+        return ws_small(std::max<int64_t>(batch, 1), std::max<int64_t>(n_max, 1), o.threads,
+                        o.tune) +
                256;
     case 3: {
         size_t nn = (size_t)n_max * n_max * std::max<int64_t>(batch, 1);
@@ -960,13 +1102,21 @@ int jacobi_eigh_batched(const double *A, const int64_t *n, int64_t batch, double
         return JACOBI_WORKSPACE;
     }
     void *aligned = (void *)(((uintptr_t)work + 255) & ~(uintptr_t)255);
-    const int threads = small_threads(n_max, o.threads);
-    const int64_t slots = (int64_t)small_slots(n_max, (int)batch, threads);
+    std::vector<SmallCfg> cands;
+    small_candidates(n_max, (int)batch, o.threads, o.tune, cands);
+    if (cands.empty()) {
+        g_last_error = hipErrorInvalidConfiguration;
+        return JACOBI_DEVICE; // the largest matrix does not fit one workgroup's LDS
+    }
+    int64_t slots_max = 1;
+    for (const SmallCfg &c : cands)
+        slots_max = std::max(slots_max, c.slots);
     Bump bp(aligned);
-    SmallWs w = layout_small(bp, batch, n_max, slots);
+    SmallWs w = layout_small(bp, batch, n_max, slots_max);
     // descriptors: packed offsets in input order, queue order = n descending
     std::vector<SmallDesc> d((size_t)batch);
     int64_t ao = 0, wo = 0;
+    uint64_t nhash = 1469598103934665603ull; // FNV-1a over the orders (graph key)
     for (int64_t i = 0; i < batch; ++i) {
         SmallDesc &e = d[(size_t)i];
         e.a_off = ao;
@@ -979,21 +1129,76 @@ int jacobi_eigh_batched(const double *A, const int64_t *n, int64_t batch, double
         e.info = nullptr;
         ao += n[i] * n[i];
         wo += n[i];
+        nhash = (nhash ^ (uint64_t)n[i]) * 1099511628211ull;
     }
     std::stable_sort(d.begin(), d.end(),
                      [](const SmallDesc &a, const SmallDesc &b) { return a.n > b.n; });
     CK(hipMemcpyAsync(w.desc, d.data(), d.size() * sizeof(SmallDesc), hipMemcpyHostToDevice, s));
-    CK(launch_fill_i32(w.queue, 1, 0, s));
-    CK(launch_fill_i32(w.status, batch, 0, s));
     const int m = (int)((n_max + 3) & ~3);
-    const DevInfo dv = dev_info();
-    const int pool = small_pool(n_max, dv.lds_max);
-    if (pool == 0) {
-        g_last_error = hipErrorInvalidConfiguration;
-        return JACOBI_DEVICE; // the largest matrix does not fit one workgroup's LDS
+    // one solve of the whole batch: reset the queue and the status, then the
+    // persistent launch (the only stream operations, so a graph can hold them)
+    auto issue = [&](const SmallCfg &c, hipStream_t st) -> int {
+        CK(launch_fill_i32(w.queue, 1, 0, st));
+        CK(launch_fill_i32(w.status, batch, 0, st));
+        CK(launch_small(A, W, V, w.desc, (int)batch, w.queue, tol, o.max_sweeps, w.vscratch,
+                        n_max * (m + 1), c.pool, m, c.threads, (int)c.slots, w.status, st));
+        return 0;
+    };
+    // configuration: measured once per (device, n_max, batch size class);
+    // not while the caller captures `s` (nothing runs then), nor stored
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    CK(hipStreamIsCapturing(s, &cap));
+    SmallCfg cfg = cands[0];
+    if (cands.size() > 1) {
+        const int bclass = 64 - __builtin_clzll((unsigned long long)batch);
+        const SmallKey key{dev, (int)n_max, bclass, o.threads};
+        SmallCfg hit{};
+        bool found = small_tuned(key, hit);
+        if (found) {
+            found = false;
+            for (const SmallCfg &c : cands)
+                if (c.threads == hit.threads && c.pool == hit.pool) {
+                    cfg = c; // this call's grid, within the laid-out scratch
+                    found = true;
+                }
+        }
+        if (!found && cap == hipStreamCaptureStatusNone) {
+            // every candidate solves the batch once; the outputs are
+            // overwritten by the solve with the chosen one below
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            CK(hipEventCreate(&e0));
+            CK(hipEventCreate(&e1));
+            float best = 0.0f;
+            int err = 0;
+            for (size_t k = 0; k < cands.size() && !err; ++k) {
+                err = hipEventRecord(e0, s) != hipSuccess || issue(cands[k], s) != 0 ||
+                      hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess;
+                float ms = 0.0f;
+                if (!err && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+                    (k == 0 || ms < best)) {
+                    best = ms;
+                    cfg = cands[k];
+                }
+            }
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            if (err) {
+                g_last_error = hipGetLastError();
+                return JACOBI_DEVICE;
+            }
+            small_tune_store(key, cfg);
+        }
     }
-    CK(launch_small(A, W, V, w.desc, (int)batch, w.queue, tol, o.max_sweeps, w.vscratch,
-                    n_max * (m + 1), pool, m, threads, (int)slots, w.status, s));
+    if (o.graph && !guard.p && cap == hipStreamCaptureStatusNone) {
+        const SmallGraphKey gk{A,   W,     V,   work, batch, slots_max, nhash, tol, o.max_sweeps,
+                               cfg.threads, cfg.pool, (int)cfg.slots, dev};
+        if (int e = small_graph_run(gk, s, [&](hipStream_t cs) { return issue(cfg, cs); }))
+            return e;
+    } else if (int e = issue(cfg, s)) {
+        return e;
+    }
     std::vector<int32_t> st((size_t)batch);
     CK(hipMemcpyAsync(st.data(), w.status, st.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
                       s));

@@ -42,7 +42,8 @@ class Opts(ctypes.Structure):
         ("timing", ctypes.c_int32),
         ("schedule", ctypes.c_int32),
         ("serial_v", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("tune", ctypes.c_int32),
+        ("graph", ctypes.c_int32),
     ]
 
 
@@ -224,10 +225,12 @@ def eigh_mixed(A, tol: float | None = None, opts: Opts | None = None,
 
 
 def eigh_batched(A_packed, ns, tol: float | None = None, opts: Opts | None = None,
-                 ws: Workspace | None = None, check: bool = True):
+                 ws: Workspace | None = None, check: bool = True, out=None):
     """Packed batch of uneven orders.  A_packed: 1-D float64 GPU tensor holding
     the matrices back to back (row-major).  Returns (W_packed, V_packed,
-    status) where status is an int32 GPU tensor of per-matrix codes."""
+    status) where status is an int32 GPU tensor of per-matrix codes.  `out`
+    = (W, V, status) reuses caller tensors (fixed addresses, which a graph
+    replay with opts.graph needs)."""
     torch = _torch()
     ns = [int(x) for x in ns]
     batch = len(ns)
@@ -237,9 +240,16 @@ def eigh_batched(A_packed, ns, tol: float | None = None, opts: Opts | None = Non
     if A_packed.numel() != tot:
         raise ValueError(f"A_packed has {A_packed.numel()} entries, orders need {tot}")
     A_packed = A_packed.contiguous()
-    W = torch.empty(sum(ns), dtype=torch.float64, device=A_packed.device)
-    V = torch.empty(tot, dtype=torch.float64, device=A_packed.device)
-    status = torch.zeros(batch, dtype=torch.int32, device=A_packed.device)
+    if out is None:
+        W = torch.empty(sum(ns), dtype=torch.float64, device=A_packed.device)
+        V = torch.empty(tot, dtype=torch.float64, device=A_packed.device)
+        status = torch.zeros(batch, dtype=torch.int32, device=A_packed.device)
+    else:
+        W, V, status = out
+        for t, cnt, dt in ((W, sum(ns), torch.float64), (V, tot, torch.float64),
+                           (status, batch, torch.int32)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.numel() != cnt:
+                raise ValueError("out tensors must be contiguous GPU tensors of the packed sizes")
     o = opts or Opts()
     n_arr = (ctypes.c_int64 * max(batch, 1))(*ns)
     need = workspace_bytes(2, max(ns) if ns else 1, batch, o)
