@@ -180,7 +180,7 @@ Geometry geometry(int64_t n, int block)
 struct BlockWs {
     double *B64, *V64, *U64, *X2, *R, *Vt, *probe;
     float *B32, *V32, *U32;
-    double *partial, *scal, *wtmp, *sg, *cmax;
+    double *partial, *scal, *wtmp, *sg, *cmax, *csq, *cinv;
     int *flags, *perm, *cidx;
     int2 *pairs, *psmap;
 };
@@ -222,6 +222,8 @@ BlockWs layout_block(Bump &bp, int64_t n, const Geometry &g, bool mixed)
     w.sg = bp.take<double>((size_t)std::max<int64_t>(n, 1));
     w.cmax = bp.take<double>((size_t)SIGN_CHUNKS_HOST * std::max<int64_t>(n, 1));
     w.cidx = bp.take<int>((size_t)SIGN_CHUNKS_HOST * std::max<int64_t>(n, 1));
+    w.csq = bp.take<double>((size_t)SIGN_CHUNKS_HOST * std::max<int64_t>(n, 1));
+    w.cinv = bp.take<double>((size_t)g.npad);
     return w;
 }
 
@@ -763,19 +765,23 @@ int eigh_small(const double *A, int64_t n, int64_t lda, double *W, double *V, in
     return st;
 }
 
-// Output stage of the block path.  W is read off the diagonal of B; then the
-// orthogonality of the accumulated V is estimated from NPROBE Rademacher
-// probes x (||V^T V x - x||, O(n^2) work) and, when the estimate exceeds
+// Output stage of the block path.  W is read off the diagonal of B.  The
+// output columns are those of the accumulated V scaled to unit norm (the
+// rounding of the rotations moves the column norms by a random walk, which is
+// nearly all of V's departure from orthogonality; the columns stay orthogonal
+// to each other far more closely).  The orthogonality of the normalized V is
+// estimated from NPROBE Rademacher probes x (||D^-1 V^T V D^-1 x - x||, with
+// D = diag of the column norms, O(n^2) work) and, when the estimate exceeds
 // POLISH_FRAC * 1e-14 n, V gets one Newton-Schulz step
 // V <- V + V (I - V^T V) / 2 (the paper's orthogonaliser, Section 4.3.4),
-// which squares its departure from orthogonality.  Rbuf and Vbuf are free
-// npad x npad scratch buffers (Rbuf may alias B: the diagonal is extracted
-// first).
-// A_rq != nullptr: the eigenvalues are the Rayleigh quotients v_k^T A v_k of
-// the final eigenvectors against the input (T = A V is formed in Rbuf) instead
-// of the diagonal of B.  The plain FP64 path uses this: after its many sweeps
-// of blockwise updates the rounding accumulated in the diagonal of B exceeds
-// what the eigenvectors themselves allow.
+// which squares its departure from orthogonality, and the column statistics
+// are taken again.  Rbuf and Vbuf are free npad x npad scratch buffers (Rbuf
+// may alias B: the diagonal is extracted first).
+// A_rq != nullptr: the eigenvalues are the Rayleigh quotients of the final
+// normalized eigenvectors against the input (T = A V is formed in Rbuf)
+// instead of the diagonal of B.  The plain FP64 path uses this: after its
+// many sweeps of blockwise updates the rounding accumulated in the diagonal of
+// B exceeds what the eigenvectors themselves allow.
 int finalize_block(const Geometry &g, int64_t n, const BlockWs &w, const double *B,
                    const double *Vin, double *Rbuf, double *Vbuf, double *W, double *V,
                    int64_t ldv, hipStream_t s, double *orth_est, int *polished,
@@ -783,13 +789,16 @@ int finalize_block(const Geometry &g, int64_t n, const BlockWs &w, const double 
 {
     const int64_t np = g.npad;
     CK(launch_diag(B, np, n, w.wtmp, s));
+    CK(launch_colstats(Vin, np, n, np, w.cmax, w.cidx, w.csq, w.cinv, s));
     double *X = w.probe, *Y = w.probe + np * NPROBE, *Z = w.probe + 2 * np * NPROBE;
     CK(launch_rademacher(X, np, n, NPROBE, 0x5eedull, s));
-    CK(launch_gemm64(0, 0, np, NPROBE, np, 1.0, Vin, np, 0, X, NPROBE, 0, 0.0, nullptr, 0, 0,
+    // Z = D^-1 X, Y = V Z, Z = V^T Y, Z = D^-1 Z - X = (D^-1 V^T V D^-1 - I) X
+    CK(launch_rowscale(X, w.cinv, nullptr, Z, np, NPROBE, s));
+    CK(launch_gemm64(0, 0, np, NPROBE, np, 1.0, Vin, np, 0, Z, NPROBE, 0, 0.0, nullptr, 0, 0,
                      0.0, Y, NPROBE, 0, 1, s));
-    // Z = V^T Y - X = (V^T V - I) X
-    CK(launch_gemm64(1, 0, np, NPROBE, np, 1.0, Vin, np, 0, Y, NPROBE, 0, -1.0, X, NPROBE, 0,
+    CK(launch_gemm64(1, 0, np, NPROBE, np, 1.0, Vin, np, 0, Y, NPROBE, 0, 0.0, nullptr, 0, 0,
                      0.0, Z, NPROBE, 0, 1, s));
+    CK(launch_rowscale(Z, w.cinv, X, Z, np, NPROBE, s));
     CK(launch_sq_partial(Z, np * NPROBE, w.partial, s));
     CK(launch_sum(w.partial, OFF_BLOCKS, w.scal + 3, s));
     Readback rb;
@@ -806,14 +815,15 @@ int finalize_block(const Geometry &g, int64_t n, const BlockWs &w, const double 
                          Vbuf, np, 0, 1, s));
         Vf = Vbuf;
         *polished = 1;
+        CK(launch_colstats(Vf, np, n, np, w.cmax, w.cidx, w.csq, w.cinv, s));
     }
     if (A_rq) {
         CK(launch_gemm64(0, 0, n, n, n, 1.0, A_rq, lda, 0, Vf, np, 0, 0.0, nullptr, 0, 0, 0.0,
                          Rbuf, np, 0, 1, s));
-        CK(launch_rayleigh(Vf, np, Rbuf, np, n, w.cmax, w.wtmp, s));
+        CK(launch_rayleigh(Vf, np, Rbuf, np, n, w.cinv, w.csq, w.wtmp, s));
     }
     CK(launch_fill_i32(w.perm, n, 0, s));
-    CK(launch_finalize(w.wtmp, Vf, np, n, W, V, ldv, w.perm, w.sg, w.cmax, w.cidx, s));
+    CK(launch_finalize(w.wtmp, Vf, np, n, W, V, ldv, w.perm, w.sg, w.cmax, w.cidx, w.cinv, s));
     return 0;
 }
 

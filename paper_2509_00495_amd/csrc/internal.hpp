@@ -77,13 +77,24 @@ hipError_t launch_fill_i32(int *p, int64_t count, int value, hipStream_t s);
 hipError_t launch_cast_f32(const double *src, float *dst, int64_t count, hipStream_t s);
 hipError_t launch_widen_f64(const float *src, double *dst, int64_t count, hipStream_t s);
 hipError_t launch_diag(const double *B, int64_t ldb, int64_t n, double *w, hipStream_t s);
-// w_k = sum_i V[i][k] T[i][k] (Rayleigh quotients when T = A V); part holds
-// 16 n doubles
+// w_k = inv_k^2 sum_i V[i][k] T[i][k] (Rayleigh quotients of the normalized
+// columns when T = A V); part holds 16 n doubles
 hipError_t launch_rayleigh(const double *V, int64_t ldv, const double *T, int64_t ldt,
-                           int64_t n, double *part, double *w, hipStream_t s);
+                           int64_t n, const double *inv, double *part, double *w,
+                           hipStream_t s);
+// per column of V (rows < n): entry of largest magnitude per row chunk (cmax,
+// cidx), squared norm per chunk (csq), all 16 n; inv = 1 / column norm (npad
+// entries, 1 past n)
+hipError_t launch_colstats(const double *V, int64_t ldv, int64_t n, int64_t npad, double *cmax,
+                           int *cidx, double *csq, double *inv, hipStream_t s);
+// dst = diag(inv) src - sub (sub may be null), rows x k row-major
+hipError_t launch_rowscale(const double *src, const double *inv, const double *sub, double *dst,
+                           int64_t rows, int k, hipStream_t s);
+// ascending order of w, output columns V[:, perm] scaled by sign / norm
 hipError_t launch_finalize(const double *w, const double *V, int64_t ldv_in, int64_t n,
                            double *W, double *Vout, int64_t ldv, int *perm, double *sg,
-                           double *cmax, int *cidx, hipStream_t s);
+                           const double *cmax, const int *cidx, const double *inv,
+                           hipStream_t s);
 constexpr int SIGN_CHUNKS_HOST = 16; // row chunks of the column-sign pass
 hipError_t launch_rademacher(double *X, int64_t rows, int64_t n, int k, uint64_t seed,
                              hipStream_t s);

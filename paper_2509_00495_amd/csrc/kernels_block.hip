@@ -769,7 +769,10 @@ __global__ __launch_bounds__(256) void rq_partial_kernel(const double *__restric
     part[blockIdx.y * n + k] = acc;
 }
 
-__global__ void rq_sum_kernel(const double *__restrict__ part, int64_t n, double *__restrict__ w)
+// w_k = (sum of the chunk partials) inv_k^2: the quotient of the normalized
+// column v_k / ||v_k||
+__global__ void rq_sum_kernel(const double *__restrict__ part, int64_t n,
+                              const double *__restrict__ inv, double *__restrict__ w)
 {
     const int64_t k = blockIdx.x * 256 + threadIdx.x;
     if (k >= n)
@@ -777,7 +780,7 @@ __global__ void rq_sum_kernel(const double *__restrict__ part, int64_t n, double
     double acc = 0.0;
     for (int c = 0; c < RQ_CHUNKS; ++c)
         acc += part[c * n + k];
-    w[k] = acc;
+    w[k] = acc * inv[k] * inv[k];
 }
 
 // Stable ascending rank of each eigenvalue: ties keep diagonal order.
@@ -805,15 +808,20 @@ __global__ __launch_bounds__(256) void rank_kernel(const double *__restrict__ w,
         perm[rank] = (int)i;
 }
 
-// Sign of each output column: the entry of largest magnitude (lowest row on
-// ties) becomes positive.  Two passes so that V is read along rows: pass 1
-// scans row chunk z for every column j (threads over j), pass 2 reduces the
-// chunks in order for each output column.
+// Column statistics of the accumulated V, read along rows: pass 1 scans row
+// chunk z for every column j (threads over j) and keeps the entry of largest
+// magnitude (lowest row on ties) and the sum of squares; pass 2 reduces the
+// chunks in order.  The output columns are scaled to unit 2-norm: the rounding
+// of the rotations lets the column norms drift by a random walk while the
+// columns stay orthogonal to each other to a much smaller error, so the scaling
+// removes nearly all of ||V^T V - I||.  The entry of largest magnitude becomes
+// positive (sign convention).
 constexpr int SIGN_CHUNKS = 16;
 
 __global__ __launch_bounds__(256) void colmax_kernel(const double *__restrict__ V, int64_t ldv,
                                                      int64_t n, double *__restrict__ cmax,
-                                                     int *__restrict__ cidx)
+                                                     int *__restrict__ cidx,
+                                                     double *__restrict__ csq)
 {
     const int64_t j = blockIdx.x * 256 + threadIdx.x;
     const int z = blockIdx.y;
@@ -821,10 +829,12 @@ __global__ __launch_bounds__(256) void colmax_kernel(const double *__restrict__ 
         return;
     const int64_t chunk = (n + SIGN_CHUNKS - 1) / SIGN_CHUNKS;
     const int64_t i0 = z * chunk, i1 = (i0 + chunk < n) ? i0 + chunk : n;
-    double best = -1.0;
+    double best = -1.0, sq = 0.0;
     int64_t bi = i0 < n ? i0 : 0;
     for (int64_t i = i0; i < i1; ++i) {
-        double a = fabs(V[i * ldv + j]);
+        const double v = V[i * ldv + j];
+        const double a = fabs(v);
+        sq = fma(v, v, sq);
         if (a > best) {
             best = a;
             bi = i;
@@ -832,12 +842,31 @@ __global__ __launch_bounds__(256) void colmax_kernel(const double *__restrict__ 
     }
     cmax[z * n + j] = best;
     cidx[z * n + j] = (int)bi;
+    csq[z * n + j] = sq;
+}
+
+// inv[j] = 1 / ||V[:, j]|| for j < n, 1 for the padding columns j < npad
+__global__ __launch_bounds__(256) void colinv_kernel(const double *__restrict__ csq, int64_t n,
+                                                     int64_t npad, double *__restrict__ inv)
+{
+    const int64_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= npad)
+        return;
+    if (j >= n) {
+        inv[j] = 1.0;
+        return;
+    }
+    double sq = 0.0;
+    for (int z = 0; z < SIGN_CHUNKS; ++z)
+        sq += csq[z * n + j];
+    inv[j] = sq > 0.0 ? 1.0 / sqrt(sq) : 1.0;
 }
 
 __global__ __launch_bounds__(256) void colsign_kernel(const double *__restrict__ V, int64_t ldv,
                                                       int64_t n, const int *__restrict__ perm,
                                                       const double *__restrict__ cmax,
                                                       const int *__restrict__ cidx,
+                                                      const double *__restrict__ inv,
                                                       double *__restrict__ sg)
 {
     const int64_t c = blockIdx.x * 256 + threadIdx.x;
@@ -853,7 +882,21 @@ __global__ __launch_bounds__(256) void colsign_kernel(const double *__restrict__
             bi = cidx[z * n + col];
         }
     }
-    sg[c] = V[(int64_t)bi * ldv + col] < 0.0 ? -1.0 : 1.0;
+    sg[c] = V[(int64_t)bi * ldv + col] < 0.0 ? -inv[col] : inv[col];
+}
+
+// dst[i][j] = inv[i] src[i][j] - sub[i][j] (sub may be null), rows x k; dst may
+// be src (each element is read and written by the same thread)
+__global__ __launch_bounds__(256) void rowscale_kernel(const double *src,
+                                                       const double *__restrict__ inv,
+                                                       const double *sub, double *dst,
+                                                       int64_t rows, int k)
+{
+    const int64_t total = rows * k;
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const double v = inv[e / k] * src[e];
+        dst[e] = sub ? v - sub[e] : v;
+    }
 }
 
 __global__ __launch_bounds__(256) void permute_out_kernel(const double *__restrict__ V,
@@ -882,12 +925,30 @@ hipError_t launch_diag(const double *B, int64_t ldb, int64_t n, double *w, hipSt
 }
 
 hipError_t launch_rayleigh(const double *V, int64_t ldv, const double *T, int64_t ldt,
-                           int64_t n, double *part, double *w, hipStream_t s)
+                           int64_t n, const double *inv, double *part, double *w, hipStream_t s)
 {
     int g = (int)((n + 255) / 256);
     hipLaunchKernelGGL(rq_partial_kernel, dim3(g, RQ_CHUNKS), dim3(256), 0, s, V, ldv, T, ldt,
                        n, part);
-    hipLaunchKernelGGL(rq_sum_kernel, dim3(g), dim3(256), 0, s, part, n, w);
+    hipLaunchKernelGGL(rq_sum_kernel, dim3(g), dim3(256), 0, s, part, n, inv, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_colstats(const double *V, int64_t ldv, int64_t n, int64_t npad, double *cmax,
+                           int *cidx, double *csq, double *inv, hipStream_t s)
+{
+    const int g = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(colmax_kernel, dim3(g, SIGN_CHUNKS), dim3(256), 0, s, V, ldv, n, cmax,
+                       cidx, csq);
+    hipLaunchKernelGGL(colinv_kernel, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, s, csq,
+                       n, npad, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowscale(const double *src, const double *inv, const double *sub, double *dst,
+                           int64_t rows, int k, hipStream_t s)
+{
+    hipLaunchKernelGGL(rowscale_kernel, dim3(64), dim3(256), 0, s, src, inv, sub, dst, rows, k);
     return hipGetLastError();
 }
 
@@ -895,14 +956,13 @@ hipError_t launch_rayleigh(const double *V, int64_t ldv, const double *T, int64_
 // permutation and sign convention.
 hipError_t launch_finalize(const double *w, const double *V, int64_t ldv_in, int64_t n,
                            double *W, double *Vout, int64_t ldv, int *perm, double *sg,
-                           double *cmax, int *cidx, hipStream_t s)
+                           const double *cmax, const int *cidx, const double *inv,
+                           hipStream_t s)
 {
     int g = (int)((n + 255) / 256);
     hipLaunchKernelGGL(rank_kernel, dim3(g), dim3(256), 0, s, w, n, perm);
-    hipLaunchKernelGGL(colmax_kernel, dim3(g, SIGN_CHUNKS), dim3(256), 0, s, V, ldv_in, n, cmax,
-                       cidx);
     hipLaunchKernelGGL(colsign_kernel, dim3(g), dim3(256), 0, s, V, ldv_in, n, perm, cmax, cidx,
-                       sg);
+                       inv, sg);
     hipLaunchKernelGGL(permute_out_kernel, dim3(2048), dim3(256), 0, s, V, ldv_in, n, perm, sg,
                        w, W, Vout, ldv);
     return hipGetLastError();

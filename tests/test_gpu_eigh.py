@@ -138,6 +138,45 @@ def test_mixed_vs_oracle(pj, n):
     assert info["off_cond"] <= 10 * n * 2.0 ** -24 * np.linalg.norm(A)
 
 
+def test_mixed_one_ns_step_polished(pj):
+    """One Newton-Schulz step leaves Q_d with an orthogonality error far above
+    the bar (about 1e-10 here).  The output stage must detect it (randomized
+    estimate) and apply its own Newton-Schulz step, so that V meets the
+    orthogonality and residual bars.  The eigenvalues of Q_d^T A Q_d still
+    differ from A's by about that error times ||A||, which is why two steps
+    are the default; that bound is what is checked for W."""
+    A = wl.goe(300, 78)
+    W, V, info = run(pj, "eigh_mixed", A, ns_iters=1)
+    n = A.shape[0]
+    assert info["ns_iters"] == 1
+    assert info["polished"] == 1
+    Wo, *_ = oracle.eigh(A)
+    nrm2 = np.abs(Wo).max()
+    res = np.linalg.norm(A @ V - V * W) / np.linalg.norm(A)
+    orth = np.linalg.norm(V.T @ V - np.eye(n))
+    err = np.abs(W - Wo).max()
+    print(f"  ns=1: orth_ns={info['orth_ns']:.2e} |dW|/|A|={err / nrm2:.2e} res={res:.2e} "
+          f"orth={orth:.2e}", flush=True)
+    assert orth <= 1e-14 * n
+    assert res <= 1e-13 * n
+    assert err <= 10 * info["orth_ns"] * nrm2
+
+
+def test_output_columns_normalized(pj):
+    """The output stage scales every eigenvector to unit norm: the column norms
+    are 1 to a few ulps, on both block paths.  (n = 300: at n = 512 the oracle's
+    own eigenvalues, the diagonal after its sweeps, already drift by about
+    1.4e-13 ||A||_2 on this input.)"""
+    A = wl.goe(300, 79)
+    for fn in ("eigh", "eigh_mixed"):
+        W, V, info = run(pj, fn, A, small_max_n=-1)
+        dev = np.abs(np.linalg.norm(V, axis=0) - 1.0).max()
+        print(f"  {fn}: max | ||v_k|| - 1 | = {dev:.2e}", flush=True)
+        assert dev <= 64 * 2.0 ** -53
+        Wo, Vo, *_ = oracle.eigh(A)
+        check(A, W, V, Wo, Vo, fn)
+
+
 def test_mixed_goe(pj):
     A = wl.goe(256, 77)
     W, V, info = run(pj, "eigh_mixed", A)
