@@ -202,7 +202,7 @@ BlockWs layout_block(Bump &bp, int64_t n, const Geometry &g, bool mixed)
     w.B64 = bp.take<double>(nn);
     w.V64 = bp.take<double>(nn);
     w.U64 = bp.take<double>(2 * uu); // double-buffered across rounds
-    w.probe = bp.take<double>((size_t)g.npad * 3 * NPROBE);
+    w.probe = bp.take<double>((size_t)g.npad * 2 * NPROBE + (size_t)16 * NPROBE * std::max<int64_t>(n, 1));
     if (!mixed)
         w.Vt = bp.take<double>(nn);
     if (mixed) {
@@ -790,17 +790,11 @@ int finalize_block(const Geometry &g, int64_t n, const BlockWs &w, const double 
     const int64_t np = g.npad;
     CK(launch_diag(B, np, n, w.wtmp, s));
     CK(launch_colstats(Vin, np, n, np, w.cmax, w.cidx, w.csq, w.cinv, s));
-    double *X = w.probe, *Y = w.probe + np * NPROBE, *Z = w.probe + 2 * np * NPROBE;
+    double *X = w.probe, *Y = w.probe + np * NPROBE, *P = w.probe + 2 * np * NPROBE;
     CK(launch_rademacher(X, np, n, NPROBE, 0x5eedull, s));
-    // Z = D^-1 X, Y = V Z, Z = V^T Y, Z = D^-1 Z - X = (D^-1 V^T V D^-1 - I) X
-    CK(launch_rowscale(X, w.cinv, nullptr, Z, np, NPROBE, s));
-    CK(launch_gemm64(0, 0, np, NPROBE, np, 1.0, Vin, np, 0, Z, NPROBE, 0, 0.0, nullptr, 0, 0,
-                     0.0, Y, NPROBE, 0, 1, s));
-    CK(launch_gemm64(1, 0, np, NPROBE, np, 1.0, Vin, np, 0, Y, NPROBE, 0, 0.0, nullptr, 0, 0,
-                     0.0, Z, NPROBE, 0, 1, s));
-    CK(launch_rowscale(Z, w.cinv, X, Z, np, NPROBE, s));
-    CK(launch_sq_partial(Z, np * NPROBE, w.partial, s));
-    CK(launch_sum(w.partial, OFF_BLOCKS, w.scal + 3, s));
+    constexpr int PROBE_BLOCKS = 64;
+    CK(launch_orth_probe(Vin, np, n, np, NPROBE, X, w.cinv, Y, P, w.partial, PROBE_BLOCKS, s));
+    CK(launch_sum(w.partial, PROBE_BLOCKS, w.scal + 3, s));
     Readback rb;
     if (int e = read_scalars(w, s, rb))
         return e;

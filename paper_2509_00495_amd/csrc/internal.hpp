@@ -87,9 +87,12 @@ hipError_t launch_rayleigh(const double *V, int64_t ldv, const double *T, int64_
 // entries, 1 past n)
 hipError_t launch_colstats(const double *V, int64_t ldv, int64_t n, int64_t npad, double *cmax,
                            int *cidx, double *csq, double *inv, hipStream_t s);
-// dst = diag(inv) src - sub (sub may be null), rows x k row-major
-hipError_t launch_rowscale(const double *src, const double *inv, const double *sub, double *dst,
-                           int64_t rows, int k, hipStream_t s);
+// partial[b] (b < nblocks) = block sums of ||D^-1 V^T V D^-1 X - X||^2 over the
+// k = 4 columns of X (npad x 4, zero past n), D^-1 = diag(inv); Y (npad x 4)
+// and P (16 n x 4) are scratch
+hipError_t launch_orth_probe(const double *V, int64_t ldv, int64_t n, int64_t npad, int k,
+                             const double *X, const double *inv, double *Y, double *P,
+                             double *partial, int nblocks, hipStream_t s);
 // ascending order of w, output columns V[:, perm] scaled by sign / norm
 hipError_t launch_finalize(const double *w, const double *V, int64_t ldv_in, int64_t n,
                            double *W, double *Vout, int64_t ldv, int *perm, double *sg,

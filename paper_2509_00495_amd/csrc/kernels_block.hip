@@ -885,20 +885,6 @@ __global__ __launch_bounds__(256) void colsign_kernel(const double *__restrict__
     sg[c] = V[(int64_t)bi * ldv + col] < 0.0 ? -inv[col] : inv[col];
 }
 
-// dst[i][j] = inv[i] src[i][j] - sub[i][j] (sub may be null), rows x k; dst may
-// be src (each element is read and written by the same thread)
-__global__ __launch_bounds__(256) void rowscale_kernel(const double *src,
-                                                       const double *__restrict__ inv,
-                                                       const double *sub, double *dst,
-                                                       int64_t rows, int k)
-{
-    const int64_t total = rows * k;
-    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-        const double v = inv[e / k] * src[e];
-        dst[e] = sub ? v - sub[e] : v;
-    }
-}
-
 __global__ __launch_bounds__(256) void permute_out_kernel(const double *__restrict__ V,
                                                           int64_t ldv_in, int64_t n,
                                                           const int *__restrict__ perm,
@@ -945,13 +931,6 @@ hipError_t launch_colstats(const double *V, int64_t ldv, int64_t n, int64_t npad
     return hipGetLastError();
 }
 
-hipError_t launch_rowscale(const double *src, const double *inv, const double *sub, double *dst,
-                           int64_t rows, int k, hipStream_t s)
-{
-    hipLaunchKernelGGL(rowscale_kernel, dim3(64), dim3(256), 0, s, src, inv, sub, dst, rows, k);
-    return hipGetLastError();
-}
-
 // Output stage from the extracted diagonal w: stable ascending order, column
 // permutation and sign convention.
 hipError_t launch_finalize(const double *w, const double *V, int64_t ldv_in, int64_t n,
@@ -988,6 +967,150 @@ hipError_t launch_rademacher(double *X, int64_t rows, int64_t n, int k, uint64_t
                              hipStream_t s)
 {
     hipLaunchKernelGGL(rademacher_kernel, dim3(64), dim3(256), 0, s, X, rows, n, k, seed);
+    return hipGetLastError();
+}
+
+// Orthogonality probe of the output stage, for 4 probe vectors X (n_pad x 4,
+// zero past n) and the column scaling D^-1 = diag(inv):
+//   Y = V D^-1 X                     (probe_vx_kernel, rows of V),
+//   P_z = V[rows of chunk z]^T Y     (probe_vty_kernel, columns of V),
+//   r = D^-1 sum_z P_z - X, partial sums of r^2 per block (probe_resid_kernel).
+// ||r||_F^2 / 4 estimates ||D^-1 V^T V D^-1 - I||_F^2.  Each pass reads V
+// once along its rows (the products are HBM-bound).
+constexpr int PROBE_K = 4, PROBE_CHUNKS = 16, PROBE_JC = 512, PROBE_ROWS = 2;
+
+__global__ __launch_bounds__(256) void probe_vx_kernel(const double *__restrict__ V,
+                                                       int64_t ldv, int64_t n, int64_t npad,
+                                                       const double *__restrict__ X,
+                                                       const double *__restrict__ inv,
+                                                       double *__restrict__ Y)
+{
+    typedef double dv2p __attribute__((ext_vector_type(2)));
+    __shared__ __align__(16) double xs[PROBE_JC * PROBE_K];
+    const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * PROBE_ROWS;
+    double acc[PROBE_ROWS][PROBE_K];
+#pragma unroll
+    for (int r = 0; r < PROBE_ROWS; ++r)
+#pragma unroll
+        for (int c = 0; c < PROBE_K; ++c)
+            acc[r][c] = 0.0;
+    for (int64_t j0 = 0; j0 < n; j0 += PROBE_JC) {
+        __syncthreads();
+        for (int e = tid; e < PROBE_JC * PROBE_K; e += 256) {
+            const int64_t j = j0 + e / PROBE_K;
+            xs[e] = j < n ? inv[j] * X[j * PROBE_K + e % PROBE_K] : 0.0;
+        }
+        __syncthreads();
+        // lane reads columns j0 + 128 q + 2 lane, + 1 (q < 4): one 16-byte load
+        // per row and q, consecutive lanes at consecutive addresses; npad is
+        // even, so a pair is in range or out of range as a whole
+#pragma unroll
+        for (int q = 0; q < PROBE_JC / 128; ++q) {
+            const int jc = 128 * q + 2 * lane;
+            if (j0 + jc >= npad)
+                break;
+            double xv[2][PROBE_K];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int c = 0; c < PROBE_K; ++c)
+                    xv[h][c] = xs[(jc + h) * PROBE_K + c];
+#pragma unroll
+            for (int r = 0; r < PROBE_ROWS; ++r) {
+                if (r0 + r >= npad)
+                    break;
+                const dv2p v = *reinterpret_cast<const dv2p *>(V + (r0 + r) * ldv + j0 + jc);
+#pragma unroll
+                for (int c = 0; c < PROBE_K; ++c)
+                    acc[r][c] = fma(v[1], xv[1][c], fma(v[0], xv[0][c], acc[r][c]));
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < PROBE_ROWS; ++r)
+#pragma unroll
+        for (int c = 0; c < PROBE_K; ++c) {
+            const double v = wave_sum(acc[r][c]);
+            if (lane == 0 && r0 + r < npad)
+                Y[(r0 + r) * PROBE_K + c] = v;
+        }
+}
+
+__global__ __launch_bounds__(256) void probe_vty_kernel(const double *__restrict__ V,
+                                                        int64_t ldv, int64_t n, int64_t npad,
+                                                        const double *__restrict__ Y,
+                                                        double *__restrict__ P)
+{
+    constexpr int YR = 1024; // rows of Y staged in LDS at a time
+    __shared__ __align__(16) double ys[YR * PROBE_K];
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int z = blockIdx.y;
+    const int64_t chunk = (npad + PROBE_CHUNKS - 1) / PROBE_CHUNKS;
+    const int64_t i0 = z * chunk, i1 = i0 + chunk < npad ? i0 + chunk : npad;
+    double acc[PROBE_K] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t ib = i0; ib < i1; ib += YR) {
+        const int64_t ie = ib + YR < i1 ? ib + YR : i1;
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < (ie - ib) * PROBE_K; e += 256)
+            ys[e] = Y[ib * PROBE_K + e];
+        __syncthreads();
+        if (j < n) {
+#pragma unroll 8
+            for (int64_t i = ib; i < ie; ++i) {
+                const double v = V[i * ldv + j];
+#pragma unroll
+                for (int c = 0; c < PROBE_K; ++c)
+                    acc[c] = fma(v, ys[(i - ib) * PROBE_K + c], acc[c]);
+            }
+        }
+    }
+    if (j < n) {
+#pragma unroll
+        for (int c = 0; c < PROBE_K; ++c)
+            P[((int64_t)z * n + j) * PROBE_K + c] = acc[c];
+    }
+}
+
+__global__ __launch_bounds__(256) void probe_resid_kernel(const double *__restrict__ P,
+                                                          int64_t n,
+                                                          const double *__restrict__ X,
+                                                          const double *__restrict__ inv,
+                                                          double *__restrict__ partial)
+{
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * 256) {
+#pragma unroll
+        for (int c = 0; c < PROBE_K; ++c) {
+            double zsum = 0.0;
+            for (int z = 0; z < PROBE_CHUNKS; ++z)
+                zsum += P[((int64_t)z * n + j) * PROBE_K + c];
+            const double r = inv[j] * zsum - X[j * PROBE_K + c];
+            acc = fma(r, r, acc);
+        }
+    }
+    acc = wave_sum(acc);
+    if (threadIdx.x % WAVE == 0)
+        red[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+hipError_t launch_orth_probe(const double *V, int64_t ldv, int64_t n, int64_t npad, int k,
+                             const double *X, const double *inv, double *Y, double *P,
+                             double *partial, int nblocks, hipStream_t s)
+{
+    if (k != PROBE_K || npad % 8 != 0 || nblocks < 1)
+        return hipErrorInvalidValue;
+    const unsigned g1 = (unsigned)((npad + 4 * PROBE_ROWS - 1) / (4 * PROBE_ROWS));
+    hipLaunchKernelGGL(probe_vx_kernel, dim3(g1), dim3(256), 0, s, V, ldv, n, npad, X, inv, Y);
+    hipLaunchKernelGGL(probe_vty_kernel, dim3((unsigned)((n + 255) / 256), PROBE_CHUNKS),
+                       dim3(256), 0, s, V, ldv, n, npad, Y, P);
+    hipLaunchKernelGGL(probe_resid_kernel, dim3((unsigned)nblocks), dim3(256), 0, s, P, n, X,
+                       inv, partial);
     return hipGetLastError();
 }
 

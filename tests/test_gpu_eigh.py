@@ -173,6 +173,10 @@ def test_output_columns_normalized(pj):
         dev = np.abs(np.linalg.norm(V, axis=0) - 1.0).max()
         print(f"  {fn}: max | ||v_k|| - 1 | = {dev:.2e}", flush=True)
         assert dev <= 64 * 2.0 ** -53
+        # the randomized estimate (4 probes) tracks the true orthogonality
+        orth = np.linalg.norm(V.T @ V - np.eye(A.shape[0]))
+        print(f"  {fn}: orth={orth:.2e} estimate={info['orth_est']:.2e}", flush=True)
+        assert orth / 4 <= info["orth_est"] <= 4 * orth
         Wo, Vo, *_ = oracle.eigh(A)
         check(A, W, V, Wo, Vo, fn)
 
