@@ -804,7 +804,7 @@ int finalize_block(const Geometry &g, int64_t n, const BlockWs &w, const double 
     const double *Vf = Vin;
     if (!(est <= POLISH_FRAC * 1e-14 * (double)n)) {
         CK(launch_gemm64_sym(1, 0, np, np, -1.0, Vin, np, Vin, np, 0.0, nullptr, 0, 1.0, Rbuf,
-                             np, s));
+                             np, s, Vbuf, np * np));
         CK(launch_gemm64(0, 0, np, np, np, 0.5, Vin, np, 0, Rbuf, np, 0, 1.0, Vin, np, 0, 0.0,
                          Vbuf, np, 0, 1, s));
         Vf = Vbuf;
@@ -916,7 +916,7 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     double orth = 0.0;
     for (int it = 0; it < max_it; ++it) {
         CK(launch_gemm64_sym(1, 0, g.npad, g.npad, -1.0, X, g.npad, X, g.npad, 0.0, nullptr, 0,
-                             1.0, R, g.npad, s));
+                             1.0, R, g.npad, s, X2, nn));
         if (adaptive || it == max_it - 1) {
             CK(launch_sq_partial(R, nn, w.partial, s));
             CK(launch_sum(w.partial, OFF_BLOCKS, w.scal + 2, s));
@@ -937,7 +937,7 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     CK(launch_gemm64(0, 0, g.npad, g.npad, g.npad, 1.0, A64, g.npad, 0, X, g.npad, 0, 0.0,
                      nullptr, 0, 0, 0.0, R, g.npad, 0, 1, s));
     CK(launch_gemm64_sym(1, 0, g.npad, g.npad, 1.0, X, g.npad, R, g.npad, 0.0, nullptr, 0, 0.0,
-                         A64, g.npad, s));
+                         A64, g.npad, s, X2, nn));
     const double tol = tol_in > 0.0 ? tol_in : 1e-15 * (double)n * normf;
     int sw64 = 0;
     double off = 0.0, offc = 0.0;

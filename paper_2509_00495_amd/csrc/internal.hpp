@@ -114,11 +114,16 @@ hipError_t launch_gemm64(int transA, int transB, int64_t M, int64_t N, int64_t K
                          double *C, int64_t ldc, int64_t sC, int64_t batch,
                          hipStream_t s);
 // The same for a square N x N result known to be symmetric (alpha op(A) op(B)
-// symmetric and C0 symmetric): upper tiles computed, mirrored below.
+// symmetric and C0 symmetric): upper tiles computed, mirrored below.  With a
+// scratch buffer (device, scratch_doubles entries, not aliasing the operands)
+// large enough for the split tiles, a product with more tiles than resident
+// workgroups splits its (tile, K stage) iterations evenly over them and adds
+// the two parts of each split tile in a fix-up pass.
 hipError_t launch_gemm64_sym(int transA, int transB, int64_t N, int64_t K, double alpha,
                              const double *A, int64_t lda, const double *B, int64_t ldb,
                              double beta, const double *C0, int64_t ldc0, double gamma, double *C,
-                             int64_t ldc, hipStream_t s);
+                             int64_t ldc, hipStream_t s, double *scratch = nullptr,
+                             int64_t scratch_doubles = 0);
 hipError_t launch_sq_partial(const double *X, int64_t count, double *partial,
                              hipStream_t s);
 // backward elementwise: M <- diag(dW) + F o M (F from gaps), flags DEGENERATE

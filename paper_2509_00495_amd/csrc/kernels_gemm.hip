@@ -127,33 +127,34 @@ __global__ __launch_bounds__(256) void gemm64_kernel(int64_t M, int64_t N, int64
 constexpr int BT = 128, BK = 16, BLD = BT + 16;
 typedef double dv2g __attribute__((ext_vector_type(2)));
 
-template <int TA, int TB, bool SYM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void gemm128_kernel(int64_t M, int64_t N, int64_t K,
-                                                      double alpha,
-                                                      const double *__restrict__ A, int64_t lda,
-                                                      const double *__restrict__ B, int64_t ldb,
-                                                      double beta,
-                                                      const double *__restrict__ C0,
-                                                      int64_t ldc0, double gamma,
-                                                      double *__restrict__ C, int64_t ldc,
-                                                      int tiles_n)
+// Upper-triangular tile t of a tiles_n x tiles_n grid (row by <= column bx),
+// numbered along rows.
+__device__ inline void tri_tile(int t, int tiles_n, int &by, int &bx)
 {
-    __shared__ __align__(16) double sm[2][2][BK * BLD]; // [buffer][A or B][k][i or j]
+    int r = 0;
+    while (t >= tiles_n - r) {
+        t -= tiles_n - r;
+        ++r;
+    }
+    by = r;
+    bx = r + t;
+}
+
+// K stages [s0, s1) of tile (by, bx).  part == nullptr: the tile is complete
+// and goes to C (alpha, beta C0, gamma I, mirrored when SYM and off the
+// diagonal); otherwise the raw accumulator goes to part (BT x BT, row-major)
+// for the fix-up pass that adds the tile's two parts.
+template <int TA, int TB, bool SYM>
+__device__ inline void gemm128_segment(int64_t M, int64_t N, int64_t K, double alpha,
+                                       const double *__restrict__ A, int64_t lda,
+                                       const double *__restrict__ B, int64_t ldb, double beta,
+                                       const double *__restrict__ C0, int64_t ldc0,
+                                       double gamma, double *__restrict__ C, int64_t ldc,
+                                       int by, int bx, int s0, int s1, double *__restrict__ part,
+                                       double (*sm)[2][BK * BLD])
+{
     const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
     const int li = lane % 16, lk = lane / 16;
-    int by, bx;
-    if (SYM) { // linear index -> upper-triangular tile (by <= bx)
-        int t = blockIdx.x, r = 0;
-        while (t >= tiles_n - r) {
-            t -= tiles_n - r;
-            ++r;
-        }
-        by = r;
-        bx = r + t;
-    } else {
-        by = blockIdx.y;
-        bx = blockIdx.x;
-    }
     const int64_t i0 = (int64_t)by * BT, j0 = (int64_t)bx * BT;
     const int row0 = (w / 2) * 64, col0 = (w % 2) * 64;
     // operand staging: 2048 doubles per matrix and stage = 8 per thread as
@@ -250,13 +251,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 acc[a][b][v] = 0.0;
-    const int nst = (int)((K + BK - 1) / BK);
-    load(0);
+    load((int64_t)s0 * BK);
     store(0);
     __syncthreads();
-    for (int st = 0; st < nst; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < nst)
+    for (int st = s0; st < s1; ++st) {
+        const int buf = (st - s0) & 1;
+        if (st + 1 < s1)
             load((int64_t)(st + 1) * BK);
         const double *As = sm[buf][0], *Bs = sm[buf][1];
 #pragma unroll
@@ -274,9 +274,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 for (int b = 0; b < 4; ++b)
                     acc[a][b] = mfma16(fa[a], fb[b], acc[a][b]);
         }
-        if (st + 1 < nst)
+        if (st + 1 < s1)
             store(buf ^ 1); // the other buffer was last read before the previous barrier
         __syncthreads();
+    }
+    if (part) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    part[(row0 + a * 16 + acc_row<double>(lk, v)) * BT + col0 + b * 16 + li] =
+                        acc[a][b][v];
+        return;
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -299,6 +310,95 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             }
 }
 
+
+template <int TA, int TB, bool SYM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void gemm128_kernel(
+    int64_t M, int64_t N, int64_t K, double alpha, const double *__restrict__ A, int64_t lda,
+    const double *__restrict__ B, int64_t ldb, double beta, const double *__restrict__ C0,
+    int64_t ldc0, double gamma, double *__restrict__ C, int64_t ldc, int tiles_n)
+{
+    __shared__ __align__(16) double sm[2][2][BK * BLD]; // [buffer][A or B][k][i or j]
+    int by, bx;
+    if (SYM) {
+        tri_tile(blockIdx.x, tiles_n, by, bx);
+    } else {
+        by = blockIdx.y;
+        bx = blockIdx.x;
+    }
+    gemm128_segment<TA, TB, SYM>(M, N, K, alpha, A, lda, B, ldb, beta, C0, ldc0, gamma, C, ldc,
+                                 by, bx, 0, (int)((K + BK - 1) / BK), nullptr, sm);
+}
+
+// Symmetric product with more upper tiles than resident workgroups: the
+// (tile, K stage) iterations are split evenly over the G workgroups
+// (workgroup g takes [g T / G, (g + 1) T / G) of T = tiles x stages), so
+// every workgroup does the same work and none runs a second, partly empty
+// wave.  With at least G tiles a workgroup's run is at least one tile long,
+// so a tile is split by at most one boundary: boundary g (between
+// workgroups g - 1 and g) leaves its tile's first part in scratch slot
+// 2 (g - 1) and its second part in slot 2 (g - 1) + 1, and the fix-up pass
+// adds them (two terms: the same sum whichever finishes first).
+template <int TA, int TB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void gemm128_sk_kernel(
+    int64_t M, int64_t N, int64_t K, double alpha, const double *__restrict__ A, int64_t lda,
+    const double *__restrict__ B, int64_t ldb, double beta, const double *__restrict__ C0,
+    int64_t ldc0, double gamma, double *__restrict__ C, int64_t ldc, int tiles_n, int ntiles,
+    double *__restrict__ scratch)
+{
+    __shared__ __align__(16) double sm[2][2][BK * BLD];
+    const int nst = (int)((K + BK - 1) / BK);
+    const int64_t total = (int64_t)ntiles * nst;
+    const int g = blockIdx.x, G = gridDim.x;
+    int64_t p0 = (int64_t)g * total / G;
+    const int64_t p1 = (int64_t)(g + 1) * total / G;
+    while (p0 < p1) {
+        const int t = (int)(p0 / nst), s0 = (int)(p0 % nst);
+        const int s1 = (int)((p1 - (int64_t)t * nst) < nst ? p1 - (int64_t)t * nst : nst);
+        int by, bx;
+        tri_tile(t, tiles_n, by, bx);
+        double *part = nullptr;
+        if (s0 > 0)
+            part = scratch + (int64_t)(2 * (g - 1) + 1) * BT * BT;
+        else if (s1 < nst)
+            part = scratch + (int64_t)(2 * g) * BT * BT;
+        gemm128_segment<TA, TB, true>(M, N, K, alpha, A, lda, B, ldb, beta, C0, ldc0, gamma, C,
+                                      ldc, by, bx, s0, s1, part, sm);
+        p0 += s1 - s0;
+    }
+}
+
+// Fix-up of the split tiles: workgroup g - 1 handles boundary g (1 <= g < G).
+__global__ __launch_bounds__(256) void gemm128_sk_fixup_kernel(
+    int64_t M, int64_t N, int64_t K, double alpha, double beta, const double *__restrict__ C0,
+    int64_t ldc0, double gamma, double *__restrict__ C, int64_t ldc, int tiles_n, int ntiles,
+    int G, const double *__restrict__ scratch)
+{
+    const int g = blockIdx.x + 1;
+    const int nst = (int)((K + BK - 1) / BK);
+    const int64_t total = (int64_t)ntiles * nst;
+    const int64_t p = (int64_t)g * total / G;
+    if (p % nst == 0)
+        return; // the boundary falls between tiles
+    int by, bx;
+    tri_tile((int)(p / nst), tiles_n, by, bx);
+    const double *p0 = scratch + (int64_t)(2 * (g - 1)) * BT * BT;
+    const double *p1 = p0 + BT * BT;
+    const int64_t i0 = (int64_t)by * BT, j0 = (int64_t)bx * BT;
+    for (int e = threadIdx.x; e < BT * BT; e += 256) {
+        const int64_t gi = i0 + e / BT, gj = j0 + e % BT;
+        if (gi < M && gj < N) {
+            double r = alpha * (p0[e] + p1[e]);
+            if (beta != 0.0)
+                r += beta * C0[gi * ldc0 + gj];
+            if (gi == gj)
+                r += gamma;
+            C[gi * ldc + gj] = r;
+            if (bx != by)
+                C[gj * ldc + gi] = r;
+        }
+    }
+}
+
 template <bool SYM>
 static bool gemm128_fits(int64_t M, int64_t N, const double *A, int64_t lda, const double *B,
                          int64_t ldb)
@@ -307,14 +407,47 @@ static bool gemm128_fits(int64_t M, int64_t N, const double *A, int64_t lda, con
            (reinterpret_cast<uintptr_t>(A) % 16) == 0 && (reinterpret_cast<uintptr_t>(B) % 16) == 0;
 }
 
+static int gemm_resident_slots()
+{
+    static int slots = 0; // two workgroups per compute unit (waves_per_eu(2, 2))
+    if (slots == 0) {
+        int dev = 0, cus = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        slots = 2 * (cus > 0 ? cus : 256);
+    }
+    return slots;
+}
+
 template <bool SYM>
 static hipError_t launch_gemm128(int transA, int transB, int64_t M, int64_t N, int64_t K,
                                  double alpha, const double *A, int64_t lda, const double *B,
                                  int64_t ldb, double beta, const double *C0, int64_t ldc0,
-                                 double gamma, double *C, int64_t ldc, hipStream_t s)
+                                 double gamma, double *C, int64_t ldc, double *scratch,
+                                 int64_t scratch_doubles, hipStream_t s)
 {
     const int tn = (int)((N + BT - 1) / BT), tm = (int)((M + BT - 1) / BT);
-    dim3 grid = SYM ? dim3((unsigned)(tn * (tn + 1) / 2)) : dim3((unsigned)tn, (unsigned)tm);
+    const int ntiles = tn * (tn + 1) / 2;
+    const int G = gemm_resident_slots();
+    if (SYM && ntiles > G && K >= BK && scratch &&
+        scratch_doubles >= (int64_t)2 * (G - 1) * BT * BT) {
+#define LJ_GSK(TA_, TB_)                                                                           \
+    hipLaunchKernelGGL((gemm128_sk_kernel<TA_, TB_>), dim3((unsigned)G), dim3(256), 0, s, M, N, K,  \
+                       alpha, A, lda, B, ldb, beta, C0, ldc0, gamma, C, ldc, tn, ntiles, scratch)
+        if (!transA && !transB)
+            LJ_GSK(0, 0);
+        else if (transA && !transB)
+            LJ_GSK(1, 0);
+        else if (!transA && transB)
+            LJ_GSK(0, 1);
+        else
+            LJ_GSK(1, 1);
+#undef LJ_GSK
+        hipLaunchKernelGGL(gemm128_sk_fixup_kernel, dim3((unsigned)(G - 1)), dim3(256), 0, s, M,
+                           N, K, alpha, beta, C0, ldc0, gamma, C, ldc, tn, ntiles, G, scratch);
+        return hipGetLastError();
+    }
+    dim3 grid = SYM ? dim3((unsigned)ntiles) : dim3((unsigned)tn, (unsigned)tm);
 #define LJ_G128(TA_, TB_)                                                                          \
     hipLaunchKernelGGL((gemm128_kernel<TA_, TB_, SYM>), grid, dim3(256), 0, s, M, N, K, alpha, A,  \
                        lda, B, ldb, beta, C0, ldc0, gamma, C, ldc, tn)
@@ -335,13 +468,14 @@ static hipError_t launch_gemm64_t(int transA, int transB, int64_t M, int64_t N, 
                                   double alpha, const double *A, int64_t lda, int64_t sA,
                                   const double *B, int64_t ldb, int64_t sB, double beta,
                                   const double *C0, int64_t ldc0, int64_t sC0, double gamma,
-                                  double *C, int64_t ldc, int64_t sC, int64_t batch, hipStream_t s)
+                                  double *C, int64_t ldc, int64_t sC, int64_t batch,
+                                  double *scratch, int64_t scratch_doubles, hipStream_t s)
 {
     if (M <= 0 || N <= 0 || batch <= 0)
         return hipSuccess;
     if (batch == 1 && gemm128_fits<SYM>(M, N, A, lda, B, ldb))
         return launch_gemm128<SYM>(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C0,
-                                   ldc0, gamma, C, ldc, s);
+                                   ldc0, gamma, C, ldc, scratch, scratch_doubles, s);
     dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT), (unsigned)batch);
     if (!transA && !transB)
         hipLaunchKernelGGL((gemm64_kernel<0, 0, SYM>), grid, dim3(256), 0, s, M, N, K, alpha, A,
@@ -365,16 +499,16 @@ hipError_t launch_gemm64(int transA, int transB, int64_t M, int64_t N, int64_t K
                          hipStream_t s)
 {
     return launch_gemm64_t<false>(transA, transB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta,
-                                  C0, ldc0, sC0, gamma, C, ldc, sC, batch, s);
+                                  C0, ldc0, sC0, gamma, C, ldc, sC, batch, nullptr, 0, s);
 }
 
 hipError_t launch_gemm64_sym(int transA, int transB, int64_t N, int64_t K, double alpha,
                              const double *A, int64_t lda, const double *B, int64_t ldb,
                              double beta, const double *C0, int64_t ldc0, double gamma, double *C,
-                             int64_t ldc, hipStream_t s)
+                             int64_t ldc, hipStream_t s, double *scratch, int64_t scratch_doubles)
 {
     return launch_gemm64_t<true>(transA, transB, N, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C0,
-                                 ldc0, 0, gamma, C, ldc, 0, 1, s);
+                                 ldc0, 0, gamma, C, ldc, 0, 1, scratch, scratch_doubles, s);
 }
 
 __global__ __launch_bounds__(256) void sq_partial_kernel(const double *__restrict__ X,
