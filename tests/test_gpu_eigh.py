@@ -114,6 +114,20 @@ def test_block_path_serial_v(pj, fn, serial_v):
     check(A, W, V, Wo, Vo, f"serial_v={serial_v} {fn}")
 
 
+@pytest.mark.parametrize("fn", ["eigh", "eigh_mixed"])
+def test_shared_launch_bitwise(pj, fn):
+    """The V update inside the next round's pair-solve launch (row ranges of
+    each pair's columns on the workgroups the solves leave free) does per tile
+    exactly the arithmetic of the standalone update kernel: the default and
+    serial_v = 1 agree bitwise.  A tile skipped or updated twice would break
+    this."""
+    A = wl.random_symmetric(520, 5200)
+    W0, V0, i0 = run(pj, fn, A, small_max_n=-1, block=32)
+    W1, V1, i1 = run(pj, fn, A, small_max_n=-1, block=32, serial_v=1)
+    assert i0["sweeps"] == i1["sweeps"]
+    assert np.array_equal(W0, W1) and np.array_equal(V0, V1)
+
+
 @pytest.mark.parametrize("n,block,inner", [(128, 16, 2), (192, 32, 3)])
 def test_block_path_inner_sweeps(pj, n, block, inner):
     A = wl.random_symmetric(n, 3000 + n)
