@@ -104,7 +104,9 @@ typedef struct jacobi_info {
     int32_t ns_iters;       /* Newton-Schulz iterations run (mixed only) */
     int32_t path;           /* 0 = one-workgroup solver, 1 = block path */
     int32_t block;          /* block size used by the block path */
-    int32_t polished;       /* 1 if the final Newton-Schulz refresh of V ran */
+    int32_t polished;       /* 1 if the output stage's Newton-Schulz step on V
+                               ran (the estimate below exceeded 0.2 of the
+                               1e-14 n bar) */
     int32_t reserved_i[2];
     double norm_f;          /* ||A||_F of the symmetrised input */
     double tol;             /* absolute threshold on off(B) actually used */
@@ -114,8 +116,9 @@ typedef struct jacobi_info {
     double orth_ns;         /* ||I - X^T X||_F of the last Newton-Schulz step of
                                the mixed pipeline (the residual it corrected) */
     double orth_est;        /* block path: randomized estimate of ||V^T V - I||_F
-                               of the accumulated eigenvectors before the final
-                               refresh (4 Rademacher probes) */
+                               of the accumulated eigenvectors with unit-norm
+                               columns, before any Newton-Schulz step (4
+                               Rademacher probes) */
     /* with opts->timing: summed kernel time (ms) and launch counts of the
      * block path, index 0 = FP64 stage, 1 = FP32 stage; "apply" is the update
      * of the off-diagonal tiles of B, "applyv" the update of V */
@@ -134,7 +137,9 @@ typedef struct jacobi_info {
  *   A    [in]  n x n, leading dimension lda >= max(1, n)
  *   n    [in]  order, n >= 0 (n = 0 is a no-op)
  *   W    [out] n eigenvalues, ascending
- *   V    [out] n x n eigenvectors (columns), leading dimension ldv >= max(1, n)
+ *   V    [out] n x n eigenvectors (columns), leading dimension ldv >= max(1, n);
+ *              on the block path every column is scaled to unit 2-norm and
+ *              its entry of largest magnitude is positive
  *   tol  [in]  stop when off(B) <= tol (absolute); tol <= 0 selects
  *              1e-15 * n * ||A||_F.  NaN is an invalid argument.
  * Returns JACOBI_OK, JACOBI_NOCONV (outputs still written), JACOBI_NOTSYM,
