@@ -64,7 +64,8 @@ typedef struct jacobi_opts {
     int32_t small_max_n;    /* n up to which one workgroup solves the whole matrix;
                                default 128, 0 keeps the default, -1 forces the block path */
     int32_t threads;        /* threads per workgroup of the one-workgroup solver:
-                               256 or 512; default by n */
+                               256, 512 or 1024; default by n (512 up to
+                               n = 72, 1024 above) */
     int32_t timing;         /* nonzero: time every pair-solve and apply launch of
                                the block path with HIP events on `stream`
                                (results in jacobi_info.t_*) */
@@ -82,7 +83,7 @@ typedef struct jacobi_opts {
                                library-owned stream beside the next round;
                                other values are rejected */
     int32_t tune;           /* batched path, when `threads` is 0: 0 (default) = the
-                               workgroup size (256 or 512 threads) and the place
+                               workgroup size (256, 512 or 1024 threads) and the place
                                of V (LDS beside S, or global scratch) are
                                chosen by measurement: the first call for a
                                (device, n_max, batch size class) times every

@@ -104,7 +104,7 @@ int resolve_opts(const jacobi_opts *o, Opts &r)
         r.small_max_n = 0;
     else if (o->small_max_n > 0)
         r.small_max_n = o->small_max_n;
-    if (o->threads != 0 && o->threads != 256 && o->threads != 512)
+    if (o->threads != 0 && o->threads != 256 && o->threads != 512 && o->threads != 1024)
         return 1;
     r.threads = o->threads;
     return 0;
@@ -246,7 +246,9 @@ SmallWs layout_small(Bump &bp, int64_t count, int64_t n_max, int64_t slots)
     return w;
 }
 
-int small_threads(int64_t n_max, int req) { return req ? req : (n_max > 64 ? 512 : 256); }
+// Workgroup size of the one-workgroup solver by the largest order (measured:
+// 512 threads are fastest up to n = 64, 1024 from n = 80 on)
+int small_threads(int64_t n_max, int req) { return req ? req : (n_max > 72 ? 1024 : 512); }
 
 // LDS pool (doubles) of the one-workgroup solver: S of the largest matrix,
 // plus its V when both fit the per-workgroup limit; otherwise as much as the
@@ -283,11 +285,11 @@ size_t small_slots(int64_t n_max, int count, int threads, int pool)
     return (size_t)std::min<int64_t>((int64_t)cus * per_cu, std::max(count, 1));
 }
 
-// The configurations the batched autotuner measures: 256 and 512 threads,
-// each with V beside S in LDS (when it fits) and with only S in LDS (V in the
-// global scratch, which leaves room for more resident workgroups).  With a
-// fixed workgroup size (opts.threads) only that size; without tuning, the
-// first candidate is the choice by n_max.
+// The configurations the batched autotuner measures: 256, 512 and 1024
+// threads, each with V beside S in LDS (when it fits) and with only S in LDS
+// (V in the global scratch, which leaves room for more resident workgroups).
+// With a fixed workgroup size (opts.threads) only that size; without tuning,
+// the first candidate is the choice by n_max.
 void small_candidates(int64_t n_max, int count, int req_threads, int tune,
                       std::vector<SmallCfg> &out)
 {
@@ -299,8 +301,12 @@ void small_candidates(int64_t n_max, int count, int req_threads, int tune,
     const int m = (int)((n_max + 3) & ~3);
     const int s_only = m * (m + 1);
     const int first = small_threads(n_max, req_threads);
-    int sizes[2] = {first, first == 512 ? 256 : 512};
-    const int nsz = (req_threads || tune == 1) ? 1 : 2;
+    int sizes[3] = {first, 0, 0};
+    int nsz = 1;
+    if (!req_threads && tune == 0)
+        for (int t : {256, 512, 1024})
+            if (t != first)
+                sizes[nsz++] = t;
     for (int k = 0; k < nsz; ++k) {
         out.push_back({sizes[k], full, (int64_t)small_slots(n_max, count, sizes[k], full)});
         if (tune == 0 && s_only < full)

@@ -75,11 +75,15 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
         const double eps = 0x1p-53;
         __syncthreads();
         double off2 = lds_off2<double, NT>(S, ld, m, red);
+        constexpr int SI = (64 / 2 * (64 + 1) + NT - 1) / NT; // 2x2 blocks per thread, m <= 128
+        RoundItems<NT, SI> items;
+        items.init(m);
         int sweeps = 0, any = 1;
         while (off2 > tol * tol && sweeps < max_sweeps && any) {
             int rot = 0;
             for (int r = 0; r < m - 1; ++r)
-                rot |= lds_jacobi_round<double, NT>(S, ld, m, r, eps, thr, V, ldv, n, cs);
+                rot |= lds_jacobi_round_w<double, NT, SI>(S, ld, m, r, eps, thr, V, ldv, n, cs,
+                                                         items);
             any = block_or<NT>(rot, ired);
             ++sweeps;
             off2 = lds_off2<double, NT>(S, ld, m, red);
@@ -148,7 +152,17 @@ hipError_t launch_small(const double *A, double *W, double *V, const SmallDesc *
                         hipStream_t stream)
 {
     size_t smem = small_smem_bytes(m_max, pool);
-    if (nthreads == 512) {
+    if (nthreads == 1024) {
+        auto k = small_jacobi_kernel<1024>;
+        hipError_t e = hipFuncSetAttribute((const void *)k,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)smem);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(1024), smem, stream, A, W, V, desc, count,
+                           queue, tol, max_sweeps, vscratch, vscratch_stride, pool, m_max,
+                           status);
+    } else if (nthreads == 512) {
         auto k = small_jacobi_kernel<512>;
         hipError_t e = hipFuncSetAttribute((const void *)k,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -176,7 +190,9 @@ int small_max_active(int m_max, int pool, int nthreads)
 {
     size_t smem = small_smem_bytes(m_max, pool);
     int nb = 0;
-    if (nthreads == 512)
+    if (nthreads == 1024)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, small_jacobi_kernel<1024>, 1024, smem);
+    else if (nthreads == 512)
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, small_jacobi_kernel<512>, 512, smem);
     else
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, small_jacobi_kernel<256>, 256, smem);

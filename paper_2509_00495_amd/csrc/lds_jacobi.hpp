@@ -102,6 +102,138 @@ __device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps,
     return rotated;
 }
 
+// Player of slot `slot` in round r of the circle schedule on m players, for
+// 0 <= r < m - 1 (one conditional subtraction instead of a remainder).
+__device__ inline int rr_player_r(int slot, int r, int m)
+{
+    int v = slot - 1 + r;
+    v = v >= m - 1 ? v - (m - 1) : v;
+    return slot == 0 ? 0 : 1 + v;
+}
+
+__device__ inline void rr_pair_r(int k, int r, int m, int &p, int &q)
+{
+    const int a = rr_player_r(k, r, m), b = rr_player_r(m - 1 - k, r, m);
+    p = a < b ? a : b;
+    q = a < b ? b : a;
+}
+
+// Per-thread work lists of lds_jacobi_round_w for one matrix (they do not
+// depend on the round): the 2x2 blocks (k <= l) a thread updates, packed as
+// k << 16 | l (-1 = none), and the start and stride of its (row, pair) items
+// of V.
+template <int NT, int SI>
+struct RoundItems {
+    int kl[SI];
+    int vk0, vi0, vdk, vdi;
+    __device__ void init(int m)
+    {
+        const int h = m / 2, nblk = (h / 2) * (h + 1);
+#pragma unroll
+        for (int u = 0; u < SI; ++u) {
+            const int idx = threadIdx.x + u * NT;
+            kl[u] = -1;
+            if (idx < nblk) {
+                int k, l;
+                tri_fold(idx, h, k, l);
+                kl[u] = (k << 16) | l;
+            }
+        }
+        vk0 = threadIdx.x % h;
+        vi0 = threadIdx.x / h;
+        vdk = NT % h;
+        vdi = NT / h;
+    }
+};
+
+// lds_jacobi_round with the round's index work taken from precomputed lists
+// and the angle from jacobi_angle_fast; the per-entry updates are the same.
+template <typename T, int NT, int SI>
+__device__ inline int lds_jacobi_round_w(T *S, int ld, int m, int r, double eps, double thr,
+                                         T *V, int ldv, int nv, double *cs,
+                                         const RoundItems<NT, SI> &it)
+{
+    const int h = m / 2;
+    const int tid = threadIdx.x;
+    int rotated = 0;
+    for (int k = tid; k < h; k += NT) {
+        int p, q;
+        rr_pair_r(k, r, m, p, q);
+        const double app = (double)S[p * ld + p];
+        const double aqq = (double)S[q * ld + q];
+        const double apq = (double)S[p * ld + q];
+        double c = 1.0, s = 0.0, t = 0.0;
+        if (jacobi_should_rotate_sq(app, aqq, apq, eps, thr)) {
+            jacobi_angle_fast(app, aqq, apq, c, s, t);
+            rotated = 1;
+        }
+        cs[k] = c;
+        cs[h + k] = s;
+        cs[2 * h + k] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < SI; ++u) {
+        if (it.kl[u] < 0)
+            continue;
+        const int k = it.kl[u] >> 16, l = it.kl[u] & 0xffff;
+        const double sk = cs[h + k], sl = cs[h + l];
+        if (sk == 0.0 && sl == 0.0)
+            continue;
+        int pk, qk, pl, ql;
+        rr_pair_r(k, r, m, pk, qk);
+        rr_pair_r(l, r, m, pl, ql);
+        if (k == l) {
+            const double tk = cs[2 * h + k];
+            const double apq = (double)S[pk * ld + qk];
+            const double app = (double)S[pk * ld + pk];
+            const double aqq = (double)S[qk * ld + qk];
+            S[pk * ld + pk] = (T)(app - tk * apq);
+            S[qk * ld + qk] = (T)(aqq + tk * apq);
+            S[pk * ld + qk] = (T)0;
+            S[qk * ld + pk] = (T)0;
+            continue;
+        }
+        const T ck = (T)cs[k], skT = (T)sk, cl = (T)cs[l], slT = (T)sl;
+        const T x00 = S[pk * ld + pl], x01 = S[pk * ld + ql];
+        const T x10 = S[qk * ld + pl], x11 = S[qk * ld + ql];
+        const T y00 = ck * x00 - skT * x10, y01 = ck * x01 - skT * x11;
+        const T y10 = skT * x00 + ck * x10, y11 = skT * x01 + ck * x11;
+        const T z00 = cl * y00 - slT * y01, z01 = slT * y00 + cl * y01;
+        const T z10 = cl * y10 - slT * y11, z11 = slT * y10 + cl * y11;
+        S[pk * ld + pl] = z00;
+        S[pk * ld + ql] = z01;
+        S[qk * ld + pl] = z10;
+        S[qk * ld + ql] = z11;
+        S[pl * ld + pk] = z00;
+        S[ql * ld + pk] = z01;
+        S[pl * ld + qk] = z10;
+        S[ql * ld + qk] = z11;
+    }
+    if (V) {
+        int k = it.vk0, i = it.vi0;
+        while (i < nv) {
+            const double s = cs[h + k];
+            if (s != 0.0) {
+                int p, q;
+                rr_pair_r(k, r, m, p, q);
+                const T c = (T)cs[k], sT = (T)s;
+                const T vp = V[(int64_t)i * ldv + p], vq = V[(int64_t)i * ldv + q];
+                V[(int64_t)i * ldv + p] = c * vp - sT * vq;
+                V[(int64_t)i * ldv + q] = sT * vp + c * vq;
+            }
+            k += it.vdk;
+            i += it.vdi;
+            if (k >= h) {
+                k -= h;
+                ++i;
+            }
+        }
+    }
+    __syncthreads();
+    return rotated;
+}
+
 // off(S)^2 = sum of squares of the off-diagonal entries (the definition in
 // Section 3.1), accumulated in FP64 directly (never as ||S||_F^2 - sum a_ii^2,
 // which cancels catastrophically once S is nearly diagonal).

@@ -67,7 +67,7 @@ def test_eigh_argument_validation(lib, pj, fn):
     assert _eigh(lib, fn, FAKE, 4, 4, FAKE, FAKE, 2, 0.0) == -6
     assert _eigh(lib, fn, FAKE, 4, 4, FAKE, FAKE, 4, float("nan")) == -7
     assert _eigh(lib, fn, FAKE, 4, 4, FAKE, FAKE, 4, float("inf")) == -7
-    for bad in (dict(block=48), dict(threads=100), dict(max_sweeps=-1), dict(c32=-1.0),
+    for bad in (dict(block=48), dict(threads=100), dict(threads=768), dict(max_sweeps=-1), dict(c32=-1.0),
                 dict(ns_iters=-2), dict(inner_sweeps=-1), dict(small_max_n=500),
                 dict(serial_v=3), dict(serial_v=-1), dict(schedule=2), dict(tune=2),
                 dict(tune=-1)):

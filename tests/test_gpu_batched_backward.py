@@ -63,7 +63,7 @@ def test_batched_clustered_sample(pj):
         _check(A, Wk, Vk, lam, f"clustered {k}")
 
 
-@pytest.mark.parametrize("threads", [256, 512])
+@pytest.mark.parametrize("threads", [256, 512, 1024])
 def test_batched_matches_single(pj, threads):
     """The persistent batched launch and the single-matrix call agree bitwise
     (same kernel, same per-matrix arithmetic), for either workgroup size and
