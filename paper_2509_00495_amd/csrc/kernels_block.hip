@@ -14,7 +14,6 @@
 // Entries of B coupling a padding index are zero and stay exactly zero, so
 // padding never mixes with the matrix.
 #include "internal.hpp"
-#include "lds_jacobi.hpp"
 #include "update_v.hpp"
 
 namespace lj {

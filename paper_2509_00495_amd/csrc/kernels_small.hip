@@ -82,8 +82,8 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
         while (off2 > tol * tol && sweeps < max_sweeps && any) {
             int rot = 0;
             for (int r = 0; r < m - 1; ++r)
-                rot |= lds_jacobi_round_w<double, NT, SI>(S, ld, m, r, eps, thr, V, ldv, n, cs,
-                                                         items);
+                rot |= lds_jacobi_round<double, NT, SI>(S, ld, m, r, eps, thr, V, ldv, n, cs,
+                                                       items);
             any = block_or<NT>(rot, ired);
             ++sweeps;
             off2 = lds_off2<double, NT>(S, ld, m, red);

@@ -1,106 +1,11 @@
 // One parallel Jacobi round on a symmetric matrix held in LDS.
 //
-// Used by the one-workgroup solver (the whole matrix lives in LDS) and by the
-// block path's pair solve (a 2b x 2b diagonal block lives in LDS).
+// Used by the one-workgroup solver (the whole matrix lives in LDS).
 #pragma once
 
 #include "common.hpp"
 
 namespace lj {
-
-// S: m x m symmetric, row stride ld (LDS), m a multiple of 4.
-// cs: LDS scratch of 3 * m/2 doubles (c, s, t of each pair).
-// V: nv x m row-major with stride ldv (LDS or global), updated as
-//    V(:, [p q]) <- V(:, [p q]) J; may be null.
-// In round r the m/2 disjoint pairs (p, q) of the round-robin schedule are
-// rotated simultaneously: angles first (phase 1), then the two-sided update
-// B <- J^T B J restricted to the 2x2 blocks [p_k q_k] x [p_l q_l] (phase 2),
-// which touches every entry once.  Only blocks with k <= l are computed; the
-// mirror is written from the same values so S stays exactly symmetric.  The
-// rotated pair itself gets the closed-form diagonal (a_pp - t a_pq,
-// a_qq + t a_pq) and an exact zero off the diagonal.
-// Returns (per thread) whether this thread computed a rotation in phase 1.
-template <typename T, int NT>
-__device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps,
-                                       double thr, T *V, int ldv, int nv,
-                                       double *cs)
-{
-    const int h = m / 2;
-    const int tid = threadIdx.x;
-    int rotated = 0;
-    for (int k = tid; k < h; k += NT) {
-        int p, q;
-        rr_pair(k, r, m, p, q);
-        double app = (double)S[p * ld + p];
-        double aqq = (double)S[q * ld + q];
-        double apq = (double)S[p * ld + q];
-        double c = 1.0, s = 0.0, t = 0.0;
-        if (jacobi_should_rotate(app, aqq, apq, eps, thr)) {
-            jacobi_angle(app, aqq, apq, c, s, t);
-            rotated = 1;
-        }
-        cs[k] = c;
-        cs[h + k] = s;
-        cs[2 * h + k] = t;
-    }
-    __syncthreads();
-    const int nblk = (h / 2) * (h + 1);
-    for (int idx = tid; idx < nblk; idx += NT) {
-        int k, l;
-        tri_fold(idx, h, k, l);
-        double sk = cs[h + k], sl = cs[h + l];
-        if (sk == 0.0 && sl == 0.0)
-            continue;
-        int pk, qk, pl, ql;
-        rr_pair(k, r, m, pk, qk);
-        rr_pair(l, r, m, pl, ql);
-        if (k == l) {
-            double tk = cs[2 * h + k];
-            double apq = (double)S[pk * ld + qk];
-            double app = (double)S[pk * ld + pk];
-            double aqq = (double)S[qk * ld + qk];
-            S[pk * ld + pk] = (T)(app - tk * apq);
-            S[qk * ld + qk] = (T)(aqq + tk * apq);
-            S[pk * ld + qk] = (T)0;
-            S[qk * ld + pk] = (T)0;
-            continue;
-        }
-        const T ck = (T)cs[k], skT = (T)sk, cl = (T)cs[l], slT = (T)sl;
-        T x00 = S[pk * ld + pl], x01 = S[pk * ld + ql];
-        T x10 = S[qk * ld + pl], x11 = S[qk * ld + ql];
-        // rows: J_k^T X
-        T y00 = ck * x00 - skT * x10, y01 = ck * x01 - skT * x11;
-        T y10 = skT * x00 + ck * x10, y11 = skT * x01 + ck * x11;
-        // columns: (J_k^T X) J_l
-        T z00 = cl * y00 - slT * y01, z01 = slT * y00 + cl * y01;
-        T z10 = cl * y10 - slT * y11, z11 = slT * y10 + cl * y11;
-        S[pk * ld + pl] = z00;
-        S[pk * ld + ql] = z01;
-        S[qk * ld + pl] = z10;
-        S[qk * ld + ql] = z11;
-        S[pl * ld + pk] = z00;
-        S[ql * ld + pk] = z01;
-        S[pl * ld + qk] = z10;
-        S[ql * ld + qk] = z11;
-    }
-    if (V) {
-        const int nv_items = nv * h;
-        for (int idx = tid; idx < nv_items; idx += NT) {
-            int k = idx % h, i = idx / h;
-            double s = cs[h + k];
-            if (s == 0.0)
-                continue;
-            int p, q;
-            rr_pair(k, r, m, p, q);
-            const T c = (T)cs[k], sT = (T)s;
-            T vp = V[(int64_t)i * ldv + p], vq = V[(int64_t)i * ldv + q];
-            V[(int64_t)i * ldv + p] = c * vp - sT * vq;
-            V[(int64_t)i * ldv + q] = sT * vp + c * vq;
-        }
-    }
-    __syncthreads();
-    return rotated;
-}
 
 // Player of slot `slot` in round r of the circle schedule on m players, for
 // 0 <= r < m - 1 (one conditional subtraction instead of a remainder).
@@ -118,7 +23,7 @@ __device__ inline void rr_pair_r(int k, int r, int m, int &p, int &q)
     q = a < b ? b : a;
 }
 
-// Per-thread work lists of lds_jacobi_round_w for one matrix (they do not
+// Per-thread work lists of lds_jacobi_round for one matrix (they do not
 // depend on the round): the 2x2 blocks (k <= l) a thread updates, packed as
 // k << 16 | l (-1 = none), and the start and stride of its (row, pair) items
 // of V.
@@ -146,12 +51,24 @@ struct RoundItems {
     }
 };
 
-// lds_jacobi_round with the round's index work taken from precomputed lists
-// and the angle from jacobi_angle_fast; the per-entry updates are the same.
+// S: m x m symmetric, row stride ld (LDS), m a multiple of 4.
+// cs: LDS scratch of 3 * m/2 doubles (c, s, t of each pair).
+// V: nv x m row-major with stride ldv (LDS or global), updated as
+//    V(:, [p q]) <- V(:, [p q]) J; may be null.
+// In round r the m/2 disjoint pairs (p, q) of the round-robin schedule are
+// rotated simultaneously: angles first (phase 1), then the two-sided update
+// B <- J^T B J restricted to the 2x2 blocks [p_k q_k] x [p_l q_l] (phase 2),
+// which touches every entry once.  Only blocks with k <= l are computed; the
+// mirror is written from the same values so S stays exactly symmetric.  The
+// rotated pair itself gets the closed-form diagonal (a_pp - t a_pq,
+// a_qq + t a_pq) and an exact zero off the diagonal.
+// The index work of a thread comes from its lists `it` (built once per
+// matrix) and the angles from jacobi_angle_fast.
+// Returns (per thread) whether this thread computed a rotation in phase 1.
 template <typename T, int NT, int SI>
-__device__ inline int lds_jacobi_round_w(T *S, int ld, int m, int r, double eps, double thr,
-                                         T *V, int ldv, int nv, double *cs,
-                                         const RoundItems<NT, SI> &it)
+__device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps, double thr,
+                                       T *V, int ldv, int nv, double *cs,
+                                       const RoundItems<NT, SI> &it)
 {
     const int h = m / 2;
     const int tid = threadIdx.x;
