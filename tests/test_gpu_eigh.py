@@ -195,6 +195,22 @@ def test_output_columns_normalized(pj):
         check(A, W, V, Wo, Vo, fn)
 
 
+@pytest.mark.parametrize("fn", ["eigh", "eigh_mixed"])
+def test_ari_known_spectrum(pj, fn):
+    """Arithmetic family (magnitudes linear from 1 to 1/kappa, random signs),
+    block path: eigenvalues against the spectrum the matrix was built from."""
+    A, lam = wl.ari_spectrum(520, 7, kappa=1e2)
+    W, V, info = run(pj, fn, A, small_max_n=-1)
+    assert info["status"] == 0
+    n = A.shape[0]
+    nrm2 = np.abs(lam).max()
+    print(f"  ari {fn}: sweeps={info['sweeps']} sweeps32={info['sweeps32']} "
+          f"|W-lam|/|A|_2={np.abs(W - lam).max() / nrm2:.2e}", flush=True)
+    assert np.abs(W - lam).max() <= 1e-13 * nrm2
+    assert np.linalg.norm(A @ V - V * W) / np.linalg.norm(A) <= 1e-13 * n
+    assert np.linalg.norm(V.T @ V - np.eye(n)) <= 1e-14 * n
+
+
 def test_mixed_goe(pj):
     A = wl.goe(256, 77)
     W, V, info = run(pj, "eigh_mixed", A)

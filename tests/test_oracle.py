@@ -126,6 +126,21 @@ def test_known_spectrum(orc):
     assert np.linalg.norm(V.T @ V - np.eye(n)) <= 1e-14 * n
 
 
+def test_known_spectrum_ari(orc):
+    """The arithmetic family: eigenvalues known by construction, well
+    separated (gap ~ 2 / n), so the oracle converges quadratically in few
+    sweeps (Section 5.2 observes two to three for this family)."""
+    n = 64
+    A, lam = wl.ari_spectrum(n, 6, kappa=1e2)
+    assert abs(np.abs(lam).max() - 1.0) < 1e-15 and abs(np.abs(lam).min() - 1e-2) < 1e-15
+    W, V, sw, st, _ = orc.eigh(A)
+    nrm2 = np.abs(lam).max()
+    assert st == 0
+    assert np.abs(W - lam).max() <= 10 * n * U_D * nrm2
+    assert np.linalg.norm(A @ V - V * W) / np.linalg.norm(A) <= 10 * n * U_D
+    assert sw <= 8
+
+
 @pytest.mark.parametrize("n,seed", [(7, 1), (30, 2), (64, 3)])
 def test_invariants(orc, n, seed):
     """Orthogonal invariance (Section 2.2): trace and Frobenius norm."""

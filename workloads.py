@@ -81,6 +81,19 @@ def geo_spectrum(n: int = 1024, seed: int = 2, kappa: float = 1e6):
     return from_spectrum(lam, Q), np.sort(lam)
 
 
+def ari_spectrum(n: int = 1024, seed: int = 6, kappa: float = 1e2):
+    """Arithmetic magnitudes: |lambda_i| falls linearly from 1 to 1/kappa
+    (the second family of test matrices of Section 2.4), Rademacher signs,
+    Haar Q.  Returns (A, lam_sorted)."""
+    g = rng(seed)
+    i = np.arange(n, dtype=np.float64)
+    mag = 1.0 - i / max(n - 1, 1) * (1.0 - 1.0 / kappa)
+    signs = g.choice(np.array([-1.0, 1.0]), n)
+    lam = signs * mag
+    Q = haar(n, g)
+    return from_spectrum(lam, Q), np.sort(lam)
+
+
 def goe(n: int = 4096, seed: int = 3) -> np.ndarray:
     """A = (G + G^T)/2, G i.i.d. N(0,1); spectrum not known in closed form."""
     g = rng(seed)
