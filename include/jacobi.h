@@ -64,7 +64,7 @@ typedef struct jacobi_opts {
     int32_t small_max_n;    /* n up to which one workgroup solves the whole matrix;
                                default 128, 0 keeps the default, -1 forces the block path */
     int32_t threads;        /* threads per workgroup of the one-workgroup solver:
-                               256, 512 or 1024; default by n (512 up to
+                               256, 512 or 1024; default by n (256 up to
                                n = 72, 1024 above) */
     int32_t timing;         /* nonzero: time every pair-solve and apply launch of
                                the block path with HIP events on `stream`

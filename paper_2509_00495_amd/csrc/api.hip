@@ -247,8 +247,8 @@ SmallWs layout_small(Bump &bp, int64_t count, int64_t n_max, int64_t slots)
 }
 
 // Workgroup size of the one-workgroup solver by the largest order (measured:
-// 512 threads are fastest up to n = 64, 1024 from n = 80 on)
-int small_threads(int64_t n_max, int req) { return req ? req : (n_max > 72 ? 1024 : 512); }
+// 256 threads are fastest up to n = 64, 1024 from n = 80 on)
+int small_threads(int64_t n_max, int req) { return req ? req : (n_max > 72 ? 1024 : 256); }
 
 // LDS pool (doubles) of the one-workgroup solver: S of the largest matrix,
 // plus its V when both fit the per-workgroup limit; otherwise as much as the

@@ -25,12 +25,13 @@ __device__ inline void rr_pair_r(int k, int r, int m, int &p, int &q)
 
 // Per-thread work lists of lds_jacobi_round for one matrix (they do not
 // depend on the round): the 2x2 blocks (k <= l) a thread updates, packed as
-// k << 16 | l (-1 = none), and the start and stride of its (row, pair) items
-// of V.
+// k << 16 | l (-1 = none), and its share of the V update: pair vk, rows
+// vi0, vi0 + vr, vi0 + 2 vr, ... (vr = NT / (m/2) threads per pair; a thread
+// with vi0 >= vr has no V rows).
 template <int NT, int SI>
 struct RoundItems {
     int kl[SI];
-    int vk0, vi0, vdk, vdi;
+    int vk, vi0, vr;
     __device__ void init(int m)
     {
         const int h = m / 2, nblk = (h / 2) * (h + 1);
@@ -44,10 +45,9 @@ struct RoundItems {
                 kl[u] = (k << 16) | l;
             }
         }
-        vk0 = threadIdx.x % h;
+        vk = threadIdx.x % h;
         vi0 = threadIdx.x / h;
-        vdk = NT % h;
-        vdi = NT / h;
+        vr = NT / h;
     }
 };
 
@@ -127,24 +127,31 @@ __device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps, d
         S[pl * ld + qk] = z10;
         S[ql * ld + qk] = z11;
     }
-    if (V) {
-        int k = it.vk0, i = it.vi0;
-        while (i < nv) {
-            const double s = cs[h + k];
-            if (s != 0.0) {
-                int p, q;
-                rr_pair_r(k, r, m, p, q);
-                const T c = (T)cs[k], sT = (T)s;
-                const T vp = V[(int64_t)i * ldv + p], vq = V[(int64_t)i * ldv + q];
-                V[(int64_t)i * ldv + p] = c * vp - sT * vq;
-                V[(int64_t)i * ldv + q] = sT * vp + c * vq;
+    if (V && it.vi0 < it.vr && cs[h + it.vk] != 0.0) {
+        // one pair per thread, its rotation and columns read once; rows in
+        // groups of four, all loads of a group before its stores
+        const int k = it.vk, R = it.vr;
+        int p, q;
+        rr_pair_r(k, r, m, p, q);
+        const T c = (T)cs[k], sT = (T)cs[h + k];
+        int i = it.vi0;
+        for (; i + 3 * R < nv; i += 4 * R) {
+            T vp[4], vq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                vp[u] = V[(int64_t)(i + u * R) * ldv + p];
+                vq[u] = V[(int64_t)(i + u * R) * ldv + q];
             }
-            k += it.vdk;
-            i += it.vdi;
-            if (k >= h) {
-                k -= h;
-                ++i;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                V[(int64_t)(i + u * R) * ldv + p] = c * vp[u] - sT * vq[u];
+                V[(int64_t)(i + u * R) * ldv + q] = sT * vp[u] + c * vq[u];
             }
+        }
+        for (; i < nv; i += R) {
+            const T vp = V[(int64_t)i * ldv + p], vq = V[(int64_t)i * ldv + q];
+            V[(int64_t)i * ldv + p] = c * vp - sT * vq;
+            V[(int64_t)i * ldv + q] = sT * vp + c * vq;
         }
     }
     __syncthreads();
