@@ -237,10 +237,9 @@ struct SmallWs {
 SmallWs layout_small(Bump &bp, int64_t count, int64_t n_max, int64_t slots)
 {
     SmallWs w{};
-    const int64_t m = (n_max + 3) & ~3;
     w.desc = bp.take<SmallDesc>((size_t)std::max<int64_t>(count, 1));
     w.queue = bp.take<int>(4);
-    w.vscratch = bp.take<double>((size_t)slots * n_max * (m + 1));
+    w.vscratch = bp.take<double>((size_t)slots * small_vt_elems(n_max));
     w.info = bp.take<double>(8);
     w.status = bp.take<int32_t>((size_t)std::max<int64_t>(count, 1));
     return w;
@@ -258,7 +257,7 @@ int small_pool(int64_t n_max, int lds_max)
 {
     const int m = (int)((n_max + 3) & ~3);
     const int s = m * (m + 1);
-    const int want = s + (int)(n_max * (m + 1));
+    const int want = s + (int)small_vt_elems(n_max);
     if (lds_max <= 0 || small_smem_bytes(m, want) <= (size_t)lds_max)
         return want;
     const size_t fixed = small_smem_bytes(m, 0);
@@ -761,7 +760,7 @@ int eigh_small(const double *A, int64_t n, int64_t lda, double *W, double *V, in
     const int m = (int)((n + 3) & ~3);
     const int pool = small_pool(n, dv.lds_max);
     CK(launch_small(A, W, V, w.desc, 1, w.queue, tol, o.max_sweeps, w.vscratch,
-                    (int64_t)n * (m + 1), pool, m, threads, 1, w.status, s));
+                    small_vt_elems(n), pool, m, threads, 1, w.status, s));
     double hinfo[4] = {0, 0, 0, 0};
     int32_t st = 0;
     CK(hipMemcpyAsync(hinfo, w.info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
@@ -1151,7 +1150,7 @@ int jacobi_eigh_batched(const double *A, const int64_t *n, int64_t batch, double
         CK(launch_fill_i32(w.queue, 1, 0, st));
         CK(launch_fill_i32(w.status, batch, 0, st));
         CK(launch_small(A, W, V, w.desc, (int)batch, w.queue, tol, o.max_sweeps, w.vscratch,
-                        n_max * (m + 1), c.pool, m, c.threads, (int)c.slots, w.status, st));
+                        small_vt_elems(n_max), c.pool, m, c.threads, (int)c.slots, w.status, st));
         return 0;
     };
     // configuration: measured once per (device, n_max, batch size class);

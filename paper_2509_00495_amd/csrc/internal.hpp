@@ -21,6 +21,12 @@ struct SmallDesc {
 
 // ---- one-workgroup solver (kernels_small.hip)
 size_t small_smem_bytes(int m_max, int pool);
+// doubles of the one-workgroup solver's eigenvector store for order n: V is
+// kept transposed, m = n rounded up to 4 rows of (n rounded up to 2) entries
+__host__ __device__ inline int64_t small_vt_elems(int64_t n)
+{
+    return ((n + 3) & ~(int64_t)3) * ((n + 1) & ~(int64_t)1);
+}
 hipError_t launch_small(const double *A, double *W, double *V, const SmallDesc *desc,
                         int count, int *queue, double tol, int max_sweeps,
                         double *vscratch, int64_t vscratch_stride, int pool,

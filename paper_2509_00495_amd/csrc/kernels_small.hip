@@ -16,7 +16,7 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
     int max_sweeps, double *__restrict__ vscratch, int64_t vscratch_stride,
     int pool, int m_max, int32_t *status)
 {
-    extern __shared__ double smem[];
+    extern __shared__ __align__(16) double smem[];
     const int tid = threadIdx.x;
     double *S = smem;                                  // pool: S, then V if it fits
     double *cs = smem + pool;                          // 3 * m_max / 2
@@ -63,12 +63,13 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
                 status[d.orig] = JACOBI_NONFINITE;
             continue;
         }
-        const bool v_lds = (int64_t)(m + n) * ld <= pool;
-        double *V = v_lds ? S + m * ld : vscratch + (int64_t)blockIdx.x * vscratch_stride;
-        const int ldv = ld;
-        for (int idx = tid; idx < n * ld; idx += NT) {
-            int i = idx / ld, j = idx - (idx / ld) * ld;
-            V[idx] = (i == j) ? 1.0 : 0.0;
+        // V is kept transposed: Vt[p][i] = V[i][p], m rows of stride ldt
+        const int ldt = (n + 1) & ~1;
+        const bool v_lds = (int64_t)m * ld + small_vt_elems(n) <= pool;
+        double *Vt = v_lds ? S + m * ld : vscratch + (int64_t)blockIdx.x * vscratch_stride;
+        for (int idx = tid; idx < m * ldt; idx += NT) {
+            int p = idx / ldt, i = idx - (idx / ldt) * ldt;
+            Vt[idx] = (p == i) ? 1.0 : 0.0;
         }
         const double tol = tol_in > 0.0 ? tol_in : 1e-15 * (double)n * sqrt(nrm2);
         const double thr = n > 0 ? tol / (double)n : 0.0;
@@ -77,12 +78,12 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
         double off2 = lds_off2<double, NT>(S, ld, m, red);
         constexpr int SI = (64 / 2 * (64 + 1) + NT - 1) / NT; // 2x2 blocks per thread, m <= 128
         RoundItems<NT, SI> items;
-        items.init(m);
+        items.init(m, n);
         int sweeps = 0, any = 1;
         while (off2 > tol * tol && sweeps < max_sweeps && any) {
             int rot = 0;
             for (int r = 0; r < m - 1; ++r)
-                rot |= lds_jacobi_round<double, NT, SI>(S, ld, m, r, eps, thr, V, ldv, n, cs,
+                rot |= lds_jacobi_round<double, NT, SI>(S, ld, m, r, eps, thr, Vt, ldt, cs,
                                                        items);
             any = block_or<NT>(rot, ired);
             ++sweeps;
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
             int col = perm[c];
             double best = -1.0, val = 0.0;
             for (int i = 0; i < n; ++i) {
-                double v = V[(int64_t)i * ldv + col];
+                double v = Vt[(int64_t)col * ldt + i];
                 if (fabs(v) > best) {
                     best = fabs(v);
                     val = v;
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
         double *Vo = Vout + d.v_off;
         for (int idx = tid; idx < n * n; idx += NT) {
             int i = idx / n, c = idx - (idx / n) * n;
-            Vo[(int64_t)i * d.ldv + c] = sg[c] * V[(int64_t)i * ldv + perm[c]];
+            Vo[(int64_t)i * d.ldv + c] = sg[c] * Vt[(int64_t)perm[c] * ldt + i];
         }
         if (tid == 0) {
             int st = (off2 <= tol * tol || !any) ? JACOBI_OK : JACOBI_NOCONV;

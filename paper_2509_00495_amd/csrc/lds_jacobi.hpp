@@ -25,14 +25,14 @@ __device__ inline void rr_pair_r(int k, int r, int m, int &p, int &q)
 
 // Per-thread work lists of lds_jacobi_round for one matrix (they do not
 // depend on the round): the 2x2 blocks (k <= l) a thread updates, packed as
-// k << 16 | l (-1 = none), and its share of the V update: pair vk, rows
-// vi0, vi0 + vr, vi0 + 2 vr, ... (vr = NT / (m/2) threads per pair; a thread
-// with vi0 >= vr has no V rows).
+// k << 16 | l (-1 = none), and its items of the V update: item e = tid +
+// j NT is (pair k, two-entry chunk c) with e = k nch + c, nch = ceil(nv / 2)
+// chunks per row of V^T; the first item and the stride in (k, c).
 template <int NT, int SI>
 struct RoundItems {
     int kl[SI];
-    int vk, vi0, vr;
-    __device__ void init(int m)
+    int tk0, tc0, dk, dch, nch;
+    __device__ void init(int m, int nv)
     {
         const int h = m / 2, nblk = (h / 2) * (h + 1);
 #pragma unroll
@@ -45,16 +45,20 @@ struct RoundItems {
                 kl[u] = (k << 16) | l;
             }
         }
-        vk = threadIdx.x % h;
-        vi0 = threadIdx.x / h;
-        vr = NT / h;
+        nch = (nv + 1) / 2;
+        tk0 = threadIdx.x / nch;
+        tc0 = threadIdx.x % nch;
+        dk = NT / nch;
+        dch = NT % nch;
     }
 };
 
 // S: m x m symmetric, row stride ld (LDS), m a multiple of 4.
 // cs: LDS scratch of 3 * m/2 doubles (c, s, t of each pair).
-// V: nv x m row-major with stride ldv (LDS or global), updated as
-//    V(:, [p q]) <- V(:, [p q]) J; may be null.
+// Vt: V transposed, m rows of stride ldt (even, >= nv; LDS or global, 16-byte
+//    aligned rows), updated as Vt([p q], :) <- J^T Vt([p q], :), i.e.
+//    V(:, [p q]) <- V(:, [p q]) J; may be null.  A pair's two rows are
+//    contiguous, so the update reads and writes them two entries at a time.
 // In round r the m/2 disjoint pairs (p, q) of the round-robin schedule are
 // rotated simultaneously: angles first (phase 1), then the two-sided update
 // B <- J^T B J restricted to the 2x2 blocks [p_k q_k] x [p_l q_l] (phase 2),
@@ -67,7 +71,7 @@ struct RoundItems {
 // Returns (per thread) whether this thread computed a rotation in phase 1.
 template <typename T, int NT, int SI>
 __device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps, double thr,
-                                       T *V, int ldv, int nv, double *cs,
+                                       T *Vt, int ldt, double *cs,
                                        const RoundItems<NT, SI> &it)
 {
     const int h = m / 2;
@@ -127,31 +131,46 @@ __device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps, d
         S[pl * ld + qk] = z10;
         S[ql * ld + qk] = z11;
     }
-    if (V && it.vi0 < it.vr && cs[h + it.vk] != 0.0) {
-        // one pair per thread, its rotation and columns read once; rows in
-        // groups of four, all loads of a group before its stores
-        const int k = it.vk, R = it.vr;
-        int p, q;
-        rr_pair_r(k, r, m, p, q);
-        const T c = (T)cs[k], sT = (T)cs[h + k];
-        int i = it.vi0;
-        for (; i + 3 * R < nv; i += 4 * R) {
-            T vp[4], vq[4];
+    if (Vt) {
+        // items in groups of VB, all loads of a group before its stores
+        constexpr int VB = 2;
+        typedef T t2 __attribute__((ext_vector_type(2)));
+        int k = it.tk0, c = it.tc0;
+        while (k < h) {
+            int ks[VB], pp[VB], qq[VB], cc[VB];
+            t2 a[VB], b[VB];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                vp[u] = V[(int64_t)(i + u * R) * ldv + p];
-                vq[u] = V[(int64_t)(i + u * R) * ldv + q];
+            for (int u = 0; u < VB; ++u) {
+                ks[u] = -1;
+                if (k < h) {
+                    if (cs[h + k] != 0.0) {
+                        ks[u] = k;
+                        cc[u] = c;
+                        rr_pair_r(k, r, m, pp[u], qq[u]);
+                        a[u] = *reinterpret_cast<const t2 *>(Vt + (int64_t)pp[u] * ldt + 2 * c);
+                        b[u] = *reinterpret_cast<const t2 *>(Vt + (int64_t)qq[u] * ldt + 2 * c);
+                    }
+                    c += it.dch;
+                    k += it.dk;
+                    if (c >= it.nch) {
+                        c -= it.nch;
+                        ++k;
+                    }
+                }
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                V[(int64_t)(i + u * R) * ldv + p] = c * vp[u] - sT * vq[u];
-                V[(int64_t)(i + u * R) * ldv + q] = sT * vp[u] + c * vq[u];
+            for (int u = 0; u < VB; ++u) {
+                if (ks[u] >= 0) {
+                    const T cv = (T)cs[ks[u]], sv = (T)cs[h + ks[u]];
+                    t2 x, y;
+                    x.x = cv * a[u].x - sv * b[u].x;
+                    x.y = cv * a[u].y - sv * b[u].y;
+                    y.x = sv * a[u].x + cv * b[u].x;
+                    y.y = sv * a[u].y + cv * b[u].y;
+                    *reinterpret_cast<t2 *>(Vt + (int64_t)pp[u] * ldt + 2 * cc[u]) = x;
+                    *reinterpret_cast<t2 *>(Vt + (int64_t)qq[u] * ldt + 2 * cc[u]) = y;
+                }
             }
-        }
-        for (; i < nv; i += R) {
-            const T vp = V[(int64_t)i * ldv + p], vq = V[(int64_t)i * ldv + q];
-            V[(int64_t)i * ldv + p] = c * vp - sT * vq;
-            V[(int64_t)i * ldv + q] = sT * vp + c * vq;
         }
     }
     __syncthreads();
