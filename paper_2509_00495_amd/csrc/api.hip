@@ -452,9 +452,9 @@ int read_scalars(const BlockWs &w, hipStream_t s, Readback &rb)
     return 0;
 }
 
-// Kernel timing of the block path with HIP events recorded around every
-// pair-solve and B-update launch on the caller's stream and around every
-// V-update launch on the side stream (opts->timing).  Events are read after
+// Kernel timing of the block path (opts->timing): every pair-solve, B-update
+// and V-update launch records a start and an end event at the kernel itself
+// (launched through hipExtLaunchKernel on its stream).  Events are read after
 // the per-sweep readback.
 struct RoundTimer {
     bool on = false;
@@ -587,8 +587,6 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
             const int2 *pr = w.pairs + (size_t)r * g.npairs;
             if (side && ss.recV[j])
                 CK(hipStreamWaitEvent(s, ss.evV[j], 0));
-            if (timed)
-                CK(hipEventRecord(tm->ev[6 * r], s));
             const int cross = schedule == 0 && r > 0;
             const int2 *map = w.psmap + (cross ? (size_t)g.b * (g.b + 1) / 2 : 0);
             if (vpend_pairs) {
@@ -598,19 +596,16 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
                 vpend_pairs = nullptr;
             } else {
                 CK(launch_pair_solve<T>(B, g.npad, g.b, g.npairs, pr, map, Ub, eps, thr, inner,
-                                        cross, w.partial, w.flags + 2, s));
+                                        cross, w.partial, w.flags + 2, s,
+                                        timed ? tm->ev[6 * r] : nullptr,
+                                        timed ? tm->ev[6 * r + 1] : nullptr));
             }
-            if (timed)
-                CK(hipEventRecord(tm->ev[6 * r + 1], s));
             if (side)
                 CK(hipEventRecord(ss.evU[j], s));
-            if (timed)
-                CK(hipEventRecord(tm->ev[6 * r + 2], s));
             CK(launch_update_b<T>(B, g.npad, g.b, g.npairs, pr, Ub,
                                   w.partial + (size_t)g.npairs * pair_solve_waves(g.M),
-                                  r == g.N - 2, s));
-            if (timed)
-                CK(hipEventRecord(tm->ev[6 * r + 3], s));
+                                  r == g.N - 2, s, timed ? tm->ev[6 * r + 2] : nullptr,
+                                  timed ? tm->ev[6 * r + 3] : nullptr));
             if (fuse) {
                 vpend_pairs = pr;
                 vpend_U = Ub;
@@ -619,11 +614,9 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
             hipStream_t sv = side ? ss.s2 : s;
             if (side)
                 CK(hipStreamWaitEvent(ss.s2, ss.evU[j], 0));
-            if (timed)
-                CK(hipEventRecord(tm->ev[6 * r + 4], sv));
-            CK(launch_update_v<T>(V, g.npad, g.npad, g.b, g.npairs, pr, Ub, sv));
-            if (timed)
-                CK(hipEventRecord(tm->ev[6 * r + 5], sv));
+            CK(launch_update_v<T>(V, g.npad, g.npad, g.b, g.npairs, pr, Ub, sv,
+                                  timed ? tm->ev[6 * r + 4] : nullptr,
+                                  timed ? tm->ev[6 * r + 5] : nullptr));
             if (side) {
                 CK(hipEventRecord(ss.evV[j], ss.s2));
                 ss.recV[j] = true;

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/jacobi.h"
+#include <hip/hip_ext.h>
 
 namespace lj {
 
@@ -34,11 +35,25 @@ hipError_t launch_small(const double *A, double *W, double *V, const SmallDesc *
                         hipStream_t stream);
 int small_max_active(int m_max, int pool, int nthreads);
 
+// Launch on `s`; with e0 and e1 (timing events) the launch records them at the
+// kernel's own start and end (hipExtLaunchKernel), so their difference is the
+// kernel's duration without the gaps that separate event records add.
+template <typename F, typename... Args>
+inline void launch_timed(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t s,
+                         hipEvent_t e0, hipEvent_t e1, Args... args)
+{
+    if (e0)
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, s, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
+}
+
 // ---- block path (kernels_block.hip); T = double or float
 template <typename T>
 hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                              const int2 *psmap, T *U, double eps, double thr, int inner,
-                             int cross, double *partial, int *rot_flag, hipStream_t s);
+                             int cross, double *partial, int *rot_flag, hipStream_t s,
+                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // the same pair solves, plus the V update V[:, cols] <- V[:, cols] vU of the
 // previous round (pairs vpairs, rotations vU) on further workgroups of the
 // same launch
@@ -61,7 +76,8 @@ void pair_solve_map(int M, int cross, int2 *out);
 // (kernels_update.hip)
 template <typename T>
 hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pairs, const T *U,
-                           double *partial, int want_off, hipStream_t s);
+                           double *partial, int want_off, hipStream_t s,
+                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <typename T>
 int update_b_blocks_per_cu(int b);
 // grid sizing of the V update: total resident wavefronts (0 = from occupancy)
@@ -70,7 +86,8 @@ void tune_update_v(int total_waves);
 // V[:, cols(pair)] <- V[:, cols(pair)] U_pair for all pairs (kernels_update.hip)
 template <typename T>
 hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
-                           const int2 *pairs, const T *U, hipStream_t s);
+                           const int2 *pairs, const T *U, hipStream_t s,
+                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_sum(const double *x, int64_t count, double *out, hipStream_t s);
 template <typename T>
 hipError_t launch_ingest(const double *A, int64_t lda, int64_t n, T *B, int64_t npad,

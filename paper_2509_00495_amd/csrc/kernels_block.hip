@@ -429,7 +429,7 @@ template <typename T, int M, int NT, bool CROSS>
 static hipError_t launch_pair_solve_t(T *B, int64_t ldb, int npairs, const int2 *pairs,
                                       const int2 *psmap, T *U, double eps, double thr,
                                       int inner, double *partial, int *rot_flag, size_t smem,
-                                      hipStream_t s)
+                                      hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     auto k = pair_solve_kernel<T, M, NT, CROSS>;
     static size_t smem_set = 0; // the attribute is set once per size (host-side cost)
@@ -440,8 +440,8 @@ static hipError_t launch_pair_solve_t(T *B, int64_t ldb, int npairs, const int2 
             return e;
         smem_set = smem;
     }
-    hipLaunchKernelGGL(k, dim3(npairs), dim3(NT), smem, s, B, ldb, pairs, psmap, U, eps, thr,
-                       inner, partial, rot_flag);
+    launch_timed(k, dim3(npairs), dim3(NT), (uint32_t)smem, s, e0, e1, B, ldb, pairs, psmap, U,
+                 eps, thr, inner, partial, rot_flag);
     return hipGetLastError();
 }
 
@@ -459,7 +459,8 @@ static size_t pair_solve_smem(int b)
 template <typename T>
 hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                              const int2 *psmap, T *U, double eps, double thr, int inner,
-                             int cross, double *partial, int *rot_flag, hipStream_t s)
+                             int cross, double *partial, int *rot_flag, hipStream_t s,
+                             hipEvent_t e0, hipEvent_t e1)
 {
     const int M = 2 * b;
     const size_t smem = pair_solve_smem<T>(b);
@@ -471,17 +472,17 @@ hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *p
     if (M == 64)
         return cross ? launch_pair_solve_t<T, 64, NT64, true>(B, ldb, npairs, pairs, psmap, U,
                                                               eps, thr, inner, partial,
-                                                              rot_flag, smem, s)
+                                                              rot_flag, smem, s, e0, e1)
                      : launch_pair_solve_t<T, 64, NT64, false>(B, ldb, npairs, pairs, psmap,
                                                                U, eps, thr, inner, partial,
-                                                               rot_flag, smem, s);
+                                                               rot_flag, smem, s, e0, e1);
     if (M == 32)
         return cross ? launch_pair_solve_t<T, 32, 256, true>(B, ldb, npairs, pairs, psmap, U,
                                                              eps, thr, inner, partial, rot_flag,
-                                                             smem, s)
+                                                             smem, s, e0, e1)
                      : launch_pair_solve_t<T, 32, 256, false>(B, ldb, npairs, pairs, psmap, U,
                                                               eps, thr, inner, partial,
-                                                              rot_flag, smem, s);
+                                                              rot_flag, smem, s, e0, e1);
     return hipErrorInvalidValue;
 }
 
@@ -1124,10 +1125,12 @@ template hipError_t launch_pair_solve_v<float>(float *, int64_t, int, int, const
                                               const int2 *, const float *, hipStream_t);
 template hipError_t launch_pair_solve<double>(double *, int64_t, int, int, const int2 *,
                                               const int2 *, double *, double, double, int, int,
-                                              double *, int *, hipStream_t);
+                                              double *, int *, hipStream_t, hipEvent_t,
+                                              hipEvent_t);
 template hipError_t launch_pair_solve<float>(float *, int64_t, int, int, const int2 *,
                                              const int2 *, float *, double, double, int, int,
-                                             double *, int *, hipStream_t);
+                                             double *, int *, hipStream_t, hipEvent_t,
+                                             hipEvent_t);
 
 // Thread -> 2x2 block map of the pair solve for M = 2b positions: entry t < M/2
 // is the block hosting pair t of the next round, then the M/2 diagonal blocks

@@ -308,7 +308,7 @@ int g_update_v_waves = 0; // total resident wavefronts to size the V-update grid
 
 template <typename T, int M>
 hipError_t launch_update_v_t(T *V, int64_t ldv, int64_t nrows, int npairs, const int2 *pairs,
-                             const T *U, hipStream_t s)
+                             const T *U, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     static int occ_waves = 0;
     if (occ_waves == 0) {
@@ -329,8 +329,8 @@ hipError_t launch_update_v_t(T *V, int64_t ldv, int64_t nrows, int npairs, const
         chunks = ntile;
     const int64_t waves = chunks * npairs;
     const unsigned grid = (unsigned)((waves + 3) / 4);
-    hipLaunchKernelGGL((update_v_kernel<T, M>), dim3(grid), dim3(256), 0, s, V, ldv, ntile, pairs,
-                       npairs, U, (int)chunks);
+    launch_timed(update_v_kernel<T, M>, dim3(grid), dim3(256), 0, s, e0, e1, V, ldv, ntile, pairs,
+                 npairs, U, (int)chunks);
     return hipGetLastError();
 }
 
@@ -358,7 +358,8 @@ void tune_update_v(int total_waves) { g_update_v_waves = total_waves; }
 
 template <typename T>
 hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pairs, const T *U,
-                           double *partial, int want_off, hipStream_t s)
+                           double *partial, int want_off, hipStream_t s, hipEvent_t e0,
+                           hipEvent_t e1)
 {
     if (ldb % (16 / (int64_t)sizeof(T)) != 0 || ((uintptr_t)B % 16) != 0)
         return hipErrorInvalidValue;
@@ -376,11 +377,11 @@ hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pai
     const int slots = cus * update_b_blocks_per_cu<T>(b);
     const unsigned grid = (unsigned)(ntiles < slots ? ntiles : slots);
     if (b == 32)
-        hipLaunchKernelGGL((update_b_kernel<T, 64>), dim3(grid), dim3(256), 0, s, B, ldb, pairs,
-                           npairs, U, partial, want_off);
+        launch_timed(update_b_kernel<T, 64>, dim3(grid), dim3(256), 0, s, e0, e1, B, ldb, pairs,
+                     npairs, U, partial, want_off);
     else if (b == 16)
-        hipLaunchKernelGGL((update_b_kernel<T, 32>), dim3(grid), dim3(128), 0, s, B, ldb, pairs,
-                           npairs, U, partial, want_off);
+        launch_timed(update_b_kernel<T, 32>, dim3(grid), dim3(128), 0, s, e0, e1, B, ldb, pairs,
+                     npairs, U, partial, want_off);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -388,7 +389,8 @@ hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pai
 
 template <typename T>
 hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
-                           const int2 *pairs, const T *U, hipStream_t s)
+                           const int2 *pairs, const T *U, hipStream_t s, hipEvent_t e0,
+                           hipEvent_t e1)
 {
     if (nrows % 16 != 0 || ldv % (16 / (int64_t)sizeof(T)) != 0 ||
         ((uintptr_t)V % 16) != 0)
@@ -396,21 +398,24 @@ hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
     if (nrows == 0 || npairs == 0)
         return hipSuccess;
     if (b == 32)
-        return launch_update_v_t<T, 64>(V, ldv, nrows, npairs, pairs, U, s);
+        return launch_update_v_t<T, 64>(V, ldv, nrows, npairs, pairs, U, s, e0, e1);
     if (b == 16)
-        return launch_update_v_t<T, 32>(V, ldv, nrows, npairs, pairs, U, s);
+        return launch_update_v_t<T, 32>(V, ldv, nrows, npairs, pairs, U, s, e0, e1);
     return hipErrorInvalidValue;
 }
 
 template int update_b_blocks_per_cu<double>(int);
 template int update_b_blocks_per_cu<float>(int);
 template hipError_t launch_update_b<double>(double *, int64_t, int, int, const int2 *,
-                                            const double *, double *, int, hipStream_t);
+                                            const double *, double *, int, hipStream_t,
+                                            hipEvent_t, hipEvent_t);
 template hipError_t launch_update_b<float>(float *, int64_t, int, int, const int2 *,
-                                           const float *, double *, int, hipStream_t);
+                                           const float *, double *, int, hipStream_t,
+                                           hipEvent_t, hipEvent_t);
 template hipError_t launch_update_v<double>(double *, int64_t, int64_t, int, int, const int2 *,
-                                            const double *, hipStream_t);
+                                            const double *, hipStream_t, hipEvent_t,
+                                            hipEvent_t);
 template hipError_t launch_update_v<float>(float *, int64_t, int64_t, int, int, const int2 *,
-                                           const float *, hipStream_t);
+                                           const float *, hipStream_t, hipEvent_t, hipEvent_t);
 
 } // namespace lj
