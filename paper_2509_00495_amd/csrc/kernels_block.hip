@@ -14,6 +14,8 @@
 // Entries of B coupling a padding index are zero and stay exactly zero, so
 // padding never mixes with the matrix.
 #include "internal.hpp"
+
+#include <algorithm>
 #include "update_v.hpp"
 
 namespace lj {
@@ -405,24 +407,35 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
 
 // The pair solves of a round on workgroups 0 .. npairs-1 and, on the
 // workgroups after them, the V update of the previous round (its pairs vpairs
-// and rotations vU, vranges row ranges per pair).  The two parts touch
-// disjoint data: B and U versus V (vU is the other U buffer).
+// and rotations vU).  The two parts touch disjoint data: B and U versus V (vU
+// is the other U buffer).  The ntile 16-row tiles of pair l's columns are
+// split at ntile - vx: V workgroup (l, part) takes part `part` of vranges
+// equal ranges of [0, ntile - vx), and pair-solve workgroup l, once its solve
+// is done, takes [ntile - vx, ntile).
 template <typename T, int M, int NT, bool CROSS>
 __global__ __launch_bounds__(NT) void pair_solve_v_kernel(
     T *__restrict__ B, int64_t ldb, const int2 *__restrict__ pairs,
     const int2 *__restrict__ psmap, T *__restrict__ U, double eps, double thr, int inner,
     double *__restrict__ partial, int *rot_flag, int npairs, T *__restrict__ V, int64_t ldv,
     int64_t ntile, const int2 *__restrict__ vpairs, const T *__restrict__ vU, int vranges,
-    int vwaves)
+    int vwaves, int vx)
 {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *ufl = reinterpret_cast<T *>(smem_raw);
+    const int64_t split = ntile - vx;
     if ((int)blockIdx.x < npairs) {
         pair_solve_body<T, M, NT, CROSS>(B, ldb, pairs, psmap, U, eps, thr, inner, partial,
                                          rot_flag, blockIdx.x);
+        if (vx > 0) {
+            __syncthreads(); // the solve's LDS is free again
+            vupd::v_update_wg<T, M, NT>(V, ldv, vpairs, blockIdx.x, vU, split, ntile, vwaves,
+                                        ufl);
+        }
         return;
     }
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    vupd::v_update_wg<T, M, NT>(V, ldv, ntile, vpairs, npairs, vU, vranges, vwaves,
-                                (int)blockIdx.x - npairs, reinterpret_cast<T *>(smem_raw));
+    const int wg = (int)blockIdx.x - npairs, l = wg % npairs, part = wg / npairs;
+    vupd::v_update_wg<T, M, NT>(V, ldv, vpairs, l, vU, (int64_t)part * split / vranges,
+                                (int64_t)(part + 1) * split / vranges, vwaves, ufl);
 }
 
 template <typename T, int M, int NT, bool CROSS>
@@ -528,6 +541,25 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
     // (long runs of tiles per wavefront; measured at n = 4096)
     const int vdef = (sizeof(T) == 4 ? 4 : 8) < NT / WAVE ? (sizeof(T) == 4 ? 4 : 8) : NT / WAVE;
     const int vwaves = g_pair_v_waves > 0 && g_pair_v_waves <= NT / WAVE ? g_pair_v_waves : vdef;
+    // tiles the pair-solve workgroups take once their solves are done, so
+    // that both kinds of workgroup finish together: with R V workgroups per
+    // pair at rho tiles/us each and a pair workgroup free for V after tp us,
+    // the launch ends at T = (ntile + rho tp) / ((R + 1) rho) and the pair
+    // workgroup takes rho (T - tp) tiles (none when the V part finishes
+    // first).  rho and tp measured on MI355X at 2b = 64, n = 4096: the pair
+    // solve takes 29.6 us (FP32) / 31.7 us (FP64), plus about 3 us to stage
+    // U_l and fill the V pipeline; 2.63 / 1.19 tiles/us.  (Measured: FP64
+    // splits of 20, 33, 36 and 52 tiles at n = 4096 gave plain solves of
+    // 188.7, 184.6, 184.3 and 194.4 ms; FP32 splits of 6 tiles were slower
+    // than none.)
+    int vx = 0;
+    if (M == 64) {
+        const double tp = sizeof(T) == 4 ? 32.6 : 34.7, rho = sizeof(T) == 4 ? 2.63 : 1.19;
+        const double T_end = ((double)ntile + rho * tp) / ((double)(ranges + 1) * rho);
+        const double x = rho * (T_end - tp);
+        if (x > 0.0)
+            vx = (int)std::min<double>(x + 0.5, (double)ntile / (double)(ranges + 1));
+    }
     const size_t lds = smem > g_pair_v_lds ? smem : g_pair_v_lds;
     if (lds != smem_set) {
         hipError_t e = hipFuncSetAttribute((const void *)k,
@@ -538,7 +570,7 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
     }
     hipLaunchKernelGGL(k, dim3(grid), dim3(NT), lds, s, B, ldb, pairs, psmap, U, eps, thr,
                        inner, partial, rot_flag, npairs, V, ldv, ntile, vpairs, vU,
-                       (int)ranges, vwaves);
+                       (int)ranges, vwaves, vx);
     return hipGetLastError();
 }
 

@@ -170,17 +170,17 @@ __device__ inline void v_update_wave(T *__restrict__ V, int64_t ldv, int64_t nti
         work(xb, t);
 }
 
-// Workgroup variant for the launch shared with the pair solves: workgroup wg
-// takes pair l = wg % npairs and part wg / npairs of `ranges` equal row ranges
-// of V.  U_l^T is staged once into LDS (ufl, M*M entries) in per-lane fragment
-// order, and every wavefront reads it from there with 16-byte LDS loads at
-// consecutive addresses; the first nw wavefronts take the range's 16-row tiles
-// in turn (tile t0 + w + i nw), each with two X buffers in flight as above.
-// Every thread reaches the barrier.
+// Workgroup variant for the launch shared with the pair solves: the 16-row
+// tiles [t0, t1) of pair l's columns.  U_l^T is staged once into LDS (ufl,
+// M*M entries) in per-lane fragment order, and every wavefront reads it from
+// there with 16-byte LDS loads at consecutive addresses; the first nw
+// wavefronts take the range's tiles in turn (tile t0 + w + i nw), each with
+// two X buffers in flight as above.  Every thread reaches the barrier.
 template <typename T, int M, int NT>
-__device__ inline void v_update_wg(T *__restrict__ V, int64_t ldv, int64_t ntile,
-                                   const int2 *__restrict__ pairs, int npairs,
-                                   const T *__restrict__ U, int ranges, int nw, int wg, T *ufl)
+__device__ inline void v_update_wg(T *__restrict__ V, int64_t ldv,
+                                   const int2 *__restrict__ pairs, int l,
+                                   const T *__restrict__ U, int64_t t0, int64_t t1, int nw,
+                                   T *ufl)
 {
     constexpr int b = M / 2;
     constexpr int VK = 16 / (int)sizeof(T);
@@ -190,8 +190,6 @@ __device__ inline void v_update_wg(T *__restrict__ V, int64_t ldv, int64_t ntile
     typedef typename acc4<T>::type accT;
     const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
     const int li = lane % 16, lk = lane / 16;
-    const int l = wg % npairs, part = wg / npairs;
-    const int64_t t0 = (int64_t)part * ntile / ranges, t1 = (int64_t)(part + 1) * ntile / ranges;
     const int2 pl = pairs[l];
     const T *Ult = U + (int64_t)l * M * M; // transposed: Ult[j][i] = U_l[i][j]
     for (int e = tid; e < TC * KG * WAVE; e += NT) {
