@@ -547,14 +547,16 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
     // the launch ends at T = (ntile + rho tp) / ((R + 1) rho) and the pair
     // workgroup takes rho (T - tp) tiles (none when the V part finishes
     // first).  rho and tp measured on MI355X at 2b = 64, n = 4096: the pair
-    // solve takes 29.6 us (FP32) / 31.7 us (FP64), plus about 3 us to stage
-    // U_l and fill the V pipeline; 2.63 / 1.19 tiles/us.  (Measured: FP64
+    // solve takes 29.6 us (FP32) / 31.7 us (FP64) on the cross schedule and
+    // 58.6 / 66.1 us on the full one, plus about 3 us to stage U_l and fill
+    // the V pipeline; 2.63 / 1.19 tiles/us.  (Measured: FP64
     // splits of 20, 33, 36 and 52 tiles at n = 4096 gave plain solves of
     // 188.7, 184.6, 184.3 and 194.4 ms; FP32 splits of 6 tiles were slower
     // than none.)
     int vx = 0;
     if (M == 64) {
-        const double tp = sizeof(T) == 4 ? 32.6 : 34.7, rho = sizeof(T) == 4 ? 2.63 : 1.19;
+        const double tp = 3.0 + (sizeof(T) == 4 ? (CROSS ? 29.6 : 58.6) : (CROSS ? 31.7 : 66.1));
+        const double rho = sizeof(T) == 4 ? 2.63 : 1.19;
         const double T_end = ((double)ntile + rho * tp) / ((double)(ranges + 1) * rho);
         const double x = rho * (T_end - tp);
         if (x > 0.0)
