@@ -128,6 +128,19 @@ def test_shared_launch_bitwise(pj, fn):
     assert np.array_equal(W0, W1) and np.array_equal(V0, V1)
 
 
+@pytest.mark.parametrize("fn", ["eigh", "eigh_mixed"])
+def test_shared_launch_bitwise_4096(pj, fn):
+    """At n = 4096 the pair-solve workgroups of the FP64 shared launch also take
+    the last tiles of their pair's V update (the split the timing model picks
+    there is nonzero); the result still equals the standalone update's bitwise."""
+    A = torch.tensor(wl.goe(4096, 3), device="cuda")
+    print(f"  -> {fn} n=4096 default vs serial_v=1", flush=True)
+    W0, V0 = getattr(pj, fn)(A)
+    W1, V1 = getattr(pj, fn)(A, opts=pj.make_opts(serial_v=1))
+    torch.cuda.synchronize()
+    assert torch.equal(W0, W1) and torch.equal(V0, V1)
+
+
 @pytest.mark.parametrize("n,block,inner", [(128, 16, 2), (192, 32, 3)])
 def test_block_path_inner_sweeps(pj, n, block, inner):
     A = wl.random_symmetric(n, 3000 + n)
