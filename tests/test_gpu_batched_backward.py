@@ -63,6 +63,41 @@ def test_batched_clustered_sample(pj):
         _check(A, Wk, Vk, lam, f"clustered {k}")
 
 
+def test_batched_clustered_full(pj):
+    """The full batched workload in the launch configuration a caller gets by
+    default (autotuned): 10 000 matrices, n uniform in [8, 128], spectra in 5
+    clusters of width 1e-8.  Every matrix is checked, on the GPU per order
+    group: status, residual and orthogonality bars, and eigenvalues against the
+    spectrum it was built from."""
+    ns, mats, lams = wl.clustered_batch(batch=10000, seed=4)
+    A = _pack(mats)
+    print(f"  -> eigh_batched clustered batch={len(ns)}", flush=True)
+    W, V, st = pj.eigh_batched(A, ns)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    lam = torch.tensor(np.concatenate(lams), device="cuda")
+    aoff = np.concatenate([[0], np.cumsum([n * n for n in ns])[:-1]])
+    woff = np.concatenate([[0], np.cumsum(ns)[:-1]])
+    worst = [0.0, 0.0, 0.0]
+    for n in sorted(set(ns)):
+        ks = [k for k, m in enumerate(ns) if m == n]
+        An = torch.stack([A[aoff[k]:aoff[k] + n * n].view(n, n) for k in ks])
+        Vn = torch.stack([V[aoff[k]:aoff[k] + n * n].view(n, n) for k in ks])
+        Wn = torch.stack([W[woff[k]:woff[k] + n] for k in ks])
+        Ln = torch.stack([lam[woff[k]:woff[k] + n] for k in ks])
+        R = torch.bmm(An, Vn) - Vn * Wn[:, None, :]
+        res = torch.linalg.norm(R, dim=(1, 2)) / torch.linalg.norm(An, dim=(1, 2))
+        I = torch.eye(n, dtype=torch.float64, device="cuda")
+        orth = torch.linalg.norm(torch.bmm(Vn.transpose(1, 2).contiguous(), Vn) - I, dim=(1, 2))
+        err = (Wn - Ln).abs().amax(dim=1) / Ln.abs().amax(dim=1)
+        worst = [max(worst[0], res.max().item() / (1e-13 * n)),
+                 max(worst[1], orth.max().item() / (1e-14 * n)),
+                 max(worst[2], err.max().item() / 1e-13)]
+    print(f"  worst fractions of the bars: residual {worst[0]:.3f} orthogonality "
+          f"{worst[1]:.3f} eigenvalues {worst[2]:.3f}", flush=True)
+    assert max(worst) <= 1.0
+
+
 @pytest.mark.parametrize("threads", [256, 512, 1024])
 def test_batched_matches_single(pj, threads):
     """The persistent batched launch and the single-matrix call agree bitwise
