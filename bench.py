@@ -254,15 +254,19 @@ def main():
     if os.path.exists(gold):
         Wo = np.loadtxt(gold)
         acc["eig_err_vs_oracle"] = float(np.abs(Wn - Wo).max() / np.abs(Wo).max())
+        if lam is not None:
+            acc["oracle_err_vs_known_spectrum"] = float(np.abs(Wo - lam).max() / np.abs(lam).max())
         acc["eig_bar"] = 1e-13
     if plain is not None:
         acc["mixed_vs_plain_max_dW_rel"] = float(
             np.abs(Wn - Wp.cpu().numpy()).max() / np.abs(Wn).max())
     gate = acc["residual_rel_F"] <= acc["residual_bar"] and acc["orth_F"] <= acc["orth_bar"]
-    if "eig_err_vs_oracle" in acc:
-        gate = gate and acc["eig_err_vs_oracle"] <= 1e-13
     if "eig_err_vs_known_spectrum" in acc:
+        # the exact spectrum decides; the oracle's stored eigenvalues (the
+        # diagonal after its sweeps) are themselves ~2.5e-13 off at n = 1024
         gate = gate and acc["eig_err_vs_known_spectrum"] <= 1e-13
+    elif "eig_err_vs_oracle" in acc:
+        gate = gate and acc["eig_err_vs_oracle"] <= 1e-13
     acc["gate_passed"] = bool(gate)
 
     # roofline of the dominant update kernel, from the in-library HIP events of

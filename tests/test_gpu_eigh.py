@@ -224,6 +224,31 @@ def test_ari_known_spectrum(pj, fn):
     assert np.linalg.norm(V.T @ V - np.eye(n)) <= 1e-14 * n
 
 
+@pytest.mark.parametrize("fn", ["eigh", "eigh_mixed"])
+def test_geo1024_vs_oracle_fixture(pj, fn):
+    """The n = 1024 geometric workload (magnitudes 1 .. 1e-6, random signs) at
+    full size: eigenvalues against the spectrum it was built from (the bar),
+    and against the oracle's stored run on the same matrix
+    (tests/golden/oracle_geo1024.txt, written by make_oracle_fixtures.py)
+    within the oracle's own distance from that spectrum (its eigenvalues are
+    the diagonal after 15 sweeps of rotations, which drifts by 2.5e-13 ||A||_2
+    here), plus the residual and orthogonality bars."""
+    import os
+    A, lam = wl.geo_spectrum(1024, 2)
+    gold = os.path.join(os.path.dirname(__file__), "golden", "oracle_geo1024.txt")
+    Wo = np.loadtxt(gold)
+    W, V, info = run(pj, fn, A)
+    assert info["status"] == 0
+    n = A.shape[0]
+    nrm2 = np.abs(lam).max()
+    print(f"  geo1024 {fn}: |W-W_oracle|/|A|_2={np.abs(W - Wo).max() / nrm2:.2e} "
+          f"|W-lam|/|A|_2={np.abs(W - lam).max() / nrm2:.2e}", flush=True)
+    assert np.abs(W - lam).max() <= 1e-13 * nrm2
+    assert np.abs(W - Wo).max() <= np.abs(Wo - lam).max() + 1e-13 * nrm2
+    assert np.linalg.norm(A @ V - V * W) / np.linalg.norm(A) <= 1e-13 * n
+    assert np.linalg.norm(V.T @ V - np.eye(n)) <= 1e-14 * n
+
+
 def test_mixed_goe(pj):
     A = wl.goe(256, 77)
     W, V, info = run(pj, "eigh_mixed", A)
