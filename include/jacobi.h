@@ -139,8 +139,8 @@ typedef struct jacobi_info {
  *   n    [in]  order, n >= 0 (n = 0 is a no-op)
  *   W    [out] n eigenvalues, ascending
  *   V    [out] n x n eigenvectors (columns), leading dimension ldv >= max(1, n);
- *              on the block path every column is scaled to unit 2-norm and
- *              its entry of largest magnitude is positive
+ *              every column is scaled to unit 2-norm and its entry of
+ *              largest magnitude is positive
  *   tol  [in]  stop when off(B) <= tol (absolute); tol <= 0 selects
  *              1e-15 * n * ||A||_F.  NaN is an invalid argument.
  * Returns JACOBI_OK, JACOBI_NOCONV (outputs still written), JACOBI_NOTSYM,

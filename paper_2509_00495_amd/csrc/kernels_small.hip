@@ -89,7 +89,7 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
             ++sweeps;
             off2 = lds_off2<double, NT>(S, ld, m, red);
         }
-        // output: W ascending (stable), columns permuted and sign-fixed
+        // output: W ascending (stable), columns permuted, sign-fixed and normalized
         for (int i = tid; i < m; i += NT) {
             perm[i] = i < n ? i : 0;
             if (i < n)
@@ -106,17 +106,21 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
             perm[rank] = i;
         }
         __syncthreads();
+        // sign convention (largest entry positive) and unit 2-norm: the
+        // rotations' rounding lets the column norms drift a little
         for (int c = tid; c < n; c += NT) {
             int col = perm[c];
-            double best = -1.0, val = 0.0;
+            double best = -1.0, val = 0.0, sq = 0.0;
             for (int i = 0; i < n; ++i) {
                 double v = Vt[(int64_t)col * ldt + i];
+                sq = fma(v, v, sq);
                 if (fabs(v) > best) {
                     best = fabs(v);
                     val = v;
                 }
             }
-            sg[c] = val < 0.0 ? -1.0 : 1.0;
+            const double inv = sq > 0.0 ? 1.0 / sqrt(sq) : 1.0;
+            sg[c] = val < 0.0 ? -inv : inv;
             W[d.w_off + c] = wv[col];
         }
         __syncthreads();
