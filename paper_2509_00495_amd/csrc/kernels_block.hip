@@ -285,25 +285,32 @@ __device__ inline void pair_solve_body(T *__restrict__ B, int64_t ldb,
                 const int a00 = sidx(pk0, pl0), a01 = sidx(pk0, pl1);
                 const int a10 = sidx(pk1, pl0), a11 = sidx(pk1, pl1);
                 const T x00 = S[a00], x01 = S[a01], x10 = S[a10], x11 = S[a11];
+                // the host of the next round's angle reads its records before
+                // any LDS store of this round (a load after a store would wait
+                // for it) and computes the angle before storing its block:
+                // this chain is the longest of the round
+                T dpe = (T)0, dqe = (T)0;
+                if (hosted) {
+                    dpe = ha ? rotated_diag<T>(A.aqq[k], A.t[k], A.apq[k], 1)
+                             : rotated_diag<T>(A.app[k], A.t[k], A.apq[k], 0);
+                    dqe = hc ? rotated_diag<T>(A.aqq[l], A.t[l], A.apq[l], 1)
+                             : rotated_diag<T>(A.app[l], A.t[l], A.apq[l], 0);
+                }
                 const T y00 = ck * x00 - sk * x10, y01 = ck * x01 - sk * x11;
                 const T y10 = sk * x00 + ck * x10, y11 = sk * x01 + ck * x11;
                 const T z00 = cl * y00 - sl * y01, z01 = sl * y00 + cl * y01;
                 const T z10 = cl * y10 - sl * y11, z11 = sl * y10 + cl * y11;
-                S[a00] = z00;
-                S[a01] = z01;
-                S[a10] = z10;
-                S[a11] = z11;
                 if (hosted) {
-                    const T dpe = ha ? rotated_diag<T>(A.aqq[k], A.t[k], A.apq[k], 1)
-                                     : rotated_diag<T>(A.app[k], A.t[k], A.apq[k], 0);
-                    const T dqe = hc ? rotated_diag<T>(A.aqq[l], A.t[l], A.apq[l], 1)
-                                     : rotated_diag<T>(A.app[l], A.t[l], A.apq[l], 0);
                     const T zz = ha ? (hc ? z11 : z10) : (hc ? z01 : z00);
                     const int rr = pair_record<T>(Bn, hk, hfirst ? dpe : dqe,
                                                   hfirst ? dqe : dpe, zz, eps, thr);
                     if (r + 1 < rounds)
                         rot |= rr;
                 }
+                S[a00] = z00;
+                S[a01] = z01;
+                S[a10] = z10;
+                S[a11] = z11;
             }
         }
 #pragma unroll
