@@ -95,7 +95,9 @@ typedef struct jacobi_opts {
                                a given set of arguments, workspace and tuned
                                configuration and replayed by later identical
                                calls (needs a caller workspace; ignored
-                               without one); 0 (default) = direct launches */
+                               without one; at most 64 graphs are kept per
+                               process, later new argument sets launch
+                               directly); 0 (default) = direct launches */
 } jacobi_opts;
 
 /* Diagnostics filled on return (host struct, may be NULL). */

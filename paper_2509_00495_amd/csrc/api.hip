@@ -378,9 +378,12 @@ struct SmallGraphKey {
 };
 
 std::map<SmallGraphKey, hipGraphExec_t> g_small_graphs;
+// graphs kept per process; a new key past this runs its launches directly
+constexpr size_t SMALL_GRAPHS_MAX = 64;
 
 // Replays the graph cached under `k` on `s`, capturing it first from
-// `issue(capture_stream)` when the key is new.
+// `issue(capture_stream)` when the key is new (or issuing directly on `s`
+// once the cache is full).
 template <typename F> int small_graph_run(const SmallGraphKey &k, hipStream_t s, F issue)
 {
     hipGraphExec_t exec = nullptr;
@@ -389,6 +392,8 @@ template <typename F> int small_graph_run(const SmallGraphKey &k, hipStream_t s,
         auto it = g_small_graphs.find(k);
         if (it != g_small_graphs.end())
             exec = it->second;
+        else if (g_small_graphs.size() >= SMALL_GRAPHS_MAX)
+            return issue(s);
     }
     if (!exec) {
         hipStream_t cs = nullptr;

@@ -168,6 +168,36 @@ def test_batched_graph_replay(pj):
         _check(A_now, Wk, Vk, Wo, "graph replay")
 
 
+def test_batched_graph_cache_full(pj):
+    """More distinct graph-mode argument sets than the library keeps graphs
+    for: the calls past the limit launch directly, the cached ones still
+    replay, and every result equals the direct launch bitwise."""
+    ns_all = [6 + (k % 5) for k in range(72)]
+    mats = [wl.random_symmetric(n, 6000 + k) for k, n in enumerate(ns_all)]
+    og = pj.make_opts(graph=1)
+    ws = pj.Workspace()
+    ws.get(pj.workspace_bytes(2, max(ns_all), len(ns_all), og))  # one fixed address
+    calls = []
+    for cnt in range(1, 73):
+        ns = ns_all[:cnt]
+        calls.append((ns, _pack(mats[:cnt]),
+                      (torch.empty(sum(ns), dtype=torch.float64, device="cuda"),
+                       torch.empty(sum(x * x for x in ns), dtype=torch.float64, device="cuda"),
+                       torch.zeros(cnt, dtype=torch.int32, device="cuda"))))
+    for k in list(range(72)) + [0, 1]:  # the last two replay cached graphs
+        ns, A, out = calls[k]
+        if k % 24 == 0:
+            print(f"  -> graph cache call batch={len(ns)}", flush=True)
+        out[0].zero_()
+        pj.eigh_batched(A, ns, opts=og, ws=ws, out=out)
+        We, Ve, se = pj.eigh_batched(A, ns)
+        torch.cuda.synchronize()
+        assert (out[2].cpu().numpy() == 0).all(), k
+        assert torch.equal(out[0], We) and torch.equal(out[1], Ve), k
+    Wk, Vk = _unpack(calls[1][2][0], calls[1][2][1], calls[1][0])[1]
+    Wo, *_ = oracle.eigh(mats[1])
+    _check(mats[1], Wk, Vk, Wo, "graph cache")
+
 def test_backward_vs_oracle(pj):
     mats, lams, ws, Cs = wl.gapped_batch(batch=3, n=32, seed=5)
     Wt, Vt = [], []
