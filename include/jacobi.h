@@ -110,7 +110,12 @@ typedef struct jacobi_info {
     int32_t polished;       /* 1 if the output stage's Newton-Schulz step on V
                                ran (the estimate below exceeded 0.2 of the
                                1e-14 n bar) */
-    int32_t reserved_i[2];
+    int32_t skipped_tiles;  /* block path, FP64 sweeps: off-diagonal tile
+                               updates of B left out because neither block
+                               pair of the tile rotated in that round (U = I
+                               there; the results are unchanged), summed over
+                               the sweeps */
+    int32_t reserved_i[1];
     double norm_f;          /* ||A||_F of the symmetrised input */
     double tol;             /* absolute threshold on off(B) actually used */
     double off_final;       /* off(B) when the FP64 stage stopped */

@@ -182,6 +182,7 @@ struct BlockWs {
     float *B32, *V32, *U32;
     double *partial, *scal, *wtmp, *sg, *cmax, *csq, *cinv;
     int *flags, *perm, *cidx;
+    int *prot; // per-pair rotation flags of a round, double-buffered like U
     int2 *pairs, *psmap;
 };
 
@@ -215,6 +216,7 @@ BlockWs layout_block(Bump &bp, int64_t n, const Geometry &g, bool mixed)
     w.partial = bp.take<double>(partial_count(g));
     w.scal = bp.take<double>(8);
     w.flags = bp.take<int>(8);
+    w.prot = bp.take<int>((size_t)2 * g.npairs * PROT_STRIDE);
     w.pairs = bp.take<int2>((size_t)(g.N - 1) * g.npairs);
     w.psmap = bp.take<int2>((size_t)g.b * (g.b + 1)); // circle map, then cross map
     w.perm = bp.take<int>((size_t)std::max<int64_t>(n, 1));
@@ -547,7 +549,7 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
                bool fp32_stage,
                hipStream_t s,
                SideStream &ss, int *sweeps_out, double *off_out, double *off0_out,
-               RoundTimer *tm)
+               RoundTimer *tm, int *skipped_out)
 {
     Readback rb;
     if (tm && tm->on)
@@ -579,6 +581,14 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
     const bool fuse = serial_v == 0 && !(tm && tm->on);
     const int2 *vpend_pairs = nullptr; // V update waiting for the next launch
     const T *vpend_U = nullptr;
+    const int *vpend_prot = nullptr;
+    // Pair skipping (FP64 sweeps): a pair solve that applies no rotation
+    // (every coupling passes the skip test of the rotation) leaves U = I
+    // exactly; the B tiles of two such pairs and the V columns of such a pair
+    // are then left out of the round's updates, which changes no result.
+    // flags[3] counts the B tiles left out.  The FP32 stage runs without it
+    // (null flags): there the flag store slows the pair solve, which sets the
+    // pace of its rounds, by more than the skips return.
     while (off > tol) {
         if (sweeps >= max_sweeps) {
             status = JACOBI_NOCONV;
@@ -589,6 +599,7 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
         for (int r = 0; r < g.N - 1; ++r, ++ss.round) {
             const int j = (int)(ss.round & 1);
             T *Ub = U + j * ustride;
+            int *pf = sizeof(T) == 8 ? w.prot + (size_t)j * g.npairs * PROT_STRIDE : nullptr;
             const int2 *pr = w.pairs + (size_t)r * g.npairs;
             if (side && ss.recV[j])
                 CK(hipStreamWaitEvent(s, ss.evV[j], 0));
@@ -596,12 +607,12 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
             const int2 *map = w.psmap + (cross ? (size_t)g.b * (g.b + 1) / 2 : 0);
             if (vpend_pairs) {
                 CK(launch_pair_solve_v<T>(B, g.npad, g.b, g.npairs, pr, map, Ub, eps, thr, inner,
-                                          cross, w.partial, w.flags + 2, V, g.npad, g.npad,
-                                          vpend_pairs, vpend_U, s));
+                                          cross, w.partial, w.flags + 2, pf, V, g.npad,
+                                          g.npad, vpend_pairs, vpend_U, vpend_prot, s));
                 vpend_pairs = nullptr;
             } else {
                 CK(launch_pair_solve<T>(B, g.npad, g.b, g.npairs, pr, map, Ub, eps, thr, inner,
-                                        cross, w.partial, w.flags + 2, s,
+                                        cross, w.partial, w.flags + 2, pf, s,
                                         timed ? tm->ev[6 * r] : nullptr,
                                         timed ? tm->ev[6 * r + 1] : nullptr));
             }
@@ -609,17 +620,19 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
                 CK(hipEventRecord(ss.evU[j], s));
             CK(launch_update_b<T>(B, g.npad, g.b, g.npairs, pr, Ub,
                                   w.partial + (size_t)g.npairs * pair_solve_waves(g.M),
-                                  r == g.N - 2, s, timed ? tm->ev[6 * r + 2] : nullptr,
+                                  r == g.N - 2, pf, w.flags + 3, s,
+                                  timed ? tm->ev[6 * r + 2] : nullptr,
                                   timed ? tm->ev[6 * r + 3] : nullptr));
             if (fuse) {
                 vpend_pairs = pr;
                 vpend_U = Ub;
+                vpend_prot = pf;
                 continue;
             }
             hipStream_t sv = side ? ss.s2 : s;
             if (side)
                 CK(hipStreamWaitEvent(ss.s2, ss.evU[j], 0));
-            CK(launch_update_v<T>(V, g.npad, g.npad, g.b, g.npairs, pr, Ub, sv,
+            CK(launch_update_v<T>(V, g.npad, g.npad, g.b, g.npairs, pr, Ub, pf, sv,
                                   timed ? tm->ev[6 * r + 4] : nullptr,
                                   timed ? tm->ev[6 * r + 5] : nullptr));
             if (side) {
@@ -655,12 +668,15 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
             break;
     }
     if (vpend_pairs)
-        CK(launch_update_v<T>(V, g.npad, g.npad, g.b, g.npairs, vpend_pairs, vpend_U, s));
+        CK(launch_update_v<T>(V, g.npad, g.npad, g.b, g.npairs, vpend_pairs, vpend_U, vpend_prot,
+                              s));
     // V is complete on the caller's stream from here on
     if (side && ss.round > 0 && ss.recV[(ss.round - 1) & 1])
         CK(hipStreamWaitEvent(s, ss.evV[(ss.round - 1) & 1], 0));
     *sweeps_out = sweeps;
     *off_out = off;
+    if (skipped_out)
+        *skipped_out = rb.flags[3]; // read after the last sweep
     return status;
 }
 
@@ -677,6 +693,7 @@ int setup_block(const Geometry &g, const BlockWs &w, hipStream_t s)
     CK(hipMemcpyAsync(w.psmap, psmap.data(), psmap.size() * sizeof(int2), hipMemcpyHostToDevice,
                       s));
     CK(launch_fill_i32(w.flags, 8, 0, s));
+    CK(launch_fill_i32(w.prot, (int64_t)2 * g.npairs * PROT_STRIDE, 0, s));
     CK(hipStreamSynchronize(s)); // the host tables go out of scope
     return 0;
 }
@@ -853,7 +870,7 @@ int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, in
         return e;
     CK(launch_eye<double>(w.V64, g.npad, s));
     const double tol = tol_in > 0.0 ? tol_in : 1e-15 * (double)n * normf;
-    int sweeps = 0;
+    int sweeps = 0, skipped = 0;
     double off = 0.0;
     RoundTimer tm;
     tm.on = o.timing;
@@ -861,7 +878,8 @@ int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, in
     if (int e = ss.init())
         return e;
     int st = run_sweeps<double>(g, n, w, w.B64, w.V64, w.U64, tol, U_D, o.max_sweeps, o.inner,
-                                o.schedule, o.serial_v, false, s, ss, &sweeps, &off, nullptr, &tm);
+                                o.schedule, o.serial_v, false, s, ss, &sweeps, &off, nullptr, &tm,
+                                &skipped);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;
     double est = 0.0;
@@ -874,6 +892,7 @@ int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, in
     if (info) {
         info->orth_est = est;
         info->polished = pol;
+        info->skipped_tiles = skipped;
     }
     tm.store(info, 0);
     return st;
@@ -906,7 +925,8 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     if (int e = ss.init())
         return e;
     int st32 = run_sweeps<float>(g, n, w, w.B32, w.V32, w.U32, tol32, U_L, o.max_sweeps,
-                                 o.inner, o.schedule, o.serial_v, true, s, ss, &sw32, &off32, nullptr, &tm32);
+                                 o.inner, o.schedule, o.serial_v, true, s, ss, &sw32, &off32, nullptr, &tm32,
+                                 nullptr);
     if (st32 == JACOBI_DEVICE)
         return st32;
     // stage 2: Newton-Schulz, X <- X + X (I - X^T X) / 2  (= X (3I - X^T X) / 2)
@@ -942,10 +962,11 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     CK(launch_gemm64_sym(1, 0, g.npad, g.npad, 1.0, X, g.npad, R, g.npad, 0.0, nullptr, 0, 0.0,
                          A64, g.npad, s, X2, nn));
     const double tol = tol_in > 0.0 ? tol_in : 1e-15 * (double)n * normf;
-    int sw64 = 0;
+    int sw64 = 0, skipped = 0;
     double off = 0.0, offc = 0.0;
     int st = run_sweeps<double>(g, n, w, A64, X, w.U64, tol, U_D, o.max_sweeps, o.inner,
-                                o.schedule, o.serial_v, false, s, ss, &sw64, &off, &offc, &tm64);
+                                o.schedule, o.serial_v, false, s, ss, &sw64, &off, &offc, &tm64,
+                                &skipped);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;
     double est = 0.0;
@@ -957,6 +978,7 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     if (info) {
         info->orth_est = est;
         info->polished = pol;
+        info->skipped_tiles = skipped;
     }
     tm64.store(info, 0);
     tm32.store(info, 1);

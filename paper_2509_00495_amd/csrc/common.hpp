@@ -143,6 +143,26 @@ __device__ inline bool jacobi_should_rotate_sq(double app, double aqq, double ap
     return apq != 0.0 && a > thr && a * a > eps * eps * fabs(app * aqq);
 }
 
+// Per-pair rotation flags of a round: the pair solve of pair p stores one int
+// per wavefront at prot[p * PROT_STRIDE + wavefront], nonzero when that
+// wavefront applied a rotation.  A pair solve that applied none leaves its
+// tile and its U exactly as they were (U = I: every record then holds
+// c = 1, s = 0, t = 0), so the updates of B and V may leave that pair out.
+constexpr int PROT_STRIDE = 16;
+template <int PW>
+__device__ inline bool pair_rotated(const int *__restrict__ prot, int p)
+{
+    static_assert(PW % 4 == 0 && PW <= PROT_STRIDE, "flags per pair");
+    const int4 *q = reinterpret_cast<const int4 *>(prot + (int64_t)p * PROT_STRIDE);
+    int r = 0;
+#pragma unroll
+    for (int i = 0; i < PW / 4; ++i) {
+        const int4 v = q[i];
+        r |= v.x | v.y | v.z | v.w;
+    }
+    return r != 0;
+}
+
 // Workgroup barrier that orders LDS accesses only.  __syncthreads() also
 // makes every wavefront wait for all of its outstanding global stores and
 // loads; phases that share data only through LDS use this one, so stores and

@@ -52,16 +52,17 @@ inline void launch_timed(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStrea
 template <typename T>
 hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                              const int2 *psmap, T *U, double eps, double thr, int inner,
-                             int cross, double *partial, int *rot_flag, hipStream_t s,
-                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                             int cross, double *partial, int *rot_flag, int *prot,
+                             hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // the same pair solves, plus the V update V[:, cols] <- V[:, cols] vU of the
-// previous round (pairs vpairs, rotations vU) on further workgroups of the
-// same launch
+// previous round (pairs vpairs, rotations vU, rotation flags vprot or null)
+// on further workgroups of the same launch
 template <typename T>
 hipError_t launch_pair_solve_v(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                                const int2 *psmap, T *U, double eps, double thr, int inner,
-                               int cross, double *partial, int *rot_flag, T *V, int64_t ldv,
-                               int64_t nrows, const int2 *vpairs, const T *vU, hipStream_t s);
+                               int cross, double *partial, int *rot_flag, int *prot, T *V,
+                               int64_t ldv, int64_t nrows, const int2 *vpairs, const T *vU,
+                               const int *vprot, hipStream_t s);
 // experiments: V workgroups of the shared launch (0 = default), a minimum
 // dynamic LDS per workgroup (larger keeps one workgroup per compute unit) and
 // the working wavefronts per V workgroup (0 = all)
@@ -72,21 +73,24 @@ constexpr int pair_solve_waves(int M) { return M == 64 ? 16 : 4; }
 void pair_solve_map(int M, int cross, int2 *out);
 // B_kl <- U_k^T B_kl U_l (into B's upper blocks) for every two pairs k < l of
 // the round; tile t = l (l - 1) / 2 + k; partial[t (2b / 16) + w] gets twice
-// the squared sum of wavefront w's part of tile t when want_off
-// (kernels_update.hip)
+// the squared sum of wavefront w's part of tile t when want_off.  With the
+// round's rotation flags prot (or null) and no want_off, the tiles of two
+// unrotated pairs are left out and counted into *skipped (kernels_update.hip)
 template <typename T>
 hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pairs, const T *U,
-                           double *partial, int want_off, hipStream_t s,
-                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                           double *partial, int want_off, const int *prot, int *skipped,
+                           hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <typename T>
 int update_b_blocks_per_cu(int b);
 // grid sizing of the V update: total resident wavefronts (0 = from occupancy)
 void tune_update_v(int total_waves);
 
-// V[:, cols(pair)] <- V[:, cols(pair)] U_pair for all pairs (kernels_update.hip)
+// V[:, cols(pair)] <- V[:, cols(pair)] U_pair for all pairs, leaving out the
+// unrotated ones when the round's rotation flags prot are given
+// (kernels_update.hip)
 template <typename T>
 hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
-                           const int2 *pairs, const T *U, hipStream_t s,
+                           const int2 *pairs, const T *U, const int *prot, hipStream_t s,
                            hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_sum(const double *x, int64_t count, double *out, hipStream_t s);
 template <typename T>

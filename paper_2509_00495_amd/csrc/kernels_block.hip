@@ -129,11 +129,12 @@ __device__ inline int pair_record(PairRec<T> &R, int k, T app, T aqq, T apq, dou
 // of pair i + 1 (mod b), so block (i, i + 1), or (0, b - 1) for i = b - 1,
 // hosts it.
 template <typename T, int M, int NT, bool CROSS>
-__device__ inline void pair_solve_body(T *__restrict__ B, int64_t ldb,
+__device__ __forceinline__ void pair_solve_body(T *__restrict__ B, int64_t ldb,
                                        const int2 *__restrict__ pairs,
                                        const int2 *__restrict__ psmap, T *__restrict__ U,
                                        double eps, double thr, int inner,
-                                       double *__restrict__ partial, int *rot_flag, int pk)
+                                       double *__restrict__ partial, int *rot_flag,
+                                       int *__restrict__ prot, int pk)
 {
     constexpr int b = M / 2, h = M / 2, ld = M + 1;
     typedef typename vec16<T>::type TV;
@@ -395,8 +396,16 @@ __device__ inline void pair_solve_body(T *__restrict__ B, int64_t ldb,
     const int lane = tid % WAVE;
     if (lane == 0)
         partial[(int64_t)pk * (NT / WAVE) + tid / WAVE] = acc;
-    if (__any(rot) && lane == 0)
+    const int any_rot = __any(rot);
+    if (any_rot && lane == 0)
         atomicOr(rot_flag, 1);
+    // FP64 sweeps: this wavefront's rotation flag (none applied leaves c = 1,
+    // s = 0, t = 0 in every record it wrote, so the tile and U = I come out
+    // unchanged).  The FP32 pair solve, the critical path of its rounds, is
+    // measured 0.6 us slower with the store and has no flags (prot unused).
+    if constexpr (sizeof(T) == 8)
+        if (lane == 0)
+            prot[pk * PROT_STRIDE + __builtin_amdgcn_readfirstlane(tid / WAVE)] = any_rot;
 }
 
 template <typename T, int M, int NT, bool CROSS>
@@ -406,10 +415,10 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
                                                         T *__restrict__ U, double eps,
                                                         double thr, int inner,
                                                         double *__restrict__ partial,
-                                                        int *rot_flag)
+                                                        int *rot_flag, int *__restrict__ prot)
 {
     pair_solve_body<T, M, NT, CROSS>(B, ldb, pairs, psmap, U, eps, thr, inner, partial,
-                                     rot_flag, blockIdx.x);
+                                     rot_flag, prot, blockIdx.x);
 }
 
 // The pair solves of a round on workgroups 0 .. npairs-1 and, on the
@@ -423,33 +432,33 @@ template <typename T, int M, int NT, bool CROSS>
 __global__ __launch_bounds__(NT) void pair_solve_v_kernel(
     T *__restrict__ B, int64_t ldb, const int2 *__restrict__ pairs,
     const int2 *__restrict__ psmap, T *__restrict__ U, double eps, double thr, int inner,
-    double *__restrict__ partial, int *rot_flag, int npairs, T *__restrict__ V, int64_t ldv,
-    int64_t ntile, const int2 *__restrict__ vpairs, const T *__restrict__ vU, int vranges,
-    int vwaves, int vx)
+    double *__restrict__ partial, int *rot_flag, int *__restrict__ prot, int npairs,
+    T *__restrict__ V, int64_t ldv, int64_t ntile, const int2 *__restrict__ vpairs,
+    const T *__restrict__ vU, const int *__restrict__ vprot, int vranges, int vwaves, int vx)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *ufl = reinterpret_cast<T *>(smem_raw);
     const int64_t split = ntile - vx;
     if ((int)blockIdx.x < npairs) {
         pair_solve_body<T, M, NT, CROSS>(B, ldb, pairs, psmap, U, eps, thr, inner, partial,
-                                         rot_flag, blockIdx.x);
+                                         rot_flag, prot, blockIdx.x);
         if (vx > 0) {
             __syncthreads(); // the solve's LDS is free again
-            vupd::v_update_wg<T, M, NT>(V, ldv, vpairs, blockIdx.x, vU, split, ntile, vwaves,
-                                        ufl);
+            vupd::v_update_wg<T, M, NT>(V, ldv, vpairs, blockIdx.x, vU, vprot, split, ntile,
+                                        vwaves, ufl);
         }
         return;
     }
     const int wg = (int)blockIdx.x - npairs, l = wg % npairs, part = wg / npairs;
-    vupd::v_update_wg<T, M, NT>(V, ldv, vpairs, l, vU, (int64_t)part * split / vranges,
+    vupd::v_update_wg<T, M, NT>(V, ldv, vpairs, l, vU, vprot, (int64_t)part * split / vranges,
                                 (int64_t)(part + 1) * split / vranges, vwaves, ufl);
 }
 
 template <typename T, int M, int NT, bool CROSS>
 static hipError_t launch_pair_solve_t(T *B, int64_t ldb, int npairs, const int2 *pairs,
                                       const int2 *psmap, T *U, double eps, double thr,
-                                      int inner, double *partial, int *rot_flag, size_t smem,
-                                      hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+                                      int inner, double *partial, int *rot_flag, int *prot,
+                                      size_t smem, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     auto k = pair_solve_kernel<T, M, NT, CROSS>;
     static size_t smem_set = 0; // the attribute is set once per size (host-side cost)
@@ -461,7 +470,7 @@ static hipError_t launch_pair_solve_t(T *B, int64_t ldb, int npairs, const int2 
         smem_set = smem;
     }
     launch_timed(k, dim3(npairs), dim3(NT), (uint32_t)smem, s, e0, e1, B, ldb, pairs, psmap, U,
-                 eps, thr, inner, partial, rot_flag);
+                 eps, thr, inner, partial, rot_flag, prot);
     return hipGetLastError();
 }
 
@@ -479,7 +488,7 @@ static size_t pair_solve_smem(int b)
 template <typename T>
 hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                              const int2 *psmap, T *U, double eps, double thr, int inner,
-                             int cross, double *partial, int *rot_flag, hipStream_t s,
+                             int cross, double *partial, int *rot_flag, int *prot, hipStream_t s,
                              hipEvent_t e0, hipEvent_t e1)
 {
     const int M = 2 * b;
@@ -492,17 +501,17 @@ hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *p
     if (M == 64)
         return cross ? launch_pair_solve_t<T, 64, NT64, true>(B, ldb, npairs, pairs, psmap, U,
                                                               eps, thr, inner, partial,
-                                                              rot_flag, smem, s, e0, e1)
+                                                              rot_flag, prot, smem, s, e0, e1)
                      : launch_pair_solve_t<T, 64, NT64, false>(B, ldb, npairs, pairs, psmap,
                                                                U, eps, thr, inner, partial,
-                                                               rot_flag, smem, s, e0, e1);
+                                                               rot_flag, prot, smem, s, e0, e1);
     if (M == 32)
         return cross ? launch_pair_solve_t<T, 32, 256, true>(B, ldb, npairs, pairs, psmap, U,
                                                              eps, thr, inner, partial, rot_flag,
-                                                             smem, s, e0, e1)
+                                                             prot, smem, s, e0, e1)
                      : launch_pair_solve_t<T, 32, 256, false>(B, ldb, npairs, pairs, psmap, U,
                                                               eps, thr, inner, partial,
-                                                              rot_flag, smem, s, e0, e1);
+                                                              rot_flag, prot, smem, s, e0, e1);
     return hipErrorInvalidValue;
 }
 
@@ -519,9 +528,10 @@ void tune_pair_v(int wgs, size_t lds, int waves)
 template <typename T, int M, int NT, bool CROSS>
 static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int2 *pairs,
                                         const int2 *psmap, T *U, double eps, double thr,
-                                        int inner, double *partial, int *rot_flag, size_t smem,
-                                        T *V, int64_t ldv, int64_t nrows, const int2 *vpairs,
-                                        const T *vU, hipStream_t s)
+                                        int inner, double *partial, int *rot_flag, int *prot,
+                                        size_t smem, T *V, int64_t ldv, int64_t nrows,
+                                        const int2 *vpairs, const T *vU, const int *vprot,
+                                        hipStream_t s)
 {
     auto k = pair_solve_v_kernel<T, M, NT, CROSS>;
     static size_t smem_set = 0;
@@ -578,7 +588,7 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
         smem_set = lds;
     }
     hipLaunchKernelGGL(k, dim3(grid), dim3(NT), lds, s, B, ldb, pairs, psmap, U, eps, thr,
-                       inner, partial, rot_flag, npairs, V, ldv, ntile, vpairs, vU,
+                       inner, partial, rot_flag, prot, npairs, V, ldv, ntile, vpairs, vU, vprot,
                        (int)ranges, vwaves, vx);
     return hipGetLastError();
 }
@@ -586,8 +596,9 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
 template <typename T>
 hipError_t launch_pair_solve_v(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                                const int2 *psmap, T *U, double eps, double thr, int inner,
-                               int cross, double *partial, int *rot_flag, T *V, int64_t ldv,
-                               int64_t nrows, const int2 *vpairs, const T *vU, hipStream_t s)
+                               int cross, double *partial, int *rot_flag, int *prot, T *V,
+                               int64_t ldv, int64_t nrows, const int2 *vpairs, const T *vU,
+                               const int *vprot, hipStream_t s)
 {
     if (nrows % 16 != 0 || ldv % (16 / (int64_t)sizeof(T)) != 0 || ((uintptr_t)V % 16) != 0)
         return hipErrorInvalidValue;
@@ -596,21 +607,21 @@ hipError_t launch_pair_solve_v(T *B, int64_t ldb, int b, int npairs, const int2 
     if (M == 64)
         return cross ? launch_pair_solve_v_t<T, 64, 1024, true>(B, ldb, npairs, pairs, psmap, U,
                                                                 eps, thr, inner, partial,
-                                                                rot_flag, smem, V, ldv, nrows,
-                                                                vpairs, vU, s)
+                                                                rot_flag, prot, smem, V, ldv, nrows,
+                                                                vpairs, vU, vprot, s)
                      : launch_pair_solve_v_t<T, 64, 1024, false>(B, ldb, npairs, pairs, psmap,
                                                                  U, eps, thr, inner, partial,
-                                                                 rot_flag, smem, V, ldv, nrows,
-                                                                 vpairs, vU, s);
+                                                                 rot_flag, prot, smem, V, ldv, nrows,
+                                                                 vpairs, vU, vprot, s);
     if (M == 32)
         return cross ? launch_pair_solve_v_t<T, 32, 256, true>(B, ldb, npairs, pairs, psmap, U,
                                                                eps, thr, inner, partial,
-                                                               rot_flag, smem, V, ldv, nrows,
-                                                               vpairs, vU, s)
+                                                               rot_flag, prot, smem, V, ldv, nrows,
+                                                               vpairs, vU, vprot, s)
                      : launch_pair_solve_v_t<T, 32, 256, false>(B, ldb, npairs, pairs, psmap, U,
                                                                 eps, thr, inner, partial,
-                                                                rot_flag, smem, V, ldv, nrows,
-                                                                vpairs, vU, s);
+                                                                rot_flag, prot, smem, V, ldv, nrows,
+                                                                vpairs, vU, vprot, s);
     return hipErrorInvalidValue;
 }
 
@@ -1158,19 +1169,21 @@ hipError_t launch_orth_probe(const double *V, int64_t ldv, int64_t n, int64_t np
 // explicit instantiations
 template hipError_t launch_pair_solve_v<double>(double *, int64_t, int, int, const int2 *,
                                                const int2 *, double *, double, double, int, int,
-                                               double *, int *, double *, int64_t, int64_t,
-                                               const int2 *, const double *, hipStream_t);
+                                               double *, int *, int *, double *, int64_t,
+                                               int64_t, const int2 *, const double *,
+                                               const int *, hipStream_t);
 template hipError_t launch_pair_solve_v<float>(float *, int64_t, int, int, const int2 *,
                                               const int2 *, float *, double, double, int, int,
-                                              double *, int *, float *, int64_t, int64_t,
-                                              const int2 *, const float *, hipStream_t);
+                                              double *, int *, int *, float *, int64_t,
+                                              int64_t, const int2 *, const float *, const int *,
+                                              hipStream_t);
 template hipError_t launch_pair_solve<double>(double *, int64_t, int, int, const int2 *,
                                               const int2 *, double *, double, double, int, int,
-                                              double *, int *, hipStream_t, hipEvent_t,
+                                              double *, int *, int *, hipStream_t, hipEvent_t,
                                               hipEvent_t);
 template hipError_t launch_pair_solve<float>(float *, int64_t, int, int, const int2 *,
                                              const int2 *, float *, double, double, int, int,
-                                             double *, int *, hipStream_t, hipEvent_t,
+                                             double *, int *, int *, hipStream_t, hipEvent_t,
                                              hipEvent_t);
 
 // Thread -> 2x2 block map of the pair solve for M = 2b positions: entry t < M/2

@@ -19,9 +19,9 @@ template <typename T, int M>
 __global__ __launch_bounds__(256) void update_v_kernel(T *__restrict__ V, int64_t ldv,
                                                        int64_t ntile, const int2 *__restrict__ pairs,
                                                        int npairs, const T *__restrict__ U,
-                                                       int chunks)
+                                                       const int *__restrict__ prot, int chunks)
 {
-    vupd::v_update_wave<T, M>(V, ldv, ntile, pairs, npairs, U, chunks,
+    vupd::v_update_wave<T, M>(V, ldv, ntile, pairs, npairs, U, prot, chunks,
                               blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE);
 }
 
@@ -43,13 +43,19 @@ __global__ __launch_bounds__(256) void update_v_kernel(T *__restrict__ V, int64_
 // Each b x b block of Z is stored once, into B's upper block: along its rows
 // with 16-byte stores (out_perm again), or transposed with one element per
 // lane.  The next tile's X^T and U_k are loaded while the current one
-// computes.
+// computes.  With rotation flags (prot) and no off^2 wanted, a tile whose two
+// pairs applied no rotation has U_k = U_l = I, so Z = X: a workgroup whose
+// whole run consists of such tiles adds their count to *skipped and returns
+// after its first tile's loads (a per-tile test inside the pipelined loop
+// costs the loop registers).
 template <typename T, int M>
 __global__ __launch_bounds__(M * 4, sizeof(T) == 4 ? 4 : 2) void update_b_kernel(T *__restrict__ B, int64_t ldb,
                                                          const int2 *__restrict__ pairs_g,
                                                          int npairs, const T *__restrict__ U,
                                                          double *__restrict__ partial,
-                                                         int want_off)
+                                                         int want_off,
+                                                         const int *__restrict__ prot,
+                                                         int *skipped)
 {
     constexpr int b = M / 2, NW = M / 16, NT = NW * WAVE;
     constexpr int VK = 16 / (int)sizeof(T);
@@ -294,6 +300,20 @@ __global__ __launch_bounds__(M * 4, sizeof(T) == 4 ? 4 : 2) void update_b_kernel
     // prefetch after the last tile reads tile 0, which every workgroup reads)
     Buf ba, bb;
     load_tile(ba, t0);
+    // the flags are read while the first tile's loads fly
+    if (prot != nullptr && !want_off) {
+        constexpr int PW = pair_solve_waves(M);
+        bool all = true;
+        for (int t = t0; t < t1 && all; ++t) {
+            const int2 kl = tile_kl(t);
+            all = !pair_rotated<PW>(prot, kl.x) && !pair_rotated<PW>(prot, kl.y);
+        }
+        if (all) {
+            if (tid == 0)
+                atomicAdd(skipped, t1 - t0);
+            return;
+        }
+    }
     body(t0, ba, bb, t0 + 1 < t1 ? t0 + 1 : 0);
     int t = t0 + 1;
     for (; t + 1 < t1; t += 2) {
@@ -308,7 +328,8 @@ int g_update_v_waves = 0; // total resident wavefronts to size the V-update grid
 
 template <typename T, int M>
 hipError_t launch_update_v_t(T *V, int64_t ldv, int64_t nrows, int npairs, const int2 *pairs,
-                             const T *U, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+                             const T *U, const int *prot, hipStream_t s, hipEvent_t e0,
+                             hipEvent_t e1)
 {
     static int occ_waves = 0;
     if (occ_waves == 0) {
@@ -330,7 +351,7 @@ hipError_t launch_update_v_t(T *V, int64_t ldv, int64_t nrows, int npairs, const
     const int64_t waves = chunks * npairs;
     const unsigned grid = (unsigned)((waves + 3) / 4);
     launch_timed(update_v_kernel<T, M>, dim3(grid), dim3(256), 0, s, e0, e1, V, ldv, ntile, pairs,
-                 npairs, U, (int)chunks);
+                 npairs, U, prot, (int)chunks);
     return hipGetLastError();
 }
 
@@ -358,9 +379,11 @@ void tune_update_v(int total_waves) { g_update_v_waves = total_waves; }
 
 template <typename T>
 hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pairs, const T *U,
-                           double *partial, int want_off, hipStream_t s, hipEvent_t e0,
-                           hipEvent_t e1)
+                           double *partial, int want_off, const int *prot, int *skipped,
+                           hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
+    if (prot && !skipped)
+        return hipErrorInvalidValue;
     if (ldb % (16 / (int64_t)sizeof(T)) != 0 || ((uintptr_t)B % 16) != 0)
         return hipErrorInvalidValue;
     const int ntiles = npairs * (npairs - 1) / 2;
@@ -378,10 +401,10 @@ hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pai
     const unsigned grid = (unsigned)(ntiles < slots ? ntiles : slots);
     if (b == 32)
         launch_timed(update_b_kernel<T, 64>, dim3(grid), dim3(256), 0, s, e0, e1, B, ldb, pairs,
-                     npairs, U, partial, want_off);
+                     npairs, U, partial, want_off, prot, skipped);
     else if (b == 16)
         launch_timed(update_b_kernel<T, 32>, dim3(grid), dim3(128), 0, s, e0, e1, B, ldb, pairs,
-                     npairs, U, partial, want_off);
+                     npairs, U, partial, want_off, prot, skipped);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -389,8 +412,8 @@ hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pai
 
 template <typename T>
 hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
-                           const int2 *pairs, const T *U, hipStream_t s, hipEvent_t e0,
-                           hipEvent_t e1)
+                           const int2 *pairs, const T *U, const int *prot, hipStream_t s,
+                           hipEvent_t e0, hipEvent_t e1)
 {
     if (nrows % 16 != 0 || ldv % (16 / (int64_t)sizeof(T)) != 0 ||
         ((uintptr_t)V % 16) != 0)
@@ -398,24 +421,25 @@ hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
     if (nrows == 0 || npairs == 0)
         return hipSuccess;
     if (b == 32)
-        return launch_update_v_t<T, 64>(V, ldv, nrows, npairs, pairs, U, s, e0, e1);
+        return launch_update_v_t<T, 64>(V, ldv, nrows, npairs, pairs, U, prot, s, e0, e1);
     if (b == 16)
-        return launch_update_v_t<T, 32>(V, ldv, nrows, npairs, pairs, U, s, e0, e1);
+        return launch_update_v_t<T, 32>(V, ldv, nrows, npairs, pairs, U, prot, s, e0, e1);
     return hipErrorInvalidValue;
 }
 
 template int update_b_blocks_per_cu<double>(int);
 template int update_b_blocks_per_cu<float>(int);
 template hipError_t launch_update_b<double>(double *, int64_t, int, int, const int2 *,
-                                            const double *, double *, int, hipStream_t,
-                                            hipEvent_t, hipEvent_t);
+                                            const double *, double *, int, const int *, int *,
+                                            hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_update_b<float>(float *, int64_t, int, int, const int2 *,
-                                           const float *, double *, int, hipStream_t,
-                                           hipEvent_t, hipEvent_t);
+                                           const float *, double *, int, const int *, int *,
+                                           hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_update_v<double>(double *, int64_t, int64_t, int, int, const int2 *,
-                                            const double *, hipStream_t, hipEvent_t,
-                                            hipEvent_t);
+                                            const double *, const int *, hipStream_t,
+                                            hipEvent_t, hipEvent_t);
 template hipError_t launch_update_v<float>(float *, int64_t, int64_t, int, int, const int2 *,
-                                           const float *, hipStream_t, hipEvent_t, hipEvent_t);
+                                           const float *, const int *, hipStream_t, hipEvent_t,
+                                           hipEvent_t);
 
 } // namespace lj

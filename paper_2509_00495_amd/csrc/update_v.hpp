@@ -68,11 +68,13 @@ __device__ inline T vlane(const typename V16<T>::type &x, int j)
 }
 
 // Wavefront gw of the update: pair l = gw % npairs, chunk gw / npairs of the
-// ntile 16-row tiles (chunks per pair).  Wavefronts past the work return.
+// ntile 16-row tiles (chunks per pair).  Wavefronts past the work return, and
+// so do those of a pair whose rotation flags (prot, when given) are all zero.
 template <typename T, int M>
 __device__ inline void v_update_wave(T *__restrict__ V, int64_t ldv, int64_t ntile,
                                      const int2 *__restrict__ pairs, int npairs,
-                                     const T *__restrict__ U, int chunks, int gw)
+                                     const T *__restrict__ U, const int *__restrict__ prot,
+                                     int chunks, int gw)
 {
     constexpr int b = M / 2;
     constexpr int VK = 16 / (int)sizeof(T); // elements per 16-byte vector
@@ -84,6 +86,8 @@ __device__ inline void v_update_wave(T *__restrict__ V, int64_t ldv, int64_t nti
     const int l = gw % npairs, ch = gw / npairs;
     if (ch >= chunks)
         return;
+    if (prot && !pair_rotated<pair_solve_waves(M)>(prot, l))
+        return; // U_l = I
     const int64_t t0 = (int64_t)ch * ntile / chunks, t1 = (int64_t)(ch + 1) * ntile / chunks;
     if (t0 >= t1)
         return;
@@ -175,12 +179,14 @@ __device__ inline void v_update_wave(T *__restrict__ V, int64_t ldv, int64_t nti
 // M*M entries) in per-lane fragment order, and every wavefront reads it from
 // there with 16-byte LDS loads at consecutive addresses; the first nw
 // wavefronts take the range's tiles in turn (tile t0 + w + i nw), each with
-// two X buffers in flight as above.  Every thread reaches the barrier.
+// two X buffers in flight as above.  Every thread reaches the barrier, or
+// none does: a pair whose rotation flags (prot, when given) are all zero
+// returns before it.
 template <typename T, int M, int NT>
 __device__ inline void v_update_wg(T *__restrict__ V, int64_t ldv,
                                    const int2 *__restrict__ pairs, int l,
-                                   const T *__restrict__ U, int64_t t0, int64_t t1, int nw,
-                                   T *ufl)
+                                   const T *__restrict__ U, const int *__restrict__ prot,
+                                   int64_t t0, int64_t t1, int nw, T *ufl)
 {
     constexpr int b = M / 2;
     constexpr int VK = 16 / (int)sizeof(T);
@@ -190,6 +196,9 @@ __device__ inline void v_update_wg(T *__restrict__ V, int64_t ldv,
     typedef typename acc4<T>::type accT;
     const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
     const int li = lane % 16, lk = lane / 16;
+    // the flags are read while U_l is staged (the V workgroups of the shared
+    // pair-solve launch are on its critical path in FP32)
+    const bool rotated = !prot || pair_rotated<pair_solve_waves(M)>(prot, l);
     const int2 pl = pairs[l];
     const T *Ult = U + (int64_t)l * M * M; // transposed: Ult[j][i] = U_l[i][j]
     for (int e = tid; e < TC * KG * WAVE; e += NT) {
@@ -197,6 +206,8 @@ __device__ inline void v_update_wg(T *__restrict__ V, int64_t ldv,
         *reinterpret_cast<TV *>(ufl + e * VK) = *reinterpret_cast<const TV *>(
             Ult + (16 * tc + out_perm<T>(ln % 16)) * M + g * 4 * VK + (ln / 16) * VK);
     }
+    if (!rotated)
+        return; // U_l = I (the decision is the same for the whole workgroup)
     __syncthreads();
     const int64_t cnt = w < nw && t1 - t0 > w ? (t1 - t0 - w + nw - 1) / nw : 0;
     if (cnt == 0)

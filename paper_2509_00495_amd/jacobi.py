@@ -55,7 +55,8 @@ class Info(ctypes.Structure):
         ("path", ctypes.c_int32),
         ("block", ctypes.c_int32),
         ("polished", ctypes.c_int32),
-        ("reserved_i", ctypes.c_int32 * 2),
+        ("skipped_tiles", ctypes.c_int32),
+        ("reserved_i", ctypes.c_int32 * 1),
         ("norm_f", ctypes.c_double),
         ("tol", ctypes.c_double),
         ("off_final", ctypes.c_double),

@@ -225,6 +225,31 @@ def test_ari_known_spectrum(pj, fn):
 
 
 @pytest.mark.parametrize("fn", ["eigh", "eigh_mixed"])
+@pytest.mark.parametrize("sizes", [[256] * 4, [300, 200, 524]])
+def test_pair_skip_block_diagonal(pj, fn, sizes):
+    """Decoupled diagonal blocks: a block pair that joins two of them has no
+    coupling, rotates nothing and leaves U = I, so the B tiles of two such
+    pairs (and the V columns of such a pair) are left out of the updates.
+    Eigenvalues against the spectrum the blocks were built from, residual
+    and orthogonality bars; with blocks aligned to the block size, tiles
+    must actually have been left out."""
+    A, lam = wl.block_diagonal(1024, sizes=sizes, seed=21)
+    W, V, info = run(pj, fn, A)
+    assert info["status"] == 0
+    n = A.shape[0]
+    nrm2 = np.abs(lam).max()
+    print(f"  blockdiag {sizes} {fn}: sweeps={info['sweeps']} sweeps32={info['sweeps32']} "
+          f"skipped_tiles={info['skipped_tiles']} "
+          f"|W-lam|/|A|_2={np.abs(W - lam).max() / nrm2:.2e}", flush=True)
+    assert np.abs(W - lam).max() <= 1e-13 * nrm2
+    assert np.linalg.norm(A @ V - V * W) / np.linalg.norm(A) <= 1e-13 * n
+    assert np.linalg.norm(V.T @ V - np.eye(n)) <= 1e-14 * n
+    assert info["skipped_tiles"] >= 0
+    if all(m % info["block"] == 0 for m in sizes):
+        assert info["skipped_tiles"] > 0
+
+
+@pytest.mark.parametrize("fn", ["eigh", "eigh_mixed"])
 def test_geo1024_vs_oracle_fixture(pj, fn):
     """The n = 1024 geometric workload (magnitudes 1 .. 1e-6, random signs) at
     full size: eigenvalues against the spectrum it was built from (the bar),

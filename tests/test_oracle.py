@@ -141,6 +141,21 @@ def test_known_spectrum_ari(orc):
     assert sw <= 8
 
 
+def test_block_diagonal_workload(orc):
+    """The decoupled-blocks input: no coupling between its diagonal blocks,
+    and the oracle on the whole matrix returns the union of the spectra the
+    blocks were built from."""
+    sizes = [20, 13, 31]
+    A, lam = wl.block_diagonal(64, sizes=sizes, seed=21)
+    o = 0
+    for m in sizes:
+        assert not A[o:o + m, o + m:].any() and not A[o + m:, o:o + m].any()
+        o += m
+    W, V, sw, st, _ = orc.eigh(A)
+    assert st == 0
+    assert np.abs(W - lam).max() <= 10 * 64 * U_D * np.abs(lam).max()
+
+
 @pytest.mark.parametrize("n,seed", [(7, 1), (30, 2), (64, 3)])
 def test_invariants(orc, n, seed):
     """Orthogonal invariance (Section 2.2): trace and Frobenius norm."""

@@ -94,6 +94,26 @@ def ari_spectrum(n: int = 1024, seed: int = 6, kappa: float = 1e2):
     return from_spectrum(lam, Q), np.sort(lam)
 
 
+def block_diagonal(n: int = 4096, nblocks: int = 8, seed: int = 9, sizes=None):
+    """Decoupled subsystems: A = diag(A_1, ..., A_k) with zero coupling between
+    the diagonal blocks, A_i = Q_i diag(lam_i) Q_i^T, lam_i uniform on
+    [-1, 1], Haar Q_i.  `sizes` gives the block orders (default: nblocks equal
+    blocks).  Returns (A, lam_sorted)."""
+    g = rng(seed)
+    if sizes is None:
+        sizes = [n // nblocks] * nblocks
+        sizes[-1] += n - sum(sizes)
+    assert sum(sizes) == n
+    A = np.zeros((n, n))
+    lams = []
+    o = 0
+    for m in sizes:
+        lam = g.uniform(-1.0, 1.0, m)
+        A[o:o + m, o:o + m] = from_spectrum(lam, haar(m, g))
+        lams.append(lam)
+        o += m
+    return A, np.sort(np.concatenate(lams))
+
 def goe(n: int = 4096, seed: int = 3) -> np.ndarray:
     """A = (G + G^T)/2, G i.i.d. N(0,1); spectrum not known in closed form."""
     g = rng(seed)
