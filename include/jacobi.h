@@ -98,6 +98,10 @@ typedef struct jacobi_opts {
                                without one; at most 64 graphs are kept per
                                process, later new argument sets launch
                                directly); 0 (default) = direct launches */
+    int32_t no_pair_skip;   /* nonzero: the FP64 block sweeps update every B tile
+                               and V column, also those of block pairs that
+                               applied no rotation in a round (the results are
+                               the same; 0, the default, leaves those out) */
 } jacobi_opts;
 
 /* Diagnostics filled on return (host struct, may be NULL). */

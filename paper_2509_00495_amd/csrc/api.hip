@@ -42,7 +42,7 @@ bool trace_on()
 
 struct Opts {
     int max_sweeps, block, inner, ns_iters, check_sym, small_max_n, threads, timing, schedule,
-        serial_v, tune, graph;
+        serial_v, tune, graph, pair_skip;
     double c32;
 };
 
@@ -61,6 +61,7 @@ int resolve_opts(const jacobi_opts *o, Opts &r)
     r.serial_v = 0;
     r.tune = 0;
     r.graph = 0;
+    r.pair_skip = 1;
     // 0.1: the FP32 stage runs into its quadratic phase, to a few times its
     // rounding floor (off(Q_d^T A Q_d) settles near 0.05 n u_l ||A||_F), which
     // saves FP64 sweeps that cost more than the FP32 ones (measured on GOE and
@@ -79,6 +80,7 @@ int resolve_opts(const jacobi_opts *o, Opts &r)
         return 1;
     r.tune = o->tune;
     r.graph = o->graph != 0;
+    r.pair_skip = o->no_pair_skip == 0;
     if (o->max_sweeps < 0 || o->max_sweeps > 1000)
         return 1;
     if (o->max_sweeps)
@@ -546,7 +548,7 @@ struct SideStream {
 template <typename T>
 int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U, double tol,
                double eps, int max_sweeps, int inner, int schedule, int serial_v,
-               bool fp32_stage,
+               bool pair_skip, bool fp32_stage,
                hipStream_t s,
                SideStream &ss, int *sweeps_out, double *off_out, double *off0_out,
                RoundTimer *tm, int *skipped_out)
@@ -599,7 +601,8 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
         for (int r = 0; r < g.N - 1; ++r, ++ss.round) {
             const int j = (int)(ss.round & 1);
             T *Ub = U + j * ustride;
-            int *pf = sizeof(T) == 8 ? w.prot + (size_t)j * g.npairs * PROT_STRIDE : nullptr;
+            int *pf = w.prot + (size_t)j * g.npairs * PROT_STRIDE; // written by FP64 solves
+            const int *pfc = sizeof(T) == 8 && pair_skip ? pf : nullptr; // read by the updates
             const int2 *pr = w.pairs + (size_t)r * g.npairs;
             if (side && ss.recV[j])
                 CK(hipStreamWaitEvent(s, ss.evV[j], 0));
@@ -620,19 +623,19 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
                 CK(hipEventRecord(ss.evU[j], s));
             CK(launch_update_b<T>(B, g.npad, g.b, g.npairs, pr, Ub,
                                   w.partial + (size_t)g.npairs * pair_solve_waves(g.M),
-                                  r == g.N - 2, pf, w.flags + 3, s,
+                                  r == g.N - 2, pfc, w.flags + 3, s,
                                   timed ? tm->ev[6 * r + 2] : nullptr,
                                   timed ? tm->ev[6 * r + 3] : nullptr));
             if (fuse) {
                 vpend_pairs = pr;
                 vpend_U = Ub;
-                vpend_prot = pf;
+                vpend_prot = pfc;
                 continue;
             }
             hipStream_t sv = side ? ss.s2 : s;
             if (side)
                 CK(hipStreamWaitEvent(ss.s2, ss.evU[j], 0));
-            CK(launch_update_v<T>(V, g.npad, g.npad, g.b, g.npairs, pr, Ub, pf, sv,
+            CK(launch_update_v<T>(V, g.npad, g.npad, g.b, g.npairs, pr, Ub, pfc, sv,
                                   timed ? tm->ev[6 * r + 4] : nullptr,
                                   timed ? tm->ev[6 * r + 5] : nullptr));
             if (side) {
@@ -878,7 +881,7 @@ int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, in
     if (int e = ss.init())
         return e;
     int st = run_sweeps<double>(g, n, w, w.B64, w.V64, w.U64, tol, U_D, o.max_sweeps, o.inner,
-                                o.schedule, o.serial_v, false, s, ss, &sweeps, &off, nullptr, &tm,
+                                o.schedule, o.serial_v, o.pair_skip, false, s, ss, &sweeps, &off, nullptr, &tm,
                                 &skipped);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;
@@ -925,7 +928,7 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     if (int e = ss.init())
         return e;
     int st32 = run_sweeps<float>(g, n, w, w.B32, w.V32, w.U32, tol32, U_L, o.max_sweeps,
-                                 o.inner, o.schedule, o.serial_v, true, s, ss, &sw32, &off32, nullptr, &tm32,
+                                 o.inner, o.schedule, o.serial_v, o.pair_skip, true, s, ss, &sw32, &off32, nullptr, &tm32,
                                  nullptr);
     if (st32 == JACOBI_DEVICE)
         return st32;
@@ -965,7 +968,7 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     int sw64 = 0, skipped = 0;
     double off = 0.0, offc = 0.0;
     int st = run_sweeps<double>(g, n, w, A64, X, w.U64, tol, U_D, o.max_sweeps, o.inner,
-                                o.schedule, o.serial_v, false, s, ss, &sw64, &off, &offc, &tm64,
+                                o.schedule, o.serial_v, o.pair_skip, false, s, ss, &sw64, &off, &offc, &tm64,
                                 &skipped);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;

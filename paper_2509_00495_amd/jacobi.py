@@ -44,6 +44,7 @@ class Opts(ctypes.Structure):
         ("serial_v", ctypes.c_int32),
         ("tune", ctypes.c_int32),
         ("graph", ctypes.c_int32),
+        ("no_pair_skip", ctypes.c_int32),
     ]
 
 

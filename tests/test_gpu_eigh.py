@@ -250,6 +250,23 @@ def test_pair_skip_block_diagonal(pj, fn, sizes):
 
 
 @pytest.mark.parametrize("fn", ["eigh", "eigh_mixed"])
+@pytest.mark.parametrize("case", ["blockdiag", "goe"])
+def test_pair_skip_changes_nothing(pj, fn, case):
+    """A left-out update is one whose rotation is exactly the identity, so
+    the outputs with pair skipping equal those without it bit for bit."""
+    A = (wl.block_diagonal(1024, 4, seed=22)[0] if case == "blockdiag"
+         else wl.goe(1024, 23))
+    W1, V1, i1 = run(pj, fn, A)
+    W0, V0, i0 = run(pj, fn, A, no_pair_skip=1)
+    print(f"  {case} {fn}: skipped_tiles {i1['skipped_tiles']} / {i0['skipped_tiles']}", flush=True)
+    assert i0["skipped_tiles"] == 0
+    if case == "blockdiag":
+        assert i1["skipped_tiles"] > 0
+    assert (i1["sweeps"], i1["sweeps32"]) == (i0["sweeps"], i0["sweeps32"])
+    assert np.array_equal(W1, W0) and np.array_equal(V1, V0)
+
+
+@pytest.mark.parametrize("fn", ["eigh", "eigh_mixed"])
 def test_geo1024_vs_oracle_fixture(pj, fn):
     """The n = 1024 geometric workload (magnitudes 1 .. 1e-6, random signs) at
     full size: eigenvalues against the spectrum it was built from (the bar),
