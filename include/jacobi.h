@@ -118,7 +118,7 @@ typedef struct jacobi_info {
                                updates of B left out because neither block
                                pair of the tile rotated in that round (U = I
                                there; the results are unchanged), summed over
-                               the sweeps */
+                               the sweeps (a diagnostic: wraps past 2^31 - 1) */
     int32_t reserved_i[1];
     double norm_f;          /* ||A||_F of the symmetrised input */
     double tol;             /* absolute threshold on off(B) actually used */
