@@ -250,13 +250,17 @@ def test_pair_skip_block_diagonal(pj, fn, sizes):
 
 
 @pytest.mark.parametrize("fn", ["eigh", "eigh_mixed"])
-@pytest.mark.parametrize("case", ["blockdiag", "goe"])
-def test_pair_skip_changes_nothing(pj, fn, case):
+@pytest.mark.parametrize("case,serial_v", [("blockdiag", 0), ("goe", 0), ("blockdiag", 1),
+                                           ("blockdiag", 2)])
+def test_pair_skip_changes_nothing(pj, fn, case, serial_v):
     """A left-out update is one whose rotation is exactly the identity, so
-    the outputs with pair skipping equal those without it bit for bit."""
+    the outputs with pair skipping equal those without it bit for bit, with
+    the V update inside the next pair-solve launch (serial_v = 0), after the
+    B update (1) or on the side stream, which reads the flags of the
+    double-buffered round (2)."""
     A = (wl.block_diagonal(1024, 4, seed=22)[0] if case == "blockdiag"
          else wl.goe(1024, 23))
-    W1, V1, i1 = run(pj, fn, A)
+    W1, V1, i1 = run(pj, fn, A, serial_v=serial_v)
     W0, V0, i0 = run(pj, fn, A, no_pair_skip=1)
     print(f"  {case} {fn}: skipped_tiles {i1['skipped_tiles']} / {i0['skipped_tiles']}", flush=True)
     assert i0["skipped_tiles"] == 0
