@@ -136,3 +136,31 @@ def test_library_sources_do_not_touch_oracle():
     for f in ("jacobi.py", "__init__.py", "build.py"):
         text = open(os.path.join(ROOT, "paper_2509_00495_amd", f)).read()
         assert not re.search(r"^\s*(import|from)\s+oracle", text, flags=re.M), f
+
+
+def test_struct_layouts_match_header(pj, tmp_path):
+    """The binding's ctypes mirrors of jacobi_opts and jacobi_info have the C
+    header's size and the same offset for every field (a plain C program
+    built with gcc from include/jacobi.h prints them)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"jacobi_opts": pj.jacobi.Opts, "jacobi_info": pj.jacobi.Info}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "jacobi.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    c = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert c[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert c[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
