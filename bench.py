@@ -257,7 +257,7 @@ def main():
         acc["eig_err_vs_known_spectrum"] = float(np.abs(Wn - lam).max() / np.abs(lam).max())
     gold = os.path.join(ROOT, "tests", "golden", f"oracle_{wl_name}.txt")
     if os.path.exists(gold):
-        Wo = np.loadtxt(gold)
+        Wo = np.loadtxt(gold, ndmin=2)[:, 0]
         acc["eig_err_vs_oracle"] = float(np.abs(Wn - Wo).max() / np.abs(Wo).max())
         if lam is not None:
             acc["oracle_err_vs_known_spectrum"] = float(np.abs(Wo - lam).max() / np.abs(lam).max())

@@ -102,6 +102,21 @@ typedef struct jacobi_opts {
                                and V column, also those of block pairs that
                                applied no rotation in a round (the results are
                                the same; 0, the default, leaves those out) */
+    int32_t gemm_slots;     /* symmetric FP64 products of the mixed path (the
+                               Newton-Schulz residual I - X^T X and
+                               Q_d^T (A Q_d)): the number of resident
+                               workgroups a product with more 128 x 128 upper
+                               tiles than that is split over (stream-K with a
+                               fix-up pass); 0 (default) = two per compute
+                               unit.  A small value makes small orders take
+                               the split path (used by the tests) */
+    int32_t pair_v_split;   /* shared pair-solve + V-update launch of the block
+                               path (2b = 64): 16-row tiles of each pair's V
+                               update that its pair-solve workgroup takes once
+                               its solve is done; 0 (default) = a timing model
+                               (nonzero only near n = 4096 in FP64), -1 = none,
+                               k > 0 = k tiles (at most what leaves every V
+                               workgroup one tile) */
 } jacobi_opts;
 
 /* Diagnostics filled on return (host struct, may be NULL). */
@@ -172,39 +187,49 @@ int jacobi_eigh_mixed(const double *A, int64_t n, int64_t lda, double *W,
 
 /* Batched eigendecomposition of matrices of uneven order in one persistent
  * launch (each workgroup pops matrices from a device work queue, largest
- * first, and runs Algorithm 4 on the whole matrix in LDS).
- *   A      [in]  packed: matrix i is n_i x n_i row-major at offset
- *                sum_{j<i} n_j^2 doubles
+ * first, and runs Algorithm 4, Section 3.3, on the whole matrix in LDS).
+ *   A      [in]  matrix i is n_i x n_i row-major (ld = n_i) at offset a_off[i]
+ *                doubles
  *   n      [in, HOST] batch orders, 1 <= n_i <= 128
+ *   a_off  [in, HOST] batch offsets of the matrices in A (and of the
+ *                eigenvectors in V), in doubles, >= 0; NULL = packed
+ *                (sum_{j<i} n_j^2)
  *   batch  [in]  number of matrices, >= 0
- *   W      [out] packed: n_i eigenvalues at offset sum_{j<i} n_j
- *   V      [out] packed like A
+ *   W      [out] n_i eigenvalues of matrix i at offset w_off[i]
+ *   w_off  [in, HOST] batch offsets into W, >= 0; NULL = packed (sum_{j<i} n_j)
+ *   V      [out] eigenvectors of matrix i, n_i x n_i row-major at a_off[i]
  *   tol    [in]  absolute threshold on off for every matrix; <= 0 selects
  *                1e-15 * n_i * ||A_i||_F per matrix
  *   mixed  [in]  reserved, must be 0 (the batched path is plain FP64)
  *   status [out] batch int32 per-matrix status codes (device), may be NULL
- * Returns the largest per-matrix status, or -i, JACOBI_DEVICE, JACOBI_WORKSPACE. */
-int jacobi_eigh_batched(const double *A, const int64_t *n, int64_t batch,
-                        double *W, double *V, double tol, int mixed,
-                        const jacobi_opts *opts, void *work, size_t work_bytes,
-                        void *stream, int32_t *status);
+ * Output regions of different matrices must not overlap (nothing checks it).
+ * Returns the largest per-matrix status, or -i, JACOBI_DEVICE, JACOBI_WORKSPACE.
+ * Argument positions for -i: A 1, n 2, a_off 3, batch 4, W 5, w_off 6, V 7,
+ * tol 8, mixed 9, opts 10. */
+int jacobi_eigh_batched(const double *A, const int64_t *n, const int64_t *a_off,
+                        int64_t batch, double *W, const int64_t *w_off, double *V,
+                        double tol, int mixed, const jacobi_opts *opts, void *work,
+                        size_t work_bytes, void *stream, int32_t *status);
 
 /* Adjoint of the eigendecomposition for a batch of equal-order matrices
  * (first-order perturbation theory for distinct eigenvalues; the paper does
  * not treat derivatives):
  *   dA = sym(V (diag(dW) + F o (V^T dV)) V^T),  F_ij = 1/(W_j - W_i), F_ii = 0,
  *   sym(G) = (G + G^T)/2.
- *   W  [in]  batch x n eigenvalues as returned by jacobi_eigh
- *   V  [in]  batch x n x n eigenvectors (row-major, ld = n)
- *   dW [in]  batch x n, or NULL (zero)
- *   dV [in]  batch x n x n, or NULL (zero)
- *   dA [out] batch x n x n, symmetric
+ *   W  [in]  batch x n eigenvalues as returned by jacobi_eigh (packed)
+ *   V  [in]  batch matrices of n x n eigenvectors, row-major with row stride
+ *            ld, matrix k at V + k * n * ld
+ *   dW [in]  batch x n (packed), or NULL (zero)
+ *   dV [in]  laid out like V, or NULL (zero)
+ *   n  [in]  order, >= 0;  ld [in] >= max(1, n);  batch [in] >= 0
+ *   dA [out] laid out like V, symmetric
  *   gap_tol [in] pairs with |W_j - W_i| < gap_tol get F_ij = 0; if such a
  *           pair has nonzero (V^T dV)_ij the call returns JACOBI_DEGENERATE
  *           (dA is still written).
- * Returns JACOBI_OK, JACOBI_DEGENERATE, JACOBI_DEVICE, JACOBI_WORKSPACE or -i. */
+ * Returns JACOBI_OK, JACOBI_DEGENERATE, JACOBI_DEVICE, JACOBI_WORKSPACE or -i
+ * (positions: W 1, V 2, dW 3, dV 4, n 5, ld 6, batch 7, dA 8, gap_tol 9). */
 int jacobi_eigh_backward(const double *W, const double *V, const double *dW,
-                         const double *dV, int64_t n, int64_t batch,
+                         const double *dV, int64_t n, int64_t ld, int64_t batch,
                          double *dA, double gap_tol, void *work,
                          size_t work_bytes, void *stream);
 

@@ -65,6 +65,7 @@ def _load():
         lib.orc_jacobi_rows.restype = i64
         lib.orc_eigh_backward.argtypes = [i64, P, P, P, P, d, P]
         lib.orc_eigh_backward.restype = i32
+        lib.orc_rayleigh.argtypes = [i64, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -191,6 +192,17 @@ def eigh_mixed(A, tol: float | None = None, max_sweeps: int = 30,
     return W, Q, st, dict(sweeps32=int(dg[0]), sweeps64=int(dg[1]),
                           orth_ql=dg[2], orth_qd=dg[3], off_cond=dg[4],
                           status32=int(dg[5]))
+
+
+def rayleigh(A, V):
+    """Rayleigh quotients and residual norms of the columns of V against A:
+    rq_k = v_k^T A v_k / v_k^T v_k, res_k = ||A v_k - rq_k v_k|| / ||v_k||."""
+    A, V = _f64(A), _f64(V)
+    n = A.shape[0]
+    rq = np.zeros(n)
+    res = np.zeros(n)
+    _load().orc_rayleigh(n, _p(A), _p(V), _p(rq), _p(res))
+    return rq, res
 
 
 def eigh_backward(W, V, dW=None, dV=None, gap_tol: float = 0.0):

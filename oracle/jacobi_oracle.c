@@ -402,6 +402,47 @@ int orc_eigh_mixed(int64_t n, const double *A, double *W, double *Q,
     return st;
 }
 
+/* Rayleigh quotient and residual of each column of V against A (plain
+ * definitions; used to certify the oracle's own eigenpairs at sizes where its
+ * diagonal readout carries the rounding of many sweeps):
+ *   y = A v_k,  rq_k = (v_k^T y) / (v_k^T v_k),
+ *   res_k = ||y - rq_k v_k||_2 / ||v_k||_2.
+ * For an exact eigenpair res_k = 0 and rq_k = lambda_k; otherwise some
+ * eigenvalue lies within res_k of rq_k, and within res_k^2 / gap_k when every
+ * other eigenvalue is at least gap_k away (Kato-Temple).  The sums are
+ * accumulated in long double so that the check adds little rounding of its
+ * own.  V is n x n, columns are the vectors. */
+void orc_rayleigh(int64_t n, const double *A, const double *V, double *rq,
+                  double *res)
+{
+    size_t m = (size_t)(n > 0 ? n : 1);
+    long double *y = (long double *)malloc(m * sizeof(long double));
+    long double *v = (long double *)malloc(m * sizeof(long double));
+    for (int64_t k = 0; k < n; ++k) {
+        long double vv = 0.0L, vy = 0.0L;
+        for (int64_t i = 0; i < n; ++i) /* column k, contiguous */
+            v[i] = (long double)V[IDX(i, k, n)];
+        for (int64_t i = 0; i < n; ++i) {
+            long double acc = 0.0L;
+            for (int64_t j = 0; j < n; ++j)
+                acc += (long double)A[IDX(i, j, n)] * v[j];
+            y[i] = acc;
+            vv += v[i] * v[i];
+            vy += v[i] * acc;
+        }
+        long double q = vv > 0.0L ? vy / vv : 0.0L;
+        long double rr = 0.0L;
+        for (int64_t i = 0; i < n; ++i) {
+            long double d = y[i] - q * v[i];
+            rr += d * d;
+        }
+        rq[k] = (double)q;
+        res[k] = vv > 0.0L ? (double)sqrtl(rr / vv) : 0.0;
+    }
+    free(y);
+    free(v);
+}
+
 /* Adjoint of A = V diag(W) V^T (the paper does not treat derivatives; this is
  * the standard first-order perturbation result for distinct eigenvalues):
  *   M = V^T dV;  M_ij <- M_ij / (W_j - W_i) for i != j;  M_ii <- dW_i

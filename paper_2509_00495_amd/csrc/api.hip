@@ -42,7 +42,7 @@ bool trace_on()
 
 struct Opts {
     int max_sweeps, block, inner, ns_iters, check_sym, small_max_n, threads, timing, schedule,
-        serial_v, tune, graph, pair_skip;
+        serial_v, tune, graph, pair_skip, gemm_slots, pair_v_split;
     double c32;
 };
 
@@ -62,6 +62,8 @@ int resolve_opts(const jacobi_opts *o, Opts &r)
     r.tune = 0;
     r.graph = 0;
     r.pair_skip = 1;
+    r.gemm_slots = 0;
+    r.pair_v_split = 0;
     // 0.1: the FP32 stage runs into its quadratic phase, to a few times its
     // rounding floor (off(Q_d^T A Q_d) settles near 0.05 n u_l ||A||_F), which
     // saves FP64 sweeps that cost more than the FP32 ones (measured on GOE and
@@ -81,6 +83,12 @@ int resolve_opts(const jacobi_opts *o, Opts &r)
     r.tune = o->tune;
     r.graph = o->graph != 0;
     r.pair_skip = o->no_pair_skip == 0;
+    if (o->gemm_slots < 0 || o->gemm_slots > (1 << 16))
+        return 1;
+    r.gemm_slots = o->gemm_slots;
+    if (o->pair_v_split < -1 || o->pair_v_split > (1 << 16))
+        return 1;
+    r.pair_v_split = o->pair_v_split;
     if (o->max_sweeps < 0 || o->max_sweeps > 1000)
         return 1;
     if (o->max_sweeps)
@@ -180,7 +188,7 @@ Geometry geometry(int64_t n, int block)
 
 // Buffers of one block-path solve (plain or mixed).
 struct BlockWs {
-    double *B64, *V64, *U64, *X2, *R, *Vt, *probe;
+    double *B64, *V64, *U64, *X2, *R, *Vt, *A0, *probe;
     float *B32, *V32, *U32;
     double *partial, *scal, *wtmp, *sg, *cmax, *csq, *cinv;
     int *flags, *perm, *cidx;
@@ -192,7 +200,7 @@ size_t partial_count(const Geometry &g)
 {
     // pair solve (one per wavefront) + update of B (one per wavefront and tile)
     size_t c = (size_t)g.npairs * pair_solve_waves(g.M) + (size_t)g.nbt * (g.M / 16);
-    c = std::max(c, (size_t)INGEST_BLOCKS);
+    c = std::max(c, (size_t)2 * INGEST_BLOCKS); // ingest: sums of squares, then maxima
     c = std::max(c, (size_t)OFF_BLOCKS);
     return c;
 }
@@ -206,8 +214,10 @@ BlockWs layout_block(Bump &bp, int64_t n, const Geometry &g, bool mixed)
     w.V64 = bp.take<double>(nn);
     w.U64 = bp.take<double>(2 * uu); // double-buffered across rounds
     w.probe = bp.take<double>((size_t)g.npad * 2 * NPROBE + (size_t)16 * NPROBE * std::max<int64_t>(n, 1));
-    if (!mixed)
+    if (!mixed) {
         w.Vt = bp.take<double>(nn);
+        w.A0 = bp.take<double>(nn); // the scaled input, when ingest scales it
+    }
     if (mixed) {
         w.X2 = bp.take<double>(nn);
         w.R = bp.take<double>(nn);
@@ -548,7 +558,7 @@ struct SideStream {
 template <typename T>
 int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U, double tol,
                double eps, int max_sweeps, int inner, int schedule, int serial_v,
-               bool pair_skip, bool fp32_stage,
+               bool pair_skip, bool fp32_stage, int vsplit,
                hipStream_t s,
                SideStream &ss, int *sweeps_out, double *off_out, double *off0_out,
                RoundTimer *tm, int *skipped_out)
@@ -564,6 +574,8 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
     double off = std::sqrt(rb.scal[1]);
     if (off0_out)
         *off0_out = off;
+    if (!std::isfinite(off))
+        return JACOBI_NONFINITE; // the starting matrix (e.g. Q_d^T A Q_d) holds Inf or NaN
     int sweeps = 0;
     int status = JACOBI_OK;
     const double thr = n > 0 ? tol / (double)n : 0.0;
@@ -611,7 +623,7 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
             if (vpend_pairs) {
                 CK(launch_pair_solve_v<T>(B, g.npad, g.b, g.npairs, pr, map, Ub, eps, thr, inner,
                                           cross, w.partial, w.flags + 2, pf, V, g.npad,
-                                          g.npad, vpend_pairs, vpend_U, vpend_prot, s));
+                                          g.npad, vpend_pairs, vpend_U, vpend_prot, s, vsplit));
                 vpend_pairs = nullptr;
             } else {
                 CK(launch_pair_solve<T>(B, g.npad, g.b, g.npairs, pr, map, Ub, eps, thr, inner,
@@ -844,11 +856,24 @@ int finalize_block(const Geometry &g, int64_t n, const BlockWs &w, const double 
     return 0;
 }
 
+// Exponent k of the exact scaling B <- 2^k B applied on ingest: inputs whose
+// largest entry lies outside [2^-100, 2^100] are scaled so that it lands in
+// [1, 2).  Jacobi rotations, the stopping rules and every product are
+// invariant under a power-of-two scaling except for over- and underflow; the
+// scaling keeps the sums of squares (||A||_F, off), the squared per-pair test
+// and the FP32 stage of the mixed path in range.  Eigenvalues are scaled back
+// by 2^-k, eigenvectors are unaffected.
+int scale_exponent(double amax) { return scale_exp_of(amax); }
+
+// Ingest of the block path: B = sym(A) zero-padded, the non-finite and
+// symmetry checks, the scaling exponent ks (B, and copy when not null, then
+// hold 2^ks sym(A)) and ||B||_F of the scaled matrix.
 int ingest_norm(const double *A, int64_t lda, int64_t n, const Geometry &g, const BlockWs &w,
-                double *B, int check_sym, hipStream_t s, double &normf)
+                double *B, double *copy, int check_sym, hipStream_t s, double &normf, int &ks)
 {
     CK(launch_ingest<double>(A, lda, n, B, g.npad, w.partial, w.flags, check_sym, s));
     CK(launch_sum(w.partial, INGEST_BLOCKS, w.scal, s));
+    CK(launch_max(w.partial + INGEST_BLOCKS, INGEST_BLOCKS, w.scal + 4, s));
     Readback rb;
     if (int e = read_scalars(w, s, rb))
         return e;
@@ -856,8 +881,30 @@ int ingest_norm(const double *A, int64_t lda, int64_t n, const Geometry &g, cons
         return JACOBI_NONFINITE;
     if (check_sym && rb.flags[1])
         return JACOBI_NOTSYM;
+    ks = scale_exponent(rb.scal[4]);
+    if (ks) {
+        const int64_t nn = g.npad * g.npad;
+        CK(launch_scale_pow2(B, nn, ks, copy, s));
+        CK(launch_sq_partial(B, nn, w.partial, s));
+        CK(launch_sum(w.partial, OFF_BLOCKS, w.scal, s));
+        if (int e = read_scalars(w, s, rb))
+            return e;
+    }
     normf = std::sqrt(rb.scal[0]);
     return 0;
+}
+
+// info fields in the caller's scale: norm, tolerance and off values of a
+// solve that ran on 2^ks sym(A)
+void unscale_info(jacobi_info *info, int ks)
+{
+    if (!info || !ks)
+        return;
+    info->norm_f = std::ldexp(info->norm_f, -ks);
+    info->tol = std::ldexp(info->tol, -ks);
+    info->off_final = std::ldexp(info->off_final, -ks);
+    info->off32 = std::ldexp(info->off32, -ks);
+    info->off_cond = std::ldexp(info->off_cond, -ks);
 }
 
 int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, int64_t ldv,
@@ -869,10 +916,11 @@ int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, in
     if (int e = setup_block(g, w, s))
         return e;
     double normf = 0.0;
-    if (int e = ingest_norm(A, lda, n, g, w, w.B64, o.check_sym, s, normf))
+    int ks = 0;
+    if (int e = ingest_norm(A, lda, n, g, w, w.B64, w.A0, o.check_sym, s, normf, ks))
         return e;
     CK(launch_eye<double>(w.V64, g.npad, s));
-    const double tol = tol_in > 0.0 ? tol_in : 1e-15 * (double)n * normf;
+    const double tol = tol_in > 0.0 ? std::ldexp(tol_in, ks) : 1e-15 * (double)n * normf;
     int sweeps = 0, skipped = 0;
     double off = 0.0;
     RoundTimer tm;
@@ -881,17 +929,21 @@ int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, in
     if (int e = ss.init())
         return e;
     int st = run_sweeps<double>(g, n, w, w.B64, w.V64, w.U64, tol, U_D, o.max_sweeps, o.inner,
-                                o.schedule, o.serial_v, o.pair_skip, false, s, ss, &sweeps, &off, nullptr, &tm,
-                                &skipped);
+                                o.schedule, o.serial_v, o.pair_skip, false, o.pair_v_split, s,
+                                ss, &sweeps, &off, nullptr, &tm, &skipped);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;
     double est = 0.0;
     int pol = 0;
-    if (int e = finalize_block(g, n, w, w.B64, w.V64, w.B64, w.Vt, W, V, ldv, s, &est, &pol, A,
-                               lda))
+    // eigenvalues: Rayleigh quotients against the (scaled) symmetrised input
+    if (int e = finalize_block(g, n, w, w.B64, w.V64, w.B64, w.Vt, W, V, ldv, s, &est, &pol,
+                               ks ? w.A0 : A, ks ? g.npad : lda))
         return e;
+    if (ks)
+        CK(launch_scale_pow2(W, n, -ks, nullptr, s));
     CK(hipStreamSynchronize(s));
     fill_info(info, sweeps, 0, 0, 1, g.b, normf, tol, off, 0, 0, 0);
+    unscale_info(info, ks);
     if (info) {
         info->orth_est = est;
         info->polished = pol;
@@ -914,7 +966,8 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     // ingest: A64 = sym(A) (kept for the preconditioning product), B32 = fl32(A64)
     double *A64 = w.B64;
     double normf = 0.0;
-    if (int e = ingest_norm(A, lda, n, g, w, A64, o.check_sym, s, normf))
+    int ks = 0;
+    if (int e = ingest_norm(A, lda, n, g, w, A64, nullptr, o.check_sym, s, normf, ks))
         return e;
     CK(launch_cast_f32(A64, w.B32, nn, s));
     CK(launch_eye<float>(w.V32, g.npad, s));
@@ -928,9 +981,9 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     if (int e = ss.init())
         return e;
     int st32 = run_sweeps<float>(g, n, w, w.B32, w.V32, w.U32, tol32, U_L, o.max_sweeps,
-                                 o.inner, o.schedule, o.serial_v, o.pair_skip, true, s, ss, &sw32, &off32, nullptr, &tm32,
-                                 nullptr);
-    if (st32 == JACOBI_DEVICE)
+                                 o.inner, o.schedule, o.serial_v, o.pair_skip, true,
+                                 o.pair_v_split, s, ss, &sw32, &off32, nullptr, &tm32, nullptr);
+    if (st32 == JACOBI_DEVICE || st32 == JACOBI_NONFINITE)
         return st32;
     // stage 2: Newton-Schulz, X <- X + X (I - X^T X) / 2  (= X (3I - X^T X) / 2)
     double *X = w.V64, *X2 = w.X2, *R = w.R;
@@ -942,7 +995,7 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     double orth = 0.0;
     for (int it = 0; it < max_it; ++it) {
         CK(launch_gemm64_sym(1, 0, g.npad, g.npad, -1.0, X, g.npad, X, g.npad, 0.0, nullptr, 0,
-                             1.0, R, g.npad, s, X2, nn));
+                             1.0, R, g.npad, s, X2, nn, o.gemm_slots));
         if (adaptive || it == max_it - 1) {
             CK(launch_sq_partial(R, nn, w.partial, s));
             CK(launch_sum(w.partial, OFF_BLOCKS, w.scal + 2, s));
@@ -963,21 +1016,24 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     CK(launch_gemm64(0, 0, g.npad, g.npad, g.npad, 1.0, A64, g.npad, 0, X, g.npad, 0, 0.0,
                      nullptr, 0, 0, 0.0, R, g.npad, 0, 1, s));
     CK(launch_gemm64_sym(1, 0, g.npad, g.npad, 1.0, X, g.npad, R, g.npad, 0.0, nullptr, 0, 0.0,
-                         A64, g.npad, s, X2, nn));
-    const double tol = tol_in > 0.0 ? tol_in : 1e-15 * (double)n * normf;
+                         A64, g.npad, s, X2, nn, o.gemm_slots));
+    const double tol = tol_in > 0.0 ? std::ldexp(tol_in, ks) : 1e-15 * (double)n * normf;
     int sw64 = 0, skipped = 0;
     double off = 0.0, offc = 0.0;
     int st = run_sweeps<double>(g, n, w, A64, X, w.U64, tol, U_D, o.max_sweeps, o.inner,
-                                o.schedule, o.serial_v, o.pair_skip, false, s, ss, &sw64, &off, &offc, &tm64,
-                                &skipped);
+                                o.schedule, o.serial_v, o.pair_skip, false, o.pair_v_split, s,
+                                ss, &sw64, &off, &offc, &tm64, &skipped);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;
     double est = 0.0;
     int pol = 0;
     if (int e = finalize_block(g, n, w, A64, X, A64, w.R, W, V, ldv, s, &est, &pol))
         return e;
+    if (ks)
+        CK(launch_scale_pow2(W, n, -ks, nullptr, s));
     CK(hipStreamSynchronize(s));
     fill_info(info, sw64, sw32, ns, 1, g.b, normf, tol, off, off32, offc, orth);
+    unscale_info(info, ks);
     if (info) {
         info->orth_est = est;
         info->polished = pol;
@@ -1094,12 +1150,13 @@ int jacobi_eigh_mixed(const double *A, int64_t n, int64_t lda, double *W, double
     return eigh_entry(true, A, n, lda, W, V, ldv, tol, opts, work, work_bytes, stream, info);
 }
 
-int jacobi_eigh_batched(const double *A, const int64_t *n, int64_t batch, double *W, double *V,
-                        double tol, int mixed, const jacobi_opts *opts, void *work,
-                        size_t work_bytes, void *stream, int32_t *status)
+int jacobi_eigh_batched(const double *A, const int64_t *n, const int64_t *a_off, int64_t batch,
+                        double *W, const int64_t *w_off, double *V, double tol, int mixed,
+                        const jacobi_opts *opts, void *work, size_t work_bytes, void *stream,
+                        int32_t *status)
 {
     if (batch < 0)
-        return -3;
+        return -4;
     if (batch > 0 && !n)
         return -2;
     int64_t n_max = 0;
@@ -1107,20 +1164,24 @@ int jacobi_eigh_batched(const double *A, const int64_t *n, int64_t batch, double
         if (n[i] < 1 || n[i] > 128)
             return -2;
         n_max = std::max(n_max, n[i]);
+        if (a_off && a_off[i] < 0)
+            return -3;
+        if (w_off && w_off[i] < 0)
+            return -6;
     }
     if (batch > 0 && !A)
         return -1;
     if (batch > 0 && !W)
-        return -4;
-    if (batch > 0 && !V)
         return -5;
-    if (std::isnan(tol) || std::isinf(tol))
-        return -6;
-    if (mixed != 0)
+    if (batch > 0 && !V)
         return -7;
+    if (std::isnan(tol) || std::isinf(tol))
+        return -8;
+    if (mixed != 0)
+        return -9;
     Opts o;
     if (resolve_opts(opts, o))
-        return -8;
+        return -10;
     if (batch == 0)
         return JACOBI_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -1151,9 +1212,9 @@ int jacobi_eigh_batched(const double *A, const int64_t *n, int64_t batch, double
     uint64_t nhash = 1469598103934665603ull; // FNV-1a over the orders (graph key)
     for (int64_t i = 0; i < batch; ++i) {
         SmallDesc &e = d[(size_t)i];
-        e.a_off = ao;
-        e.v_off = ao;
-        e.w_off = wo;
+        e.a_off = a_off ? a_off[i] : ao;
+        e.v_off = e.a_off;
+        e.w_off = w_off ? w_off[i] : wo;
         e.n = (int)n[i];
         e.lda = (int)n[i];
         e.ldv = (int)n[i];
@@ -1162,6 +1223,8 @@ int jacobi_eigh_batched(const double *A, const int64_t *n, int64_t batch, double
         ao += n[i] * n[i];
         wo += n[i];
         nhash = (nhash ^ (uint64_t)n[i]) * 1099511628211ull;
+        nhash = (nhash ^ (uint64_t)e.a_off) * 1099511628211ull;
+        nhash = (nhash ^ (uint64_t)e.w_off) * 1099511628211ull;
     }
     std::stable_sort(d.begin(), d.end(),
                      [](const SmallDesc &a, const SmallDesc &b) { return a.n > b.n; });
@@ -1245,23 +1308,25 @@ int jacobi_eigh_batched(const double *A, const int64_t *n, int64_t batch, double
 }
 
 int jacobi_eigh_backward(const double *W, const double *V, const double *dW, const double *dV,
-                         int64_t n, int64_t batch, double *dA, double gap_tol, void *work,
-                         size_t work_bytes, void *stream)
+                         int64_t n, int64_t ld, int64_t batch, double *dA, double gap_tol,
+                         void *work, size_t work_bytes, void *stream)
 {
     if (n < 0)
         return -5;
-    if (batch < 0)
+    if (ld < std::max<int64_t>(1, n))
         return -6;
+    if (batch < 0)
+        return -7;
     if (n > 0 && batch > 0) {
         if (!W)
             return -1;
         if (!V)
             return -2;
         if (!dA)
-            return -7;
+            return -8;
     }
     if (std::isnan(gap_tol) || gap_tol < 0.0)
-        return -8;
+        return -9;
     if (n == 0 || batch == 0)
         return JACOBI_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -1276,20 +1341,20 @@ int jacobi_eigh_backward(const double *W, const double *V, const double *dW, con
     }
     void *aligned = (void *)(((uintptr_t)work + 255) & ~(uintptr_t)255);
     Bump bp(aligned);
-    const int64_t nn = n * n;
+    const int64_t nn = n * n, sv = n * ld; // packed scratch; caller matrices n x ld apart
     double *Mb = bp.take<double>((size_t)(nn * batch));
     double *Tb = bp.take<double>((size_t)(nn * batch));
     int *flag = bp.take<int>(4);
     CK(launch_fill_i32(flag, 1, 0, s));
     if (dV)
-        CK(launch_gemm64(1, 0, n, n, n, 1.0, V, n, nn, dV, n, nn, 0.0, nullptr, 0, 0, 0.0, Mb, n,
-                         nn, batch, s));
+        CK(launch_gemm64(1, 0, n, n, n, 1.0, V, ld, sv, dV, ld, sv, 0.0, nullptr, 0, 0, 0.0, Mb,
+                         n, nn, batch, s));
     CK(launch_adjoint_mid(Mb, W, dW, n, batch, gap_tol, dV != nullptr, flag, s));
-    CK(launch_gemm64(0, 0, n, n, n, 1.0, V, n, nn, Mb, n, nn, 0.0, nullptr, 0, 0, 0.0, Tb, n, nn,
-                     batch, s));
-    CK(launch_gemm64(0, 1, n, n, n, 1.0, Tb, n, nn, V, n, nn, 0.0, nullptr, 0, 0, 0.0, Mb, n, nn,
-                     batch, s));
-    CK(launch_sym_out(Mb, dA, n, batch, s));
+    CK(launch_gemm64(0, 0, n, n, n, 1.0, V, ld, sv, Mb, n, nn, 0.0, nullptr, 0, 0, 0.0, Tb, n,
+                     nn, batch, s));
+    CK(launch_gemm64(0, 1, n, n, n, 1.0, Tb, n, nn, V, ld, sv, 0.0, nullptr, 0, 0, 0.0, Mb, n,
+                     nn, batch, s));
+    CK(launch_sym_out(Mb, dA, n, ld, batch, s));
     int hflag = 0;
     CK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));

@@ -203,6 +203,40 @@ __device__ inline double block_sum(double v, double *red)
     return tot;
 }
 
+// Block-wide maximum; every thread gets the result (same LDS use as block_sum).
+template <int NT>
+__device__ inline double block_max(double v, double *red)
+{
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1)
+        v = fmax(v, __shfl_xor(v, off, WAVE));
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    __syncthreads();
+    if (lane == 0)
+        red[w] = v;
+    __syncthreads();
+    double m = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / WAVE; ++i)
+        m = fmax(m, red[i]);
+    __syncthreads();
+    return m;
+}
+
+// x 2^k, exact, in two steps so that the factor never overflows (|k| <= 2100)
+__device__ inline double ldexp2(double x, int k) { return ldexp(ldexp(x, k / 2), k - k / 2); }
+
+// Exponent of the exact scaling that brings a largest entry amax outside
+// [2^-100, 2^100] into [1, 2) (0 when amax is inside, zero or not finite).
+__host__ __device__ inline int scale_exp_of(double amax)
+{
+    if (!(amax > 0.0) || !(amax <= 0x1.fffffffffffffp1023) || (amax >= 0x1p-100 && amax <= 0x1p100))
+        return 0;
+    int e = 0;
+    frexp(amax, &e);
+    return 1 - e;
+}
+
 template <int NT>
 __device__ inline int block_or(int v, int *red)
 {

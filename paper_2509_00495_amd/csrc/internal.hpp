@@ -56,13 +56,14 @@ hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *p
                              hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // the same pair solves, plus the V update V[:, cols] <- V[:, cols] vU of the
 // previous round (pairs vpairs, rotations vU, rotation flags vprot or null)
-// on further workgroups of the same launch
+// on further workgroups of the same launch; vsplit: 16-row V tiles per pair
+// its pair-solve workgroup takes after its solve (0 = timing model, -1 = none)
 template <typename T>
 hipError_t launch_pair_solve_v(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                                const int2 *psmap, T *U, double eps, double thr, int inner,
                                int cross, double *partial, int *rot_flag, int *prot, T *V,
                                int64_t ldv, int64_t nrows, const int2 *vpairs, const T *vU,
-                               const int *vprot, hipStream_t s);
+                               const int *vprot, hipStream_t s, int vsplit = 0);
 // experiments: V workgroups of the shared launch (0 = default), a minimum
 // dynamic LDS per workgroup (larger keeps one workgroup per compute unit) and
 // the working wavefronts per V workgroup (0 = all)
@@ -93,6 +94,12 @@ hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
                            const int2 *pairs, const T *U, const int *prot, hipStream_t s,
                            hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_sum(const double *x, int64_t count, double *out, hipStream_t s);
+hipError_t launch_max(const double *x, int64_t count, double *out, hipStream_t s);
+// x <- 2^k x for count entries (exact), also written to copy when not null
+hipError_t launch_scale_pow2(double *x, int64_t count, int k, double *copy, hipStream_t s);
+// B = (A + A^T)/2 zero-padded to npad; norm_partial[0, INGEST_BLOCKS) gets the
+// partial sums of squares, [INGEST_BLOCKS, 2 INGEST_BLOCKS) the partial
+// maxima of |b_ij|; flags[0] non-finite, flags[1] asymmetric
 template <typename T>
 hipError_t launch_ingest(const double *A, int64_t lda, int64_t n, T *B, int64_t npad,
                          double *norm_partial, int *flags, int check_sym, hipStream_t s);
@@ -145,19 +152,20 @@ hipError_t launch_gemm64(int transA, int transB, int64_t M, int64_t N, int64_t K
 // scratch buffer (device, scratch_doubles entries, not aliasing the operands)
 // large enough for the split tiles, a product with more tiles than resident
 // workgroups splits its (tile, K stage) iterations evenly over them and adds
-// the two parts of each split tile in a fix-up pass.
+// the two parts of each split tile in a fix-up pass.  slots > 0 replaces the
+// resident workgroup count (two per compute unit) in that decision.
 hipError_t launch_gemm64_sym(int transA, int transB, int64_t N, int64_t K, double alpha,
                              const double *A, int64_t lda, const double *B, int64_t ldb,
                              double beta, const double *C0, int64_t ldc0, double gamma, double *C,
                              int64_t ldc, hipStream_t s, double *scratch = nullptr,
-                             int64_t scratch_doubles = 0);
+                             int64_t scratch_doubles = 0, int slots = 0);
 hipError_t launch_sq_partial(const double *X, int64_t count, double *partial,
                              hipStream_t s);
 // backward elementwise: M <- diag(dW) + F o M (F from gaps), flags DEGENERATE
 hipError_t launch_adjoint_mid(double *M, const double *W, const double *dW, int64_t n,
                               int64_t batch, double gap_tol, int has_dv, int *flag,
                               hipStream_t s);
-hipError_t launch_sym_out(const double *G, double *dA, int64_t n, int64_t batch,
+hipError_t launch_sym_out(const double *G, double *dA, int64_t n, int64_t ld, int64_t batch,
                           hipStream_t s);
 
 } // namespace lj

@@ -531,7 +531,7 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
                                         int inner, double *partial, int *rot_flag, int *prot,
                                         size_t smem, T *V, int64_t ldv, int64_t nrows,
                                         const int2 *vpairs, const T *vU, const int *vprot,
-                                        hipStream_t s)
+                                        hipStream_t s, int vsplit)
 {
     auto k = pair_solve_v_kernel<T, M, NT, CROSS>;
     static size_t smem_set = 0;
@@ -571,7 +571,9 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
     // 188.7, 184.6, 184.3 and 194.4 ms; FP32 splits of 6 tiles were slower
     // than none.)
     int vx = 0;
-    if (M == 64) {
+    if (M == 64 && vsplit > 0) {
+        vx = (int)std::min<int64_t>(vsplit, ntile - ranges);
+    } else if (M == 64 && vsplit == 0) {
         const double tp = 3.0 + (sizeof(T) == 4 ? (CROSS ? 29.6 : 58.6) : (CROSS ? 31.7 : 66.1));
         const double rho = sizeof(T) == 4 ? 2.63 : 1.19;
         const double T_end = ((double)ntile + rho * tp) / ((double)(ranges + 1) * rho);
@@ -598,7 +600,7 @@ hipError_t launch_pair_solve_v(T *B, int64_t ldb, int b, int npairs, const int2 
                                const int2 *psmap, T *U, double eps, double thr, int inner,
                                int cross, double *partial, int *rot_flag, int *prot, T *V,
                                int64_t ldv, int64_t nrows, const int2 *vpairs, const T *vU,
-                               const int *vprot, hipStream_t s)
+                               const int *vprot, hipStream_t s, int vsplit)
 {
     if (nrows % 16 != 0 || ldv % (16 / (int64_t)sizeof(T)) != 0 || ((uintptr_t)V % 16) != 0)
         return hipErrorInvalidValue;
@@ -608,20 +610,20 @@ hipError_t launch_pair_solve_v(T *B, int64_t ldb, int b, int npairs, const int2 
         return cross ? launch_pair_solve_v_t<T, 64, 1024, true>(B, ldb, npairs, pairs, psmap, U,
                                                                 eps, thr, inner, partial,
                                                                 rot_flag, prot, smem, V, ldv, nrows,
-                                                                vpairs, vU, vprot, s)
+                                                                vpairs, vU, vprot, s, vsplit)
                      : launch_pair_solve_v_t<T, 64, 1024, false>(B, ldb, npairs, pairs, psmap,
                                                                  U, eps, thr, inner, partial,
                                                                  rot_flag, prot, smem, V, ldv, nrows,
-                                                                 vpairs, vU, vprot, s);
+                                                                 vpairs, vU, vprot, s, vsplit);
     if (M == 32)
         return cross ? launch_pair_solve_v_t<T, 32, 256, true>(B, ldb, npairs, pairs, psmap, U,
                                                                eps, thr, inner, partial,
                                                                rot_flag, prot, smem, V, ldv, nrows,
-                                                               vpairs, vU, vprot, s)
+                                                               vpairs, vU, vprot, s, vsplit)
                      : launch_pair_solve_v_t<T, 32, 256, false>(B, ldb, npairs, pairs, psmap, U,
                                                                 eps, thr, inner, partial,
                                                                 rot_flag, prot, smem, V, ldv, nrows,
-                                                                vpairs, vU, vprot, s);
+                                                                vpairs, vU, vprot, s, vsplit);
     return hipErrorInvalidValue;
 }
 
@@ -648,9 +650,57 @@ hipError_t launch_sum(const double *x, int64_t count, double *out, hipStream_t s
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void max_kernel(const double *__restrict__ x, int64_t count,
+                                                  double *out)
+{
+    __shared__ double red[4];
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += 256)
+        m = fmax(m, x[i]);
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1)
+        m = fmax(m, __shfl_xor(m, off, WAVE));
+    if (threadIdx.x % WAVE == 0)
+        red[threadIdx.x / WAVE] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        out[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+hipError_t launch_max(const double *x, int64_t count, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, s, x, count, out);
+    return hipGetLastError();
+}
+
+// x <- 2^k x in place (exact: a power of two, applied in two steps so that
+// |k| up to 2100 never overflows the factor), optionally also into copy.
+__global__ __launch_bounds__(256) void scale_pow2_kernel(double *__restrict__ x, int64_t count,
+                                                         int k, double *__restrict__ copy)
+{
+    const int k1 = k / 2, k2 = k - k / 2;
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
+        const double v = ldexp(ldexp(x[e], k1), k2);
+        x[e] = v;
+        if (copy)
+            copy[e] = v;
+    }
+}
+
+hipError_t launch_scale_pow2(double *x, int64_t count, int k, double *copy, hipStream_t s)
+{
+    if (count <= 0)
+        return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(scale_pow2_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, count, k,
+                       copy);
+    return hipGetLastError();
+}
+
 // Symmetrised copy of A into the padded working matrix (32 x 32 tiles staged
 // through LDS so that both A and A^T are read along rows), plus the partial
-// sums of squares for ||B||_F and the non-finite / asymmetry flags.
+// sums of squares for ||B||_F (partial[block]), the partial maxima of |b_ij|
+// (partial[INGEST_BLOCKS + block]) and the non-finite / asymmetry flags.
 template <typename T>
 __global__ __launch_bounds__(256) void ingest_kernel(const double *__restrict__ A, int64_t lda,
                                                      int64_t n, T *__restrict__ B, int64_t npad,
@@ -661,7 +711,7 @@ __global__ __launch_bounds__(256) void ingest_kernel(const double *__restrict__ 
     __shared__ double t2[32][33];
     __shared__ double red[4];
     const int64_t nt = npad / 32;
-    double acc = 0.0;
+    double acc = 0.0, amax = 0.0;
     int bad = 0, asym = 0;
     for (int64_t tile = blockIdx.x; tile < nt * nt; tile += gridDim.x) {
         const int64_t i0 = (tile / nt) * 32, j0 = (tile % nt) * 32;
@@ -683,15 +733,24 @@ __global__ __launch_bounds__(256) void ingest_kernel(const double *__restrict__ 
             double v = 0.5 * (a + at);
             B[(i0 + r) * npad + j0 + c] = (T)v;
             acc += v * v;
+            amax = fmax(amax, fabs(v));
         }
         __syncthreads();
     }
     acc = wave_sum(acc);
-    if (threadIdx.x % WAVE == 0)
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1)
+        amax = fmax(amax, __shfl_xor(amax, off, WAVE));
+    __shared__ double redm[4];
+    if (threadIdx.x % WAVE == 0) {
         red[threadIdx.x / WAVE] = acc;
+        redm[threadIdx.x / WAVE] = amax;
+    }
     __syncthreads();
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+        partial[INGEST_BLOCKS + blockIdx.x] = fmax(fmax(redm[0], redm[1]), fmax(redm[2], redm[3]));
+    }
     if (__any(bad) && threadIdx.x % WAVE == 0)
         atomicOr(flags, 1);
     if (__any(asym) && threadIdx.x % WAVE == 0)
@@ -1171,12 +1230,12 @@ template hipError_t launch_pair_solve_v<double>(double *, int64_t, int, int, con
                                                const int2 *, double *, double, double, int, int,
                                                double *, int *, int *, double *, int64_t,
                                                int64_t, const int2 *, const double *,
-                                               const int *, hipStream_t);
+                                               const int *, hipStream_t, int);
 template hipError_t launch_pair_solve_v<float>(float *, int64_t, int, int, const int2 *,
                                               const int2 *, float *, double, double, int, int,
                                               double *, int *, int *, float *, int64_t,
                                               int64_t, const int2 *, const float *, const int *,
-                                              hipStream_t);
+                                              hipStream_t, int);
 template hipError_t launch_pair_solve<double>(double *, int64_t, int, int, const int2 *,
                                               const int2 *, double *, double, double, int, int,
                                               double *, int *, int *, hipStream_t, hipEvent_t,

@@ -424,11 +424,11 @@ static hipError_t launch_gemm128(int transA, int transB, int64_t M, int64_t N, i
                                  double alpha, const double *A, int64_t lda, const double *B,
                                  int64_t ldb, double beta, const double *C0, int64_t ldc0,
                                  double gamma, double *C, int64_t ldc, double *scratch,
-                                 int64_t scratch_doubles, hipStream_t s)
+                                 int64_t scratch_doubles, int slots, hipStream_t s)
 {
     const int tn = (int)((N + BT - 1) / BT), tm = (int)((M + BT - 1) / BT);
     const int ntiles = tn * (tn + 1) / 2;
-    const int G = gemm_resident_slots();
+    const int G = slots > 0 ? slots : gemm_resident_slots();
     if (SYM && ntiles > G && K >= BK && scratch &&
         scratch_doubles >= (int64_t)2 * (G - 1) * BT * BT) {
 #define LJ_GSK(TA_, TB_)                                                                           \
@@ -469,13 +469,14 @@ static hipError_t launch_gemm64_t(int transA, int transB, int64_t M, int64_t N, 
                                   const double *B, int64_t ldb, int64_t sB, double beta,
                                   const double *C0, int64_t ldc0, int64_t sC0, double gamma,
                                   double *C, int64_t ldc, int64_t sC, int64_t batch,
-                                  double *scratch, int64_t scratch_doubles, hipStream_t s)
+                                  double *scratch, int64_t scratch_doubles, int slots,
+                                  hipStream_t s)
 {
     if (M <= 0 || N <= 0 || batch <= 0)
         return hipSuccess;
     if (batch == 1 && gemm128_fits<SYM>(M, N, A, lda, B, ldb))
         return launch_gemm128<SYM>(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C0,
-                                   ldc0, gamma, C, ldc, scratch, scratch_doubles, s);
+                                   ldc0, gamma, C, ldc, scratch, scratch_doubles, slots, s);
     dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT), (unsigned)batch);
     if (!transA && !transB)
         hipLaunchKernelGGL((gemm64_kernel<0, 0, SYM>), grid, dim3(256), 0, s, M, N, K, alpha, A,
@@ -499,16 +500,18 @@ hipError_t launch_gemm64(int transA, int transB, int64_t M, int64_t N, int64_t K
                          hipStream_t s)
 {
     return launch_gemm64_t<false>(transA, transB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta,
-                                  C0, ldc0, sC0, gamma, C, ldc, sC, batch, nullptr, 0, s);
+                                  C0, ldc0, sC0, gamma, C, ldc, sC, batch, nullptr, 0, 0, s);
 }
 
 hipError_t launch_gemm64_sym(int transA, int transB, int64_t N, int64_t K, double alpha,
                              const double *A, int64_t lda, const double *B, int64_t ldb,
                              double beta, const double *C0, int64_t ldc0, double gamma, double *C,
-                             int64_t ldc, hipStream_t s, double *scratch, int64_t scratch_doubles)
+                             int64_t ldc, hipStream_t s, double *scratch, int64_t scratch_doubles,
+                             int slots)
 {
     return launch_gemm64_t<true>(transA, transB, N, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C0,
-                                 ldc0, 0, gamma, C, ldc, 0, 1, scratch, scratch_doubles, s);
+                                 ldc0, 0, gamma, C, ldc, 0, 1, scratch, scratch_doubles, slots,
+                                 s);
 }
 
 __global__ __launch_bounds__(256) void sq_partial_kernel(const double *__restrict__ X,
@@ -575,21 +578,24 @@ hipError_t launch_adjoint_mid(double *M, const double *W, const double *dW, int6
     return hipGetLastError();
 }
 
+// dA = (G + G^T)/2 per matrix; G packed (n x n each), dA with row stride ld and
+// matrix stride n ld
 __global__ __launch_bounds__(256) void sym_out_kernel(const double *__restrict__ G,
                                                       double *__restrict__ dA, int64_t n,
-                                                      int64_t batch)
+                                                      int64_t ld, int64_t batch)
 {
     const int64_t total = batch * n * n;
     for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
         int64_t z = e / (n * n), r = e - z * n * n;
         int64_t i = r / n, j = r - (r / n) * n;
-        dA[e] = 0.5 * (G[e] + G[z * n * n + j * n + i]);
+        dA[z * n * ld + i * ld + j] = 0.5 * (G[e] + G[z * n * n + j * n + i]);
     }
 }
 
-hipError_t launch_sym_out(const double *G, double *dA, int64_t n, int64_t batch, hipStream_t s)
+hipError_t launch_sym_out(const double *G, double *dA, int64_t n, int64_t ld, int64_t batch,
+                          hipStream_t s)
 {
-    hipLaunchKernelGGL(sym_out_kernel, dim3(2048), dim3(256), 0, s, G, dA, n, batch);
+    hipLaunchKernelGGL(sym_out_kernel, dim3(2048), dim3(256), 0, s, G, dA, n, ld, batch);
     return hipGetLastError();
 }
 

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
         const double *Ai = A + d.a_off;
 
         // ingest: S = (A + A^T)/2, zero padding to m
-        double nrm = 0.0;
+        double nrm = 0.0, amax = 0.0;
         int finite = 1;
         for (int idx = tid; idx < m * m; idx += NT) {
             int i = idx / m, j = idx - (idx / m) * m;
@@ -55,13 +55,27 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
             }
             S[i * ld + j] = v;
             nrm += v * v;
+            amax = fmax(amax, fabs(v));
         }
-        const double nrm2 = block_sum<NT>(nrm, red);
+        double nrm2 = block_sum<NT>(nrm, red);
         const int bad = block_or<NT>(!finite, ired);
         if (bad) {
             if (tid == 0 && status)
                 status[d.orig] = JACOBI_NONFINITE;
             continue;
+        }
+        // exact power-of-two scaling of inputs whose largest entry is outside
+        // [2^-100, 2^100] (the same for every thread); W is scaled back
+        const int ks = scale_exp_of(block_max<NT>(amax, red));
+        if (ks) {
+            nrm = 0.0;
+            for (int idx = tid; idx < m * m; idx += NT) {
+                const int i = idx / m, j = idx - (idx / m) * m;
+                const double v = ldexp2(S[i * ld + j], ks);
+                S[i * ld + j] = v;
+                nrm += v * v;
+            }
+            nrm2 = block_sum<NT>(nrm, red);
         }
         // V is kept transposed: Vt[p][i] = V[i][p], m rows of stride ldt
         const int ldt = (n + 1) & ~1;
@@ -71,7 +85,7 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
             int p = idx / ldt, i = idx - (idx / ldt) * ldt;
             Vt[idx] = (p == i) ? 1.0 : 0.0;
         }
-        const double tol = tol_in > 0.0 ? tol_in : 1e-15 * (double)n * sqrt(nrm2);
+        const double tol = tol_in > 0.0 ? ldexp2(tol_in, ks) : 1e-15 * (double)n * sqrt(nrm2);
         const double thr = n > 0 ? tol / (double)n : 0.0;
         const double eps = 0x1p-53;
         __syncthreads();
@@ -80,7 +94,7 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
         RoundItems<NT, SI> items;
         items.init(m, n);
         int sweeps = 0, any = 1;
-        while (off2 > tol * tol && sweeps < max_sweeps && any) {
+        while (sqrt(off2) > tol && sweeps < max_sweeps && any) {
             int rot = 0;
             for (int r = 0; r < m - 1; ++r)
                 rot |= lds_jacobi_round<double, NT, SI>(S, ld, m, r, eps, thr, Vt, ldt, cs,
@@ -121,7 +135,7 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
             }
             const double inv = sq > 0.0 ? 1.0 / sqrt(sq) : 1.0;
             sg[c] = val < 0.0 ? -inv : inv;
-            W[d.w_off + c] = wv[col];
+            W[d.w_off + c] = ks ? ldexp2(wv[col], -ks) : wv[col];
         }
         __syncthreads();
         double *Vo = Vout + d.v_off;
@@ -130,14 +144,14 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
             Vo[(int64_t)i * d.ldv + c] = sg[c] * Vt[(int64_t)perm[c] * ldt + i];
         }
         if (tid == 0) {
-            int st = (off2 <= tol * tol || !any) ? JACOBI_OK : JACOBI_NOCONV;
+            int st = (sqrt(off2) <= tol || !any) ? JACOBI_OK : JACOBI_NOCONV;
             if (status)
                 status[d.orig] = st;
             if (d.info) {
                 d.info[0] = (double)sweeps;
-                d.info[1] = sqrt(nrm2);
-                d.info[2] = tol;
-                d.info[3] = sqrt(off2);
+                d.info[1] = ldexp2(sqrt(nrm2), -ks);
+                d.info[2] = ldexp2(tol, -ks);
+                d.info[3] = ldexp2(sqrt(off2), -ks);
             }
         }
         __syncthreads();

@@ -45,6 +45,8 @@ class Opts(ctypes.Structure):
         ("tune", ctypes.c_int32),
         ("graph", ctypes.c_int32),
         ("no_pair_skip", ctypes.c_int32),
+        ("gemm_slots", ctypes.c_int32),
+        ("pair_v_split", ctypes.c_int32),
     ]
 
 
@@ -103,10 +105,11 @@ def _lib():
         lib.jacobi_eigh.restype = i32
         lib.jacobi_eigh_mixed.argtypes = eigh_args
         lib.jacobi_eigh_mixed.restype = i32
-        lib.jacobi_eigh_batched.argtypes = [P, ctypes.POINTER(i64), i64, P, P, d, i32,
+        lib.jacobi_eigh_batched.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), i64,
+                                            P, ctypes.POINTER(i64), P, d, i32,
                                             ctypes.POINTER(Opts), P, ctypes.c_size_t, P, P]
         lib.jacobi_eigh_batched.restype = i32
-        lib.jacobi_eigh_backward.argtypes = [P, P, P, P, i64, i64, P, d, P,
+        lib.jacobi_eigh_backward.argtypes = [P, P, P, P, i64, i64, i64, P, d, P,
                                              ctypes.c_size_t, P]
         lib.jacobi_eigh_backward.restype = i32
         lib.jacobi_workspace_bytes.argtypes = [i32, i64, i64, ctypes.POINTER(Opts)]
@@ -227,37 +230,57 @@ def eigh_mixed(A, tol: float | None = None, opts: Opts | None = None,
 
 
 def eigh_batched(A_packed, ns, tol: float | None = None, opts: Opts | None = None,
-                 ws: Workspace | None = None, check: bool = True, out=None):
-    """Packed batch of uneven orders.  A_packed: 1-D float64 GPU tensor holding
-    the matrices back to back (row-major).  Returns (W_packed, V_packed,
-    status) where status is an int32 GPU tensor of per-matrix codes.  `out`
-    = (W, V, status) reuses caller tensors (fixed addresses, which a graph
-    replay with opts.graph needs)."""
+                 ws: Workspace | None = None, check: bool = True, out=None, a_off=None,
+                 w_off=None):
+    """Batch of uneven orders in one persistent launch.  A_packed: 1-D float64
+    GPU tensor holding the matrices (row-major, ld = n_i), back to back or at
+    the element offsets a_off (host ints); eigenvalues go back to back or to
+    w_off.  Returns (W, V, status): V has A_packed's layout, status is an
+    int32 GPU tensor of per-matrix codes.  `out` = (W, V, status) reuses
+    caller tensors (fixed addresses, which a graph replay with opts.graph
+    needs)."""
     torch = _torch()
     ns = [int(x) for x in ns]
     batch = len(ns)
-    tot = sum(x * x for x in ns)
     if A_packed.dtype != torch.float64 or not A_packed.is_cuda:
         raise TypeError("A_packed must be a float64 GPU tensor")
-    if A_packed.numel() != tot:
-        raise ValueError(f"A_packed has {A_packed.numel()} entries, orders need {tot}")
+    if a_off is None:
+        tot = sum(x * x for x in ns)
+        if A_packed.numel() != tot:
+            raise ValueError(f"A_packed has {A_packed.numel()} entries, orders need {tot}")
+    else:
+        a_off = [int(x) for x in a_off]
+        if len(a_off) != batch or any(o < 0 for o in a_off):
+            raise ValueError("a_off needs one offset >= 0 per matrix")
+        tot = A_packed.numel()
+        if any(o + x * x > tot for o, x in zip(a_off, ns)):
+            raise ValueError("a matrix extends past the end of A_packed")
+    if w_off is None:
+        wtot = sum(ns)
+    else:
+        w_off = [int(x) for x in w_off]
+        if len(w_off) != batch or any(o < 0 for o in w_off):
+            raise ValueError("w_off needs one offset >= 0 per matrix")
+        wtot = max((o + x for o, x in zip(w_off, ns)), default=0)
     A_packed = A_packed.contiguous()
     if out is None:
-        W = torch.empty(sum(ns), dtype=torch.float64, device=A_packed.device)
+        W = torch.empty(wtot, dtype=torch.float64, device=A_packed.device)
         V = torch.empty(tot, dtype=torch.float64, device=A_packed.device)
         status = torch.zeros(batch, dtype=torch.int32, device=A_packed.device)
     else:
         W, V, status = out
-        for t, cnt, dt in ((W, sum(ns), torch.float64), (V, tot, torch.float64),
+        for t, cnt, dt in ((W, wtot, torch.float64), (V, tot, torch.float64),
                            (status, batch, torch.int32)):
             if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.numel() != cnt:
                 raise ValueError("out tensors must be contiguous GPU tensors of the packed sizes")
     o = opts or Opts()
     n_arr = (ctypes.c_int64 * max(batch, 1))(*ns)
+    ao = None if a_off is None else (ctypes.c_int64 * max(batch, 1))(*a_off)
+    wo = None if w_off is None else (ctypes.c_int64 * max(batch, 1))(*w_off)
     need = workspace_bytes(2, max(ns) if ns else 1, batch, o)
     buf = (ws or _default_ws).get(need)
-    st = _lib().jacobi_eigh_batched(A_packed.data_ptr(), n_arr, batch, W.data_ptr(),
-                                    V.data_ptr(), float(tol or 0.0), 0, ctypes.byref(o),
+    st = _lib().jacobi_eigh_batched(A_packed.data_ptr(), n_arr, ao, batch, W.data_ptr(),
+                                    wo, V.data_ptr(), float(tol or 0.0), 0, ctypes.byref(o),
                                     buf.data_ptr(), buf.numel(), _stream(torch),
                                     status.data_ptr())
     if st < 0 or st in (DEVICE, WORKSPACE) or (check and st != OK):
@@ -286,7 +309,7 @@ def eigh_backward(W, V, dW=None, dV=None, gap_tol: float = 0.0, ws: Workspace | 
     buf = (ws or _default_ws).get(need)
     st = _lib().jacobi_eigh_backward(
         W.data_ptr(), V.data_ptr(), None if dW is None else dW.data_ptr(),
-        None if dV is None else dV.data_ptr(), n, batch, dA.data_ptr(), float(gap_tol),
+        None if dV is None else dV.data_ptr(), n, max(n, 1), batch, dA.data_ptr(), float(gap_tol),
         buf.data_ptr(), buf.numel(), _stream(torch))
     if st not in (OK, DEGENERATE):
         raise JacobiError("jacobi_eigh_backward", st)
@@ -299,13 +322,21 @@ def _autograd():
 
     class EighFn(torch.autograd.Function):
         """(W, V) = eigh(A) with the adjoint of jacobi_eigh_backward.  A is a
-        (batch x) n x n float64 GPU tensor; the forward runs per matrix."""
+        (batch x) n x n float64 GPU tensor; a plain batch of order <= 128 runs
+        in one jacobi_eigh_batched launch, larger orders (and mixed) per
+        matrix."""
 
         @staticmethod
         def forward(ctx, A, mixed=False, tol=None):
             fn = eigh_mixed if mixed else eigh
             if A.dim() == 2:
                 W, V = fn(A, tol)
+            elif not mixed and 1 <= A.shape[-1] <= 128:
+                # one persistent launch for the whole batch
+                b, n = A.shape[0], A.shape[-1]
+                Wp, Vp, _ = eigh_batched(A.contiguous().reshape(-1), [n] * b, tol)
+                W = Wp.reshape(b, n)
+                V = Vp.reshape(b, n, n)
             else:
                 outs = [fn(A[k], tol) for k in range(A.shape[0])]
                 W = torch.stack([o[0] for o in outs])

@@ -70,41 +70,42 @@ def test_eigh_argument_validation(lib, pj, fn):
     for bad in (dict(block=48), dict(threads=100), dict(threads=768), dict(max_sweeps=-1), dict(c32=-1.0),
                 dict(ns_iters=-2), dict(inner_sweeps=-1), dict(small_max_n=500),
                 dict(serial_v=3), dict(serial_v=-1), dict(schedule=2), dict(tune=2),
-                dict(tune=-1)):
+                dict(tune=-1), dict(gemm_slots=-1), dict(pair_v_split=-2)):
         assert _eigh(lib, fn, FAKE, 4, 4, FAKE, FAKE, 4, 0.0, pj.make_opts(**bad)) == -8, bad
     # n = 0 is a no-op that touches nothing
     assert _eigh(lib, fn, None, 0, 1, None, None, 1, 0.0) == 0
 
 
 def test_batched_argument_validation(lib):
+    f = lib.jacobi_eigh_batched
     n = (ctypes.c_int64 * 3)(4, 0, 5)
-    assert lib.jacobi_eigh_batched(FAKE, n, 3, FAKE, FAKE, 0.0, 0, None, None, 0, None,
-                                   None) == -2
+    assert f(FAKE, n, None, 3, FAKE, None, FAKE, 0.0, 0, None, None, 0, None, None) == -2
     n = (ctypes.c_int64 * 2)(4, 129)
-    assert lib.jacobi_eigh_batched(FAKE, n, 2, FAKE, FAKE, 0.0, 0, None, None, 0, None,
-                                   None) == -2
+    assert f(FAKE, n, None, 2, FAKE, None, FAKE, 0.0, 0, None, None, 0, None, None) == -2
     n = (ctypes.c_int64 * 2)(4, 5)
-    assert lib.jacobi_eigh_batched(FAKE, n, -1, FAKE, FAKE, 0.0, 0, None, None, 0, None,
-                                   None) == -3
-    assert lib.jacobi_eigh_batched(None, n, 2, FAKE, FAKE, 0.0, 0, None, None, 0, None,
-                                   None) == -1
-    assert lib.jacobi_eigh_batched(FAKE, n, 2, FAKE, FAKE, float("nan"), 0, None, None, 0,
-                                   None, None) == -6
-    assert lib.jacobi_eigh_batched(FAKE, n, 2, FAKE, FAKE, 0.0, 1, None, None, 0, None,
-                                   None) == -7
-    assert lib.jacobi_eigh_batched(None, n, 0, None, None, 0.0, 0, None, None, 0, None,
-                                   None) == 0
+    bad_off = (ctypes.c_int64 * 2)(0, -1)
+    assert f(FAKE, n, bad_off, 2, FAKE, None, FAKE, 0.0, 0, None, None, 0, None, None) == -3
+    assert f(FAKE, n, None, -1, FAKE, None, FAKE, 0.0, 0, None, None, 0, None, None) == -4
+    assert f(None, n, None, 2, FAKE, None, FAKE, 0.0, 0, None, None, 0, None, None) == -1
+    assert f(FAKE, n, None, 2, None, None, FAKE, 0.0, 0, None, None, 0, None, None) == -5
+    assert f(FAKE, n, None, 2, FAKE, bad_off, FAKE, 0.0, 0, None, None, 0, None, None) == -6
+    assert f(FAKE, n, None, 2, FAKE, None, None, 0.0, 0, None, None, 0, None, None) == -7
+    assert f(FAKE, n, None, 2, FAKE, None, FAKE, float("nan"), 0, None, None, 0, None,
+             None) == -8
+    assert f(FAKE, n, None, 2, FAKE, None, FAKE, 0.0, 1, None, None, 0, None, None) == -9
+    assert f(None, n, None, 0, None, None, None, 0.0, 0, None, None, 0, None, None) == 0
 
 
 def test_backward_argument_validation(lib):
     f = lib.jacobi_eigh_backward
-    assert f(FAKE, FAKE, None, None, -1, 1, FAKE, 0.0, None, 0, None) == -5
-    assert f(FAKE, FAKE, None, None, 4, -1, FAKE, 0.0, None, 0, None) == -6
-    assert f(None, FAKE, None, None, 4, 1, FAKE, 0.0, None, 0, None) == -1
-    assert f(FAKE, None, None, None, 4, 1, FAKE, 0.0, None, 0, None) == -2
-    assert f(FAKE, FAKE, None, None, 4, 1, None, 0.0, None, 0, None) == -7
-    assert f(FAKE, FAKE, None, None, 4, 1, FAKE, -1.0, None, 0, None) == -8
-    assert f(None, None, None, None, 0, 5, None, 0.0, None, 0, None) == 0
+    assert f(FAKE, FAKE, None, None, -1, 1, 1, FAKE, 0.0, None, 0, None) == -5
+    assert f(FAKE, FAKE, None, None, 4, 3, 1, FAKE, 0.0, None, 0, None) == -6
+    assert f(FAKE, FAKE, None, None, 4, 4, -1, FAKE, 0.0, None, 0, None) == -7
+    assert f(None, FAKE, None, None, 4, 4, 1, FAKE, 0.0, None, 0, None) == -1
+    assert f(FAKE, None, None, None, 4, 4, 1, FAKE, 0.0, None, 0, None) == -2
+    assert f(FAKE, FAKE, None, None, 4, 4, 1, None, 0.0, None, 0, None) == -8
+    assert f(FAKE, FAKE, None, None, 4, 4, 1, FAKE, -1.0, None, 0, None) == -9
+    assert f(None, None, None, None, 0, 1, 5, None, 0.0, None, 0, None) == 0
 
 
 def test_workspace_query(pj):

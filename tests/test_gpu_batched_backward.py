@@ -291,3 +291,41 @@ def test_autograd_central_fd(pj):
         E = 0.5 * (E + E.T)
         fd = (f(A + h * E) - f(A - h * E)) / (2 * h)
         assert (G * E).sum() == pytest.approx(fd, rel=1e-5, abs=1e-7)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_autograd_central_fd_n256(pj, mixed):
+    """The differentiation workload's order (n = 256, gapped spectrum, loss
+    sum w_i lam_i + <C, V>): here the forward runs on the block path (pair
+    solves, MFMA updates, Rayleigh-quotient eigenvalues for plain FP64), so
+    the adjoint is checked against central differences (h = 1e-6) of that
+    forward along random symmetric directions, not only against the oracle's
+    adjoint formula on the forward's own output."""
+    mats, lams, ws, Cs = wl.gapped_batch(batch=2, n=256, seed=5)
+    A, w0, C0 = mats[1], ws[1], Cs[1]
+    n = A.shape[0]
+    w = torch.tensor(w0, device="cuda")
+    C = torch.tensor(C0, device="cuda")
+    At = torch.tensor(A, device="cuda", requires_grad=True)
+    print(f"  -> eigh_autograd n={n} mixed={mixed}", flush=True)
+    W, V = pj.eigh_autograd(At, mixed=mixed, tol=1e-300)
+    loss = (w * W).sum() + (C * V).sum()
+    loss.backward()
+    G = At.grad.cpu().numpy()
+    fn = pj.eigh_mixed if mixed else pj.eigh
+
+    def f(M):
+        W, V = fn(torch.tensor(M, device="cuda"), tol=1e-300)
+        return float((w * W).sum() + (C * V).sum())
+
+    h = 1e-6
+    g = wl.rng(61)
+    for k in range(3):
+        E = g.standard_normal((n, n))
+        E = 0.5 * (E + E.T)
+        E /= np.linalg.norm(E)
+        fd = (f(A + h * E) - f(A - h * E)) / (2 * h)
+        an = float((G * E).sum())
+        print(f"  direction {k}: adjoint {an:.10e} central FD {fd:.10e} "
+              f"rel {abs(an - fd) / max(abs(fd), 1e-300):.2e}", flush=True)
+        assert an == pytest.approx(fd, rel=1e-5, abs=1e-6)

@@ -282,7 +282,7 @@ def test_geo1024_vs_oracle_fixture(pj, fn):
     import os
     A, lam = wl.geo_spectrum(1024, 2)
     gold = os.path.join(os.path.dirname(__file__), "golden", "oracle_geo1024.txt")
-    Wo = np.loadtxt(gold)
+    Wo = np.loadtxt(gold, ndmin=2)[:, 0]
     W, V, info = run(pj, fn, A)
     assert info["status"] == 0
     n = A.shape[0]

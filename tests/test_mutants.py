@@ -56,6 +56,18 @@ MUTANTS = [
     ("adjoint_vtdv", "acc += V[IDX(k, i, n)] * dV[IDX(k, j, n)];",
      "acc += V[IDX(i, k, n)] * dV[IDX(k, j, n)];",
      ["test_backward_central_fd"]),
+    ("rows_skip_last", "for (int64_t q = p + 1; q < n; ++q) {\n            double apq = A[IDX(p, q, n)], app",
+     "for (int64_t q = p + 1; q < n - 1; ++q) {\n            double apq = A[IDX(p, q, n)], app",
+     ["test_jacobi_rows_is_one_sweep"]),
+    ("rows_no_v", "orc_rotate(n, A, V, p, q, c, s);\n                ++rotations;\n            }\n        }\n    return rotations;",
+     "orc_rotate(n, A, NULL, p, q, c, s);\n                ++rotations;\n            }\n        }\n    return rotations;",
+     ["test_jacobi_rows_is_one_sweep"]),
+    ("rayleigh_no_norm", "long double q = vv > 0.0L ? vy / vv : 0.0L;",
+     "long double q = vy;", ["test_rayleigh_quadratic_and_scale_free"]),
+    ("rayleigh_transposed", "acc += (long double)A[IDX(i, j, n)] * v[j];",
+     "acc += (long double)A[IDX(j, i, n)] * v[i];", ["test_rayleigh_exact_eigenvectors"]),
+    ("rayleigh_res_unscaled", "res[k] = vv > 0.0L ? (double)sqrtl(rr / vv) : 0.0;",
+     "res[k] = (double)sqrtl(rr);", ["test_rayleigh_quadratic_and_scale_free"]),
 ]
 
 

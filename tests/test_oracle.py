@@ -396,3 +396,87 @@ def test_backward_degenerate_status(orc):
     dA, st = orc.eigh_backward(W, V, dV=dV, gap_tol=1e-12)
     assert st == 4
     assert np.isfinite(dA).all()
+
+
+# ------------------------------------------------- one-sweep sample (timing)
+@pytest.mark.parametrize("n,seed", [(9, 31), (40, 32)])
+def test_jacobi_rows_is_one_sweep(orc, n, seed):
+    """orc_jacobi_rows over every pivot row [0, n-1) is one cyclic-by-row
+    sweep of Algorithm 4 without its end-of-sweep symmetrisation: after
+    (A + A^T)/2 it equals, bit for bit, the oracle's first sweep (same
+    rotations, same order), and V matches bit for bit.  A split into two row
+    ranges gives the same bits (a bounded sample is a prefix of a sweep)."""
+    A = wl.random_symmetric(n, seed)
+    A1, V1, sweeps, _, _, rot1 = orc.jacobi_cyclic(A, 0.0, max_sweeps=1)
+    assert sweeps == 1
+    A2 = np.ascontiguousarray(A.copy())
+    V2 = np.eye(n)
+    rot2 = orc.jacobi_rows(A2, V2, 0, n - 1)
+    A3 = np.ascontiguousarray(A.copy())
+    V3 = np.eye(n)
+    rot3 = orc.jacobi_rows(A3, V3, 0, n // 2) + orc.jacobi_rows(A3, V3, n // 2, n - 1)
+    assert rot2 == rot1 == rot3 == n * (n - 1) // 2
+    sym = 0.5 * (A2 + A2.T)
+    assert np.array_equal(sym, A1)
+    assert np.array_equal(V2, V1)
+    assert np.array_equal(A3, A2) and np.array_equal(V3, V2)
+
+
+# --------------------------------------------------- Rayleigh quotient check
+def test_rayleigh_exact_eigenvectors(orc):
+    """For an eigenvector of a diagonal matrix the quotient is the diagonal
+    entry exactly and the residual is zero; for A = Q diag(lam) Q^T with a
+    Haar Q the quotients of Q's columns are lam to rounding."""
+    d = np.array([3.0, -1.5, 0.25, 7.0, 0.0])
+    rq, res = orc.rayleigh(np.diag(d), np.eye(5))
+    assert np.array_equal(rq, d) and np.array_equal(res, np.zeros(5))
+    g = wl.rng(41)
+    Q = wl.haar(24, g)
+    lam = np.linspace(-2.0, 3.0, 24)
+    A = wl.from_spectrum(lam, Q)
+    rq, res = orc.rayleigh(A, Q)
+    assert np.abs(rq - lam).max() <= 24 * U_D * 3.0
+    assert res.max() <= 24 * U_D * 3.0
+
+
+def test_rayleigh_quadratic_and_scale_free(orc):
+    """The quotient of a perturbed eigenvector v + e w (w orthogonal to v)
+    is lambda + e^2 (w^T A w - lambda) / (1 + e^2) exactly (a quadratic
+    error, the property that makes it a sharp eigenvalue check), it does not
+    change when the vector is scaled, and the residual of the perturbed
+    vector is e ||(A - rq) w|| / sqrt(1 + e^2) to first order."""
+    g = wl.rng(42)
+    n = 16
+    Q = wl.haar(n, g)
+    lam = np.arange(1.0, n + 1.0)
+    A = wl.from_spectrum(lam, Q)
+    v, w = Q[:, 3], Q[:, 9]
+    for e in (1e-2, 1e-4):
+        x = v + e * w
+        V = np.zeros((n, n))
+        V[:, 0] = x
+        V[:, 1] = 3.0 * x
+        V[:, 2] = v
+        rq, res = orc.rayleigh(A, V)
+        expect = (lam[3] + e * e * lam[9]) / (1.0 + e * e)
+        assert rq[0] == pytest.approx(expect, abs=1e-13)
+        assert rq[1] == pytest.approx(rq[0], abs=1e-14)
+        assert abs(rq[0] - lam[3]) == pytest.approx(e * e * (lam[9] - lam[3]), rel=1e-3)
+        assert res[0] == pytest.approx(e * (lam[9] - lam[3]) / math.sqrt(1 + e * e), rel=1e-3)
+        assert res[1] == pytest.approx(res[0], rel=1e-12)
+        assert rq[2] == pytest.approx(lam[3], abs=1e-13)
+
+
+def test_rayleigh_vs_library(orc):
+    """Random symmetric A and random (non-normalized) vectors: the quotients
+    and residuals equal the numpy evaluation of the same formulas."""
+    g = wl.rng(43)
+    n = 33
+    A = wl.random_symmetric(n, 44)
+    V = g.standard_normal((n, n))
+    rq, res = orc.rayleigh(A, V)
+    AV = A @ V
+    q = np.einsum("ij,ij->j", V, AV) / np.einsum("ij,ij->j", V, V)
+    r = np.linalg.norm(AV - V * q, axis=0) / np.linalg.norm(V, axis=0)
+    assert np.allclose(rq, q, rtol=0, atol=1e-12 * np.abs(q).max())
+    assert np.allclose(res, r, rtol=1e-10, atol=0)
