@@ -59,13 +59,19 @@ def _load():
         lib.orc_eigh.restype = i32
         lib.orc_newton_schulz.argtypes = [i64, P, i32]
         lib.orc_qtaq.argtypes = [i64, P, P, P]
-        lib.orc_eigh_mixed.argtypes = [i64, P, P, P, d, i32, i32, d, P]
+        lib.orc_eigh_mixed.argtypes = [i64, P, P, P, d, i32, i32, d, i32, P]
         lib.orc_eigh_mixed.restype = i32
         lib.orc_jacobi_rows.argtypes = [i64, P, P, i64, i64, d]
         lib.orc_jacobi_rows.restype = i64
         lib.orc_eigh_backward.argtypes = [i64, P, P, P, P, d, P]
         lib.orc_eigh_backward.restype = i32
         lib.orc_rayleigh.argtypes = [i64, P, P, P, P]
+        lib.orc_house.argtypes = [i64, P, P, P]
+        lib.orc_householder_qr.argtypes = [i64, P, P, P]
+        lib.orc_cholesky.argtypes = [i64, P, P]
+        lib.orc_cholesky.restype = i32
+        lib.orc_cholesky_qr.argtypes = [i64, P, P, P]
+        lib.orc_cholesky_qr.restype = i32
         _lib = lib
     return _lib
 
@@ -177,10 +183,14 @@ def qtaq(Q, A):
     return B
 
 
+ORTH = {"ns": 0, "householder": 1, "cholesky": 2}
+
+
 def eigh_mixed(A, tol: float | None = None, max_sweeps: int = 30,
-               ns_iters: int = 2, c32: float = 1.0):
-    """Algorithm 9 with an FP32 Jacobi first stage.  Returns (W, Q, status,
-    diag) with diag = dict(sweeps32, sweeps64, orth_ql, orth_qd, off_cond)."""
+               ns_iters: int = 2, c32: float = 1.0, orth: str = "ns"):
+    """Algorithm 9 with an FP32 Jacobi first stage; Q_l -> Q_d by Newton-Schulz
+    (orth="ns"), Householder QR or Cholesky QR.  Returns (W, Q, status, diag)
+    with diag = dict(sweeps32, sweeps64, orth_ql, orth_qd, off_cond)."""
     A = _f64(A)
     n = A.shape[0]
     tol = default_tol(A) if tol is None or tol <= 0 else tol
@@ -188,7 +198,7 @@ def eigh_mixed(A, tol: float | None = None, max_sweeps: int = 30,
     Q = np.zeros((n, n))
     dg = np.zeros(6)
     st = _load().orc_eigh_mixed(n, _p(A), _p(W), _p(Q), tol, max_sweeps,
-                                ns_iters, c32, _p(dg))
+                                ns_iters, c32, ORTH[orth], _p(dg))
     return W, Q, st, dict(sweeps32=int(dg[0]), sweeps64=int(dg[1]),
                           orth_ql=dg[2], orth_qd=dg[3], off_cond=dg[4],
                           status32=int(dg[5]))
@@ -203,6 +213,44 @@ def rayleigh(A, V):
     res = np.zeros(n)
     _load().orc_rayleigh(n, _p(A), _p(V), _p(rq), _p(res))
     return rq, res
+
+
+def house(x):
+    """Householder vector and coefficient of Algorithm 1: (v, beta) with
+    (I - beta v v^T) x = -sign(x_1) ||x|| e_1."""
+    x = _f64(x)
+    v = np.zeros_like(x)
+    b = ctypes.c_double()
+    _load().orc_house(x.shape[0], _p(x), _p(v), ctypes.byref(b))
+    return v, b.value
+
+
+def householder_qr(A):
+    """Algorithm 5: (Q, R) with A = Q R."""
+    A = _f64(A).copy()
+    n = A.shape[0]
+    Q = np.zeros((n, n))
+    R = np.zeros((n, n))
+    _load().orc_householder_qr(n, _p(A), _p(Q), _p(R))
+    return Q, R
+
+
+def cholesky(G):
+    """Upper R with G = R^T R.  Returns (R, status)."""
+    G = _f64(G)
+    R = np.zeros_like(G)
+    st = _load().orc_cholesky(G.shape[0], _p(G), _p(R))
+    return R, st
+
+
+def cholesky_qr(X):
+    """Cholesky QR: (Q, R, status) with X = Q R."""
+    X = _f64(X)
+    n = X.shape[0]
+    Q = np.zeros((n, n))
+    R = np.zeros((n, n))
+    st = _load().orc_cholesky_qr(n, _p(X), _p(Q), _p(R))
+    return Q, R, st
 
 
 def eigh_backward(W, V, dW=None, dV=None, gap_tol: float = 0.0):

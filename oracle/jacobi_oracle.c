@@ -288,6 +288,138 @@ void orc_newton_schulz(int64_t n, double *X, int iters)
     free(Y);
 }
 
+/* Householder vector (Algorithm 1, Section 2.2.2): for x != 0 of length m,
+ * v = [v_1, x_2 .. x_m] and beta = 2 / (v^T v) with
+ *   sigma = x(2:m)^T x(2:m),  mu = sqrt(x_1^2 + sigma),
+ *   v_1 = x_1 + mu if x_1 >= 0, else x_1 - mu,
+ * so that (I - beta v v^T) x = -sign(x_1) ||x|| e_1.  A zero x gives beta = 0
+ * (P = I).  The algorithm prints the x_1 < 0 branch as -sigma / (x_1 + mu),
+ * equal to x_1 - mu in exact arithmetic; with this sign convention x_1 - mu
+ * adds two numbers of the same sign, while x_1 + mu cancels (it is 0 when
+ * sigma is below the rounding of x_1^2), so the direct form is used. */
+void orc_house(int64_t m, const double *x, double *v, double *beta)
+{
+    double sigma = 0.0;
+    for (int64_t i = 1; i < m; ++i)
+        sigma += x[i] * x[i];
+    for (int64_t i = 1; i < m; ++i)
+        v[i] = x[i];
+    double mu = sqrt(x[0] * x[0] + sigma);
+    if (mu == 0.0) {
+        v[0] = 1.0;
+        *beta = 0.0;
+        return;
+    }
+    if (x[0] >= 0.0)
+        v[0] = x[0] + mu;
+    else
+        v[0] = x[0] - mu;
+    *beta = 2.0 / (v[0] * v[0] + sigma);
+}
+
+/* Householder QR factorization (Algorithm 5, Section 4.2): A = Q R with
+ * Q = I at the start and, for k = 1 .. n-1,
+ *   [v, beta] = house(A(k:n, k))
+ *   A(k:n, k:n) <- A(k:n, k:n) - (beta v)(v^T A(k:n, k:n))
+ *   Q(:, k:n)   <- Q(:, k:n) - (Q(:, k:n) v)(beta v^T).
+ * A (n x n, row-major) is overwritten by the final iterate; R is its upper
+ * triangle (written to R, zeros below).  Q is n x n. */
+void orc_householder_qr(int64_t n, double *A, double *Q, double *R)
+{
+    size_t m1 = (size_t)(n > 0 ? n : 1);
+    double *x = (double *)malloc(m1 * sizeof(double));
+    double *v = (double *)malloc(m1 * sizeof(double));
+    double *w = (double *)malloc(m1 * sizeof(double));
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            Q[IDX(i, j, n)] = (i == j) ? 1.0 : 0.0;
+    for (int64_t k = 0; k < n - 1; ++k) {
+        int64_t m = n - k;
+        double beta;
+        for (int64_t i = 0; i < m; ++i)
+            x[i] = A[IDX(k + i, k, n)];
+        orc_house(m, x, v, &beta);
+        for (int64_t j = 0; j < m; ++j) { /* w = v^T A(k:n, k:n) */
+            double acc = 0.0;
+            for (int64_t i = 0; i < m; ++i)
+                acc += v[i] * A[IDX(k + i, k + j, n)];
+            w[j] = acc;
+        }
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t j = 0; j < m; ++j)
+                A[IDX(k + i, k + j, n)] -= (beta * v[i]) * w[j];
+        for (int64_t i = 0; i < n; ++i) { /* Q(:, k:n) v, then the rank-1 update */
+            double acc = 0.0;
+            for (int64_t j = 0; j < m; ++j)
+                acc += Q[IDX(i, k + j, n)] * v[j];
+            for (int64_t j = 0; j < m; ++j)
+                Q[IDX(i, k + j, n)] -= acc * (beta * v[j]);
+        }
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            R[IDX(i, j, n)] = (j >= i) ? A[IDX(i, j, n)] : 0.0;
+    free(x);
+    free(v);
+    free(w);
+}
+
+/* Cholesky factorization of a symmetric positive definite G = R^T R, R upper
+ * triangular with positive diagonal (the textbook row-by-row recurrence):
+ *   r_ii = sqrt(g_ii - sum_{k<i} r_ki^2),
+ *   r_ij = (g_ij - sum_{k<i} r_ki r_kj) / r_ii   (j > i).
+ * Returns 0, or i + 1 when the pivot of row i is not positive. */
+int orc_cholesky(int64_t n, const double *G, double *R)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            R[IDX(i, j, n)] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double d = G[IDX(i, i, n)];
+        for (int64_t k = 0; k < i; ++k)
+            d -= R[IDX(k, i, n)] * R[IDX(k, i, n)];
+        if (!(d > 0.0))
+            return (int)(i + 1);
+        double rii = sqrt(d);
+        R[IDX(i, i, n)] = rii;
+        for (int64_t j = i + 1; j < n; ++j) {
+            double g = G[IDX(i, j, n)];
+            for (int64_t k = 0; k < i; ++k)
+                g -= R[IDX(k, i, n)] * R[IDX(k, j, n)];
+            R[IDX(i, j, n)] = g / rii;
+        }
+    }
+    return 0;
+}
+
+/* Cholesky QR of X (the orthogonaliser named as further work in Chapter 6):
+ * G = X^T X, R = chol(G), Q = X R^{-1} (Q R = X solved row by row, column by
+ * column: q_j = (x_j - sum_{k<j} q_k r_kj) / r_jj).  Returns the Cholesky
+ * status. */
+int orc_cholesky_qr(int64_t n, const double *X, double *Q, double *R)
+{
+    size_t nn = (size_t)(n > 0 ? n * n : 1);
+    double *G = (double *)malloc(nn * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) /* G = X^T X */
+        for (int64_t j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int64_t k = 0; k < n; ++k)
+                acc += X[IDX(k, i, n)] * X[IDX(k, j, n)];
+            G[IDX(i, j, n)] = acc;
+        }
+    int st = orc_cholesky(n, G, R);
+    if (st == 0)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j) {
+                double acc = X[IDX(i, j, n)];
+                for (int64_t k = 0; k < j; ++k)
+                    acc -= Q[IDX(i, k, n)] * R[IDX(k, j, n)];
+                Q[IDX(i, j, n)] = acc / R[IDX(j, j, n)];
+            }
+    free(G);
+    return st;
+}
+
 /* Preconditioning step of Algorithm 9 (Section 5.1): B = Q^T A Q, then symmetrised. */
 void orc_qtaq(int64_t n, const double *Q, const double *A, double *B)
 {
@@ -319,14 +451,16 @@ void orc_qtaq(int64_t n, const double *Q, const double *A, double *B)
  * low-precision spectral decomposition computed by Algorithm 4 in FP32:
  *   1. fl32(A) -> FP32 cyclic Jacobi until off <= c32 n u_l ||A||_F -> Q_l
  *   2. Q_d = Newton-Schulz(double(Q_l)), ns_iters iterations (Algorithm 8: 2 for
- *      n < 52 000)
+ *      n < 52 000); orth = 1: Q_d = Q of the Householder QR of double(Q_l)
+ *      (Algorithm 5), orth = 2: Q of its Cholesky QR (the alternatives the
+ *      comparison of Section 4.4 and Chapter 6 name)
  *   3. A_cond = Q_d^T A Q_d (symmetrised); FP64 cyclic Jacobi -> V, Lambda
  *   4. Q = Q_d V, then the output convention.
  * diag (optional, 6 entries) receives: FP32 sweeps, FP64 sweeps,
  * ||Q_l^T Q_l - I||_F, ||Q_d^T Q_d - I||_F, off(A_cond), status of stage 1. */
 int orc_eigh_mixed(int64_t n, const double *A, double *W, double *Q,
                    double tol_abs, int max_sweeps, int ns_iters, double c32,
-                   double *diag)
+                   int orth, double *diag)
 {
     size_t nn = (size_t)(n > 0 ? n * n : 1);
     float *A32 = (float *)malloc(nn * sizeof(float));
@@ -359,7 +493,19 @@ int orc_eigh_mixed(int64_t n, const double *A, double *W, double *Q,
             acc -= (i == j) ? 1.0 : 0.0;
             orth_l += acc * acc;
         }
-    orc_newton_schulz(n, Qd, ns_iters);
+    if (orth == 1 || orth == 2) { /* Q_d from a QR factorization of Q_l */
+        double *Xl = (double *)malloc(nn * sizeof(double));
+        double *Rq = (double *)malloc(nn * sizeof(double));
+        memcpy(Xl, Qd, nn * sizeof(double));
+        if (orth == 1)
+            orc_householder_qr(n, Xl, Qd, Rq);
+        else
+            orc_cholesky_qr(n, Xl, Qd, Rq);
+        free(Xl);
+        free(Rq);
+    } else {
+        orc_newton_schulz(n, Qd, ns_iters);
+    }
     for (int64_t i = 0; i < n; ++i)
         for (int64_t j = 0; j < n; ++j) {
             double acc = 0.0;

@@ -195,8 +195,14 @@ def test_repeated_eigenvalues_block_path(pj, fn):
     W, V, info = solve(pj, fn, A, small_max_n=-1)
     assert info["status"] == 0
     assert np.abs(W - lam).max() <= 1e-13 * 2
-    Wo, *_ = oracle.eigh(A)
-    assert np.abs(W - Wo).max() <= 1e-13 * 2
+    # the oracle's eigenvalues as Rayleigh quotients of its eigenvectors: its
+    # diagonal readout after the many sweeps this input takes drifts by about
+    # 1.4e-13 ||A||_2 here
+    Wo, Vo, *_ = oracle.eigh(A)
+    rq, res = oracle.rayleigh(A, Vo)
+    print(f"  oracle: |w - lam| {np.abs(Wo - lam).max():.2e} |rq - lam| "
+          f"{np.abs(rq - lam).max():.2e}", flush=True)
+    assert np.abs(W - rq).max() <= 1e-13 * 2
     bars(A, W, V, f"repeated {fn}")
 
 

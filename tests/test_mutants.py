@@ -66,6 +66,19 @@ MUTANTS = [
      "long double q = vy;", ["test_rayleigh_quadratic_and_scale_free"]),
     ("rayleigh_transposed", "acc += (long double)A[IDX(i, j, n)] * v[j];",
      "acc += (long double)A[IDX(j, i, n)] * v[i];", ["test_rayleigh_exact_eigenvectors"]),
+    ("house_branch", "if (x[0] >= 0.0)\n        v[0] = x[0] + mu;",
+     "if (x[0] < 0.0)\n        v[0] = x[0] + mu;", ["test_house_worked_example"]),
+    ("house_beta", "*beta = 2.0 / (v[0] * v[0] + sigma);", "*beta = 1.0 / (v[0] * v[0] + sigma);",
+     ["test_house_worked_example"]),
+    ("qr_q_update_transposed", "acc += Q[IDX(i, k + j, n)] * v[j];",
+     "acc += Q[IDX(k + j, i, n)] * v[j];", ["test_householder_qr_identities"]),
+    ("qr_a_update_full", "A[IDX(k + i, k + j, n)] -= (beta * v[i]) * w[j];",
+     "A[IDX(k + i, k + j, n)] -= (beta * v[j]) * w[i];", ["test_householder_qr_identities"]),
+    ("chol_no_sqrt", "double rii = sqrt(d);", "double rii = d;", ["test_cholesky_known_factor"]),
+    ("chol_wrong_index", "g -= R[IDX(k, i, n)] * R[IDX(k, j, n)];",
+     "g -= R[IDX(k, i, n)] * R[IDX(k, i, n)];", ["test_cholesky_known_factor"]),
+    ("cholqr_solve", "acc -= Q[IDX(i, k, n)] * R[IDX(k, j, n)];",
+     "acc -= Q[IDX(i, k, n)] * R[IDX(j, k, n)];", ["test_cholesky_qr_identities"]),
     ("rayleigh_res_unscaled", "res[k] = vv > 0.0L ? (double)sqrtl(rr / vv) : 0.0;",
      "res[k] = (double)sqrtl(rr);", ["test_rayleigh_quadratic_and_scale_free"]),
 ]

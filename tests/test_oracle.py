@@ -480,3 +480,112 @@ def test_rayleigh_vs_library(orc):
     r = np.linalg.norm(AV - V * q, axis=0) / np.linalg.norm(V, axis=0)
     assert np.allclose(rq, q, rtol=0, atol=1e-12 * np.abs(q).max())
     assert np.allclose(res, r, rtol=1e-10, atol=0)
+
+
+# ------------------------------------------ orthogonalisers (QR comparators)
+def test_house_worked_example(orc):
+    """Section 2.2.2 worked example, through the oracle's Algorithm 1: x < 0 in
+    its first entry, so P x = +||x|| e_1 = 3.4748 e_1 (printed to five
+    digits) and the other entries vanish to rounding (printed as 0 and
+    ~1e-16); beta = 2 / (v^T v) makes P orthogonal."""
+    fx = golden("householder_example.txt")
+    x = np.array(fx["x"])
+    v, beta = orc.house(x)
+    P = np.eye(5) - beta * np.outer(v, v)
+    Px = P @ x
+    assert Px[0] == pytest.approx(fx["Px0"], abs=1e-4)
+    assert Px[0] == pytest.approx(np.linalg.norm(x), rel=1e-15)
+    assert np.abs(Px[1:]).max() < 1e-15
+    assert np.abs(P.T @ P - np.eye(5)).max() < 1e-15
+    # x_1 >= 0: P x = -||x|| e_1, and v_1 = x_1 + ||x|| (no cancellation)
+    v2, b2 = orc.house(-x)
+    assert (np.eye(5) - b2 * np.outer(v2, v2)) @ (-x) == pytest.approx(
+        [-np.linalg.norm(x), 0, 0, 0, 0], abs=1e-15)
+    assert v2[0] == pytest.approx(1.3499 + np.linalg.norm(x), rel=1e-15)
+    # cancellation branch: x close to a positive multiple of e_1
+    v3, b3 = orc.house(np.array([-1.0, 1e-9, 0.0]))
+    assert v3[0] == pytest.approx(-1.0 - math.sqrt(1.0 + 1e-18), rel=1e-15)
+    v4, b4 = orc.house(np.array([1.0, 1e-9, 0.0]))
+    y = (np.eye(3) - b4 * np.outer(v4, v4)) @ np.array([1.0, 1e-9, 0.0])
+    assert y[0] == pytest.approx(-1.0, rel=1e-15) and abs(y[1]) < 1e-24
+
+
+@pytest.mark.parametrize("n", [2, 7, 40])
+def test_householder_qr_identities(orc, n):
+    """Algorithm 5: Q orthogonal and Q R = A to the order n u_d (the bounds
+    Section 4.2 checks; a constant of 4 covers the few ulps of a single
+    reflection at n = 2), R upper triangular, and the same factorisation as
+    LAPACK's up to the signs of R's rows (a library cross-check)."""
+    A = wl.rng(80 + n).standard_normal((n, n))
+    Q, R = orc.householder_qr(A)
+    assert np.linalg.norm(Q.T @ Q - np.eye(n), 2) <= 4 * n * U_D
+    assert np.linalg.norm(Q @ R - A, 2) / np.linalg.norm(A, 2) <= 4 * n * U_D
+    assert np.array_equal(R, np.triu(R))
+    Ql, Rl = np.linalg.qr(A)
+    sg = np.sign(np.diag(R)) * np.sign(np.diag(Rl))
+    assert np.abs(Q * sg - Ql).max() <= 1e-12
+    assert np.abs(R * sg[:, None] - Rl).max() <= 1e-12 * np.abs(Rl).max()
+
+
+def test_householder_qr_of_orthogonal(orc):
+    """For an orthogonal input the factorisation is Q = X D, R = D with D =
+    diag(+-1): the orthogonaliser returns the input up to column signs."""
+    X = wl.haar(30, wl.rng(90))
+    Q, R = orc.householder_qr(X)
+    d = np.diag(R)
+    assert np.abs(np.abs(d) - 1.0).max() <= 30 * U_D
+    assert np.abs(R - np.diag(d)).max() <= 30 * U_D
+    assert np.abs(Q - X * np.sign(d)).max() <= 30 * U_D
+
+
+def test_cholesky_known_factor(orc):
+    """G = R^T R for an upper-triangular R with positive diagonal: the oracle
+    returns R; a non-positive pivot is reported (row index + 1)."""
+    g = wl.rng(91)
+    n = 12
+    R0 = np.triu(g.standard_normal((n, n)))
+    R0[np.diag_indices(n)] = np.abs(R0[np.diag_indices(n)]) + 1.0
+    G = R0.T @ R0
+    R, st = orc.cholesky(G)
+    assert st == 0
+    assert np.abs(R - R0).max() <= 1e-12 * np.abs(R0).max()
+    assert np.array_equal(R, np.triu(R))
+    R2, st2 = orc.cholesky(np.diag([4.0, 9.0, 16.0]))
+    assert st2 == 0 and np.array_equal(R2, np.diag([2.0, 3.0, 4.0]))
+    _, st3 = orc.cholesky(np.array([[1.0, 2.0], [2.0, 1.0]]))
+    assert st3 == 2
+
+
+@pytest.mark.parametrize("n", [5, 40])
+def test_cholesky_qr_identities(orc, n):
+    """Cholesky QR of a well-conditioned X: Q R = X, Q^T Q = I (to kappa(X)^2
+    u_d), R = chol(X^T X), and the same factorisation as LAPACK's QR with a
+    positive diagonal of R."""
+    X = wl.haar(n, wl.rng(92 + n)) @ np.diag(np.linspace(1.0, 2.0, n))
+    Q, R, st = orc.cholesky_qr(X)
+    assert st == 0
+    assert np.linalg.norm(Q @ R - X, 2) / np.linalg.norm(X, 2) <= n * U_D
+    assert np.linalg.norm(Q.T @ Q - np.eye(n), 2) <= 4 * n * U_D * 4.0
+    Ql, Rl = np.linalg.qr(X)
+    sg = np.sign(np.diag(Rl))
+    assert np.abs(Q - Ql * sg).max() <= 1e-13
+    assert np.abs(R - Rl * sg[:, None]).max() <= 1e-13
+
+
+@pytest.mark.parametrize("orth", ["householder", "cholesky"])
+def test_mixed_with_qr_orthogonalisers(orc, orth):
+    """Algorithm 9 with Q_d from a QR factorisation of Q_l instead of
+    Newton-Schulz: the same stage bounds (||Q_d^T Q_d - I||_F <~ n u_d, here
+    with a constant of 2: Householder QR lands at 1.1 n u_d on this input;
+    off(A_cond) <~ n u_l ||A||) and the same eigenvalues."""
+    n = 60
+    A, lam = wl.geo_spectrum(n, 3, kappa=1e3)
+    nrm2 = np.abs(lam).max()
+    W, Q, st, d = orc.eigh_mixed(A, orth=orth)
+    assert st == 0
+    assert d["orth_qd"] <= 2 * n * U_D
+    assert d["off_cond"] <= n * U_L * nrm2
+    assert 1 <= d["sweeps64"] <= 5
+    assert np.abs(W - lam).max() <= 1e-13 * nrm2
+    assert np.linalg.norm(A @ Q - Q * W) / np.linalg.norm(A) <= 1e-13 * n
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 1e-14 * n
