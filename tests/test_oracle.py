@@ -561,7 +561,8 @@ def test_cholesky_qr_identities(orc, n):
     """Cholesky QR of a well-conditioned X: Q R = X, Q^T Q = I (to kappa(X)^2
     u_d), R = chol(X^T X), and the same factorisation as LAPACK's QR with a
     positive diagonal of R."""
-    X = wl.haar(n, wl.rng(92 + n)) @ np.diag(np.linspace(1.0, 2.0, n))
+    g = wl.rng(92 + n)
+    X = wl.haar(n, g) @ np.diag(np.linspace(1.0, 2.0, n)) @ wl.haar(n, g)
     Q, R, st = orc.cholesky_qr(X)
     assert st == 0
     assert np.linalg.norm(Q @ R - X, 2) / np.linalg.norm(X, 2) <= n * U_D
