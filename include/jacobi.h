@@ -233,6 +233,27 @@ int jacobi_eigh_backward(const double *W, const double *V, const double *dW,
                          double *dA, double gap_tol, void *work,
                          size_t work_bytes, void *stream);
 
+/* jacobi_eigh_batched for callers that cannot allocate: code being captured
+ * into a HIP graph, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and status codes as jacobi_eigh_batched, without
+ * work/work_bytes: the call allocates nothing (no hipMalloc/hipFree, no
+ * host heap, no events or streams) and takes its scratch from a fixed
+ * 64 MiB device array that each GPU the library runs on holds until the
+ * process ends.  The descriptor table is built on the device; the launch
+ * configuration is the one the batched autotuner stored for this (device,
+ * n_max, batch size class, workgroup size) if any, else the fixed choice by
+ * n_max (nothing is measured and no graph is used here).  A batch whose
+ * scratch (about 76 bytes per matrix plus the eigenvector scratch of the
+ * resident workgroups, about 32 MiB at n_max = 128) exceeds the array
+ * returns JACOBI_WORKSPACE before anything is launched.  Every call on one
+ * GPU uses that GPU's array and leaves its contents behind (the call clears
+ * what must start at zero); calls that overlap on one GPU race. */
+int jacobi_eigh_batched_noalloc(const double *A, const int64_t *n,
+                                const int64_t *a_off, int64_t batch, double *W,
+                                const int64_t *w_off, double *V, double tol,
+                                int mixed, const jacobi_opts *opts,
+                                void *stream, int32_t *status);
+
 /* Workspace query (LAPACK style).  op: 0 = eigh, 1 = eigh_mixed,
  * 2 = eigh_batched (n_max = largest order, batch = count),
  * 3 = eigh_backward (n_max = n).  Returns bytes; 0 for invalid op. */

@@ -7,6 +7,6 @@ tensors into its C ABI.
 from .jacobi import (  # noqa: F401
     DEGENERATE, DEVICE, NOCONV, NONFINITE, NOTSYM, OK, WORKSPACE,
     Info, JacobiError, Opts, Workspace, declared_functions, device_summary,
-    eigh, eigh_autograd, eigh_backward, eigh_batched, eigh_mixed, make_opts,
+    eigh, eigh_autograd, eigh_backward, eigh_batched, eigh_batched_noalloc, eigh_mixed, make_opts,
     workspace_bytes, EighFn, LIB_PATH,
 )

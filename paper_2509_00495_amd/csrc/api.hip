@@ -303,14 +303,15 @@ size_t small_slots(int64_t n_max, int count, int threads, int pool)
 // (V in the global scratch, which leaves room for more resident workgroups).
 // With a fixed workgroup size (opts.threads) only that size; without tuning,
 // the first candidate is the choice by n_max.
-void small_candidates(int64_t n_max, int count, int req_threads, int tune,
-                      std::vector<SmallCfg> &out)
+constexpr int SMALL_CANDS_MAX = 6;
+int small_candidates_fixed(int64_t n_max, int count, int req_threads, int tune,
+                           SmallCfg (&out)[SMALL_CANDS_MAX])
 {
-    out.clear();
+    int cnt = 0;
     const int lds = dev_info().lds_max;
     const int full = small_pool(n_max, lds);
     if (full == 0)
-        return;
+        return 0;
     const int m = (int)((n_max + 3) & ~3);
     const int s_only = m * (m + 1);
     const int first = small_threads(n_max, req_threads);
@@ -321,12 +322,21 @@ void small_candidates(int64_t n_max, int count, int req_threads, int tune,
             if (t != first)
                 sizes[nsz++] = t;
     for (int k = 0; k < nsz; ++k) {
-        out.push_back({sizes[k], full, (int64_t)small_slots(n_max, count, sizes[k], full)});
+        out[cnt++] = {sizes[k], full, (int64_t)small_slots(n_max, count, sizes[k], full)};
         if (tune == 0 && s_only < full)
-            out.push_back({sizes[k], s_only, (int64_t)small_slots(n_max, count, sizes[k], s_only)});
+            out[cnt++] = {sizes[k], s_only, (int64_t)small_slots(n_max, count, sizes[k], s_only)};
     }
-    if (tune == 1)
-        out.resize(1);
+    if (tune == 1 && cnt > 1)
+        cnt = 1;
+    return cnt;
+}
+
+void small_candidates(int64_t n_max, int count, int req_threads, int tune,
+                      std::vector<SmallCfg> &out)
+{
+    SmallCfg c[SMALL_CANDS_MAX];
+    const int k = small_candidates_fixed(n_max, count, req_threads, tune, c);
+    out.assign(c, c + k);
 }
 
 size_t ws_small(int64_t count, int64_t n_max, int req_threads, int tune)
@@ -1359,6 +1369,239 @@ int jacobi_eigh_backward(const double *W, const double *V, const double *dW, con
     CK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
     return hflag ? JACOBI_DEGENERATE : JACOBI_OK;
+}
+
+// ------------------------------------------------------------------
+// Batched solve without any allocation.  The scratch of the batched path
+// (descriptor table, work queue, per-matrix status, eigenvector scratch of
+// the workgroups whose V does not fit LDS) lives in a fixed device array;
+// the descriptors are built on the device from the caller's orders.  Each
+// GPU holds its own copy of the array for the life of the process; calls on
+// one GPU share it, so calls that overlap on one GPU race.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+}  // extern "C"
+
+namespace {
+
+std::mutex g_na_mu;
+void *g_na_ptr[64] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current (the array's name is only a host-side
+// stand-in).
+int noalloc_scratch(void **out)
+{
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) {
+        g_last_error = hipErrorInvalidDevice;
+        return JACOBI_DEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            g_last_error = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return JACOBI_DEVICE;
+        }
+        g_na_ptr[dev] = p;
+    }
+    *out = g_na_ptr[dev];
+    return 0;
+}
+
+// Descriptor table of a batch built on the device by one workgroup: orders
+// n[i] (1..128), optional offsets aoff / woff (else packed: prefix sums of
+// n_i^2 and n_i in input order), sorted by order, largest first (a counting
+// sort; the order among equal orders is not fixed, which changes no result:
+// each matrix is solved whole by one workgroup).
+__global__ __launch_bounds__(1024) void na_build_desc_kernel(const int64_t *__restrict__ n,
+                                                             const int64_t *__restrict__ aoff,
+                                                             const int64_t *__restrict__ woff,
+                                                             int64_t batch, SmallDesc *desc)
+{
+    __shared__ int hist[130];
+    __shared__ int64_t sa[1024], sw[1024];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 130; i += 1024)
+        hist[i] = 0;
+    __syncthreads();
+    const int64_t chunk = (batch + 1023) / 1024;
+    const int64_t i0 = tid * chunk, i1 = i0 + chunk < batch ? i0 + chunk : batch;
+    int64_t la = 0, lw = 0;
+    for (int64_t i = i0; i < i1; ++i) {
+        const int64_t m = n[i];
+        atomicAdd(&hist[m], 1);
+        la += m * m;
+        lw += m;
+    }
+    sa[tid] = la;
+    sw[tid] = lw;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t a = 0, w = 0;
+        for (int t = 0; t < 1024; ++t) { // exclusive prefix sums of the chunks
+            const int64_t ta = sa[t], tw = sw[t];
+            sa[t] = a;
+            sw[t] = w;
+            a += ta;
+            w += tw;
+        }
+        int pos = 0; // start of each order's run, largest order first
+        for (int m = 128; m >= 1; --m) {
+            const int c = hist[m];
+            hist[m] = pos;
+            pos += c;
+        }
+    }
+    __syncthreads();
+    int64_t a = sa[tid], w = sw[tid];
+    for (int64_t i = i0; i < i1; ++i) {
+        const int m = (int)n[i];
+        const int p = atomicAdd(&hist[m], 1);
+        SmallDesc d;
+        d.a_off = aoff ? aoff[i] : a;
+        d.v_off = d.a_off;
+        d.w_off = woff ? woff[i] : w;
+        d.n = m;
+        d.lda = m;
+        d.ldv = m;
+        d.orig = (int)i;
+        d.info = nullptr;
+        desc[p] = d;
+        a += (int64_t)m * m;
+        w += m;
+    }
+}
+
+// worst = max over the per-matrix status codes
+__global__ __launch_bounds__(256) void na_status_max_kernel(const int32_t *__restrict__ st,
+                                                            int64_t count, int *worst)
+{
+    __shared__ int red[4];
+    int m = 0;
+    for (int64_t i = threadIdx.x; i < count; i += 256)
+        m = st[i] > m ? st[i] : m;
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        const int o = __shfl_xor(m, off, WAVE);
+        m = o > m ? o : m;
+    }
+    if (threadIdx.x % WAVE == 0)
+        red[threadIdx.x / WAVE] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int r = red[0];
+        for (int i = 1; i < 4; ++i)
+            r = red[i] > r ? red[i] : r;
+        *worst = r;
+    }
+}
+
+} // namespace
+
+extern "C" {
+
+int jacobi_eigh_batched_noalloc(const double *A, const int64_t *n, const int64_t *a_off,
+                                int64_t batch, double *W, const int64_t *w_off, double *V,
+                                double tol, int mixed, const jacobi_opts *opts, void *stream,
+                                int32_t *status)
+{
+    if (batch < 0)
+        return -4;
+    if (batch > 0 && !n)
+        return -2;
+    int64_t n_max = 0;
+    for (int64_t i = 0; i < batch; ++i) {
+        if (n[i] < 1 || n[i] > 128)
+            return -2;
+        n_max = std::max(n_max, n[i]);
+        if (a_off && a_off[i] < 0)
+            return -3;
+        if (w_off && w_off[i] < 0)
+            return -6;
+    }
+    if (batch > 0 && !A)
+        return -1;
+    if (batch > 0 && !W)
+        return -5;
+    if (batch > 0 && !V)
+        return -7;
+    if (std::isnan(tol) || std::isinf(tol))
+        return -8;
+    if (mixed != 0)
+        return -9;
+    Opts o;
+    if (resolve_opts(opts, o))
+        return -10;
+    if (batch == 0)
+        return JACOBI_OK;
+    if (batch > (int64_t)1 << 30)
+        return JACOBI_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    // launch configuration: the one the batched autotuner stored for this
+    // (device, n_max, batch size class, workgroup size) if any, else the
+    // fixed choice by n_max; nothing is measured here
+    // (fixed-size candidate lists: no heap allocation on this path)
+    const int cnt_b = (int)std::min<int64_t>(batch, 1 << 30);
+    SmallCfg cands[SMALL_CANDS_MAX], all[SMALL_CANDS_MAX];
+    if (small_candidates_fixed(n_max, cnt_b, o.threads, 1, cands) == 0) {
+        g_last_error = hipErrorInvalidConfiguration;
+        return JACOBI_DEVICE;
+    }
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    SmallCfg cfg = cands[0];
+    {
+        const int na = small_candidates_fixed(n_max, cnt_b, o.threads, 0, all);
+        const int bclass = 64 - __builtin_clzll((unsigned long long)batch);
+        SmallCfg hit{};
+        if (small_tuned(SmallKey{dev, (int)n_max, bclass, o.threads}, hit))
+            for (int k = 0; k < na; ++k)
+                if (all[k].threads == hit.threads && all[k].pool == hit.pool)
+                    cfg = all[k];
+    }
+    void *base = nullptr;
+    if (int e = noalloc_scratch(&base))
+        return e;
+    // layout of the fixed scratch (the Bump rounds every piece to 256 bytes)
+    Bump bp(base);
+    int64_t *n_d = bp.take<int64_t>((size_t)batch);
+    int64_t *ao_d = a_off ? bp.take<int64_t>((size_t)batch) : nullptr;
+    int64_t *wo_d = w_off ? bp.take<int64_t>((size_t)batch) : nullptr;
+    SmallWs w = layout_small(bp, batch, n_max, cfg.slots);
+    int *worst = bp.take<int>(1);
+    if (bp.off > NOALLOC_SCRATCH_BYTES)
+        return JACOBI_WORKSPACE; // the batch needs more than the fixed scratch holds
+    CK(hipMemcpyAsync(n_d, n, (size_t)batch * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    if (ao_d)
+        CK(hipMemcpyAsync(ao_d, a_off, (size_t)batch * sizeof(int64_t), hipMemcpyHostToDevice,
+                          s));
+    if (wo_d)
+        CK(hipMemcpyAsync(wo_d, w_off, (size_t)batch * sizeof(int64_t), hipMemcpyHostToDevice,
+                          s));
+    hipLaunchKernelGGL(na_build_desc_kernel, dim3(1), dim3(1024), 0, s, n_d, ao_d, wo_d, batch,
+                       w.desc);
+    CK(hipGetLastError());
+    // the queue and the status start at zero on every call (fill kernels)
+    CK(launch_fill_i32(w.queue, 1, 0, s));
+    CK(launch_fill_i32(w.status, batch, 0, s));
+    const int m = (int)((n_max + 3) & ~3);
+    CK(launch_small(A, W, V, w.desc, (int)batch, w.queue, tol, o.max_sweeps, w.vscratch,
+                    small_vt_elems(n_max), cfg.pool, m, cfg.threads, (int)cfg.slots, w.status,
+                    s));
+    hipLaunchKernelGGL(na_status_max_kernel, dim3(1), dim3(256), 0, s, w.status, batch, worst);
+    CK(hipGetLastError());
+    if (status)
+        CK(hipMemcpyAsync(status, w.status, (size_t)batch * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, s));
+    int hworst = 0;
+    CK(hipMemcpyAsync(&hworst, worst, sizeof(int), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    return hworst;
 }
 
 int jacobi_device_summary(char *buf, size_t len)

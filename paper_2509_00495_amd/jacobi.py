@@ -109,6 +109,11 @@ def _lib():
                                             P, ctypes.POINTER(i64), P, d, i32,
                                             ctypes.POINTER(Opts), P, ctypes.c_size_t, P, P]
         lib.jacobi_eigh_batched.restype = i32
+        lib.jacobi_eigh_batched_noalloc.argtypes = [P, ctypes.POINTER(i64),
+                                                    ctypes.POINTER(i64), i64, P,
+                                                    ctypes.POINTER(i64), P, d, i32,
+                                                    ctypes.POINTER(Opts), P, P]
+        lib.jacobi_eigh_batched_noalloc.restype = i32
         lib.jacobi_eigh_backward.argtypes = [P, P, P, P, i64, i64, i64, P, d, P,
                                              ctypes.c_size_t, P]
         lib.jacobi_eigh_backward.restype = i32
@@ -286,6 +291,29 @@ def eigh_batched(A_packed, ns, tol: float | None = None, opts: Opts | None = Non
     if st < 0 or st in (DEVICE, WORKSPACE) or (check and st != OK):
         raise JacobiError("jacobi_eigh_batched", st)
     return W, V, status
+
+
+def eigh_batched_noalloc(A_packed, ns, W, V, status, tol: float | None = None,
+                         opts: Opts | None = None, a_off=None, w_off=None):
+    """jacobi_eigh_batched_noalloc: the batched solve into caller tensors
+    (W, V, status: contiguous GPU tensors of the packed or offset layout, as
+    eigh_batched returns them) with the library's fixed device scratch; no
+    workspace and no allocation.  Returns the call's status."""
+    torch = _torch()
+    ns = [int(x) for x in ns]
+    batch = len(ns)
+    for t in (A_packed, W, V):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("A_packed, W and V must be contiguous float64 GPU tensors")
+    if status.dtype != torch.int32 or not status.is_cuda or status.numel() != batch:
+        raise TypeError("status must be an int32 GPU tensor with one entry per matrix")
+    o = opts or Opts()
+    n_arr = (ctypes.c_int64 * max(batch, 1))(*ns)
+    ao = None if a_off is None else (ctypes.c_int64 * max(batch, 1))(*[int(x) for x in a_off])
+    wo = None if w_off is None else (ctypes.c_int64 * max(batch, 1))(*[int(x) for x in w_off])
+    return int(_lib().jacobi_eigh_batched_noalloc(
+        A_packed.data_ptr(), n_arr, ao, batch, W.data_ptr(), wo, V.data_ptr(),
+        float(tol or 0.0), 0, ctypes.byref(o), _stream(torch), status.data_ptr()))
 
 
 def eigh_backward(W, V, dW=None, dV=None, gap_tol: float = 0.0, ws: Workspace | None = None,
