@@ -66,6 +66,12 @@ def _load():
         lib.orc_eigh_backward.argtypes = [i64, P, P, P, P, d, P]
         lib.orc_eigh_backward.restype = i32
         lib.orc_rayleigh.argtypes = [i64, P, P, P, P]
+        lib.orc_round_half.argtypes = [d]
+        lib.orc_round_half.restype = d
+        lib.orc_jacobi_cyclic_h.argtypes = [i64, P, P, d, d, d, i32, P, P]
+        lib.orc_jacobi_cyclic_h.restype = i32
+        lib.orc_ns_iterations.argtypes = [d, d, d]
+        lib.orc_ns_iterations.restype = i32
         lib.orc_house.argtypes = [i64, P, P, P]
         lib.orc_householder_qr.argtypes = [i64, P, P, P]
         lib.orc_cholesky.argtypes = [i64, P, P]
@@ -213,6 +219,42 @@ def rayleigh(A, V):
     res = np.zeros(n)
     _load().orc_rayleigh(n, _p(A), _p(V), _p(rq), _p(res))
     return rq, res
+
+
+U_H = 2.0 ** -11  # unit roundoff, binary16
+
+
+def round_half(x: float) -> float:
+    """x rounded to the nearest binary16 value (ties to even)."""
+    return _load().orc_round_half(float(x))
+
+
+def jacobi_cyclic_h(A, tol_abs: float = 0.0, rel_eps: float = U_H, stall: float = 0.5,
+                    max_sweeps: int = 30, V0=None):
+    """The binary16 stage: Algorithm 4 with A stored in binary16 (every update
+    rounded), float angles and float V.  A is rounded to binary16 first.
+    Returns (A_final, V, sweeps, status, off_history)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    Ah = np.array([[round_half(v) for v in row] for row in A], dtype=np.float32) \
+        if n <= 64 else _round_half_array(A)
+    V = np.eye(n, dtype=np.float32) if V0 is None else np.ascontiguousarray(V0, np.float32).copy()
+    sw = ctypes.c_int()
+    hist = np.zeros(max_sweeps + 1)
+    st = _load().orc_jacobi_cyclic_h(n, _p(Ah), _p(V), tol_abs, rel_eps, stall, max_sweeps,
+                                     ctypes.byref(sw), _p(hist))
+    return Ah, V, sw.value, st, hist[: sw.value + 1].copy()
+
+
+def _round_half_array(A):
+    f = np.vectorize(round_half, otypes=[np.float64])
+    return f(A).astype(np.float32)
+
+
+def ns_iterations(n: float, u_low: float, u_high: float = U_D) -> int:
+    """Newton-Schulz iterations for low-precision vectors with unit roundoff
+    u_low (Section 4.3.4 analysis); -1 when n u_low >= 2."""
+    return int(_load().orc_ns_iterations(float(n), float(u_low), float(u_high)))
 
 
 def house(x):

@@ -176,6 +176,122 @@ DEFINE_ROTATE(orc_rotate_f32, float)
 DEFINE_CYCLIC(orc_jacobi_cyclic, double, orc_rotate, orc_off)
 DEFINE_CYCLIC(orc_jacobi_cyclic_f32, float, orc_rotate_f32, orc_off_f32)
 
+/* Rounding to IEEE binary16 (half precision: 11 significant bits, exponents
+ * -14 .. 15, subnormals down to 2^-24), round to nearest with ties to even,
+ * |x| >= 65520 to +-infinity.  Written from the format's definition: the
+ * spacing of binary16 numbers around x is 2^(e - 10) for 2^e <= |x| < 2^(e+1)
+ * in the normal range and 2^-24 below 2^-14; rint rounds to the nearest
+ * integer with ties to even in the default rounding mode. */
+double orc_round_half(double x)
+{
+    if (x != x || x == 0.0)
+        return x;
+    double a = fabs(x);
+    if (a >= 65520.0)
+        return x > 0 ? INFINITY : -INFINITY;
+    int e;
+    frexp(a, &e); /* a = f 2^e, f in [0.5, 1): 2^(e-1) <= a < 2^e */
+    int q = (e - 1) - 10;   /* exponent of the spacing */
+    if (q < -24)
+        q = -24;            /* subnormal spacing */
+    double r = ldexp(rint(ldexp(a, -q)), q);
+    return x > 0 ? r : -r;
+}
+
+/* The half-precision stage of the precision ladder (the lower-precision
+ * first stage the paper names as further work, Chapter 6): Algorithm 4 in
+ * the cyclic order with the matrix stored in binary16: the angle is computed
+ * in double from the stored entries and rounded to float, each rotation's
+ * row and column updates are computed in float and every updated entry is
+ * rounded to binary16, (A + A^T)/2 at the end of a rotating sweep likewise;
+ * V (the accumulated rotations) stays in float.  The iteration stops when off
+ * drops to tol_abs, when a sweep rotates nothing, when a sweep lowers off by
+ * less than the factor `stall` (the binary16 rounding floor), or after
+ * max_sweeps sweeps (status 1).  A holds binary16 values on entry. */
+int orc_jacobi_cyclic_h(int64_t n, float *A, float *V, double tol_abs, double rel_eps,
+                        double stall, int max_sweeps, int *sweeps_out, double *off_hist)
+{
+    int sweeps = 0, status = 0;
+    double off = orc_off_f32(n, A);
+    if (off_hist)
+        off_hist[0] = off;
+    for (;;) {
+        if (off <= tol_abs)
+            break;
+        if (sweeps >= max_sweeps) {
+            status = 1;
+            break;
+        }
+        int rotated = 0;
+        for (int64_t p = 0; p < n - 1; ++p)
+            for (int64_t q = p + 1; q < n; ++q) {
+                double apq = (double)A[IDX(p, q, n)];
+                double app = (double)A[IDX(p, p, n)];
+                double aqq = (double)A[IDX(q, q, n)];
+                if (apq != 0.0 && fabs(apq) > rel_eps * sqrt(fabs(app * aqq))) {
+                    double cd, sd;
+                    orc_jacobi_pair(app, aqq, apq, &cd, &sd);
+                    const float c = (float)cd, s = (float)sd;
+                    for (int64_t j = 0; j < n; ++j) { /* J^T A([p q],:) */
+                        float ap = A[IDX(p, j, n)], aq = A[IDX(q, j, n)];
+                        A[IDX(p, j, n)] = (float)orc_round_half((double)(c * ap - s * aq));
+                        A[IDX(q, j, n)] = (float)orc_round_half((double)(s * ap + c * aq));
+                    }
+                    for (int64_t i = 0; i < n; ++i) { /* A(:,[p q]) J */
+                        float ap = A[IDX(i, p, n)], aq = A[IDX(i, q, n)];
+                        A[IDX(i, p, n)] = (float)orc_round_half((double)(c * ap - s * aq));
+                        A[IDX(i, q, n)] = (float)orc_round_half((double)(s * ap + c * aq));
+                    }
+                    for (int64_t i = 0; i < n; ++i) { /* V(:,[p q]) J, float */
+                        float xp = V[IDX(i, p, n)], xq = V[IDX(i, q, n)];
+                        V[IDX(i, p, n)] = c * xp - s * xq;
+                        V[IDX(i, q, n)] = s * xp + c * xq;
+                    }
+                    rotated = 1;
+                }
+            }
+        if (!rotated)
+            break;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = i + 1; j < n; ++j) {
+                float m = (float)orc_round_half(0.5 * ((double)A[IDX(i, j, n)] +
+                                                       (double)A[IDX(j, i, n)]));
+                A[IDX(i, j, n)] = m;
+                A[IDX(j, i, n)] = m;
+            }
+        ++sweeps;
+        double prev = off;
+        off = orc_off_f32(n, A);
+        if (off_hist)
+            off_hist[sweeps] = off;
+        if (off > stall * prev)
+            break;
+    }
+    if (sweeps_out)
+        *sweeps_out = sweeps;
+    return status;
+}
+
+/* Newton-Schulz iterations that the analysis of Section 4.3.4 asks for when
+ * the low-precision eigenvectors have unit roundoff u_low: the singular values
+ * of X_0 lie in [sqrt(1 - n u_low), sqrt(1 + n u_low)], the error after k
+ * iterations is about (sqrt(1 + n u_low) - 1)^(2^k), and k is the smallest
+ * count with that <= n u_high.  Returns -1 when n u_low >= 2 (sqrt(1 + n u_low)
+ * >= sqrt(3): the iteration is no longer guaranteed to converge). */
+int orc_ns_iterations(double n, double u_low, double u_high)
+{
+    if (n * u_low >= 2.0)
+        return -1;
+    double e = sqrt(1.0 + n * u_low) - 1.0;
+    int k = 0;
+    double err = e;
+    while (err > n * u_high && k < 64) {
+        err = err * err;
+        ++k;
+    }
+    return k;
+}
+
 /* A bounded piece of one sweep of Algorithm 4: the cyclic-by-row visits of
  * pivot rows p in [p_begin, p_end) (all q > p), with the same per-pair test
  * and rotation as orc_jacobi_cyclic, no end-of-sweep step.  Used to time the

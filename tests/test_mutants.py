@@ -79,6 +79,14 @@ MUTANTS = [
      "g -= R[IDX(k, i, n)] * R[IDX(k, i, n)];", ["test_cholesky_known_factor"]),
     ("cholqr_solve", "acc -= Q[IDX(i, k, n)] * R[IDX(k, j, n)];",
      "acc -= Q[IDX(i, k, n)] * R[IDX(j, k, n)];", ["test_cholesky_qr_identities"]),
+    ("half_spacing", "    int q = (e - 1) - 10;   /* exponent of the spacing */",
+     "    int q = (e - 1) - 11;   /* exponent of the spacing */", ["test_round_half_definition"]),
+    ("half_subnormal", "        q = -24;            /* subnormal spacing */",
+     "        q = -25;            /* subnormal spacing */", ["test_round_half_definition"]),
+    ("half_no_round_cols", "A[IDX(i, p, n)] = (float)orc_round_half((double)(c * ap - s * aq));",
+     "A[IDX(i, p, n)] = (c * ap - s * aq);", ["test_half_stage_bounds"]),
+    ("ns_count_linear", "        err = err * err;", "        err = err * e;",
+     ["test_ns_iteration_count_low_precision"]),
     ("rayleigh_res_unscaled", "res[k] = vv > 0.0L ? (double)sqrtl(rr / vv) : 0.0;",
      "res[k] = (double)sqrtl(rr);", ["test_rayleigh_quadratic_and_scale_free"]),
 ]

@@ -590,3 +590,73 @@ def test_mixed_with_qr_orthogonalisers(orc, orth):
     assert np.abs(W - lam).max() <= 1e-13 * nrm2
     assert np.linalg.norm(A @ Q - Q * W) / np.linalg.norm(A) <= 1e-13 * n
     assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 1e-14 * n
+
+
+# --------------------------------------- binary16 stage (precision ladder)
+def test_round_half_definition(orc):
+    """Round to nearest binary16 with ties to even, from the format's
+    definition: spacing 2^-10 at 1, ties 1 + 2^-11 -> 1 and 1 + 3 2^-11 ->
+    1 + 2^-9, largest finite 65504 (65519 stays, 65520 overflows), subnormal
+    spacing 2^-24 (2^-25 ties to 0, 3 2^-25 to 2^-23); and numpy's float16
+    conversion on random values (a library cross-check)."""
+    r = orc.round_half
+    assert r(1.0) == 1.0 and r(-2.5) == -2.5
+    assert r(1.0 + 2.0 ** -11) == 1.0
+    assert r(1.0 + 3 * 2.0 ** -11) == 1.0 + 2.0 ** -9
+    assert r(1.0 + 2.0 ** -11 + 2.0 ** -20) == 1.0 + 2.0 ** -10
+    assert r(65504.0) == 65504.0 and r(65519.0) == 65504.0
+    assert math.isinf(r(65520.0)) and r(-1e6) == -math.inf
+    assert r(2.0 ** -24) == 2.0 ** -24 and r(2.0 ** -25) == 0.0
+    assert r(3 * 2.0 ** -25) == 2.0 ** -23 and r(2.0 ** -14) == 2.0 ** -14
+    g = wl.rng(95)
+    x = g.standard_normal(2000) * 10.0 ** g.uniform(-9, 4.5, 2000)
+    got = np.array([r(v) for v in x])
+    assert np.array_equal(got, x.astype(np.float16).astype(np.float64))
+
+
+def test_ns_iteration_count_low_precision(orc):
+    """Section 4.3.4's count, (sqrt(1 + n u) - 1)^(2^k) <= n u_d: with u_l it is
+    2 up to the printed crossover n ~ 52071 and 3 beyond (to 2172548); with
+    binary16 vectors (u_h = 2^-11) it is 5 at n = 1024, and from n u_h >= 2
+    (n = 4096) the singular values of X_0 reach sqrt(3), where the iteration is
+    no longer guaranteed to converge (-1)."""
+    fx = golden("ns_iteration_count.txt")
+    c2, c3 = fx["crossover_two"], fx["crossover_three"]
+    assert orc.ns_iterations(c2 - 100, U_L) == 2
+    assert orc.ns_iterations(c2 + 100, U_L) == 3
+    assert orc.ns_iterations(c3 * 0.999, U_L) == 3
+    assert orc.ns_iterations(4096, U_L) == 2
+    u_h = 2.0 ** -11
+    assert orc.ns_iterations(1024, u_h) == 5
+    assert orc.ns_iterations(256, u_h) == 4
+    assert orc.ns_iterations(4096, u_h) == -1
+    assert orc.ns_iterations(4095, u_h) > 0
+
+
+@pytest.mark.parametrize("name", ["goe", "geo"])
+def test_half_stage_bounds(orc, name):
+    """The binary16 stage: every stored entry is a binary16 value, off falls
+    sweep after sweep until the binary16 rounding floor and ends below
+    n u_h ||A||_F (the Section 5.2.1 bound with u_h), V (kept in FP32) is
+    orthogonal to order n u_l, and Q_h^T A Q_h is diagonal to the same order:
+    the FP32 stage from it needs fewer sweeps than from A."""
+    n = 96
+    A = wl.goe(n, 96) if name == "goe" else wl.geo_spectrum(n, 97, kappa=1e3)[0]
+    nf = np.linalg.norm(A)
+    # A scalar cyclic sweep lowers off by only about a half early on, so the
+    # stall factor here is 0.9 (a block sweep, whose pair solves run to
+    # convergence, does better: the device stage stops at 0.5).
+    Ah, V, sw, st, hist = orc.jacobi_cyclic_h(A, stall=0.9)
+    assert st == 0 and sw >= 3
+    assert np.array_equal(Ah.astype(np.float64),
+                          Ah.astype(np.float16).astype(np.float64))
+    assert all(hist[k + 1] <= 0.9 * hist[k] for k in range(sw - 1))
+    assert hist[-1] <= n * 2.0 ** -11 * nf
+    V64 = V.astype(np.float64)
+    assert np.linalg.norm(V64.T @ V64 - np.eye(n)) <= 4 * n * U_L
+    B = V64.T @ A @ V64
+    assert orc.off(B) <= n * 2.0 ** -11 * nf
+    tol32 = 0.1 * n * U_L * nf
+    _, _, s_from_h, _, _ = orc.jacobi_cyclic_f32(B.astype(np.float32), tol32)
+    _, _, s_from_a, _, _ = orc.jacobi_cyclic_f32(A.astype(np.float32), tol32)
+    assert s_from_h < s_from_a
