@@ -1,12 +1,22 @@
 """Benchmark of the mixed-precision Jacobi eigensolver on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--orth NAME]
 
-A step is one full eigendecomposition through the hot path (jacobi_eigh_mixed:
-FP32 Jacobi -> FP64 Newton-Schulz -> Q_d^T A Q_d -> FP64 Jacobi -> sorted
-output) of one seeded synthetic matrix already resident in HBM.  The plain
-FP64 Jacobi (jacobi_eigh) is timed on the same matrix for comparison.  One
-JSON line is printed; see the field descriptions in main().
+Default workload goe4096: a step is one full eigendecomposition through the
+hot path (jacobi_eigh_mixed: FP32 Jacobi -> FP64 Newton-Schulz -> Q_d^T A Q_d
+-> FP64 Jacobi -> sorted output) of one seeded synthetic n = 4096 matrix
+already resident in HBM; the plain FP64 Jacobi (jacobi_eigh) is timed on the
+same matrix.  The other workloads measure the other configurations:
+  geo1024 / geo4096 / ari4096 / blk4096   mixed vs plain as above
+  uniform64        n = 64, plain FP64, one solve per step (latency), plus a
+                   4096-matrix batch of the same order through jacobi_eigh_batched
+  clustered10000   10 000 matrices of order 8..128 (clustered spectra) in one
+                   persistent jacobi_eigh_batched launch per step
+  gapped256x256    256 matrices of order 256: forward (per matrix) and the
+                   batched adjoint jacobi_eigh_backward per step
+--orth householder|cholesky replaces Newton-Schulz in the mixed path (the
+comparators of Section 4.4); --compare-orth times all three on the workload.
+One JSON line is printed.
 """
 from __future__ import annotations
 
@@ -14,6 +24,7 @@ import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -23,10 +34,13 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 METRIC = "eigendecomps/sec, mixed vs plain FP64 Jacobi on MI355X at residual ≤1e-13·n"
-PEAK = {"f64": 78.6, "f32": 157.3}   # dense MFMA TFLOP/s, MI355X
+PEAK = {"f64": 78.6, "f32": 157.3}   # MI355X: dense MFMA and vector TFLOP/s (fp32, fp64)
 HBM_PEAK = 8000.0                      # GB/s
+CUS, CLOCK_GHZ = 256, 2.4
+# one compute unit's FP64 vector peak: 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+CU_F64_TFLOPS = 4 * 16 * 2 * CLOCK_GHZ / 1e3
 
-WORKLOADS = {
+MIXED_WORKLOADS = {
     "goe4096": dict(n=4096, desc="A=(G+G^T)/2, G iid N(0,1), seed 3"),
     "geo1024": dict(n=1024, desc="A=Q diag(lam) Q^T, lam_i=+-10^(-6i/(n-1)), Haar Q, seed 2"),
     "geo4096": dict(n=4096, desc="A=Q diag(lam) Q^T, |lam_i|=100^(-i/(n-1)), random signs, "
@@ -36,6 +50,14 @@ WORKLOADS = {
     "blk4096": dict(n=4096, desc="8 decoupled diagonal blocks of 512, A_i=Q_i diag(lam_i) "
                                  "Q_i^T, lam_i ~ U[-1,1], Haar Q_i, seed 9"),
 }
+OTHER_WORKLOADS = {
+    "uniform64": "n=64, A=Q diag(lam) Q^T, lam ~ U[-1,1], Haar Q, seed 1; plain FP64, "
+                 "tol 1e-15 n ||A||_F",
+    "clustered10000": "10000 matrices, n ~ U{8..128}, lam in 5 clusters of width 1e-8, seed 4",
+    "gapped256x256": "256 matrices n=256, sorted lam with min gap 1e-3, seed 5; loss "
+                     "sum w.lam + <C, V>",
+}
+ORTH = {"ns": 0, "householder": 1, "cholesky": 2}
 
 
 def make_input(name):
@@ -43,8 +65,7 @@ def make_input(name):
     if name == "goe4096":
         return wl.goe(4096, 3), None
     if name == "geo1024":
-        A, lam = wl.geo_spectrum(1024, 2)
-        return A, lam
+        return wl.geo_spectrum(1024, 2)
     if name == "geo4096":
         return wl.geo_spectrum(4096, 8, kappa=1e2)
     if name == "ari4096":
@@ -54,37 +75,58 @@ def make_input(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def host_info():
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
 def _tiles(n, b):
     N = -(-n // b)
     N += N % 2
     npairs = N // 2
     M = 2 * b
     nbt = npairs * (npairs - 1) // 2      # off-diagonal pair tiles k < l of B
-    nvt = (N * b // M) * npairs           # row tiles x pairs of V
-    return M, nbt, nvt
+    nvt = (N * b // 16) * npairs          # 16-row tiles of V x pairs
+    return M, nbt, nvt, npairs
 
 
 def apply_flops(n, b, part):
-    """Algorithmic flops of one update launch (one round).  part "B": every
-    off-diagonal pair tile k < l becomes U_k^T B_kl U_l, two (2b)^3 products
-    (the mirror tile is its transpose, not recomputed); part "V": every row
-    tile of V becomes V U_l, one (2b)^3 product."""
-    M, nbt, nvt = _tiles(n, b)
-    return 2.0 * M ** 3 * (2 * nbt if part == "B" else nvt)
+    """Algorithmic flops of one update launch (one round).  "B": every
+    off-diagonal pair tile k < l becomes U_k^T B_kl U_l, two (2b)^3 products;
+    "V": every 16-row tile of V times U_l, 2 * 16 * (2b)^2."""
+    M, nbt, nvt, _ = _tiles(n, b)
+    return 2.0 * M ** 3 * 2 * nbt if part == "B" else 2.0 * 16 * M * M * nvt
 
 
 def apply_bytes(n, b, elem, part):
     """Algorithmic HBM bytes of one update launch: each off-diagonal pair tile
     of B read and written once (B keeps only its upper b x b blocks during the
-    sweeps, so a tile is four stored blocks in either orientation); V tiles
-    read and written once.  The small U blocks are cache resident and not
-    counted."""
-    M, nbt, nvt = _tiles(n, b)
-    tile = M * M * elem
-    return tile * (2 * nbt if part == "B" else 2 * nvt)
+    sweeps), V read and written once.  The small U blocks are cache resident
+    and not counted."""
+    M, nbt, nvt, _ = _tiles(n, b)
+    if part == "B":
+        return M * M * elem * 2 * nbt
+    return 16 * M * elem * 2 * nvt
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "update_kernels_goe4096_traffic.md")
+def pair_solve_flops(n, b):
+    """Algorithmic ALU flops of one round's pair solves (cross schedule): per
+    block pair b inner rounds of b rotations; a rotation updates two rows and
+    two columns of the 2b x 2b tile and two columns of U, 3 x 2 x 2b entry
+    pairs at 6 flops each (36 b flops), so 36 b^3 per pair."""
+    _, _, _, npairs = _tiles(n, b)
+    return 36.0 * b ** 3 * npairs
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dominant_kernel_goe4096_traffic.md")
 
 
 def measured_traffic(kernel, workload):
@@ -109,17 +151,60 @@ def measured_traffic(kernel, workload):
     return None
 
 
+def load_fixture(name):
+    """(w, rq, res, header) of an oracle fixture, or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_{name}.txt")
+    if not os.path.exists(path):
+        return None
+    head = {}
+    host = None
+    with open(path) as f:
+        for line in f:
+            if not line.startswith("#"):
+                break
+            parts = line[1:].split()
+            if parts and parts[0] == "n":
+                head = {parts[i]: parts[i + 1] for i in range(0, len(parts) - 1, 2)}
+            if parts and parts[0] == "host":
+                host = line[1:].strip()
+    data = np.loadtxt(path, ndmin=2)
+    if data.shape[1] < 3:
+        return None
+    head["host"] = host
+    return data[:, 0], data[:, 1], data[:, 2], head
+
+
+def certified_distance(W, rq, res):
+    """max_k distance of W_k to the oracle's Kato-Temple interval rq_k +-
+    res_k^2 / delta_k over the separated eigenvalues, and their count."""
+    gap = np.minimum(np.r_[np.inf, np.diff(rq)], np.r_[np.diff(rq), np.inf])
+    delta = gap - 2 * res.max()
+    kt = np.where(delta > 0, res ** 2 / np.where(delta > 0, delta, 1.0), np.inf)
+    sep = np.isfinite(kt)
+    return float(np.maximum(np.abs(W - rq) - kt, 0.0)[sep].max()), int(sep.sum())
+
+
+def self_certified(A, W, V):
+    """Kato-Temple bound from the computed pairs themselves: max_k |w_k - rho_k|
+    + r_k^2 / delta_k over the separated eigenvalues."""
+    AV = A @ V
+    rho = np.einsum("ij,ij->j", V, AV) / np.einsum("ij,ij->j", V, V)
+    rk = np.linalg.norm(AV - V * rho, axis=0)
+    gap = np.minimum(np.r_[np.inf, np.diff(W)], np.r_[np.diff(W), np.inf])
+    delta = gap - 2 * rk.max()
+    sep = delta > 0
+    kt = np.where(sep, rk ** 2 / np.where(sep, delta, 1.0), np.inf)
+    return float((np.abs(W - rho) + kt)[sep].max()), int(sep.sum())
+
+
 def oracle_sweeps_estimate(name, n):
-    """The oracle's sweep count for this workload: read from the fixture when
+    """The oracle's sweep count for this workload: read from its fixture when
     the oracle was run at this size, else extrapolated linearly in log2(n) from
-    the oracle's sweep counts on the same distribution at smaller n."""
-    gold = os.path.join(ROOT, "tests", "golden")
-    if name == "geo1024":
-        with open(os.path.join(gold, "oracle_geo1024.txt")) as f:
-            for line in f:
-                if line.startswith("# n "):
-                    return float(line.split()[4]), "oracle run (tests/golden/oracle_geo1024.txt)"
-    path = os.path.join(gold, "oracle_goe_sweeps.txt")
+    its sweep counts on the same distribution at smaller n."""
+    fx = load_fixture(name)
+    if fx is not None and "sweeps" in fx[3]:
+        return float(fx[3]["sweeps"]), f"oracle run (tests/golden/oracle_{name}.txt)"
+    path = os.path.join(ROOT, "tests", "golden", "oracle_goe_sweeps.txt")
     pts = []
     with open(path) as f:
         for line in f:
@@ -130,15 +215,16 @@ def oracle_sweeps_estimate(name, n):
     x = np.array([p[0] for p in pts])
     y = np.array([p[1] for p in pts])
     slope, icpt = np.polyfit(x, y, 1)
-    est = slope * math.log2(n) + icpt
-    return float(est), ("log2(n) fit of oracle sweep counts at n=" +
-                        ",".join(str(int(2 ** v)) for v in x))
+    return float(slope * math.log2(n) + icpt), (
+        "log2(n) fit of oracle sweep counts at n=" + ",".join(str(int(2 ** v)) for v in x))
 
 
-def cpu_baseline(name, A, budget_s=12.0):
+def cpu_baseline_rows(name, A, budget_s=12.0):
     """Time the CPU oracle on a bounded sample of the same workload: pivot rows
     of the first cyclic-by-row sweep on this very matrix, until budget_s of
-    CPU time, then scale by the oracle's sweeps per eigendecomposition."""
+    CPU time, then scale by the oracle's sweeps per eigendecomposition.  Where
+    the oracle's full solve of this matrix is stored (fixture), its measured
+    time is reported beside it."""
     import oracle
     n = A.shape[0]
     B = np.array(A, dtype=np.float64, copy=True)
@@ -155,7 +241,7 @@ def cpu_baseline(name, A, budget_s=12.0):
     rate = rot / wall
     sweeps, how = oracle_sweeps_estimate(name, n)
     per_eig = sweeps * n * (n - 1) / 2.0
-    return {
+    out = {
         "value": rate / per_eig,
         "unit": "eigendecomps/s",
         "cores": 1,
@@ -164,6 +250,403 @@ def cpu_baseline(name, A, budget_s=12.0):
                    f"of the first cyclic-by-row sweep on the same n={n} matrix; "
                    f"{rate:.0f} rotations/s scaled by {sweeps:.1f} sweeps x n(n-1)/2 "
                    f"rotations per eigendecomposition ({how})"),
+        "host": host_info(),
+    }
+    fx = load_fixture(name)
+    if fx is not None and "seconds" in fx[3]:
+        out["full_solve_s"] = float(fx[3]["seconds"])
+        out["full_solve_host"] = fx[3].get("host")
+    return out
+
+
+def sync_time(torch, fn, steps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, out
+
+
+# --------------------------------------------------------------- mixed vs plain
+def bench_mixed(args, torch, pj):
+    wl_name = args.workload
+    A, lam = make_input(wl_name)
+    n = A.shape[0]
+    At = torch.tensor(A, device="cuda")
+    orth = ORTH[args.orth]
+    opts = pj.make_opts(orth=orth)
+    ws = pj.Workspace()
+
+    def run_mixed(o=opts):
+        return pj.eigh_mixed(At, opts=o, ws=ws, return_info=True)
+
+    def run_plain(o=None):
+        return pj.eigh(At, opts=o or pj.make_opts(), ws=ws, return_info=True)
+
+    for _ in range(args.warmup):
+        run_mixed()
+    dt, (W, V, info) = sync_time(torch, run_mixed, args.steps)
+    value = args.steps / dt
+
+    plain = None
+    if not args.no_plain:
+        for _ in range(args.warmup):
+            run_plain()
+        dtp, (Wp, Vp, pinfo) = sync_time(torch, run_plain, args.steps)
+        plain = {"value": args.steps / dtp, "ms_per_step": 1e3 * dtp / args.steps,
+                 "sweeps": pinfo["sweeps"], "orth_est": pinfo["orth_est"],
+                 "orth_refresh": pinfo["polished"], "skipped_tiles": pinfo["skipped_tiles"]}
+
+    # accuracy of the timed output
+    Wn, Vn = W.cpu().numpy(), V.cpu().numpy()
+    nrmF = np.linalg.norm(A)
+    nrm2 = np.abs(Wn).max()
+    acc = {
+        "residual_rel_F": float(np.linalg.norm(A @ Vn - Vn * Wn) / nrmF),
+        "residual_bar": 1e-13 * n,
+        "orth_F": float(np.linalg.norm(Vn.T @ Vn - np.eye(n))),
+        "orth_bar": 1e-14 * n,
+        "trace_rel_err": float(abs(Wn.sum() - np.trace(A)) / np.abs(A).sum()),
+        "frobenius_rel_err": float(abs(math.sqrt((Wn ** 2).sum()) - nrmF) / nrmF),
+        "eig_bar": 1e-13,
+    }
+    gate = acc["residual_rel_F"] <= acc["residual_bar"] and acc["orth_F"] <= acc["orth_bar"]
+    if lam is not None:
+        acc["eig_err_vs_known_spectrum"] = float(np.abs(Wn - lam).max() / np.abs(lam).max())
+        gate = gate and acc["eig_err_vs_known_spectrum"] <= 1e-13
+    fx = load_fixture(wl_name)
+    if fx is not None:
+        # the oracle's eigenvalues as certified intervals around the Rayleigh
+        # quotients of its eigenvectors (its diagonal readout drifts at this size)
+        d, nsep = certified_distance(Wn, fx[1], fx[2])
+        acc["eig_dist_to_oracle_certified"] = d / nrm2
+        acc["oracle_separated"] = nsep
+        gate = gate and d / nrm2 <= 1e-13
+    elif lam is None:
+        d, nsep = self_certified(A, Wn, Vn)
+        acc["eig_err_kato_temple"] = d / nrm2
+        acc["separated"] = nsep
+        gate = gate and d / nrm2 <= 1e-13
+    if plain is not None:
+        acc["mixed_vs_plain_max_dW_rel"] = float(
+            np.abs(Wn - Wp.cpu().numpy()).max() / np.abs(Wn).max())
+    acc["gate_passed"] = bool(gate)
+
+    # kernel durations from the in-library HIP events of instrumented
+    # (untimed) solves: every launch records events at the kernel itself on its
+    # stream.  Solve 1: the launch structure of the timed solves (pair solves
+    # sharing their launch with the previous round's V update); solve 2:
+    # serial_v = 1, every launch on its own, for the pair solve alone.
+    inf1 = run_mixed(pj.make_opts(timing=1, orth=orth))[2]
+    inf2 = run_mixed(pj.make_opts(timing=1, serial_v=1, orth=orth))[2]
+    torch.cuda.synchronize()
+    b = inf1["block"]
+    cands = {}
+    for idx, dt_ in ((1, "f32"), (0, "f64")):
+        cands[f"pair_solve_v_{dt_}"] = (inf1["t_pair_ms"][idx], inf1["n_pair"][idx], "PV", dt_)
+        cands[f"update_b_{dt_}"] = (inf1["t_apply_ms"][idx], inf1["n_apply"][idx], "B", dt_)
+        cands[f"update_v_{dt_}"] = (inf1["t_applyv_ms"][idx], inf1["n_applyv"][idx], "V", dt_)
+    kern_ms = {k: round(v[0], 2) for k, v in cands.items()}
+    kern_ms["pair_solve_alone_f32"] = round(inf2["t_pair_ms"][1], 2)
+    kern_ms["pair_solve_alone_f64"] = round(inf2["t_pair_ms"][0], 2)
+    kern_ms["orthogonaliser"] = round(inf1["t_orth_ms"], 2)
+    names = {"PV": "pair_solve_v_kernel<{t}, 64, 1024, true> (pair solves + previous V update)",
+             "B": "update_b_kernel<{t}, 64> (off-diagonal B tiles)",
+             "V": "update_v_kernel<{t}, 64> (V row tiles)"}
+    dom = max(cands, key=lambda k: cands[k][0])
+    t_ms, cnt, part, dtype = cands[dom]
+    elem = 4 if dtype == "f32" else 8
+    avg_s = t_ms / max(cnt, 1) / 1e3
+    sweeps_stage = info["sweeps32"] if dtype == "f32" else info["sweeps"]
+    if part == "PV":
+        # its HBM-bound part: the previous round's V update, which every launch
+        # but the first of each sweep carries (V read and written once)
+        share = 1.0 - max(sweeps_stage, 1) / max(cnt, 1)
+        flops = apply_flops(n, b, "V") * share
+        nbytes = apply_bytes(n, b, elem, "V") * share
+    else:
+        flops = apply_flops(n, b, part)
+        nbytes = apply_bytes(n, b, elem, part)
+    mfma_bound = flops / (PEAK[dtype] * 1e12) >= nbytes / (HBM_PEAK * 1e9)
+    achieved = flops / avg_s / 1e12 if mfma_bound else nbytes / avg_s / 1e9
+    peak = PEAK[dtype] if mfma_bound else HBM_PEAK
+    kname = names[part].format(t="float" if dtype == "f32" else "double")
+    roofline = {
+        "kernel": "lj::" + kname,
+        "bound": "mfma" if mfma_bound else "hbm",
+        "achieved": round(achieved, 2),
+        "peak": peak,
+        "unit": "TFLOP/s" if mfma_bound else "GB/s",
+        "frac": round(achieved / peak, 4),
+        "traffic": measured_traffic(kname.split(" ")[0], wl_name),
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-probe scaled)",
+        "avg_launch_us": round(avg_s * 1e6, 2),
+        "launches": cnt,
+        "flops_per_launch": flops,
+        "bytes_per_launch": nbytes,
+        "kernel_ms_per_step": kern_ms,
+    }
+    # the pair solves alone: latency-bound ALU work (FP64 angles, FP32 or FP64
+    # data), against the vector peak of the data's precision
+    ps = {}
+    for idx, dt_ in ((1, "f32"), (0, "f64")):
+        cnt_ = inf2["n_pair"][idx]
+        if cnt_:
+            a_s = inf2["t_pair_ms"][idx] / cnt_ / 1e3
+            fl = pair_solve_flops(n, b)
+            ps[dt_] = {"avg_launch_us": round(a_s * 1e6, 2), "flops_per_launch": fl,
+                       "achieved": round(fl / a_s / 1e12, 3), "peak": PEAK[dt_],
+                       "frac": round(fl / a_s / 1e12 / PEAK[dt_], 4)}
+    roofline_pair = {"kernel": "lj::pair_solve_kernel<T, 64, 1024, true> (alone)",
+                     "bound": "alu", "unit": "TFLOP/s", "per_precision": ps}
+
+    cpu = None
+    if not args.no_cpu_baseline and wl_name in ("goe4096", "geo1024"):
+        cpu = cpu_baseline_rows(wl_name, A)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "eigendecomps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": wl_name,
+            "n": n,
+            "input": MIXED_WORKLOADS[wl_name]["desc"],
+            "path": "jacobi_eigh_mixed",
+            "orthogonaliser": args.orth,
+            "block": b,
+            "sweeps32": info["sweeps32"],
+            "sweeps64": info["sweeps"],
+            "ns_iters": info["ns_iters"],
+            "orth_qd": inf1["orth_qd"],
+            "orth_est": info["orth_est"],
+            "orth_refresh": info["polished"],
+            "skipped_tiles": info["skipped_tiles"],
+        },
+        "plain_fp64": plain,
+        "speedup_vs_plain": None if plain is None else round(value / plain["value"], 3),
+        "accuracy": acc,
+        "roofline": roofline,
+        "roofline_pair_solve": roofline_pair,
+        "cpu_baseline": cpu,
+    }
+    if args.compare_orth:
+        comp = {}
+        for name, code in ORTH.items():
+            _, _, i0 = run_mixed(pj.make_opts(timing=1, orth=code))
+            t0 = time.perf_counter()
+            Wc, Vc, ic = run_mixed(pj.make_opts(orth=code))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            Wcn = Wc.cpu().numpy()
+            comp[name] = {"orth_qd": i0["orth_qd"], "t_orth_ms": round(i0["t_orth_ms"], 3),
+                          "solve_ms": round(1e3 * (t1 - t0), 2),
+                          "sweeps64": ic["sweeps"], "off_cond": ic["off_cond"],
+                          "max_dW_vs_ns": float(np.abs(Wcn - Wn).max() / nrm2)}
+        out["orthogonalisers"] = comp
+    if args.compare_ladder:
+        # the binary16 stage ahead of the FP32 stage (opts.ladder = 1): sweep
+        # counts per stage, wall time of one solve, agreement with the default
+        run_mixed(pj.make_opts(ladder=1))
+        t0 = time.perf_counter()
+        Wc, Vc, ic = run_mixed(pj.make_opts(ladder=1))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out["ladder"] = {"sweeps16": ic["sweeps16"], "sweeps32": ic["sweeps32"],
+                         "sweeps64": ic["sweeps"], "off16": ic["off16"],
+                         "solve_ms": round(1e3 * (t1 - t0), 2),
+                         "max_dW_vs_default": float(np.abs(Wc.cpu().numpy() - Wn).max() / nrm2)}
+    return out
+
+
+# ----------------------------------------------------------- config 1 (n = 64)
+def bench_uniform64(args, torch, pj):
+    import workloads as wl
+    import oracle
+    A, lam = wl.uniform_spectrum(64, 1)
+    n = 64
+    At = torch.tensor(A, device="cuda")
+    ws = pj.Workspace()
+
+    def run():
+        return pj.eigh(At, ws=ws, return_info=True)
+
+    for _ in range(max(args.warmup, 2)):
+        run()
+    steps = max(args.steps, 50)
+    dt, (W, V, info) = sync_time(torch, run, steps)
+    Wn, Vn = W.cpu().numpy(), V.cpu().numpy()
+    # the same order as a batch of 4096 copies in one persistent launch
+    nb = 4096
+    Ab = At.reshape(-1).repeat(nb)
+    pj.eigh_batched(Ab, [n] * nb, ws=ws)
+    dtb, _ = sync_time(torch, lambda: pj.eigh_batched(Ab, [n] * nb, ws=ws), 5)
+    sweeps = info["sweeps"]
+    # 12 n flops per rotation (the symmetric two-sided update and V), n^2 / 2
+    # rotations per sweep
+    flops = 6.0 * n ** 3 * sweeps
+    avg_s = dt / steps
+    acc = {"eig_err_vs_known_spectrum": float(np.abs(Wn - lam).max() / np.abs(lam).max()),
+           "residual_rel_F": float(np.linalg.norm(A @ Vn - Vn * Wn) / np.linalg.norm(A)),
+           "orth_F": float(np.linalg.norm(Vn.T @ Vn - np.eye(n)))}
+    acc["gate_passed"] = bool(acc["eig_err_vs_known_spectrum"] <= 1e-13 and
+                              acc["residual_rel_F"] <= 1e-13 * n and acc["orth_F"] <= 1e-14 * n)
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < 5.0:
+            oracle.eigh(A)
+            k += 1
+        cpu = {"value": k / (time.perf_counter() - t0), "unit": "eigendecomps/s", "cores": 1,
+               "kind": "oracle", "sample": f"{k} full oracle solves of the same n=64 matrix",
+               "host": host_info()}
+    return {
+        "metric": "eigendecomps/sec, plain FP64 Jacobi, one n=64 matrix per call (latency)",
+        "value": round(steps / dt, 2), "unit": "eigendecomps/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * dt / steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "uniform64", "n": n, "input": OTHER_WORKLOADS["uniform64"],
+                   "path": "jacobi_eigh (one-workgroup solver)", "sweeps": sweeps},
+        "batched_same_order": {"matrices": nb, "ms_per_batch": round(1e3 * dtb / 5, 3),
+                               "value": round(5 * nb / dtb, 1), "unit": "eigendecomps/s"},
+        "accuracy": acc,
+        "roofline": {"kernel": "lj::small_jacobi_kernel<256> (one workgroup, one CU)",
+                     "bound": "alu", "achieved": round(flops / avg_s / 1e12, 4),
+                     "peak": round(CU_F64_TFLOPS, 4), "unit": "TFLOP/s",
+                     "frac": round(flops / avg_s / 1e12 / CU_F64_TFLOPS, 4), "traffic": None,
+                     "note": "peak = one compute unit's FP64 vector rate (the solve runs on "
+                             "one workgroup); time per call includes the host launch and "
+                             "status readback"},
+        "cpu_baseline": cpu,
+    }
+
+
+# ------------------------------------------------------------ config 4 (batch)
+def bench_clustered(args, torch, pj):
+    import workloads as wl
+    import oracle
+    ns, mats, lams = wl.clustered_batch(10000, 4)
+    A = torch.tensor(np.concatenate([m.ravel() for m in mats]), device="cuda")
+    ws = pj.Workspace()
+    for _ in range(max(args.warmup, 1)):
+        pj.eigh_batched(A, ns, ws=ws)
+    steps = max(args.steps, 3)
+    dt, (W, V, st) = sync_time(torch, lambda: pj.eigh_batched(A, ns, ws=ws), steps)
+    Wn = W.cpu().numpy()
+    o, worst = 0, 0.0
+    for n, lam in zip(ns, lams):
+        worst = max(worst, float(np.abs(Wn[o:o + n] - lam).max() / np.abs(lam).max()))
+        o += n
+    # sweeps per matrix from single solves of a sample (same kernel), by order
+    g = np.random.default_rng(0)
+    idx = g.choice(len(ns), 120, replace=False)
+    sw = {}
+    for i in idx:
+        _, _, inf = pj.eigh(torch.tensor(mats[i], device="cuda"), return_info=True)
+        sw.setdefault(ns[i] // 16, []).append(inf["sweeps"])
+    mean_all = float(np.mean([x for v in sw.values() for x in v]))
+    flops = sum(6.0 * n ** 3 * float(np.mean(sw.get(n // 16, [mean_all]))) for n in ns)
+    avg_s = dt / steps
+    cpu = None
+    if not args.no_cpu_baseline:
+        import concurrent.futures as cf
+        sample = [mats[i] for i in g.choice(len(ns), 400, replace=False)]
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(os.cpu_count()) as ex:
+            list(ex.map(oracle.eigh, sample))
+        t = time.perf_counter() - t0
+        cpu = {"value": len(sample) / t, "unit": "matrices/s", "cores": os.cpu_count(),
+               "kind": "oracle", "sample": f"{len(sample)} random matrices of the batch, "
+                                           "one per task on a thread pool over all cores",
+               "host": host_info()}
+    return {
+        "metric": "matrices/s, 10000 clustered FP64 matrices n in [8,128], one persistent launch",
+        "value": round(steps * len(ns) / dt, 1), "unit": "matrices/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "clustered10000", "input": OTHER_WORKLOADS["clustered10000"],
+                   "path": "jacobi_eigh_batched (autotuned)", "matrices": len(ns)},
+        "accuracy": {"max_eig_err_vs_known_spectra": worst,
+                     "status_max": int(st.max().item()),
+                     "gate_passed": bool(worst <= 1e-13 and int(st.max().item()) == 0)},
+        "roofline": {"kernel": "lj::small_jacobi_kernel (persistent, atomic work queue)",
+                     "bound": "alu", "achieved": round(flops / avg_s / 1e12, 3),
+                     "peak": PEAK["f64"], "unit": "TFLOP/s",
+                     "frac": round(flops / avg_s / 1e12 / PEAK["f64"], 4), "traffic": None,
+                     "flops_per_launch": flops,
+                     "note": "flops = sum 6 n^3 x sweeps (12 n per rotation for the "
+                             "symmetric two-sided update and V, n^2/2 rotations per sweep); "
+                             "sweeps from single solves of 120 sampled matrices by order"},
+        "cpu_baseline": cpu,
+    }
+
+
+# --------------------------------------------------------- config 5 (adjoint)
+def bench_gapped(args, torch, pj):
+    import workloads as wl
+    import oracle
+    mats, lams, ws_, Cs = wl.gapped_batch(256, 256, 5)
+    n = 256
+    A = torch.tensor(mats, device="cuda")
+    w = torch.tensor(ws_, device="cuda")
+    C = torch.tensor(Cs, device="cuda")
+    wsp = pj.Workspace()
+    # forward per matrix (order 256: block path)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [pj.eigh(A[k], ws=wsp) for k in range(A.shape[0])]
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    W = torch.stack([o[0] for o in outs]).contiguous()
+    V = torch.stack([o[1] for o in outs]).contiguous()
+    # loss = sum w lam + <C, V>: dW = w, dV = C
+    for _ in range(max(args.warmup, 2)):
+        pj.eigh_backward(W, V, w, C, ws=wsp)
+    steps = max(args.steps, 10)
+    dt, dA = sync_time(torch, lambda: pj.eigh_backward(W, V, w, C, ws=wsp), steps)
+    avg_s = dt / steps
+    flops = 6.0 * n ** 3 * 256  # V^T dV, V M and (V M) V^T
+    # parity sample: the oracle's adjoint on two matrices
+    dAn = dA.cpu().numpy()
+    Wn, Vn = W.cpu().numpy(), V.cpu().numpy()
+    err = 0.0
+    for k in (0, 255):
+        ref, _ = oracle.eigh_backward(Wn[k], Vn[k], ws_[k], Cs[k])
+        err = max(err, float(np.abs(dAn[k] - ref).max() / np.abs(ref).max()))
+    return {
+        "metric": "backward ms per batch, 256 FP64 matrices n=256 (jacobi_eigh_backward)",
+        "value": round(1e3 * avg_s, 4), "unit": "ms", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * avg_s, 4), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "gapped256x256", "input": OTHER_WORKLOADS["gapped256x256"],
+                   "path": "jacobi_eigh_backward (batched FP64 GEMMs)", "batch": 256, "n": n},
+        "forward": {"ms_per_batch": round(1e3 * t_fwd, 2),
+                    "value": round(256 / t_fwd, 2), "unit": "eigendecomps/s",
+                    "path": "jacobi_eigh per matrix (block path)"},
+        "accuracy": {"max_rel_err_vs_oracle_adjoint_sample": err,
+                     "gate_passed": bool(err <= 1e-10)},
+        "roofline": {"kernel": "jacobi_eigh_backward (three batched gemm64 launches + "
+                               "elementwise)", "bound": "mfma",
+                     "achieved": round(flops / avg_s / 1e12, 3), "peak": PEAK["f64"],
+                     "unit": "TFLOP/s", "frac": round(flops / avg_s / 1e12 / PEAK["f64"], 4),
+                     "traffic": None, "flops_per_launch": flops,
+                     "note": "whole backward call (the elementwise steps included) against "
+                             "the FP64 MFMA peak"},
+        "cpu_baseline": None,
     }
 
 
@@ -172,7 +655,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="goe4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="goe4096",
+                    choices=sorted(MIXED_WORKLOADS) + sorted(OTHER_WORKLOADS))
+    ap.add_argument("--orth", default="ns", choices=sorted(ORTH))
+    ap.add_argument("--compare-orth", action="store_true")
+    ap.add_argument("--compare-ladder", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -198,175 +685,14 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": x.numel() * 8, "launches": 3}), flush=True)
         return
-
-    wl_name = args.workload
-    A, lam = make_input(wl_name)
-    n = A.shape[0]
-    At = torch.tensor(A, device="cuda")
-    opts = pj.make_opts()
-    topts = pj.make_opts(timing=1)  # per-kernel HIP events: separate, untimed pass
-    ws = pj.Workspace()
-
-    def run_mixed(o=opts):
-        return pj.eigh_mixed(At, opts=o, ws=ws, return_info=True)
-
-    def run_plain():
-        return pj.eigh(At, opts=opts, ws=ws, return_info=True)
-
-    for _ in range(args.warmup):
-        run_mixed()
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        W, V, info = run_mixed()
-        infos.append(info)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    value = args.steps / dt
-
-    plain = None
-    if not args.no_plain:
-        for _ in range(args.warmup):
-            run_plain()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        pinfos = []
-        for _ in range(args.steps):
-            Wp, Vp, pinfo = run_plain()
-            pinfos.append(pinfo)
-        torch.cuda.synchronize()
-        dtp = time.perf_counter() - t1
-        plain = {"value": args.steps / dtp, "ms_per_step": 1e3 * dtp / args.steps,
-                 "sweeps": pinfos[-1]["sweeps"], "orth_est": pinfos[-1]["orth_est"],
-                 "orth_refresh": pinfos[-1]["polished"],
-                 "skipped_tiles": pinfos[-1]["skipped_tiles"]}
-
-    # accuracy of the timed output (properties that hold at any size)
-    Wn, Vn = W.cpu().numpy(), V.cpu().numpy()
-    nrmF = np.linalg.norm(A)
-    acc = {
-        "residual_rel_F": float(np.linalg.norm(A @ Vn - Vn * Wn) / nrmF),
-        "residual_bar": 1e-13 * n,
-        "orth_F": float(np.linalg.norm(Vn.T @ Vn - np.eye(n))),
-        "orth_bar": 1e-14 * n,
-        "trace_rel_err": float(abs(Wn.sum() - np.trace(A)) / np.abs(A).sum()),
-        "frobenius_rel_err": float(abs(math.sqrt((Wn ** 2).sum()) - nrmF) / nrmF),
-    }
-    if lam is not None:
-        acc["eig_err_vs_known_spectrum"] = float(np.abs(Wn - lam).max() / np.abs(lam).max())
-    gold = os.path.join(ROOT, "tests", "golden", f"oracle_{wl_name}.txt")
-    if os.path.exists(gold):
-        Wo = np.loadtxt(gold, ndmin=2)[:, 0]
-        acc["eig_err_vs_oracle"] = float(np.abs(Wn - Wo).max() / np.abs(Wo).max())
-        if lam is not None:
-            acc["oracle_err_vs_known_spectrum"] = float(np.abs(Wo - lam).max() / np.abs(lam).max())
-        acc["eig_bar"] = 1e-13
-    if plain is not None:
-        acc["mixed_vs_plain_max_dW_rel"] = float(
-            np.abs(Wn - Wp.cpu().numpy()).max() / np.abs(Wn).max())
-    gate = acc["residual_rel_F"] <= acc["residual_bar"] and acc["orth_F"] <= acc["orth_bar"]
-    if "eig_err_vs_known_spectrum" in acc:
-        # the exact spectrum decides; the oracle's stored eigenvalues (the
-        # diagonal after its sweeps) are themselves ~2.5e-13 off at n = 1024
-        gate = gate and acc["eig_err_vs_known_spectrum"] <= 1e-13
-    elif "eig_err_vs_oracle" in acc:
-        gate = gate and acc["eig_err_vs_oracle"] <= 1e-13
-    acc["gate_passed"] = bool(gate)
-
-    # roofline of the dominant update kernel, from the in-library HIP events of
-    # one instrumented (untimed) solve: events around every launch on its stream
-    infos = [run_mixed(topts)[2]]
-    torch.cuda.synchronize()
-    last = infos[-1]
-    b = last["block"]
-
-    def tot(key, idx):
-        return sum(i[key][idx] for i in infos)
-
-    cands = {
-        "apply_B_f32": (tot("t_apply_ms", 1), tot("n_apply", 1), "B", "f32"),
-        "apply_V_f32": (tot("t_applyv_ms", 1), tot("n_applyv", 1), "V", "f32"),
-        "apply_B_f64": (tot("t_apply_ms", 0), tot("n_apply", 0), "B", "f64"),
-        "apply_V_f64": (tot("t_applyv_ms", 0), tot("n_applyv", 0), "V", "f64"),
-    }
-    kern_ms = {k: round(v[0], 2) for k, v in cands.items()}
-    kern_ms["pair_solve_f32"] = round(tot("t_pair_ms", 1), 2)
-    kern_ms["pair_solve_f64"] = round(tot("t_pair_ms", 0), 2)
-    # the FP32 V update runs inside the pair-solve launch in the timed solves
-    # (the instrumented solve times it as its own kernel), so the dominant
-    # kernel is taken among the update kernels the timed solves launch as such
-    dom = max((k for k in cands if k != "apply_V_f32"), key=lambda k: cands[k][0])
-    t_ms, cnt, part, dtype = cands[dom]
-    avg_s = t_ms / max(cnt, 1) / 1e3
-    elem = 4 if dtype == "f32" else 8
-    flops = apply_flops(n, b, part)
-    nbytes = apply_bytes(n, b, elem, part)
-    # the bound is whichever floor is higher for this launch's algorithmic work
-    mfma_bound = flops / (PEAK[dtype] * 1e12) >= nbytes / (HBM_PEAK * 1e9)
-    names = {("B", "f32"): "update_b_kernel<float, 64>",
-             ("V", "f32"): "update_v_kernel<float, 64>",
-             ("B", "f64"): "update_b_kernel<double, 64>",
-             ("V", "f64"): "update_v_kernel<double, 64>"}
-    achieved = flops / avg_s / 1e12 if mfma_bound else nbytes / avg_s / 1e9
-    peak = PEAK[dtype] if mfma_bound else HBM_PEAK
-    roofline = {
-        "kernel": "lj::" + names[(part, dtype)] + (" (off-diagonal B tiles)" if part == "B"
-                                                   else " (V row tiles)"),
-        "bound": "mfma" if mfma_bound else "hbm",
-        "achieved": round(achieved, 2),
-        "peak": peak,
-        "unit": "TFLOP/s" if mfma_bound else "GB/s",
-        "frac": round(achieved / peak, 4),
-        "traffic": measured_traffic(names[(part, dtype)], wl_name),
-        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-probe scaled)",
-        "avg_launch_us": round(avg_s * 1e6, 2),
-        "launches": cnt,
-        "flops_per_launch": flops,
-        "bytes_per_launch": nbytes,
-        "achieved_TFLOPs": round(flops / avg_s / 1e12, 2),
-        "achieved_GBps": round(nbytes / avg_s / 1e9, 1),
-        "kernel_ms_per_step": kern_ms,
-    }
-
-    cpu = None
-    # the oracle's sweep count is known (fixture) or fitted (GOE runs) only
-    # for these two workloads; the others report no CPU baseline
-    if not args.no_cpu_baseline and wl_name in ("goe4096", "geo1024"):
-        cpu = cpu_baseline(wl_name, A)
-
-    out = {
-        "metric": METRIC,
-        "value": round(value, 4),
-        "unit": "eigendecomps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1e3 * dt / args.steps, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {
-            "workload": wl_name,
-            "n": n,
-            "input": WORKLOADS[wl_name]["desc"],
-            "path": "jacobi_eigh_mixed",
-            "block": b,
-            "sweeps32": last["sweeps32"],
-            "sweeps64": last["sweeps"],
-            "ns_iters": last["ns_iters"],
-            "orth_est": last["orth_est"],
-            "orth_refresh": last["polished"],
-            "skipped_tiles": last["skipped_tiles"],
-        },
-        "plain_fp64": plain,
-        "speedup_vs_plain": None if plain is None else round(value / plain["value"], 3),
-        "accuracy": acc,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-    }
+    if args.workload in MIXED_WORKLOADS:
+        out = bench_mixed(args, torch, pj)
+    elif args.workload == "uniform64":
+        out = bench_uniform64(args, torch, pj)
+    elif args.workload == "clustered10000":
+        out = bench_clustered(args, torch, pj)
+    else:
+        out = bench_gapped(args, torch, pj)
     print(json.dumps(out), flush=True)
 
 

@@ -117,6 +117,19 @@ typedef struct jacobi_opts {
                                (nonzero only near n = 4096 in FP64), -1 = none,
                                k > 0 = k tiles (at most what leaves every V
                                workgroup one tile) */
+    int32_t orth;           /* mixed path, how Q_l becomes Q_d: 0 (default) =
+                               Newton-Schulz (Algorithm 8, Section 4.3.4);
+                               1 = Q of the Householder QR of Q_l (Algorithm 5,
+                               Section 4.2), blocked; 2 = Q of its Cholesky QR
+                               (X^T X = R^T R, Q = X R^-1).  1 and 2 are the
+                               comparators of Section 4.4 */
+    int32_t ladder;         /* mixed path: 1 = a binary16 stage first (the
+                               lower-precision ladder named as further work,
+                               Chapter 6): Jacobi sweeps with every stored
+                               entry of B rounded to binary16 (FP32 arithmetic,
+                               FP64 angles, V in FP32) until a sweep lowers off
+                               by less than 10%, then B = Q_h^T A Q_h and the FP32
+                               stage from V = Q_h; 0 (default) = none */
 } jacobi_opts;
 
 /* Diagnostics filled on return (host struct, may be NULL). */
@@ -134,7 +147,7 @@ typedef struct jacobi_info {
                                pair of the tile rotated in that round (U = I
                                there; the results are unchanged), summed over
                                the sweeps (a diagnostic: wraps past 2^31 - 1) */
-    int32_t reserved_i[1];
+    int32_t sweeps16;       /* binary16-stage sweeps (mixed path with opts->ladder) */
     double norm_f;          /* ||A||_F of the symmetrised input */
     double tol;             /* absolute threshold on off(B) actually used */
     double off_final;       /* off(B) when the FP64 stage stopped */
@@ -147,8 +160,12 @@ typedef struct jacobi_info {
                                columns, before any Newton-Schulz step (4
                                Rademacher probes) */
     /* with opts->timing: summed kernel time (ms) and launch counts of the
-     * block path, index 0 = FP64 stage, 1 = FP32 stage; "apply" is the update
-     * of the off-diagonal tiles of B, "applyv" the update of V */
+     * block path, index 0 = FP64 stage, 1 = FP32 stage; "pair" is the launch
+     * of a round's pair solves (with serial_v = 0 it also carries the previous
+     * round's V update, as in untimed solves), "apply" the update of the
+     * off-diagonal tiles of B, "applyv" a V update launched on its own (with
+     * serial_v = 0 only the last round of each stage; the other rounds count
+     * as zero-length launches) */
     double t_pair_ms[2];
     double t_apply_ms[2];
     double t_applyv_ms[2];
@@ -156,7 +173,11 @@ typedef struct jacobi_info {
     int32_t n_apply[2];
     int32_t n_applyv[2];
     int32_t reserved_i2[2];
-    double reserved_d[3];
+    double orth_qd;         /* with opts->timing, mixed path: ||Q_d^T Q_d - I||_F of
+                               the orthogonaliser's output (0 otherwise) */
+    double t_orth_ms;       /* with opts->timing, mixed path: time of the Q_l -> Q_d
+                               step (HIP events on `stream`) */
+    double off16;           /* off(B) when the binary16 stage stopped (ladder) */
 } jacobi_info;
 
 /* Plain FP64 Jacobi eigendecomposition (Algorithm 4, Section 3.3, run as a

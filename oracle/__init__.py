@@ -229,7 +229,7 @@ def round_half(x: float) -> float:
     return _load().orc_round_half(float(x))
 
 
-def jacobi_cyclic_h(A, tol_abs: float = 0.0, rel_eps: float = U_H, stall: float = 0.5,
+def jacobi_cyclic_h(A, tol_abs: float = 0.0, rel_eps: float = U_H, stall: float = 0.9,
                     max_sweeps: int = 30, V0=None):
     """The binary16 stage: Algorithm 4 with A stored in binary16 (every update
     rounded), float angles and float V.  A is rounded to binary16 first.

@@ -32,6 +32,7 @@ thread_local hipError_t g_last_error = hipSuccess;
 
 constexpr double U_D = 0x1p-53; // unit roundoff, double
 constexpr double U_L = 0x1p-24; // unit roundoff, single
+constexpr double U_H = 0x1p-11; // unit roundoff, binary16
 
 // JACOBI_TRACE set in the environment: one line per block-path sweep on stderr
 bool trace_on()
@@ -42,7 +43,7 @@ bool trace_on()
 
 struct Opts {
     int max_sweeps, block, inner, ns_iters, check_sym, small_max_n, threads, timing, schedule,
-        serial_v, tune, graph, pair_skip, gemm_slots, pair_v_split;
+        serial_v, tune, graph, pair_skip, gemm_slots, pair_v_split, orth, ladder;
     double c32;
 };
 
@@ -64,6 +65,8 @@ int resolve_opts(const jacobi_opts *o, Opts &r)
     r.pair_skip = 1;
     r.gemm_slots = 0;
     r.pair_v_split = 0;
+    r.orth = 0;
+    r.ladder = 0;
     // 0.1: the FP32 stage runs into its quadratic phase, to a few times its
     // rounding floor (off(Q_d^T A Q_d) settles near 0.05 n u_l ||A||_F), which
     // saves FP64 sweeps that cost more than the FP32 ones (measured on GOE and
@@ -89,6 +92,12 @@ int resolve_opts(const jacobi_opts *o, Opts &r)
     if (o->pair_v_split < -1 || o->pair_v_split > (1 << 16))
         return 1;
     r.pair_v_split = o->pair_v_split;
+    if (o->orth < 0 || o->orth > 2)
+        return 1;
+    r.orth = o->orth;
+    if (o->ladder < 0 || o->ladder > 1)
+        return 1;
+    r.ladder = o->ladder;
     if (o->max_sweeps < 0 || o->max_sweeps > 1000)
         return 1;
     if (o->max_sweeps)
@@ -191,6 +200,7 @@ struct BlockWs {
     double *B64, *V64, *U64, *X2, *R, *Vt, *A0, *probe;
     float *B32, *V32, *U32;
     double *partial, *scal, *wtmp, *sg, *cmax, *csq, *cinv;
+    double *orth; // mixed: Cholesky block inverses / Householder factors and scratch
     int *flags, *perm, *cidx;
     int *prot; // per-pair rotation flags of a round, double-buffered like U
     int2 *pairs, *psmap;
@@ -224,6 +234,8 @@ BlockWs layout_block(Bump &bp, int64_t n, const Geometry &g, bool mixed)
         w.B32 = bp.take<float>(nn);
         w.V32 = bp.take<float>(nn);
         w.U32 = bp.take<float>(2 * uu);
+        // max(ceil(npad / 64) 64^2, ceil(npad / 16) 16^2 + 2 * 16 npad)
+        w.orth = bp.take<double>((size_t)(g.npad + ORTH_CB) * ORTH_CB);
     }
     w.partial = bp.take<double>(partial_count(g));
     w.scal = bp.take<double>(8);
@@ -568,7 +580,7 @@ struct SideStream {
 template <typename T>
 int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U, double tol,
                double eps, int max_sweeps, int inner, int schedule, int serial_v,
-               bool pair_skip, bool fp32_stage, int vsplit,
+               bool pair_skip, int stage, int vsplit,
                hipStream_t s,
                SideStream &ss, int *sweeps_out, double *off_out, double *off0_out,
                RoundTimer *tm, int *skipped_out)
@@ -602,7 +614,7 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
     // precisions; each cross-stream event adds a gap of several microseconds,
     // and a pair solve beside a running V update slows down.
     const bool side = serial_v == 2;
-    const bool fuse = serial_v == 0 && !(tm && tm->on);
+    const bool fuse = serial_v == 0;
     const int2 *vpend_pairs = nullptr; // V update waiting for the next launch
     const T *vpend_U = nullptr;
     const int *vpend_prot = nullptr;
@@ -632,12 +644,14 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
             const int2 *map = w.psmap + (cross ? (size_t)g.b * (g.b + 1) / 2 : 0);
             if (vpend_pairs) {
                 CK(launch_pair_solve_v<T>(B, g.npad, g.b, g.npairs, pr, map, Ub, eps, thr, inner,
-                                          cross, w.partial, w.flags + 2, pf, V, g.npad,
-                                          g.npad, vpend_pairs, vpend_U, vpend_prot, s, vsplit));
+                                          stage == 2, cross, w.partial, w.flags + 2, pf, V, g.npad,
+                                          g.npad, vpend_pairs, vpend_U, vpend_prot, s, vsplit,
+                                          timed ? tm->ev[6 * r] : nullptr,
+                                          timed ? tm->ev[6 * r + 1] : nullptr));
                 vpend_pairs = nullptr;
             } else {
                 CK(launch_pair_solve<T>(B, g.npad, g.b, g.npairs, pr, map, Ub, eps, thr, inner,
-                                        cross, w.partial, w.flags + 2, pf, s,
+                                        stage == 2, cross, w.partial, w.flags + 2, pf, s,
                                         timed ? tm->ev[6 * r] : nullptr,
                                         timed ? tm->ev[6 * r + 1] : nullptr));
             }
@@ -645,13 +659,17 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
                 CK(hipEventRecord(ss.evU[j], s));
             CK(launch_update_b<T>(B, g.npad, g.b, g.npairs, pr, Ub,
                                   w.partial + (size_t)g.npairs * pair_solve_waves(g.M),
-                                  r == g.N - 2, pfc, w.flags + 3, s,
+                                  r == g.N - 2, stage == 2, pfc, w.flags + 3, s,
                                   timed ? tm->ev[6 * r + 2] : nullptr,
                                   timed ? tm->ev[6 * r + 3] : nullptr));
             if (fuse) {
                 vpend_pairs = pr;
                 vpend_U = Ub;
                 vpend_prot = pfc;
+                if (timed) { // this round's V update is timed inside the next launch
+                    CK(hipEventRecord(tm->ev[6 * r + 4], s));
+                    CK(hipEventRecord(tm->ev[6 * r + 5], s));
+                }
                 continue;
             }
             hipStream_t sv = side ? ss.s2 : s;
@@ -682,15 +700,18 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
         off = std::sqrt(rb.scal[1]);
         if (trace_on())
             std::fprintf(stderr, "jacobi: %s sweep %d off %.3e rotated %d\n",
-                         fp32_stage ? "fp32" : "fp64", sweeps, off, rb.flags[2]);
+                         stage == 2 ? "fp16" : (stage == 1 ? "fp32" : "fp64"), sweeps, off,
+                         rb.flags[2]);
         if (!std::isfinite(off)) {
             status = JACOBI_NONFINITE;
             break;
         }
         if (!rb.flags[2])
             break; // no pair rotated: converged by the per-pair test
-        if (fp32_stage && off >= prev)
-            break;
+        if (stage == 1 && off >= prev)
+            break; // the FP32 rounding floor
+        if (stage == 2 && off > 0.9 * prev)
+            break; // the binary16 rounding floor: a sweep lowers off by less than 10%
     }
     if (vpend_pairs)
         CK(launch_update_v<T>(V, g.npad, g.npad, g.b, g.npairs, vpend_pairs, vpend_U, vpend_prot,
@@ -879,7 +900,8 @@ int scale_exponent(double amax) { return scale_exp_of(amax); }
 // symmetry checks, the scaling exponent ks (B, and copy when not null, then
 // hold 2^ks sym(A)) and ||B||_F of the scaled matrix.
 int ingest_norm(const double *A, int64_t lda, int64_t n, const Geometry &g, const BlockWs &w,
-                double *B, double *copy, int check_sym, hipStream_t s, double &normf, int &ks)
+                double *B, double *copy, int check_sym, hipStream_t s, double &normf, int &ks,
+                double *amax_out = nullptr)
 {
     CK(launch_ingest<double>(A, lda, n, B, g.npad, w.partial, w.flags, check_sym, s));
     CK(launch_sum(w.partial, INGEST_BLOCKS, w.scal, s));
@@ -892,6 +914,8 @@ int ingest_norm(const double *A, int64_t lda, int64_t n, const Geometry &g, cons
     if (check_sym && rb.flags[1])
         return JACOBI_NOTSYM;
     ks = scale_exponent(rb.scal[4]);
+    if (amax_out)
+        *amax_out = std::ldexp(rb.scal[4], ks);
     if (ks) {
         const int64_t nn = g.npad * g.npad;
         CK(launch_scale_pow2(B, nn, ks, copy, s));
@@ -939,7 +963,7 @@ int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, in
     if (int e = ss.init())
         return e;
     int st = run_sweeps<double>(g, n, w, w.B64, w.V64, w.U64, tol, U_D, o.max_sweeps, o.inner,
-                                o.schedule, o.serial_v, o.pair_skip, false, o.pair_v_split, s,
+                                o.schedule, o.serial_v, o.pair_skip, 0, o.pair_v_split, s,
                                 ss, &sweeps, &off, nullptr, &tm, &skipped);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;
@@ -975,75 +999,168 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     const int64_t nn = g.npad * g.npad;
     // ingest: A64 = sym(A) (kept for the preconditioning product), B32 = fl32(A64)
     double *A64 = w.B64;
-    double normf = 0.0;
+    double normf = 0.0, amax = 0.0;
     int ks = 0;
-    if (int e = ingest_norm(A, lda, n, g, w, A64, nullptr, o.check_sym, s, normf, ks))
+    if (int e = ingest_norm(A, lda, n, g, w, A64, nullptr, o.check_sym, s, normf, ks, &amax))
         return e;
-    CK(launch_cast_f32(A64, w.B32, nn, s));
+    RoundTimer tm32, tm64, tm16;
+    tm32.on = tm64.on = tm16.on = o.timing;
+    SideStream ss;
+    if (int e = ss.init())
+        return e;
     CK(launch_eye<float>(w.V32, g.npad, s));
+    // stage 0 (ladder = 1): the binary16 stage.  Its matrix is fl16(2^kh A),
+    // scaled by an exact power of two so that the largest entry lies in
+    // [1, 2) (the entries of the iterates stay below ||A||_2 <= n max|a_ij|,
+    // inside the binary16 range for n up to 2^14), every stored entry rounded to
+    // binary16; V accumulates in FP32.  It stops when a sweep lowers off by
+    // less than 10% (the binary16 rounding floor; early sweeps of a dense
+    // matrix can lower it by only about a half) or at off <= 0.01 n u_h ||A||_F.  Then
+    // B32 = fl32(Q_h^T A Q_h) (FP64 products) and the FP32 stage continues from
+    // V = Q_h.
+    int sw16 = 0;
+    double off16 = 0.0;
+    if (o.ladder == 1) {
+        int e2 = 0;
+        std::frexp(amax > 0.0 ? amax : 1.0, &e2);
+        const int kh = 1 - e2;
+        CK(launch_cast_f32_scaled(A64, w.B32, nn, kh, 1, s));
+        const double tol16 = 0.01 * (double)n * U_H * std::ldexp(normf, kh);
+        int st16 = run_sweeps<float>(g, n, w, w.B32, w.V32, w.U32, tol16, U_H, o.max_sweeps,
+                                     o.inner, o.schedule, o.serial_v, o.pair_skip, 2,
+                                     o.pair_v_split, s, ss, &sw16, &off16, nullptr, &tm16,
+                                     nullptr);
+        if (st16 == JACOBI_DEVICE || st16 == JACOBI_NONFINITE)
+            return st16;
+        off16 = std::ldexp(off16, -kh);
+        double *Xh = w.V64, *T = w.R, *Bh = w.X2;
+        CK(launch_widen_f64(w.V32, Xh, nn, s));
+        CK(launch_gemm64(0, 0, g.npad, g.npad, g.npad, 1.0, A64, g.npad, 0, Xh, g.npad, 0, 0.0,
+                         nullptr, 0, 0, 0.0, T, g.npad, 0, 1, s));
+        CK(launch_gemm64_sym(1, 0, g.npad, g.npad, 1.0, Xh, g.npad, T, g.npad, 0.0, nullptr, 0,
+                             0.0, Bh, g.npad, s));
+        CK(launch_cast_f32(Bh, w.B32, nn, s));
+    } else {
+        CK(launch_cast_f32(A64, w.B32, nn, s));
+    }
     // stage 1: FP32 Jacobi -> Q_l
     const double tol32 = o.c32 * (double)n * U_L * normf;
     int sw32 = 0;
     double off32 = 0.0;
-    RoundTimer tm32, tm64;
-    tm32.on = tm64.on = o.timing;
-    SideStream ss;
-    if (int e = ss.init())
-        return e;
     int st32 = run_sweeps<float>(g, n, w, w.B32, w.V32, w.U32, tol32, U_L, o.max_sweeps,
-                                 o.inner, o.schedule, o.serial_v, o.pair_skip, true,
+                                 o.inner, o.schedule, o.serial_v, o.pair_skip, 1,
                                  o.pair_v_split, s, ss, &sw32, &off32, nullptr, &tm32, nullptr);
     if (st32 == JACOBI_DEVICE || st32 == JACOBI_NONFINITE)
         return st32;
-    // stage 2: Newton-Schulz, X <- X + X (I - X^T X) / 2  (= X (3I - X^T X) / 2)
+    // stage 2: Q_l -> Q_d.  Newton-Schulz (default): X <- X + X (I - X^T X) / 2
+    // (= X (3I - X^T X) / 2); or the Q factor of a Householder or Cholesky QR
+    // of Q_l.  Qd ends in one of V64 / X2 / R, T1 and T2 are the two others
+    // (free n_pad^2 buffers for the products below).
     double *X = w.V64, *X2 = w.X2, *R = w.R;
     CK(launch_widen_f64(w.V32, X, nn, s));
-    const int fixed = o.ns_iters > 0 ? o.ns_iters : (n < 52000 ? 2 : 3);
-    const bool adaptive = o.ns_iters == -1;
-    const int max_it = adaptive ? 3 : fixed;
+    hipEvent_t eo0 = nullptr, eo1 = nullptr;
+    if (o.timing) {
+        CK(hipEventCreate(&eo0));
+        CK(hipEventCreate(&eo1));
+        CK(hipEventRecord(eo0, s));
+    }
+    double *Qd = X, *T1 = R, *T2 = X2;
     int ns = 0;
     double orth = 0.0;
-    for (int it = 0; it < max_it; ++it) {
-        CK(launch_gemm64_sym(1, 0, g.npad, g.npad, -1.0, X, g.npad, X, g.npad, 0.0, nullptr, 0,
-                             1.0, R, g.npad, s, X2, nn, o.gemm_slots));
-        if (adaptive || it == max_it - 1) {
-            CK(launch_sq_partial(R, nn, w.partial, s));
-            CK(launch_sum(w.partial, OFF_BLOCKS, w.scal + 2, s));
-            Readback rb;
-            if (int e = read_scalars(w, s, rb))
-                return e;
-            orth = std::sqrt(rb.scal[2]);
-            if (adaptive && orth <= (double)n * U_D)
-                break;
+    if (o.orth == 1) {
+        double *Ts = w.orth, *Wb = Ts + (g.npad / ORTH_HB + 1) * ORTH_HB * ORTH_HB,
+               *W2b = Wb + (size_t)ORTH_HB * g.npad;
+        CK(householder_qr(X, X2, R, g.npad, g.npad, Ts, Wb, W2b, s));
+        Qd = X2;
+        T1 = R;
+        T2 = X;
+    } else if (o.orth == 2) {
+        CK(launch_fill_i32(w.flags + 4, 1, 0, s));
+        CK(cholesky_qr(X, R, R, X2, g.npad, g.npad, w.orth, w.flags + 4, s));
+        Qd = R;
+        T1 = X;
+        T2 = X2;
+    } else {
+        const int fixed = o.ns_iters > 0 ? o.ns_iters : (n < 52000 ? 2 : 3);
+        const bool adaptive = o.ns_iters == -1;
+        const int max_it = adaptive ? 3 : fixed;
+        for (int it = 0; it < max_it; ++it) {
+            CK(launch_gemm64_sym(1, 0, g.npad, g.npad, -1.0, X, g.npad, X, g.npad, 0.0, nullptr,
+                                 0, 1.0, R, g.npad, s, X2, nn, o.gemm_slots));
+            if (adaptive || it == max_it - 1) {
+                CK(launch_sq_partial(R, nn, w.partial, s));
+                CK(launch_sum(w.partial, OFF_BLOCKS, w.scal + 2, s));
+                Readback rb;
+                if (int e = read_scalars(w, s, rb))
+                    return e;
+                orth = std::sqrt(rb.scal[2]);
+                if (adaptive && orth <= (double)n * U_D)
+                    break;
+            }
+            CK(launch_gemm64(0, 0, g.npad, g.npad, g.npad, 0.5, X, g.npad, 0, R, g.npad, 0, 1.0,
+                             X, g.npad, 0, 0.0, X2, g.npad, 0, 1, s));
+            std::swap(X, X2);
+            ++ns;
         }
-        CK(launch_gemm64(0, 0, g.npad, g.npad, g.npad, 0.5, X, g.npad, 0, R, g.npad, 0, 1.0, X,
-                         g.npad, 0, 0.0, X2, g.npad, 0, 1, s));
-        std::swap(X, X2);
-        ++ns;
+        Qd = X;
+        T1 = R;
+        T2 = X2;
+    }
+    double orth_qd = 0.0, t_orth = 0.0;
+    if (o.timing) {
+        CK(hipEventRecord(eo1, s));
+        // ||Q_d^T Q_d - I||_F of the orthogonaliser's output (diagnostic)
+        CK(launch_gemm64_sym(1, 0, g.npad, g.npad, -1.0, Qd, g.npad, Qd, g.npad, 0.0, nullptr, 0,
+                             1.0, T1, g.npad, s, T2, nn, o.gemm_slots));
+        CK(launch_sq_partial(T1, nn, w.partial, s));
+        CK(launch_sum(w.partial, OFF_BLOCKS, w.scal + 5, s));
+        Readback rb;
+        if (int e = read_scalars(w, s, rb))
+            return e;
+        orth_qd = std::sqrt(rb.scal[5]);
+        float ms = 0.0f;
+        CK(hipEventElapsedTime(&ms, eo0, eo1));
+        t_orth = ms;
+        hipEventDestroy(eo0);
+        hipEventDestroy(eo1);
+    }
+    if (o.orth == 2) {
+        Readback rb;
+        if (int e = read_scalars(w, s, rb))
+            return e;
+        if (rb.flags[4])
+            return JACOBI_NONFINITE; // Q_l^T Q_l not positive definite
     }
     // stage 3: B = Q_d^T A Q_d, symmetric by construction (upper tiles of the
     // second product mirrored), then FP64 Jacobi from V = Q_d
-    CK(launch_gemm64(0, 0, g.npad, g.npad, g.npad, 1.0, A64, g.npad, 0, X, g.npad, 0, 0.0,
-                     nullptr, 0, 0, 0.0, R, g.npad, 0, 1, s));
-    CK(launch_gemm64_sym(1, 0, g.npad, g.npad, 1.0, X, g.npad, R, g.npad, 0.0, nullptr, 0, 0.0,
-                         A64, g.npad, s, X2, nn, o.gemm_slots));
+    CK(launch_gemm64(0, 0, g.npad, g.npad, g.npad, 1.0, A64, g.npad, 0, Qd, g.npad, 0, 0.0,
+                     nullptr, 0, 0, 0.0, T1, g.npad, 0, 1, s));
+    CK(launch_gemm64_sym(1, 0, g.npad, g.npad, 1.0, Qd, g.npad, T1, g.npad, 0.0, nullptr, 0, 0.0,
+                         A64, g.npad, s, T2, nn, o.gemm_slots));
+    X = Qd;
     const double tol = tol_in > 0.0 ? std::ldexp(tol_in, ks) : 1e-15 * (double)n * normf;
     int sw64 = 0, skipped = 0;
     double off = 0.0, offc = 0.0;
     int st = run_sweeps<double>(g, n, w, A64, X, w.U64, tol, U_D, o.max_sweeps, o.inner,
-                                o.schedule, o.serial_v, o.pair_skip, false, o.pair_v_split, s,
+                                o.schedule, o.serial_v, o.pair_skip, 0, o.pair_v_split, s,
                                 ss, &sw64, &off, &offc, &tm64, &skipped);
     if (st == JACOBI_DEVICE || st == JACOBI_NONFINITE)
         return st;
     double est = 0.0;
     int pol = 0;
-    if (int e = finalize_block(g, n, w, A64, X, A64, w.R, W, V, ldv, s, &est, &pol))
+    if (int e = finalize_block(g, n, w, A64, X, A64, T1, W, V, ldv, s, &est, &pol))
         return e;
     if (ks)
         CK(launch_scale_pow2(W, n, -ks, nullptr, s));
     CK(hipStreamSynchronize(s));
     fill_info(info, sw64, sw32, ns, 1, g.b, normf, tol, off, off32, offc, orth);
     unscale_info(info, ks);
+    if (info) {
+        info->orth_qd = orth_qd;
+        info->t_orth_ms = t_orth;
+        info->sweeps16 = sw16;
+        info->off16 = std::ldexp(off16, -ks);
+    }
     if (info) {
         info->orth_est = est;
         info->polished = pol;

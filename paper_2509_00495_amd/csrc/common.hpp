@@ -122,6 +122,22 @@ __device__ inline void jacobi_angle_fast(double app, double aqq, double apq, dou
     s = t * c;
 }
 
+// A value as the stage stores it: FP32 data of the binary16 stage (r16 set)
+// are rounded to the nearest binary16 value (ties to even, the hardware
+// conversion) and held widened in FP32; every other stage stores as is.
+template <typename T>
+__device__ inline T store_round(T x, int r16);
+template <>
+__device__ inline float store_round<float>(float x, int r16)
+{
+    return r16 ? (float)(_Float16)x : x;
+}
+template <>
+__device__ inline double store_round<double>(double x, int)
+{
+    return x;
+}
+
 // Per-pair test: rotate only when a_pq is not negligible relative to the
 // diagonal (the per-pair threshold of Algorithm 4 with tol = eps) and above
 // the absolute floor thr = tol_off / n (if every |a_pq| <= tol_off / n then

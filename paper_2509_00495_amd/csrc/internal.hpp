@@ -35,6 +35,19 @@ hipError_t launch_small(const double *A, double *W, double *V, const SmallDesc *
                         hipStream_t stream);
 int small_max_active(int m_max, int pool, int nthreads);
 
+// a launch with nothing to do: its timing events (if any) are recorded back
+// to back, so that reading them gives zero instead of an error
+inline hipError_t record_pair(hipEvent_t e0, hipEvent_t e1, hipStream_t s)
+{
+    if (e0) {
+        hipError_t e = hipEventRecord(e0, s);
+        if (e != hipSuccess)
+            return e;
+        return hipEventRecord(e1, s);
+    }
+    return hipSuccess;
+}
+
 // Launch on `s`; with e0 and e1 (timing events) the launch records them at the
 // kernel's own start and end (hipExtLaunchKernel), so their difference is the
 // kernel's duration without the gaps that separate event records add.
@@ -51,7 +64,7 @@ inline void launch_timed(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStrea
 // ---- block path (kernels_block.hip); T = double or float
 template <typename T>
 hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
-                             const int2 *psmap, T *U, double eps, double thr, int inner,
+                             const int2 *psmap, T *U, double eps, double thr, int inner, int r16,
                              int cross, double *partial, int *rot_flag, int *prot,
                              hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // the same pair solves, plus the V update V[:, cols] <- V[:, cols] vU of the
@@ -61,9 +74,10 @@ hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *p
 template <typename T>
 hipError_t launch_pair_solve_v(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                                const int2 *psmap, T *U, double eps, double thr, int inner,
-                               int cross, double *partial, int *rot_flag, int *prot, T *V,
+                               int r16, int cross, double *partial, int *rot_flag, int *prot, T *V,
                                int64_t ldv, int64_t nrows, const int2 *vpairs, const T *vU,
-                               const int *vprot, hipStream_t s, int vsplit = 0);
+                               const int *vprot, hipStream_t s, int vsplit = 0,
+                               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // experiments: V workgroups of the shared launch (0 = default), a minimum
 // dynamic LDS per workgroup (larger keeps one workgroup per compute unit) and
 // the working wavefronts per V workgroup (0 = all)
@@ -72,6 +86,8 @@ void tune_pair_v(int wgs, size_t lds, int waves);
 constexpr int pair_solve_waves(int M) { return M == 64 ? 16 : 4; }
 // thread -> block map of the pair solve (b(b+1)/2 entries for M = 2b)
 void pair_solve_map(int M, int cross, int2 *out);
+// r16 (FP32 data only): every stored entry of B is rounded to binary16 (the
+// binary16 stage of the precision ladder).
 // B_kl <- U_k^T B_kl U_l (into B's upper blocks) for every two pairs k < l of
 // the round; tile t = l (l - 1) / 2 + k; partial[t (2b / 16) + w] gets twice
 // the squared sum of wavefront w's part of tile t when want_off.  With the
@@ -79,7 +95,7 @@ void pair_solve_map(int M, int cross, int2 *out);
 // unrotated pairs are left out and counted into *skipped (kernels_update.hip)
 template <typename T>
 hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pairs, const T *U,
-                           double *partial, int want_off, const int *prot, int *skipped,
+                           double *partial, int want_off, int r16, const int *prot, int *skipped,
                            hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <typename T>
 int update_b_blocks_per_cu(int b);
@@ -110,6 +126,8 @@ hipError_t launch_off2_partial(const T *B, int64_t npad, double *partial, hipStr
 hipError_t launch_fill_i32(int *p, int64_t count, int value, hipStream_t s);
 hipError_t launch_cast_f32(const double *src, float *dst, int64_t count, hipStream_t s);
 hipError_t launch_widen_f64(const float *src, double *dst, int64_t count, hipStream_t s);
+hipError_t launch_cast_f32_scaled(const double *src, float *dst, int64_t count, int k, int r16,
+                                  hipStream_t s);
 hipError_t launch_diag(const double *B, int64_t ldb, int64_t n, double *w, hipStream_t s);
 // w_k = inv_k^2 sum_i V[i][k] T[i][k] (Rayleigh quotients of the normalized
 // columns when T = A V); part holds 16 n doubles
@@ -167,5 +185,18 @@ hipError_t launch_adjoint_mid(double *M, const double *W, const double *dW, int6
                               hipStream_t s);
 hipError_t launch_sym_out(const double *G, double *dA, int64_t n, int64_t ld, int64_t batch,
                           hipStream_t s);
+
+// ---- orthogonalisers (orthogonalize.hip): Q from a QR factorisation of X,
+// n x n with leading dimension ld, X destroyed
+constexpr int ORTH_CB = 64; // diagonal block order of the blocked Cholesky
+constexpr int ORTH_HB = 16; // panel width of the blocked Householder QR
+// Cholesky QR: G scratch (may alias Q), Rf receives R's upper triangle, Rinv
+// ceil(n / 64) 64 x 64 blocks, bad set when a pivot is not positive
+hipError_t cholesky_qr(double *X, double *Q, double *G, double *Rf, int64_t n, int64_t ld,
+                       double *Rinv, int *bad, hipStream_t s);
+// Householder QR: Vs (n x n, ld) keeps the reflectors, Ts ceil(n / 16) 16 x 16
+// factors, W and W2 16 x n scratch
+hipError_t householder_qr(double *X, double *Q, double *Vs, int64_t n, int64_t ld, double *Ts,
+                          double *W, double *W2, hipStream_t s);
 
 } // namespace lj

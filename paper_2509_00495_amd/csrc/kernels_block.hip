@@ -132,7 +132,7 @@ template <typename T, int M, int NT, bool CROSS>
 __device__ __forceinline__ void pair_solve_body(T *__restrict__ B, int64_t ldb,
                                        const int2 *__restrict__ pairs,
                                        const int2 *__restrict__ psmap, T *__restrict__ U,
-                                       double eps, double thr, int inner,
+                                       double eps, double thr, int inner, int r16,
                                        double *__restrict__ partial, int *rot_flag,
                                        int *__restrict__ prot, int pk)
 {
@@ -277,8 +277,8 @@ __device__ __forceinline__ void pair_solve_body(T *__restrict__ B, int64_t ldb,
             if (k == l) {
                 const double tk = A.t[k];
                 const T apq = A.apq[k];
-                S[pk0 * ld + pk0] = rotated_diag<T>(A.app[k], tk, apq, 0);
-                S[pk1 * ld + pk1] = rotated_diag<T>(A.aqq[k], tk, apq, 1);
+                S[pk0 * ld + pk0] = store_round<T>(rotated_diag<T>(A.app[k], tk, apq, 0), r16);
+                S[pk1 * ld + pk1] = store_round<T>(rotated_diag<T>(A.aqq[k], tk, apq, 1), r16);
                 S[sidx(pk0, pk1)] = A.cs[k].y == (T)0 ? apq : (T)0;
             } else {
                 const typename PairRec<T>::T2 csk = A.cs[k], csl = A.cs[l];
@@ -292,15 +292,19 @@ __device__ __forceinline__ void pair_solve_body(T *__restrict__ B, int64_t ldb,
                 // this chain is the longest of the round
                 T dpe = (T)0, dqe = (T)0;
                 if (hosted) {
-                    dpe = ha ? rotated_diag<T>(A.aqq[k], A.t[k], A.apq[k], 1)
-                             : rotated_diag<T>(A.app[k], A.t[k], A.apq[k], 0);
-                    dqe = hc ? rotated_diag<T>(A.aqq[l], A.t[l], A.apq[l], 1)
-                             : rotated_diag<T>(A.app[l], A.t[l], A.apq[l], 0);
+                    dpe = store_round<T>(ha ? rotated_diag<T>(A.aqq[k], A.t[k], A.apq[k], 1)
+                                            : rotated_diag<T>(A.app[k], A.t[k], A.apq[k], 0),
+                                         r16);
+                    dqe = store_round<T>(hc ? rotated_diag<T>(A.aqq[l], A.t[l], A.apq[l], 1)
+                                            : rotated_diag<T>(A.app[l], A.t[l], A.apq[l], 0),
+                                         r16);
                 }
                 const T y00 = ck * x00 - sk * x10, y01 = ck * x01 - sk * x11;
                 const T y10 = sk * x00 + ck * x10, y11 = sk * x01 + ck * x11;
-                const T z00 = cl * y00 - sl * y01, z01 = sl * y00 + cl * y01;
-                const T z10 = cl * y10 - sl * y11, z11 = sl * y10 + cl * y11;
+                const T z00 = store_round<T>(cl * y00 - sl * y01, r16);
+                const T z01 = store_round<T>(sl * y00 + cl * y01, r16);
+                const T z10 = store_round<T>(cl * y10 - sl * y11, r16);
+                const T z11 = store_round<T>(sl * y10 + cl * y11, r16);
                 if (hosted) {
                     const T zz = ha ? (hc ? z11 : z10) : (hc ? z01 : z00);
                     const int rr = pair_record<T>(Bn, hk, hfirst ? dpe : dqe,
@@ -408,7 +412,9 @@ __device__ __forceinline__ void pair_solve_body(T *__restrict__ B, int64_t ldb,
             prot[pk * PROT_STRIDE + __builtin_amdgcn_readfirstlane(tid / WAVE)] = any_rot;
 }
 
-template <typename T, int M, int NT, bool CROSS>
+// R16 (template argument, so that the FP32 stage's kernels carry no trace of
+// it): every stored entry of the tile rounded to binary16 (the binary16 stage)
+template <typename T, int M, int NT, bool CROSS, bool R16>
 __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64_t ldb,
                                                         const int2 *__restrict__ pairs,
                                                         const int2 *__restrict__ psmap,
@@ -417,8 +423,8 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
                                                         double *__restrict__ partial,
                                                         int *rot_flag, int *__restrict__ prot)
 {
-    pair_solve_body<T, M, NT, CROSS>(B, ldb, pairs, psmap, U, eps, thr, inner, partial,
-                                     rot_flag, prot, blockIdx.x);
+    pair_solve_body<T, M, NT, CROSS>(B, ldb, pairs, psmap, U, eps, thr, inner, R16 ? 1 : 0,
+                                     partial, rot_flag, prot, blockIdx.x);
 }
 
 // The pair solves of a round on workgroups 0 .. npairs-1 and, on the
@@ -428,7 +434,7 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
 // split at ntile - vx: V workgroup (l, part) takes part `part` of vranges
 // equal ranges of [0, ntile - vx), and pair-solve workgroup l, once its solve
 // is done, takes [ntile - vx, ntile).
-template <typename T, int M, int NT, bool CROSS>
+template <typename T, int M, int NT, bool CROSS, bool R16>
 __global__ __launch_bounds__(NT) void pair_solve_v_kernel(
     T *__restrict__ B, int64_t ldb, const int2 *__restrict__ pairs,
     const int2 *__restrict__ psmap, T *__restrict__ U, double eps, double thr, int inner,
@@ -440,8 +446,8 @@ __global__ __launch_bounds__(NT) void pair_solve_v_kernel(
     T *ufl = reinterpret_cast<T *>(smem_raw);
     const int64_t split = ntile - vx;
     if ((int)blockIdx.x < npairs) {
-        pair_solve_body<T, M, NT, CROSS>(B, ldb, pairs, psmap, U, eps, thr, inner, partial,
-                                         rot_flag, prot, blockIdx.x);
+        pair_solve_body<T, M, NT, CROSS>(B, ldb, pairs, psmap, U, eps, thr, inner, R16 ? 1 : 0,
+                                         partial, rot_flag, prot, blockIdx.x);
         if (vx > 0) {
             __syncthreads(); // the solve's LDS is free again
             vupd::v_update_wg<T, M, NT>(V, ldv, vpairs, blockIdx.x, vU, vprot, split, ntile,
@@ -454,13 +460,14 @@ __global__ __launch_bounds__(NT) void pair_solve_v_kernel(
                                 (int64_t)(part + 1) * split / vranges, vwaves, ufl);
 }
 
-template <typename T, int M, int NT, bool CROSS>
+template <typename T, int M, int NT, bool CROSS, bool R16>
 static hipError_t launch_pair_solve_t(T *B, int64_t ldb, int npairs, const int2 *pairs,
                                       const int2 *psmap, T *U, double eps, double thr,
-                                      int inner, double *partial, int *rot_flag, int *prot,
-                                      size_t smem, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+                                      int inner, double *partial, int *rot_flag,
+                                      int *prot, size_t smem, hipStream_t s, hipEvent_t e0,
+                                      hipEvent_t e1)
 {
-    auto k = pair_solve_kernel<T, M, NT, CROSS>;
+    auto k = pair_solve_kernel<T, M, NT, CROSS, R16>;
     static size_t smem_set = 0; // the attribute is set once per size (host-side cost)
     if (smem_set != smem) {
         hipError_t e = hipFuncSetAttribute((const void *)k,
@@ -485,11 +492,11 @@ static size_t pair_solve_smem(int b)
            16 * sizeof(int);
 }
 
-template <typename T>
-hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
-                             const int2 *psmap, T *U, double eps, double thr, int inner,
-                             int cross, double *partial, int *rot_flag, int *prot, hipStream_t s,
-                             hipEvent_t e0, hipEvent_t e1)
+template <typename T, bool R16>
+static hipError_t launch_pair_solve_r(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
+                                      const int2 *psmap, T *U, double eps, double thr,
+                                      int inner, int cross, double *partial, int *rot_flag,
+                                      int *prot, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     const int M = 2 * b;
     const size_t smem = pair_solve_smem<T>(b);
@@ -499,20 +506,37 @@ hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *p
     // slower: the extra wavefronts hide LDS latency).
     constexpr int NT64 = 1024;
     if (M == 64)
-        return cross ? launch_pair_solve_t<T, 64, NT64, true>(B, ldb, npairs, pairs, psmap, U,
-                                                              eps, thr, inner, partial,
-                                                              rot_flag, prot, smem, s, e0, e1)
-                     : launch_pair_solve_t<T, 64, NT64, false>(B, ldb, npairs, pairs, psmap,
-                                                               U, eps, thr, inner, partial,
-                                                               rot_flag, prot, smem, s, e0, e1);
+        return cross ? launch_pair_solve_t<T, 64, NT64, true, R16>(B, ldb, npairs, pairs, psmap,
+                                                                   U, eps, thr, inner, partial,
+                                                                   rot_flag, prot, smem, s, e0,
+                                                                   e1)
+                     : launch_pair_solve_t<T, 64, NT64, false, R16>(B, ldb, npairs, pairs, psmap,
+                                                                    U, eps, thr, inner, partial,
+                                                                    rot_flag, prot, smem, s, e0,
+                                                                    e1);
     if (M == 32)
-        return cross ? launch_pair_solve_t<T, 32, 256, true>(B, ldb, npairs, pairs, psmap, U,
-                                                             eps, thr, inner, partial, rot_flag,
-                                                             prot, smem, s, e0, e1)
-                     : launch_pair_solve_t<T, 32, 256, false>(B, ldb, npairs, pairs, psmap, U,
-                                                              eps, thr, inner, partial,
-                                                              rot_flag, prot, smem, s, e0, e1);
+        return cross ? launch_pair_solve_t<T, 32, 256, true, R16>(B, ldb, npairs, pairs, psmap, U,
+                                                                  eps, thr, inner, partial,
+                                                                  rot_flag, prot, smem, s, e0, e1)
+                     : launch_pair_solve_t<T, 32, 256, false, R16>(B, ldb, npairs, pairs, psmap,
+                                                                   U, eps, thr, inner, partial,
+                                                                   rot_flag, prot, smem, s, e0,
+                                                                   e1);
     return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
+                             const int2 *psmap, T *U, double eps, double thr, int inner, int r16,
+                             int cross, double *partial, int *rot_flag, int *prot, hipStream_t s,
+                             hipEvent_t e0, hipEvent_t e1)
+{
+    if (sizeof(T) == 4 && r16)
+        return launch_pair_solve_r<T, sizeof(T) == 4>(B, ldb, b, npairs, pairs, psmap, U, eps,
+                                                      thr, inner, cross, partial, rot_flag, prot,
+                                                      s, e0, e1);
+    return launch_pair_solve_r<T, false>(B, ldb, b, npairs, pairs, psmap, U, eps, thr, inner,
+                                         cross, partial, rot_flag, prot, s, e0, e1);
 }
 
 int g_pair_v_wgs = 0;    // V workgroups of the shared launch; 0 = free compute units
@@ -525,15 +549,15 @@ void tune_pair_v(int wgs, size_t lds, int waves)
     g_pair_v_waves = waves;
 }
 
-template <typename T, int M, int NT, bool CROSS>
+template <typename T, int M, int NT, bool CROSS, bool R16>
 static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int2 *pairs,
                                         const int2 *psmap, T *U, double eps, double thr,
-                                        int inner, double *partial, int *rot_flag, int *prot,
-                                        size_t smem, T *V, int64_t ldv, int64_t nrows,
+                                        int inner, double *partial, int *rot_flag,
+                                        int *prot, size_t smem, T *V, int64_t ldv, int64_t nrows,
                                         const int2 *vpairs, const T *vU, const int *vprot,
-                                        hipStream_t s, int vsplit)
+                                        hipStream_t s, int vsplit, hipEvent_t e0, hipEvent_t e1)
 {
-    auto k = pair_solve_v_kernel<T, M, NT, CROSS>;
+    auto k = pair_solve_v_kernel<T, M, NT, CROSS, R16>;
     static size_t smem_set = 0;
     static int cus = 0;
     if (cus == 0) {
@@ -589,42 +613,57 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
             return e;
         smem_set = lds;
     }
-    hipLaunchKernelGGL(k, dim3(grid), dim3(NT), lds, s, B, ldb, pairs, psmap, U, eps, thr,
-                       inner, partial, rot_flag, prot, npairs, V, ldv, ntile, vpairs, vU, vprot,
-                       (int)ranges, vwaves, vx);
+    launch_timed(k, dim3(grid), dim3(NT), (uint32_t)lds, s, e0, e1, B, ldb, pairs, psmap, U, eps,
+                 thr, inner, partial, rot_flag, prot, npairs, V, ldv, ntile, vpairs, vU, vprot,
+                 (int)ranges, vwaves, vx);
     return hipGetLastError();
+}
+
+template <typename T, bool R16>
+static hipError_t launch_pair_solve_v_r(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
+                                        const int2 *psmap, T *U, double eps, double thr,
+                                        int inner, int cross, double *partial, int *rot_flag,
+                                        int *prot, T *V, int64_t ldv, int64_t nrows,
+                                        const int2 *vpairs, const T *vU, const int *vprot,
+                                        hipStream_t s, int vsplit, hipEvent_t e0, hipEvent_t e1)
+{
+    const int M = 2 * b;
+    const size_t smem = pair_solve_smem<T>(b);
+    if (M == 64)
+        return cross ? launch_pair_solve_v_t<T, 64, 1024, true, R16>(
+                           B, ldb, npairs, pairs, psmap, U, eps, thr, inner, partial, rot_flag,
+                           prot, smem, V, ldv, nrows, vpairs, vU, vprot, s, vsplit, e0, e1)
+                     : launch_pair_solve_v_t<T, 64, 1024, false, R16>(
+                           B, ldb, npairs, pairs, psmap, U, eps, thr, inner, partial, rot_flag,
+                           prot, smem, V, ldv, nrows, vpairs, vU, vprot, s, vsplit, e0, e1);
+    if (M == 32)
+        return cross ? launch_pair_solve_v_t<T, 32, 256, true, R16>(
+                           B, ldb, npairs, pairs, psmap, U, eps, thr, inner, partial, rot_flag,
+                           prot, smem, V, ldv, nrows, vpairs, vU, vprot, s, vsplit, e0, e1)
+                     : launch_pair_solve_v_t<T, 32, 256, false, R16>(
+                           B, ldb, npairs, pairs, psmap, U, eps, thr, inner, partial, rot_flag,
+                           prot, smem, V, ldv, nrows, vpairs, vU, vprot, s, vsplit, e0, e1);
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t launch_pair_solve_v(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                                const int2 *psmap, T *U, double eps, double thr, int inner,
-                               int cross, double *partial, int *rot_flag, int *prot, T *V,
+                               int r16, int cross, double *partial, int *rot_flag, int *prot, T *V,
                                int64_t ldv, int64_t nrows, const int2 *vpairs, const T *vU,
-                               const int *vprot, hipStream_t s, int vsplit)
+                               const int *vprot, hipStream_t s, int vsplit, hipEvent_t e0,
+                               hipEvent_t e1)
 {
     if (nrows % 16 != 0 || ldv % (16 / (int64_t)sizeof(T)) != 0 || ((uintptr_t)V % 16) != 0)
         return hipErrorInvalidValue;
-    const int M = 2 * b;
-    const size_t smem = pair_solve_smem<T>(b);
-    if (M == 64)
-        return cross ? launch_pair_solve_v_t<T, 64, 1024, true>(B, ldb, npairs, pairs, psmap, U,
-                                                                eps, thr, inner, partial,
-                                                                rot_flag, prot, smem, V, ldv, nrows,
-                                                                vpairs, vU, vprot, s, vsplit)
-                     : launch_pair_solve_v_t<T, 64, 1024, false>(B, ldb, npairs, pairs, psmap,
-                                                                 U, eps, thr, inner, partial,
-                                                                 rot_flag, prot, smem, V, ldv, nrows,
-                                                                 vpairs, vU, vprot, s, vsplit);
-    if (M == 32)
-        return cross ? launch_pair_solve_v_t<T, 32, 256, true>(B, ldb, npairs, pairs, psmap, U,
-                                                               eps, thr, inner, partial,
-                                                               rot_flag, prot, smem, V, ldv, nrows,
-                                                               vpairs, vU, vprot, s, vsplit)
-                     : launch_pair_solve_v_t<T, 32, 256, false>(B, ldb, npairs, pairs, psmap, U,
-                                                                eps, thr, inner, partial,
-                                                                rot_flag, prot, smem, V, ldv, nrows,
-                                                                vpairs, vU, vprot, s, vsplit);
-    return hipErrorInvalidValue;
+    if (sizeof(T) == 4 && r16)
+        return launch_pair_solve_v_r<T, sizeof(T) == 4>(B, ldb, b, npairs, pairs, psmap, U, eps,
+                                                        thr, inner, cross, partial, rot_flag,
+                                                        prot, V, ldv, nrows, vpairs, vU, vprot,
+                                                        s, vsplit, e0, e1);
+    return launch_pair_solve_v_r<T, false>(B, ldb, b, npairs, pairs, psmap, U, eps, thr, inner,
+                                           cross, partial, rot_flag, prot, V, ldv, nrows, vpairs,
+                                           vU, vprot, s, vsplit, e0, e1);
 }
 
 
@@ -837,6 +876,23 @@ __global__ void cast_f32_kernel(const double *__restrict__ src, float *__restric
 hipError_t launch_cast_f32(const double *src, float *dst, int64_t count, hipStream_t s)
 {
     hipLaunchKernelGGL(cast_f32_kernel, dim3(2048), dim3(256), 0, s, src, dst, count);
+    return hipGetLastError();
+}
+
+// dst = fl32(2^k src), rounded on to binary16 when r16 (the binary16 stage's
+// starting matrix); k is a small exponent (|k| < 1000)
+__global__ void cast_f32_scaled_kernel(const double *__restrict__ src, float *__restrict__ dst,
+                                       int64_t count, int k, int r16)
+{
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
+        dst[i] = store_round<float>((float)ldexp(src[i], k), r16);
+}
+
+hipError_t launch_cast_f32_scaled(const double *src, float *dst, int64_t count, int k, int r16,
+                                  hipStream_t s)
+{
+    hipLaunchKernelGGL(cast_f32_scaled_kernel, dim3(2048), dim3(256), 0, s, src, dst, count, k,
+                       r16);
     return hipGetLastError();
 }
 
@@ -1227,21 +1283,22 @@ hipError_t launch_orth_probe(const double *V, int64_t ldv, int64_t n, int64_t np
 
 // explicit instantiations
 template hipError_t launch_pair_solve_v<double>(double *, int64_t, int, int, const int2 *,
-                                               const int2 *, double *, double, double, int, int,
+                                               const int2 *, double *, double, double, int, int, int,
                                                double *, int *, int *, double *, int64_t,
                                                int64_t, const int2 *, const double *,
-                                               const int *, hipStream_t, int);
+                                               const int *, hipStream_t, int, hipEvent_t,
+                                               hipEvent_t);
 template hipError_t launch_pair_solve_v<float>(float *, int64_t, int, int, const int2 *,
-                                              const int2 *, float *, double, double, int, int,
+                                              const int2 *, float *, double, double, int, int, int,
                                               double *, int *, int *, float *, int64_t,
                                               int64_t, const int2 *, const float *, const int *,
-                                              hipStream_t, int);
+                                              hipStream_t, int, hipEvent_t, hipEvent_t);
 template hipError_t launch_pair_solve<double>(double *, int64_t, int, int, const int2 *,
-                                              const int2 *, double *, double, double, int, int,
+                                              const int2 *, double *, double, double, int, int, int,
                                               double *, int *, int *, hipStream_t, hipEvent_t,
                                               hipEvent_t);
 template hipError_t launch_pair_solve<float>(float *, int64_t, int, int, const int2 *,
-                                             const int2 *, float *, double, double, int, int,
+                                             const int2 *, float *, double, double, int, int, int,
                                              double *, int *, int *, hipStream_t, hipEvent_t,
                                              hipEvent_t);
 

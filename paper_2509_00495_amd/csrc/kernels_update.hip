@@ -48,7 +48,9 @@ __global__ __launch_bounds__(256) void update_v_kernel(T *__restrict__ V, int64_
 // whole run consists of such tiles adds their count to *skipped and returns
 // after its first tile's loads (a per-tile test inside the pipelined loop
 // costs the loop registers).
-template <typename T, int M>
+// R16: Z rounded to binary16 on its way to B (the binary16 stage), a
+// template argument so that the FP32 stage's kernel carries no trace of it.
+template <typename T, int M, bool R16>
 __global__ __launch_bounds__(M * 4, sizeof(T) == 4 ? 4 : 2) void update_b_kernel(T *__restrict__ B, int64_t ldb,
                                                          const int2 *__restrict__ pairs_g,
                                                          int npairs, const T *__restrict__ U,
@@ -57,6 +59,7 @@ __global__ __launch_bounds__(M * 4, sizeof(T) == 4 ? 4 : 2) void update_b_kernel
                                                          const int *__restrict__ prot,
                                                          int *skipped)
 {
+    constexpr int r16 = R16 ? 1 : 0;
     constexpr int b = M / 2, NW = M / 16, NT = NW * WAVE;
     constexpr int VK = 16 / (int)sizeof(T);
     constexpr int TC = M / 16, TJ = M / 16, KG = M / (4 * VK);
@@ -124,17 +127,25 @@ __global__ __launch_bounds__(M * 4, sizeof(T) == 4 ? 4 : 2) void update_b_kernel
     // a sub-block with C < R is read in X^T orientation, one with C > R as its
     // stored transpose (the decision is uniform per sub-block, and a
     // sub-block covers whole wavefronts).
+    // Every piece is a column gather: thread piece q of a sub-block holds the
+    // VK entries (a0 .. a0 + VK - 1, c) of the stored block, c = q mod b,
+    // a0 = VK (q / b), one element load each (consecutive lanes read
+    // consecutive columns of a row, so every load is coalesced).  That is
+    // one 16-byte row piece of X^T when the block is stored transposed, and a
+    // column piece otherwise; both orientations issue the same loads.
     auto load_tile = [&](Buf &nb, int t) __attribute__((always_inline)) {
         const int2 kl = tile_kl(t);
         const int2 pk = pairs[kl.x], pl = pairs[kl.y];
 #pragma unroll
         for (int e = 0; e < PERV; ++e) {
-            const int idx = tid + e * NT, sb = idx / VPB, a = (idx % VPB) / BV,
-                      col = (idx % BV) * VK;
+            const int idx = tid + e * NT, sb = idx / VPB, q = idx % VPB;
+            const int c = q % b, a0 = (q / b) * VK;
             const int C = (sb >> 1) ? pl.y : pl.x, R = (sb & 1) ? pk.y : pk.x;
-            const int64_t row = (int64_t)(C < R ? C : R) * b + a;
-            const int64_t cl = (int64_t)(C < R ? R : C) * b + col;
-            nb.xr[e] = *reinterpret_cast<const TV *>(B + row * ldb + cl);
+            const T *src = B + ((int64_t)(C < R ? C : R) * b + a0) * ldb +
+                           (int64_t)(C < R ? R : C) * b + c;
+#pragma unroll
+            for (int j = 0; j < VK; ++j)
+                nb.xr[e][j] = src[j * ldb];
         }
         const T *Ukt = U + (int64_t)kl.x * M * M; // transposed: Ukt[j][i] = U_k[i][j]
 #pragma unroll
@@ -157,16 +168,16 @@ __global__ __launch_bounds__(M * 4, sizeof(T) == 4 ? 4 : 2) void update_b_kernel
         const int2 pk = pairs[kl.x], pl = pairs[kl.y];
 #pragma unroll
         for (int e = 0; e < PERV; ++e) {
-            const int idx = tid + e * NT, sb = idx / VPB, a = (idx % VPB) / BV,
-                      col = (idx % BV) * VK;
+            const int idx = tid + e * NT, sb = idx / VPB, q = idx % VPB;
+            const int c = q % b, a0 = (q / b) * VK;
             const int ci = sb >> 1, ri = sb & 1;
             const int C = ci ? pl.y : pl.x, R = ri ? pk.y : pk.x;
-            if (C < R) {
-                *reinterpret_cast<TV *>(xs + (ci * b + a) * LDX + ri * b + col) = cb.xr[e];
-            } else {
+            if (C < R) { // stored (C, R): entry (a, c) is X^T(C a, R c)
 #pragma unroll
                 for (int j = 0; j < VK; ++j)
-                    xs[(ci * b + col + j) * LDX + ri * b + a] = vlane<T>(cb.xr[e], j);
+                    xs[(ci * b + a0 + j) * LDX + ri * b + c] = vlane<T>(cb.xr[e], j);
+            } else { // stored (R, C): entry (a, c) is X^T(C c, R a)
+                *reinterpret_cast<TV *>(xs + (ci * b + c) * LDX + ri * b + a0) = cb.xr[e];
             }
         }
         lds_barrier();
@@ -265,7 +276,7 @@ __global__ __launch_bounds__(M * 4, sizeof(T) == 4 ? 4 : 2) void update_b_kernel
                 dst = zrow + gj0;
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    zv[v] = zt[tj][v];
+                    zv[v] = store_round<T>(zt[tj][v], r16);
             } else {
                 // through the wavefront's LDS scratch: lane (li, lk) then holds
                 // four consecutive rows 16 w + 4 lk .. of Z's column 16 tj + li
@@ -274,7 +285,7 @@ __global__ __launch_bounds__(M * 4, sizeof(T) == 4 ? 4 : 2) void update_b_kernel
                     zw[(4 * lk + v) * ZLD + li] = zt[tj][v];
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    zv[v] = zw[li * ZLD + 4 * lk + v];
+                    zv[v] = store_round<T>(zw[li * ZLD + 4 * lk + v], r16);
                 dst = B + (int64_t)pair_col(pl, 16 * tj + li, b) * ldb + pair_col(pk, 16 * w + 4 * lk, b);
             }
             if constexpr (sizeof(T) == 4) {
@@ -286,8 +297,10 @@ __global__ __launch_bounds__(M * 4, sizeof(T) == 4 ? 4 : 2) void update_b_kernel
                 *reinterpret_cast<dv2 *>(dst + 2) = z1;
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                sq += (double)zt[tj][v] * (double)zt[tj][v];
+            for (int v = 0; v < 4; ++v) {
+                const double zq = (double)store_round<T>(zt[tj][v], r16);
+                sq += zq * zq;
+            }
         }
         if (want_off) {
             sq = wave_sum(sq);
@@ -361,7 +374,7 @@ int update_b_blocks_per_cu_t()
     static int per = -1;
     if (per < 0) {
         int p = 0;
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, update_b_kernel<T, M>, M * 4, 0);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, update_b_kernel<T, M, false>, M * 4, 0);
         per = p > 0 ? p : 1;
     }
     return per;
@@ -379,7 +392,7 @@ void tune_update_v(int total_waves) { g_update_v_waves = total_waves; }
 
 template <typename T>
 hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pairs, const T *U,
-                           double *partial, int want_off, const int *prot, int *skipped,
+                           double *partial, int want_off, int r16, const int *prot, int *skipped,
                            hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
     if (prot && !skipped)
@@ -387,8 +400,8 @@ hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pai
     if (ldb % (16 / (int64_t)sizeof(T)) != 0 || ((uintptr_t)B % 16) != 0)
         return hipErrorInvalidValue;
     const int ntiles = npairs * (npairs - 1) / 2;
-    if (ntiles == 0)
-        return hipSuccess;
+    if (ntiles == 0) // one block pair: no tiles; the timing events still mark the spot
+        return record_pair(e0, e1, s);
     static int cus = 0;
     if (cus == 0) {
         int dev = 0;
@@ -399,12 +412,15 @@ hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pai
     }
     const int slots = cus * update_b_blocks_per_cu<T>(b);
     const unsigned grid = (unsigned)(ntiles < slots ? ntiles : slots);
+    const bool h = sizeof(T) == 4 && r16;
     if (b == 32)
-        launch_timed(update_b_kernel<T, 64>, dim3(grid), dim3(256), 0, s, e0, e1, B, ldb, pairs,
-                     npairs, U, partial, want_off, prot, skipped);
+        launch_timed(h ? update_b_kernel<T, 64, sizeof(T) == 4> : update_b_kernel<T, 64, false>,
+                     dim3(grid), dim3(256), 0, s, e0, e1, B, ldb, pairs, npairs, U, partial,
+                     want_off, prot, skipped);
     else if (b == 16)
-        launch_timed(update_b_kernel<T, 32>, dim3(grid), dim3(128), 0, s, e0, e1, B, ldb, pairs,
-                     npairs, U, partial, want_off, prot, skipped);
+        launch_timed(h ? update_b_kernel<T, 32, sizeof(T) == 4> : update_b_kernel<T, 32, false>,
+                     dim3(grid), dim3(128), 0, s, e0, e1, B, ldb, pairs, npairs, U, partial,
+                     want_off, prot, skipped);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -419,7 +435,7 @@ hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
         ((uintptr_t)V % 16) != 0)
         return hipErrorInvalidValue;
     if (nrows == 0 || npairs == 0)
-        return hipSuccess;
+        return record_pair(e0, e1, s);
     if (b == 32)
         return launch_update_v_t<T, 64>(V, ldv, nrows, npairs, pairs, U, prot, s, e0, e1);
     if (b == 16)
@@ -430,10 +446,10 @@ hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
 template int update_b_blocks_per_cu<double>(int);
 template int update_b_blocks_per_cu<float>(int);
 template hipError_t launch_update_b<double>(double *, int64_t, int, int, const int2 *,
-                                            const double *, double *, int, const int *, int *,
+                                            const double *, double *, int, int, const int *, int *,
                                             hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_update_b<float>(float *, int64_t, int, int, const int2 *,
-                                           const float *, double *, int, const int *, int *,
+                                           const float *, double *, int, int, const int *, int *,
                                            hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_update_v<double>(double *, int64_t, int64_t, int, int, const int2 *,
                                             const double *, const int *, hipStream_t,

@@ -47,6 +47,8 @@ class Opts(ctypes.Structure):
         ("no_pair_skip", ctypes.c_int32),
         ("gemm_slots", ctypes.c_int32),
         ("pair_v_split", ctypes.c_int32),
+        ("orth", ctypes.c_int32),
+        ("ladder", ctypes.c_int32),
     ]
 
 
@@ -59,7 +61,7 @@ class Info(ctypes.Structure):
         ("block", ctypes.c_int32),
         ("polished", ctypes.c_int32),
         ("skipped_tiles", ctypes.c_int32),
-        ("reserved_i", ctypes.c_int32 * 1),
+        ("sweeps16", ctypes.c_int32),
         ("norm_f", ctypes.c_double),
         ("tol", ctypes.c_double),
         ("off_final", ctypes.c_double),
@@ -74,7 +76,9 @@ class Info(ctypes.Structure):
         ("n_apply", ctypes.c_int32 * 2),
         ("n_applyv", ctypes.c_int32 * 2),
         ("reserved_i2", ctypes.c_int32 * 2),
-        ("reserved_d", ctypes.c_double * 3),
+        ("orth_qd", ctypes.c_double),
+        ("t_orth_ms", ctypes.c_double),
+        ("off16", ctypes.c_double),
     ]
 
     def as_dict(self):

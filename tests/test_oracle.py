@@ -643,9 +643,8 @@ def test_half_stage_bounds(orc, name):
     n = 96
     A = wl.goe(n, 96) if name == "goe" else wl.geo_spectrum(n, 97, kappa=1e3)[0]
     nf = np.linalg.norm(A)
-    # A scalar cyclic sweep lowers off by only about a half early on, so the
-    # stall factor here is 0.9 (a block sweep, whose pair solves run to
-    # convergence, does better: the device stage stops at 0.5).
+    # early sweeps lower off by only about a half, so the stall factor (the
+    # stop at the rounding floor) is 0.9
     Ah, V, sw, st, hist = orc.jacobi_cyclic_h(A, stall=0.9)
     assert st == 0 and sw >= 3
     assert np.array_equal(Ah.astype(np.float64),
