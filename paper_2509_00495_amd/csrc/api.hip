@@ -803,7 +803,10 @@ void fill_info(jacobi_info *info, int sweeps, int sweeps32, int ns, int path, in
 int eigh_small(const double *A, int64_t n, int64_t lda, double *W, double *V, int64_t ldv,
                double tol, const Opts &o, void *work, hipStream_t s, jacobi_info *info)
 {
-    const int threads = small_threads(n, o.threads);
+    // one matrix: the solve's latency is all that counts, so the whole
+    // compute unit's 1024 threads (the batched default of 256 threads for
+    // n <= 72 is for throughput, several workgroups per compute unit)
+    const int threads = o.threads ? o.threads : 1024;
     Bump bp(work);
     SmallWs w = layout_small(bp, 1, n, 1);
     SmallDesc d{};

@@ -78,8 +78,15 @@ __global__ __launch_bounds__(M * 4, sizeof(T) == 4 ? 4 : 2) void update_b_kernel
     const int li = lane % 16, lk = lane / 16;
     T *zw = zsc + w * 16 * ZLD;
     const int ntiles = npairs * (npairs - 1) / 2;
-    const int t0 = (int)((int64_t)blockIdx.x * ntiles / gridDim.x);
-    const int t1 = (int)((int64_t)(blockIdx.x + 1) * ntiles / gridDim.x);
+    // XCD-aware run order: workgroups go to the 8 XCDs round-robin (blockIdx
+    // mod 8), so the workgroups of one XCD take one contiguous eighth of the
+    // tile list (a range of l): that XCD's L2 then holds the U_l of its range
+    // only, instead of every XCD fetching every U block
+    const int G = (int)gridDim.x;
+    const int g = G % 8 == 0 ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8)
+                             : (int)blockIdx.x;
+    const int t0 = (int)((int64_t)g * ntiles / G);
+    const int t1 = (int)((int64_t)(g + 1) * ntiles / G);
     if (t0 >= t1)
         return;
     // tile t of the list (k < l, by l then k) is (t - l (l - 1) / 2, l), and
