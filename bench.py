@@ -523,7 +523,7 @@ def bench_uniform64(args, torch, pj):
         "batched_same_order": {"matrices": nb, "ms_per_batch": round(1e3 * dtb / 5, 3),
                                "value": round(5 * nb / dtb, 1), "unit": "eigendecomps/s"},
         "accuracy": acc,
-        "roofline": {"kernel": "lj::small_jacobi_kernel<256> (one workgroup, one CU)",
+        "roofline": {"kernel": "lj::small_jacobi_kernel<1024> (one workgroup, one CU)",
                      "bound": "alu", "achieved": round(flops / avg_s / 1e12, 4),
                      "peak": round(CU_F64_TFLOPS, 4), "unit": "TFLOP/s",
                      "frac": round(flops / avg_s / 1e12 / CU_F64_TFLOPS, 4), "traffic": None,
