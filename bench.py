@@ -343,6 +343,18 @@ def bench_mixed(args, torch, pj):
     inf2 = run_mixed(pj.make_opts(timing=1, serial_v=1, orth=orth))[2]
     torch.cuda.synchronize()
     b = inf1["block"]
+    # each stage's result and its bound (Sections 4.3.4 and 5.2.1), from the
+    # instrumented solve (same arithmetic as the timed ones); the final
+    # result's error against the oracle is in `accuracy`
+    u_l, u_d = 2.0 ** -24, 2.0 ** -53
+    stages = {
+        "Q_l": {"orth_F": inf1["orth_ql"], "scale_n_u_l": n * u_l,
+                "off32_rel_F": inf1["off32"] / nrmF, "sweeps32": inf1["sweeps32"]},
+        "Q_d": {"orth_F": inf1["orth_qd"], "scale_n_u_d": n * u_d,
+                "ns_iters": inf1["ns_iters"]},
+        "A_cond": {"off_rel_F": inf1["off_cond"] / nrmF, "scale_n_u_l": n * u_l},
+        "final": {"off_rel_F": inf1["off_final"] / nrmF, "sweeps64": inf1["sweeps"]},
+    }
     cands = {}
     for idx, dt_ in ((1, "f32"), (0, "f64")):
         cands[f"pair_solve_v_{dt_}"] = (inf1["t_pair_ms"][idx], inf1["n_pair"][idx], "PV", dt_)
@@ -437,6 +449,7 @@ def bench_mixed(args, torch, pj):
         "plain_fp64": plain,
         "speedup_vs_plain": None if plain is None else round(value / plain["value"], 3),
         "accuracy": acc,
+        "stages": stages,
         "roofline": roofline,
         "roofline_pair_solve": roofline_pair,
         "cpu_baseline": cpu,

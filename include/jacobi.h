@@ -178,6 +178,9 @@ typedef struct jacobi_info {
     double t_orth_ms;       /* with opts->timing, mixed path: time of the Q_l -> Q_d
                                step (HIP events on `stream`) */
     double off16;           /* off(B) when the binary16 stage stopped (ladder) */
+    double orth_ql;         /* mixed path: ||Q_l^T Q_l - I||_F of the FP32 stage's
+                               eigenvectors (with Newton-Schulz always; with the
+                               QR orthogonalisers only with opts->timing, else 0) */
 } jacobi_info;
 
 /* Plain FP64 Jacobi eigendecomposition (Algorithm 4, Section 3.3, run as a

@@ -1061,6 +1061,18 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     // (free n_pad^2 buffers for the products below).
     double *X = w.V64, *X2 = w.X2, *R = w.R;
     CK(launch_widen_f64(w.V32, X, nn, s));
+    // ||Q_l^T Q_l - I||_F (stage diagnostic, into scal[6]): Newton-Schulz
+    // computes I - X^T X in its first step anyway; for the QR orthogonalisers
+    // it costs a product of its own, made only with opts.timing (R and X2 are
+    // free until the factorisation starts)
+    double orth_ql = 0.0;
+    const bool ql_diag = o.orth == 0 || o.timing;
+    if (o.orth != 0 && o.timing) {
+        CK(launch_gemm64_sym(1, 0, g.npad, g.npad, -1.0, X, g.npad, X, g.npad, 0.0, nullptr, 0,
+                             1.0, R, g.npad, s, X2, nn, o.gemm_slots));
+        CK(launch_sq_partial(R, nn, w.partial, s));
+        CK(launch_sum(w.partial, OFF_BLOCKS, w.scal + 6, s));
+    }
     hipEvent_t eo0 = nullptr, eo1 = nullptr;
     if (o.timing) {
         CK(hipEventCreate(&eo0));
@@ -1090,6 +1102,10 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
         for (int it = 0; it < max_it; ++it) {
             CK(launch_gemm64_sym(1, 0, g.npad, g.npad, -1.0, X, g.npad, X, g.npad, 0.0, nullptr,
                                  0, 1.0, R, g.npad, s, X2, nn, o.gemm_slots));
+            if (it == 0) {
+                CK(launch_sq_partial(R, nn, w.partial, s));
+                CK(launch_sum(w.partial, OFF_BLOCKS, w.scal + 6, s));
+            }
             if (adaptive || it == max_it - 1) {
                 CK(launch_sq_partial(R, nn, w.partial, s));
                 CK(launch_sum(w.partial, OFF_BLOCKS, w.scal + 2, s));
@@ -1097,6 +1113,7 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
                 if (int e = read_scalars(w, s, rb))
                     return e;
                 orth = std::sqrt(rb.scal[2]);
+                orth_ql = std::sqrt(rb.scal[6]);
                 if (adaptive && orth <= (double)n * U_D)
                     break;
             }
@@ -1121,6 +1138,8 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
         if (int e = read_scalars(w, s, rb))
             return e;
         orth_qd = std::sqrt(rb.scal[5]);
+        if (ql_diag)
+            orth_ql = std::sqrt(rb.scal[6]);
         float ms = 0.0f;
         CK(hipEventElapsedTime(&ms, eo0, eo1));
         t_orth = ms;
@@ -1163,6 +1182,7 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
         info->t_orth_ms = t_orth;
         info->sweeps16 = sw16;
         info->off16 = std::ldexp(off16, -ks);
+        info->orth_ql = orth_ql;
     }
     if (info) {
         info->orth_est = est;

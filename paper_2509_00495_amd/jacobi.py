@@ -79,6 +79,7 @@ class Info(ctypes.Structure):
         ("orth_qd", ctypes.c_double),
         ("t_orth_ms", ctypes.c_double),
         ("off16", ctypes.c_double),
+        ("orth_ql", ctypes.c_double),
     ]
 
     def as_dict(self):

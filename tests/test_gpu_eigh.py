@@ -165,6 +165,38 @@ def test_mixed_vs_oracle(pj, n):
     assert info["off_cond"] <= 10 * n * 2.0 ** -24 * np.linalg.norm(A)
 
 
+@pytest.mark.parametrize("n", [96, 300])
+def test_mixed_stages_vs_oracle(pj, n):
+    """Each stage of the mixed path beside the oracle's same stage on the
+    same matrix (Algorithm 9 with the FP32 Jacobi first stage, both with the
+    FP32 stop at 0.1 n u_l ||A||_F): ||Q_l^T Q_l - I||_F (order n u_l, the
+    starting point of Section 4.3.4's count), ||Q_d^T Q_d - I||_F (order n u_d
+    after two Newton-Schulz steps), off(Q_d^T A Q_d) (Section 5.2.1: order
+    n u_l ||A||_F) and the final eigenvalues (1e-13 ||A||_2, element by
+    element).  The two use different orderings (block round-robin against
+    cyclic-by-row), so the stage values are compared through their bounds
+    and their order of magnitude, not digit by digit."""
+    U_L, U_D = 2.0 ** -24, 2.0 ** -53
+    A, lam = wl.geo_spectrum(n, 8000 + n, kappa=1e4)
+    W, V, info = run(pj, "eigh_mixed", A, timing=1)
+    Wo, _, st, d = oracle.eigh_mixed(A, c32=0.1)
+    assert info["status"] == 0 and st == 0
+    nf = np.linalg.norm(A)
+    nrm2 = np.abs(lam).max()
+    gpu = dict(orth_ql=info["orth_ql"], orth_qd=info["orth_qd"], off_cond=info["off_cond"])
+    print(f"  stages n={n}: gpu {gpu}  oracle orth_ql={d['orth_ql']:.2e} "
+          f"orth_qd={d['orth_qd']:.2e} off_cond={d['off_cond']:.2e}", flush=True)
+    for k in ("orth_ql", "orth_qd", "off_cond"):
+        assert gpu[k] > 0.0
+        assert 0.02 <= gpu[k] / d[k] <= 50.0, k
+    assert gpu["orth_ql"] <= 10 * n * U_L and d["orth_ql"] <= 10 * n * U_L
+    npad = -(-n // 16) * 16 if n <= 256 else -(-n // 64) * 64
+    assert gpu["orth_qd"] <= 4 * npad * U_D and d["orth_qd"] <= 4 * n * U_D
+    assert gpu["off_cond"] <= 10 * n * U_L * nf and d["off_cond"] <= 10 * n * U_L * nf
+    assert np.abs(W - Wo).max() <= 1e-13 * nrm2
+    assert np.abs(W - lam).max() <= 1e-13 * nrm2
+
+
 def test_mixed_one_ns_step_polished(pj):
     """One Newton-Schulz step leaves Q_d with an orthogonality error far above
     the bar (about 1e-10 here).  The output stage must detect it (randomized
