@@ -315,7 +315,8 @@ template <int TA, int TB, bool SYM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void gemm128_kernel(
     int64_t M, int64_t N, int64_t K, double alpha, const double *__restrict__ A, int64_t lda,
     const double *__restrict__ B, int64_t ldb, double beta, const double *__restrict__ C0,
-    int64_t ldc0, double gamma, double *__restrict__ C, int64_t ldc, int tiles_n)
+    int64_t ldc0, double gamma, double *__restrict__ C, int64_t ldc, int tiles_n, int64_t sA,
+    int64_t sB, int64_t sC0, int64_t sC)
 {
     __shared__ __align__(16) double sm[2][2][BK * BLD]; // [buffer][A or B][k][i or j]
     int by, bx;
@@ -324,6 +325,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     } else {
         by = blockIdx.y;
         bx = blockIdx.x;
+        // batch entry blockIdx.z (strides in doubles; one entry when 0)
+        const int64_t z = blockIdx.z;
+        A += z * sA;
+        B += z * sB;
+        C += z * sC;
+        if (C0)
+            C0 += z * sC0;
     }
     gemm128_segment<TA, TB, SYM>(M, N, K, alpha, A, lda, B, ldb, beta, C0, ldc0, gamma, C, ldc,
                                  by, bx, 0, (int)((K + BK - 1) / BK), nullptr, sm);
@@ -424,8 +432,12 @@ static hipError_t launch_gemm128(int transA, int transB, int64_t M, int64_t N, i
                                  double alpha, const double *A, int64_t lda, const double *B,
                                  int64_t ldb, double beta, const double *C0, int64_t ldc0,
                                  double gamma, double *C, int64_t ldc, double *scratch,
-                                 int64_t scratch_doubles, int slots, hipStream_t s)
+                                 int64_t scratch_doubles, int slots, hipStream_t s,
+                                 int64_t batch = 1, int64_t sA = 0, int64_t sB = 0,
+                                 int64_t sC0 = 0, int64_t sC = 0)
 {
+    if (SYM && batch != 1)
+        return hipErrorInvalidValue;
     const int tn = (int)((N + BT - 1) / BT), tm = (int)((M + BT - 1) / BT);
     const int ntiles = tn * (tn + 1) / 2;
     const int G = slots > 0 ? slots : gemm_resident_slots();
@@ -447,10 +459,10 @@ static hipError_t launch_gemm128(int transA, int transB, int64_t M, int64_t N, i
                            N, K, alpha, beta, C0, ldc0, gamma, C, ldc, tn, ntiles, G, scratch);
         return hipGetLastError();
     }
-    dim3 grid = SYM ? dim3((unsigned)ntiles) : dim3((unsigned)tn, (unsigned)tm);
+    dim3 grid = SYM ? dim3((unsigned)ntiles) : dim3((unsigned)tn, (unsigned)tm, (unsigned)batch);
 #define LJ_G128(TA_, TB_)                                                                          \
     hipLaunchKernelGGL((gemm128_kernel<TA_, TB_, SYM>), grid, dim3(256), 0, s, M, N, K, alpha, A,  \
-                       lda, B, ldb, beta, C0, ldc0, gamma, C, ldc, tn)
+                       lda, B, ldb, beta, C0, ldc0, gamma, C, ldc, tn, sA, sB, sC0, sC)
     if (!transA && !transB)
         LJ_G128(0, 0);
     else if (transA && !transB)
@@ -474,9 +486,13 @@ static hipError_t launch_gemm64_t(int transA, int transB, int64_t M, int64_t N, 
 {
     if (M <= 0 || N <= 0 || batch <= 0)
         return hipSuccess;
-    if (batch == 1 && gemm128_fits<SYM>(M, N, A, lda, B, ldb))
+    // the 128 x 128 tiles (double-buffered LDS) for a single product and for
+    // batches of plain products whose entries keep the 16-byte alignment
+    if (gemm128_fits<SYM>(M, N, A, lda, B, ldb) &&
+        (batch == 1 || (!SYM && sA % 2 == 0 && sB % 2 == 0)))
         return launch_gemm128<SYM>(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C0,
-                                   ldc0, gamma, C, ldc, scratch, scratch_doubles, slots, s);
+                                   ldc0, gamma, C, ldc, scratch, scratch_doubles, slots, s, batch,
+                                   sA, sB, sC0, sC);
     dim3 grid((unsigned)((N + GT - 1) / GT), (unsigned)((M + GT - 1) / GT), (unsigned)batch);
     if (!transA && !transB)
         hipLaunchKernelGGL((gemm64_kernel<0, 0, SYM>), grid, dim3(256), 0, s, M, N, K, alpha, A,
