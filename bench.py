@@ -652,8 +652,8 @@ def bench_gapped(args, torch, pj):
                     "path": "jacobi_eigh per matrix (block path)"},
         "accuracy": {"max_rel_err_vs_oracle_adjoint_sample": err,
                      "gate_passed": bool(err <= 1e-10)},
-        "roofline": {"kernel": "jacobi_eigh_backward (three batched gemm64 launches + "
-                               "elementwise)", "bound": "mfma",
+        "roofline": {"kernel": "jacobi_eigh_backward (three batched 128x128-tile FP64 GEMM "
+                               "launches + elementwise)", "bound": "mfma",
                      "achieved": round(flops / avg_s / 1e12, 3), "peak": PEAK["f64"],
                      "unit": "TFLOP/s", "frac": round(flops / avg_s / 1e12 / PEAK["f64"], 4),
                      "traffic": None, "flops_per_launch": flops,
