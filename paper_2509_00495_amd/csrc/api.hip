@@ -234,8 +234,12 @@ BlockWs layout_block(Bump &bp, int64_t n, const Geometry &g, bool mixed)
         w.B32 = bp.take<float>(nn);
         w.V32 = bp.take<float>(nn);
         w.U32 = bp.take<float>(2 * uu);
-        // max(ceil(npad / 64) 64^2, ceil(npad / 16) 16^2 + 2 * 16 npad)
-        w.orth = bp.take<double>((size_t)(g.npad + ORTH_CB) * ORTH_CB);
+        // the Cholesky QR's diagonal-block inverses ((npad / CB + 1) CB^2) or
+        // the Householder QR's compact factors ((npad / HB + 1) HB^2) and its
+        // two HB x npad products, whichever is larger
+        const size_t chol = (size_t)(g.npad + ORTH_CB) * ORTH_CB;
+        const size_t house = (size_t)(g.npad + ORTH_HB) * ORTH_HB + 2 * (size_t)ORTH_HB * g.npad;
+        w.orth = bp.take<double>(chol > house ? chol : house);
     }
     w.partial = bp.take<double>(partial_count(g));
     w.scal = bp.take<double>(8);
@@ -691,7 +695,8 @@ int run_sweeps(const Geometry &g, int64_t n, const BlockWs &w, T *B, T *V, T *U,
         if (int e = read_scalars(w, s, rb))
             return e;
         if (timed) {
-            CK(hipStreamSynchronize(ss.s2));
+            if (ss.s2)
+                CK(hipStreamSynchronize(ss.s2));
             if (int e = tm->collect(g.N - 1))
                 return e;
         }
@@ -962,9 +967,10 @@ int eigh_block(const double *A, int64_t n, int64_t lda, double *W, double *V, in
     double off = 0.0;
     RoundTimer tm;
     tm.on = o.timing;
-    SideStream ss;
-    if (int e = ss.init())
-        return e;
+    SideStream ss; // its stream and events exist only for serial_v = 2
+    if (o.serial_v == 2)
+        if (int e = ss.init())
+            return e;
     int st = run_sweeps<double>(g, n, w, w.B64, w.V64, w.U64, tol, U_D, o.max_sweeps, o.inner,
                                 o.schedule, o.serial_v, o.pair_skip, 0, o.pair_v_split, s,
                                 ss, &sweeps, &off, nullptr, &tm, &skipped);
@@ -1008,9 +1014,10 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
         return e;
     RoundTimer tm32, tm64, tm16;
     tm32.on = tm64.on = tm16.on = o.timing;
-    SideStream ss;
-    if (int e = ss.init())
-        return e;
+    SideStream ss; // its stream and events exist only for serial_v = 2
+    if (o.serial_v == 2)
+        if (int e = ss.init())
+            return e;
     CK(launch_eye<float>(w.V32, g.npad, s));
     // stage 0 (ladder = 1): the binary16 stage.  Its matrix is fl16(2^kh A),
     // scaled by an exact power of two so that the largest entry lies in

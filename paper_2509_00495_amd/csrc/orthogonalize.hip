@@ -132,13 +132,19 @@ hipError_t cholesky_qr(double *X, double *Q, double *G, double *Rf, int64_t n, i
 // ------------------------------------------------------- Householder QR
 // One panel of HB columns (j0 .. j0 + HB - 1, rows j0 .. n - 1) of A, by one
 // workgroup: for each column c = j0 + k, Algorithm 1 on A(c:n, c) (sigma and
-// mu by block reductions, v_1 = x_1 + mu for x_1 >= 0, else x_1 - mu, beta =
+// mu by a block reduction, v_1 = x_1 + mu for x_1 >= 0, else x_1 - mu, beta =
 // 2 / (v_1^2 + sigma), beta = 0 for a zero column), the column becomes
 // -sign(x_1) mu e_1, and the panel's later columns get
 // A(c:n, c') -= beta v (v^T A(c:n, c')).  The reflectors go to V (column
 // j0 + k, rows c .. n - 1, v_1 at row c; zero above) and the compact factor
 // T of P_1 ... P_HB = I - V T V^T (upper triangular, T_kk = beta_k,
 // T(0:k, k) = -beta_k T(0:k, 0:k) V(:, 0:k)^T v_k) to T (HB x HB).
+// Thread t works on column slot t mod HB of the rows j0 + t / HB + i HNT / HB,
+// so the HB lanes of a row read its HB panel entries as one contiguous
+// piece; v_i, the entry of column k, reaches the other lanes of its row by a
+// shuffle, and the dot products of all panel columns with v come out of one
+// reduction per column step (lanes of one slot combined by shuffles, waves
+// through LDS).
 constexpr int HB = ORTH_HB;
 constexpr int HNT = 1024;
 __global__ __launch_bounds__(HNT) void house_panel_kernel(double *__restrict__ A, int64_t ld,
@@ -146,12 +152,17 @@ __global__ __launch_bounds__(HNT) void house_panel_kernel(double *__restrict__ A
                                                           double *__restrict__ V, int64_t ldv,
                                                           double *__restrict__ T)
 {
-    constexpr int NW = HNT / WAVE;
+    constexpr int NW = HNT / WAVE, RG = HNT / HB;
+    static_assert(WAVE % HB == 0, "a row's slots lie in one wavefront");
     __shared__ double red[NW][HB];
     __shared__ double tot[HB];
     __shared__ double ts[HB][HB];
     const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+    const int cs = tid % HB, rg = tid / HB;       // column slot, row group
+    const int src = (lane / HB) * HB;             // lane of slot 0 of this row
     const int nbc = (int)(n - j0 < HB ? n - j0 : HB); // columns in this panel
+    const bool colok = cs < nbc;
+    const int64_t col = j0 + cs;
     for (int e = tid; e < HB * HB; e += HNT)
         ts[e / HB][e % HB] = 0.0;
     // the panel's V columns are zero above their pivots
@@ -161,18 +172,15 @@ __global__ __launch_bounds__(HNT) void house_panel_kernel(double *__restrict__ A
         if (i < j0 + k && i < n)
             V[i * ldv + j0 + k] = 0.0;
     }
-    // block sums of the cnt (<= HB) values v[] of every thread, into tot[]
-    auto block_sums = [&](const double *v, int cnt) {
-        for (int q = 0; q < cnt; ++q) {
-            double s = v[q];
+    // tot[c] = sum over all threads of slot c of v
+    auto slot_sums = [&](double v) {
 #pragma unroll
-            for (int off = WAVE / 2; off > 0; off >>= 1)
-                s += __shfl_xor(s, off, WAVE);
-            if (lane == 0)
-                red[w][q] = s;
-        }
+        for (int off = HB; off < WAVE; off <<= 1)
+            v += __shfl_xor(v, off, WAVE);
+        if (lane < HB)
+            red[w][lane] = v;
         __syncthreads();
-        if (tid < cnt) {
+        if (tid < HB) {
             double s = 0.0;
             for (int i = 0; i < NW; ++i)
                 s += red[i][tid];
@@ -180,18 +188,18 @@ __global__ __launch_bounds__(HNT) void house_panel_kernel(double *__restrict__ A
         }
         __syncthreads();
     };
-    double part[HB];
     for (int k = 0; k < nbc; ++k) {
-        const int64_t c = j0 + k, r = j0 + k;
+        const int64_t r = j0 + k, c = j0 + k;
         // sigma = x(2:m)^T x(2:m)
         double sg = 0.0;
-        for (int64_t i = r + 1 + tid; i < n; i += HNT) {
-            const double xi = A[i * ld + c];
-            sg += xi * xi;
-        }
-        part[0] = sg;
-        block_sums(part, 1);
-        const double sigma = tot[0];
+        if (cs == k)
+            for (int64_t i = j0 + rg; i < n; i += RG)
+                if (i > r) {
+                    const double xi = A[i * ld + c];
+                    sg += xi * xi;
+                }
+        slot_sums(sg);
+        const double sigma = tot[k];
         const double x0 = A[r * ld + c];
         const double mu = sqrt(x0 * x0 + sigma);
         double v0 = 1.0, beta = 0.0;
@@ -199,32 +207,39 @@ __global__ __launch_bounds__(HNT) void house_panel_kernel(double *__restrict__ A
             v0 = x0 >= 0.0 ? x0 + mu : x0 - mu;
             beta = 2.0 / (v0 * v0 + sigma);
         }
-        // one pass over the rows r .. n-1: w_q = v^T A(r:n, c + 1 + q) for the
-        // panel's later columns (q < nl) and g_a = V(:, j0 + a)^T v for its
-        // earlier reflectors (a < k, for the compact factor T)
-        const int nl = nbc - k - 1;
-        for (int q = 0; q < nl + k; ++q)
-            part[q] = 0.0;
-        for (int64_t i = r + tid; i < n; i += HNT) {
-            const double vi = i == r ? v0 : A[i * ld + c];
-            for (int q = 0; q < nl; ++q)
-                part[q] += vi * A[i * ld + c + 1 + q];
-            for (int a = 0; a < k; ++a)
-                part[nl + a] += vi * V[i * ldv + j0 + a];
+        // w_c = v^T A(r:n, c) for the panel's later columns and g_a =
+        // V(:, j0 + a)^T v for its earlier reflectors (the compact factor T)
+        double pd = 0.0;
+        for (int64_t i = j0 + rg; i < n; i += RG) {
+            if (i < r)
+                continue; // the same for the HB lanes of the row
+            const double a = colok ? A[i * ld + col] : 0.0;
+            const double xk = __shfl(a, src + k, WAVE);
+            const double vi = i == r ? v0 : xk;
+            if (cs > k && colok)
+                pd += vi * a;
+            else if (cs < k)
+                pd += vi * V[i * ldv + col];
         }
-        block_sums(part, nl + k);
-        for (int64_t i = r + tid; i < n; i += HNT) {
-            const double vi = i == r ? v0 : A[i * ld + c];
-            V[i * ldv + c] = vi;
-            for (int q = 0; q < nl; ++q)
-                A[i * ld + c + 1 + q] -= beta * vi * tot[q];
-            A[i * ld + c] = i == r ? (x0 >= 0.0 ? -mu : mu) : 0.0;
+        slot_sums(pd);
+        for (int64_t i = j0 + rg; i < n; i += RG) {
+            if (i < r)
+                continue;
+            const double a = colok ? A[i * ld + col] : 0.0;
+            const double xk = __shfl(a, src + k, WAVE);
+            const double vi = i == r ? v0 : xk;
+            if (cs > k && colok) {
+                A[i * ld + col] = a - beta * vi * tot[cs];
+            } else if (cs == k) {
+                V[i * ldv + col] = vi;
+                A[i * ld + col] = i == r ? (x0 >= 0.0 ? -mu : mu) : 0.0;
+            }
         }
         // T(k, k) = beta_k, T(0:k, k) = -beta_k T(0:k, 0:k) g
         if (tid < k) {
             double s = 0.0;
             for (int b = tid; b < k; ++b)
-                s += ts[tid][b] * tot[nl + b];
+                s += ts[tid][b] * tot[b];
             ts[tid][k] = -beta * s;
         }
         if (tid == 0)
