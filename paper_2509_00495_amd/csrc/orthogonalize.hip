@@ -141,10 +141,13 @@ hipError_t cholesky_qr(double *X, double *Q, double *G, double *Rf, int64_t n, i
 // T(0:k, k) = -beta_k T(0:k, 0:k) V(:, 0:k)^T v_k) to T (HB x HB).
 // Thread t works on column slot t mod HB of the rows j0 + t / HB + i HNT / HB,
 // so the HB lanes of a row read its HB panel entries as one contiguous
-// piece; v_i, the entry of column k, reaches the other lanes of its row by a
-// shuffle, and the dot products of all panel columns with v come out of one
-// reduction per column step (lanes of one slot combined by shuffles, waves
-// through LDS).
+// piece; x_i, the entry of column k, reaches the other lanes of its row by a
+// shuffle.  One pass over the rows below the pivot gives, in a single
+// reduction, sigma (column k with itself) and x^T A(r+1:n, c) and
+// x^T V(r+1:n, c) for every other slot; the pivot row's term v_1 A(r, c) is
+// added afterwards, once v_1 is known.  A second pass applies the update.
+// Rows are loaded RU at a time per thread before they are used, so the
+// loads of a pass overlap.
 constexpr int HB = ORTH_HB;
 constexpr int HNT = 1024;
 __global__ __launch_bounds__(HNT) void house_panel_kernel(double *__restrict__ A, int64_t ld,
@@ -152,7 +155,7 @@ __global__ __launch_bounds__(HNT) void house_panel_kernel(double *__restrict__ A
                                                           double *__restrict__ V, int64_t ldv,
                                                           double *__restrict__ T)
 {
-    constexpr int NW = HNT / WAVE, RG = HNT / HB;
+    constexpr int NW = HNT / WAVE, RG = HNT / HB, RU = 4;
     static_assert(WAVE % HB == 0, "a row's slots lie in one wavefront");
     __shared__ double red[NW][HB];
     __shared__ double tot[HB];
@@ -190,15 +193,27 @@ __global__ __launch_bounds__(HNT) void house_panel_kernel(double *__restrict__ A
     };
     for (int k = 0; k < nbc; ++k) {
         const int64_t r = j0 + k, c = j0 + k;
-        // sigma = x(2:m)^T x(2:m)
-        double sg = 0.0;
-        if (cs == k)
-            for (int64_t i = j0 + rg; i < n; i += RG)
-                if (i > r) {
-                    const double xi = A[i * ld + c];
-                    sg += xi * xi;
-                }
-        slot_sums(sg);
+        // pass 1, rows r+1 .. n-1: slot k sums x_i^2 (sigma), a later slot
+        // x_i A(i, c), an earlier slot x_i V(i, c).  The chunk loop is the
+        // same for every lane of a wavefront (its rows are guarded one by
+        // one), so every shuffle has its whole row active.
+        double pd = 0.0;
+        for (int64_t i0 = j0; i0 < n; i0 += (int64_t)RU * RG) {
+            double a[RU], b[RU];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int64_t i = i0 + rg + (int64_t)u * RG;
+                const bool in = i > r && i < n;
+                a[u] = in && colok ? A[i * ld + col] : 0.0;
+                b[u] = in && cs < k ? V[i * ldv + col] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const double xk = __shfl(a[u], src + k, WAVE);
+                pd += xk * (cs < k ? b[u] : a[u]);
+            }
+        }
+        slot_sums(pd);
         const double sigma = tot[k];
         const double x0 = A[r * ld + c];
         const double mu = sqrt(x0 * x0 + sigma);
@@ -207,47 +222,100 @@ __global__ __launch_bounds__(HNT) void house_panel_kernel(double *__restrict__ A
             v0 = x0 >= 0.0 ? x0 + mu : x0 - mu;
             beta = 2.0 / (v0 * v0 + sigma);
         }
-        // w_c = v^T A(r:n, c) for the panel's later columns and g_a =
-        // V(:, j0 + a)^T v for its earlier reflectors (the compact factor T)
-        double pd = 0.0;
-        for (int64_t i = j0 + rg; i < n; i += RG) {
-            if (i < r)
-                continue; // the same for the HB lanes of the row
-            const double a = colok ? A[i * ld + col] : 0.0;
-            const double xk = __shfl(a, src + k, WAVE);
-            const double vi = i == r ? v0 : xk;
-            if (cs > k && colok)
-                pd += vi * a;
-            else if (cs < k)
-                pd += vi * V[i * ldv + col];
-        }
-        slot_sums(pd);
-        for (int64_t i = j0 + rg; i < n; i += RG) {
-            if (i < r)
-                continue;
-            const double a = colok ? A[i * ld + col] : 0.0;
-            const double xk = __shfl(a, src + k, WAVE);
-            const double vi = i == r ? v0 : xk;
-            if (cs > k && colok) {
-                A[i * ld + col] = a - beta * vi * tot[cs];
-            } else if (cs == k) {
-                V[i * ldv + col] = vi;
-                A[i * ld + col] = i == r ? (x0 >= 0.0 ? -mu : mu) : 0.0;
-            }
-        }
-        // T(k, k) = beta_k, T(0:k, k) = -beta_k T(0:k, 0:k) g
+        // w_c = v^T A(r:n, c) of this thread's (later) slot
+        const double wc = cs > k && colok ? tot[cs] + v0 * A[r * ld + col] : 0.0;
+        // T(k, k) = beta_k, T(0:k, k) = -beta_k T(0:k, 0:k) g with g_b =
+        // V(:, j0 + b)^T v (b < k)
         if (tid < k) {
-            double s = 0.0;
+            double sacc = 0.0;
             for (int b = tid; b < k; ++b)
-                s += ts[tid][b] * tot[b];
-            ts[tid][k] = -beta * s;
+                sacc += ts[tid][b] * (tot[b] + v0 * V[r * ldv + j0 + b]);
+            ts[tid][k] = -beta * sacc;
         }
         if (tid == 0)
             ts[k][k] = beta;
+        __syncthreads(); // tot and the pivot row are read before pass 2 writes
+        // pass 2, rows r .. n-1: the update
+        for (int64_t i0 = j0; i0 < n; i0 += (int64_t)RU * RG) {
+            double a[RU];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int64_t i = i0 + rg + (int64_t)u * RG;
+                a[u] = i >= r && i < n && colok ? A[i * ld + col] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int64_t i = i0 + rg + (int64_t)u * RG;
+                const double xk = __shfl(a[u], src + k, WAVE);
+                if (i < r || i >= n)
+                    continue;
+                const double vi = i == r ? v0 : xk;
+                if (cs > k && colok) {
+                    A[i * ld + col] = a[u] - beta * vi * wc;
+                } else if (cs == k) {
+                    V[i * ldv + col] = vi;
+                    A[i * ld + col] = i == r ? (x0 >= 0.0 ? -mu : mu) : 0.0;
+                }
+            }
+        }
         __syncthreads();
     }
     for (int e = tid; e < HB * HB; e += HNT)
         T[e] = ts[e / HB][e % HB];
+}
+
+// W = V^T B for a panel of nb <= 16 reflectors: V is K x nb (row stride ldv),
+// B is K x N (row stride ldb), W is nb x N (row stride ldw).  One workgroup
+// per 16 columns of W; its four wavefronts split K, each accumulating a
+// 16 x 16 part on the FP64 16x16x4 MFMA with both operands read straight
+// from the rows of V and B (four rows of 128 bytes per step), and the parts
+// are added in LDS.  (The generic 64 x 64-tile GEMM spends three quarters of
+// its tile on the nb = 16 rows and puts only N / 64 workgroups on a long K.)
+constexpr int VTB_U = 8; // MFMA steps whose loads are issued together
+__global__ __launch_bounds__(256) void vtb_kernel(const double *__restrict__ V, int64_t ldv,
+                                                  int nb, const double *__restrict__ B,
+                                                  int64_t ldb, int64_t K, int64_t N,
+                                                  double *__restrict__ W, int64_t ldw)
+{
+    __shared__ double part[4][16 * 17];
+    const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+    const int li = lane % 16, lk = lane / 16;
+    const int64_t j = (int64_t)blockIdx.x * 16 + li;
+    const int64_t steps = (K + 3) / 4;
+    const int64_t s0 = w * steps / 4, s1 = (w + 1) * steps / 4;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t st = s0; st < s1; st += VTB_U) {
+        double a[VTB_U], b[VTB_U];
+#pragma unroll
+        for (int u = 0; u < VTB_U; ++u) {
+            const int64_t k = 4 * (st + u) + lk;
+            const bool in = st + u < s1 && k < K;
+            a[u] = in && li < nb ? V[k * ldv + li] : 0.0; // V^T(li, k)
+            b[u] = in && j < N ? B[k * ldb + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < VTB_U; ++u)
+            acc = mfma16(a[u], b[u], acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        part[w][acc_row<double>(lk, v) * 17 + li] = acc[v];
+    __syncthreads();
+    const int i = tid / 16, c = tid % 16;
+    const int64_t jc = (int64_t)blockIdx.x * 16 + c;
+    if (i < nb && jc < N)
+        W[i * ldw + jc] = part[0][i * 17 + c] + part[1][i * 17 + c] + part[2][i * 17 + c] +
+                          part[3][i * 17 + c];
+}
+
+static hipError_t launch_vtb(const double *V, int64_t ldv, int nb, const double *B, int64_t ldb,
+                             int64_t K, int64_t N, double *W, int64_t ldw, hipStream_t s)
+{
+    if (N <= 0 || nb <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(vtb_kernel, dim3((unsigned)((N + 15) / 16)), dim3(256), 0, s, V, ldv, nb,
+                       B, ldb, K, N, W, ldw);
+    return hipGetLastError();
 }
 
 // Householder QR of X (n x n, ld): Q (n x n, ld) with X = Q R.  X is
@@ -265,9 +333,8 @@ hipError_t householder_qr(double *X, double *Q, double *Vs, int64_t n, int64_t l
                            Ts + p * HB * HB);
         if (rest > 0) {
             // A(j0:, j0+nb:) <- (I - V T V^T)^T A = A - V T^T (V^T A)
-            e = launch_gemm64(1, 0, nb, rest, m, 1.0, Vs + j0 * ld + j0, ld, 0,
-                              X + j0 * ld + j0 + nb, ld, 0, 0.0, nullptr, 0, 0, 0.0, W, rest, 0,
-                              1, s);
+            e = launch_vtb(Vs + j0 * ld + j0, ld, (int)nb, X + j0 * ld + j0 + nb, ld, m, rest, W,
+                           rest, s);
             if (e != hipSuccess)
                 return e;
             e = launch_gemm64(1, 0, nb, rest, nb, 1.0, Ts + p * HB * HB, HB, 0, W, rest, 0, 0.0,
@@ -288,8 +355,7 @@ hipError_t householder_qr(double *X, double *Q, double *Vs, int64_t n, int64_t l
         return e;
     for (int64_t p = np - 1; p >= 0; --p) {
         const int64_t j0 = p * HB, nb = n - j0 < HB ? n - j0 : HB, m = n - j0;
-        e = launch_gemm64(1, 0, nb, m, m, 1.0, Vs + j0 * ld + j0, ld, 0, Q + j0 * ld + j0, ld, 0,
-                          0.0, nullptr, 0, 0, 0.0, W, m, 0, 1, s);
+        e = launch_vtb(Vs + j0 * ld + j0, ld, (int)nb, Q + j0 * ld + j0, ld, m, m, W, m, s);
         if (e != hipSuccess)
             return e;
         e = launch_gemm64(0, 0, nb, m, nb, 1.0, Ts + p * HB * HB, HB, 0, W, m, 0, 0.0, nullptr, 0,
