@@ -110,6 +110,25 @@ def test_goe4096_vs_oracle_fixture(pj, fn):
     bars(A, W, V, fn)
 
 
+GOE_VARIANTS = [dict(orth=1), dict(orth=2), dict(ladder=1)]
+
+
+@pytest.mark.parametrize("kw", GOE_VARIANTS, ids=["householder", "cholesky", "ladder"])
+def test_goe4096_variants_vs_oracle_fixture(pj, kw):
+    """The mixed path's other orthogonalisers (Section 4.4) and the binary16
+    first stage at n = 4096, against the same stored oracle run."""
+    if not os.path.exists(os.path.join(GOLD, "oracle_goe4096.txt")):
+        pytest.skip("oracle fixture for the n = 4096 workload not written")
+    A = wl.goe(4096, 3)
+    W, V, info = solve(pj, "eigh_mixed", A, **kw)
+    assert info["status"] == 0 and info["path"] == 1
+    _, rq, _, _ = fixtures.load("goe4096")
+    worst, nsep = vs_fixture(W, "goe4096", np.abs(rq).max(), f"eigh_mixed {kw}")
+    assert nsep >= 0.99 * len(rq)
+    assert worst <= 1e-13
+    bars(A, W, V, f"eigh_mixed {kw}")
+
+
 FORCED = [("eigh", dict(pair_v_split=4)),
           ("eigh_mixed", dict(pair_v_split=4)),
           ("eigh_mixed", dict(gemm_slots=16)),
