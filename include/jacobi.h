@@ -52,7 +52,7 @@ extern "C" {
 typedef struct jacobi_opts {
     int32_t max_sweeps;     /* per stage; default 30 */
     int32_t block;          /* block size b of the block path: 16 or 32; default
-                               16 for n <= 256, else 32 */
+                               16 for n <= 160, else 32 */
     int32_t inner_sweeps;   /* inner sweeps of each 2b x 2b pair solve; default 1 */
     int32_t ns_iters;       /* Newton-Schulz iterations: 0 = the count of
                                Algorithm 8 (2 for n < 52 000, else 3); -1 =
