@@ -212,13 +212,20 @@ int jacobi_eigh_mixed(const double *A, int64_t n, int64_t lda, double *W,
 /* Batched eigendecomposition of matrices of uneven order in one persistent
  * launch (each workgroup pops matrices from a device work queue, largest
  * first, and runs Algorithm 4, Section 3.3, on the whole matrix in LDS).
+ * A batch whose orders are all equal and above 128 runs on the block path
+ * instead (the parallel block Jacobi of jacobi_eigh, Section 3.3): one launch
+ * per step serves every matrix still sweeping, ingest and output stay per
+ * matrix, and each matrix's W, V and status are bitwise those of jacobi_eigh
+ * on it with the same opts (opts.timing, serial_v, graph, tune and threads do
+ * not apply there; the workspace holds one single-solve workspace per matrix).
  *   A      [in]  matrix i is n_i x n_i row-major (ld = n_i) at offset a_off[i]
  *                doubles
- *   n      [in, HOST] batch orders, 1 <= n_i <= 128
+ *   n      [in, HOST] batch orders, 1 <= n_i <= 128, or all equal (any order
+ *                up to 2^20)
  *   a_off  [in, HOST] batch offsets of the matrices in A (and of the
  *                eigenvectors in V), in doubles, >= 0; NULL = packed
  *                (sum_{j<i} n_j^2)
- *   batch  [in]  number of matrices, >= 0
+ *   batch  [in]  number of matrices, >= 0 (at most 65535 for the block path)
  *   W      [out] n_i eigenvalues of matrix i at offset w_off[i]
  *   w_off  [in, HOST] batch offsets into W, >= 0; NULL = packed (sum_{j<i} n_j)
  *   V      [out] eigenvectors of matrix i, n_i x n_i row-major at a_off[i]
@@ -259,7 +266,8 @@ int jacobi_eigh_backward(const double *W, const double *V, const double *dW,
 
 /* jacobi_eigh_batched for callers that cannot allocate: code being captured
  * into a HIP graph, tight serving loops, harnesses that forbid hipMalloc.
- * Same arguments, results and status codes as jacobi_eigh_batched, without
+ * Same arguments, results and status codes as jacobi_eigh_batched for orders
+ * 1 <= n_i <= 128 (larger orders return -2), without
  * work/work_bytes: the call allocates nothing (no hipMalloc/hipFree, no
  * host heap, no events or streams) and takes its scratch from a fixed
  * 64 MiB device array that each GPU the library runs on holds until the
@@ -279,7 +287,8 @@ int jacobi_eigh_batched_noalloc(const double *A, const int64_t *n,
                                 void *stream, int32_t *status);
 
 /* Workspace query (LAPACK style).  op: 0 = eigh, 1 = eigh_mixed,
- * 2 = eigh_batched (n_max = largest order, batch = count),
+ * 2 = eigh_batched (n_max = largest order, batch = count; above 128 the
+ * block path's batch of one order),
  * 3 = eigh_backward (n_max = n).  Returns bytes; 0 for invalid op. */
 size_t jacobi_workspace_bytes(int op, int64_t n_max, int64_t batch,
                               const jacobi_opts *opts);

@@ -174,6 +174,7 @@ struct Bump {
 int default_block(int64_t n) { return n <= 160 ? 16 : 32; }
 
 constexpr int NPROBE = 4;           // Rademacher probes of the orthogonality estimate
+constexpr int PROBE_BLOCKS = 64;    // workgroups of the probe's residual sums
 constexpr double POLISH_FRAC = 0.2; // refresh V when the estimate exceeds this
                                     // fraction of 1e-14 n
 
@@ -859,23 +860,30 @@ int eigh_small(const double *A, int64_t n, int64_t lda, double *W, double *V, in
 // instead of the diagonal of B.  The plain FP64 path uses this: after its
 // many sweeps of blockwise updates the rounding accumulated in the diagonal of
 // B exceeds what the eigenvectors themselves allow.
-int finalize_block(const Geometry &g, int64_t n, const BlockWs &w, const double *B,
-                   const double *Vin, double *Rbuf, double *Vbuf, double *W, double *V,
-                   int64_t ldv, hipStream_t s, double *orth_est, int *polished,
-                   const double *A_rq = nullptr, int64_t lda = 0)
+// The output stage in two parts, so that a batch reads every matrix's
+// estimate back at once: finalize_probe issues the diagonal, the column
+// statistics and the probe (its sum lands in w.scal[3]); finalize_finish takes
+// the estimate read back and issues the rest.
+int finalize_probe(const Geometry &g, int64_t n, const BlockWs &w, const double *B,
+                   const double *Vin, hipStream_t s)
 {
     const int64_t np = g.npad;
     CK(launch_diag(B, np, n, w.wtmp, s));
     CK(launch_colstats(Vin, np, n, np, w.cmax, w.cidx, w.csq, w.cinv, s));
     double *X = w.probe, *Y = w.probe + np * NPROBE, *P = w.probe + 2 * np * NPROBE;
     CK(launch_rademacher(X, np, n, NPROBE, 0x5eedull, s));
-    constexpr int PROBE_BLOCKS = 64;
     CK(launch_orth_probe(Vin, np, n, np, NPROBE, X, w.cinv, Y, P, w.partial, PROBE_BLOCKS, s));
     CK(launch_sum(w.partial, PROBE_BLOCKS, w.scal + 3, s));
-    Readback rb;
-    if (int e = read_scalars(w, s, rb))
-        return e;
-    const double est = std::sqrt(rb.scal[3] / NPROBE);
+    return 0;
+}
+
+int finalize_finish(const Geometry &g, int64_t n, const BlockWs &w, double probe_sum,
+                    const double *Vin, double *Rbuf, double *Vbuf, double *W, double *V,
+                    int64_t ldv, hipStream_t s, double *orth_est, int *polished,
+                    const double *A_rq, int64_t lda)
+{
+    const int64_t np = g.npad;
+    const double est = std::sqrt(probe_sum / NPROBE);
     *orth_est = est;
     *polished = 0;
     const double *Vf = Vin;
@@ -896,6 +904,20 @@ int finalize_block(const Geometry &g, int64_t n, const BlockWs &w, const double 
     CK(launch_fill_i32(w.perm, n, 0, s));
     CK(launch_finalize(w.wtmp, Vf, np, n, W, V, ldv, w.perm, w.sg, w.cmax, w.cidx, w.cinv, s));
     return 0;
+}
+
+int finalize_block(const Geometry &g, int64_t n, const BlockWs &w, const double *B,
+                   const double *Vin, double *Rbuf, double *Vbuf, double *W, double *V,
+                   int64_t ldv, hipStream_t s, double *orth_est, int *polished,
+                   const double *A_rq = nullptr, int64_t lda = 0)
+{
+    if (int e = finalize_probe(g, n, w, B, Vin, s))
+        return e;
+    Readback rb;
+    if (int e = read_scalars(w, s, rb))
+        return e;
+    return finalize_finish(g, n, w, rb.scal[3], Vin, Rbuf, Vbuf, W, V, ldv, s, orth_est,
+                           polished, A_rq, lda);
 }
 
 // Exponent k of the exact scaling B <- 2^k B applied on ingest: inputs whose
@@ -1204,6 +1226,242 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
     return st;
 }
 
+// ---- a batch of equal-order matrices on the block path (plain FP64)
+// Every matrix gets a workspace region with the single-solve layout, all of
+// one size R, so that one launch per step serves the whole batch (blockIdx.y
+// = matrix, its pointers moved by m R); the pair tables live in region 0 and
+// are shared.  Ingest and the output stage stay per matrix (O(n^2) launches)
+// with one host synchronisation per phase for the whole batch.  Each matrix
+// goes through the launches of a single solve (the same kernels, the same
+// order of operations and the same stopping tests, its pending V update
+// riding in the next sweep's first launch while it is active), so its results
+// are bitwise those of jacobi_eigh on it; a matrix leaves the sweeps when its
+// own tests say so (act = 0 from then on, its pending V update applied by one
+// launch over the matrices leaving together).
+size_t block_region_bytes(int64_t n, const Opts &o)
+{
+    Bump bp(nullptr);
+    layout_block(bp, n, geometry(n, o.block), false);
+    return (bp.off + 255) & ~(size_t)255;
+}
+
+size_t ws_block_batched(int64_t n, int64_t batch, const Opts &o)
+{
+    // the regions, then two sets of per-matrix flags and the thresholds
+    const size_t per = ((size_t)std::max<int64_t>(batch, 1) * sizeof(double) + 255) & ~(size_t)255;
+    return block_region_bytes(n, o) * (size_t)std::max<int64_t>(batch, 1) + 3 * per + 256;
+}
+
+int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t batch,
+                       double *W, const int64_t *w_off, double *V, double tol_in, const Opts &o,
+                       void *work, hipStream_t s, std::vector<int32_t> &st)
+{
+    const Geometry g = geometry(n, o.block);
+    const size_t R = block_region_bytes(n, o);
+    char *base = (char *)work;
+    std::vector<BlockWs> ws((size_t)batch);
+    for (int64_t m = 0; m < batch; ++m) {
+        Bump bp(base + (size_t)m * R);
+        ws[(size_t)m] = layout_block(bp, n, g, false);
+    }
+    Bump tail(base + (size_t)batch * R);
+    int *act_d = tail.take<int>((size_t)batch);   // in the sweeps
+    int *fin_d = tail.take<int>((size_t)batch);   // leaving the sweeps together
+    double *thr_d = tail.take<double>((size_t)batch);
+    const BlockWs &w0 = ws[0];
+    const int64_t nn = g.npad * g.npad;
+    auto aoff = [&](int64_t m) { return a_off ? a_off[m] : m * n * n; };
+    auto woff = [&](int64_t m) { return w_off ? w_off[m] : m * n; };
+    st.assign((size_t)batch, JACOBI_OK);
+    if (int e = setup_block(g, w0, s))
+        return e;
+    const Batch all{batch, (int64_t)R, nullptr, nullptr};
+    CK(launch_fill_batch_i32(w0.flags, 8, 0, all, s));
+    CK(launch_fill_batch_i32(w0.prot, (int64_t)2 * g.npairs * PROT_STRIDE, 0, all, s));
+    // every region's scalars and flags back to the host at once
+    std::vector<double> sc((size_t)batch * 8);
+    std::vector<int> fl((size_t)batch * 8);
+    auto read_all = [&]() -> int {
+        CK(hipMemcpy2DAsync(sc.data(), 8 * sizeof(double), w0.scal, R, 8 * sizeof(double),
+                            (size_t)batch, hipMemcpyDeviceToHost, s));
+        CK(hipMemcpy2DAsync(fl.data(), 8 * sizeof(int), w0.flags, R, 8 * sizeof(int),
+                            (size_t)batch, hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        return 0;
+    };
+    // ingest (ingest_norm per matrix)
+    for (int64_t m = 0; m < batch; ++m) {
+        const BlockWs &w = ws[(size_t)m];
+        CK(launch_ingest<double>(A + aoff(m), n, n, w.B64, g.npad, w.partial, w.flags,
+                                 o.check_sym, s));
+        CK(launch_sum(w.partial, INGEST_BLOCKS, w.scal, s));
+        CK(launch_max(w.partial + INGEST_BLOCKS, INGEST_BLOCKS, w.scal + 4, s));
+    }
+    if (int e = read_all())
+        return e;
+    std::vector<int> ks((size_t)batch, 0), act((size_t)batch, 0), fin((size_t)batch, 0),
+        sweeps((size_t)batch, 0);
+    std::vector<double> tol((size_t)batch, 0.0), thr((size_t)batch, 0.0);
+    bool rescaled = false;
+    for (int64_t m = 0; m < batch; ++m) {
+        const size_t i = (size_t)m;
+        if (fl[8 * i]) {
+            st[i] = JACOBI_NONFINITE;
+            continue;
+        }
+        if (o.check_sym && fl[8 * i + 1]) {
+            st[i] = JACOBI_NOTSYM;
+            continue;
+        }
+        ks[i] = scale_exponent(sc[8 * i + 4]);
+        if (ks[i]) {
+            const BlockWs &w = ws[i];
+            CK(launch_scale_pow2(w.B64, nn, ks[i], w.A0, s));
+            CK(launch_sq_partial(w.B64, nn, w.partial, s));
+            CK(launch_sum(w.partial, OFF_BLOCKS, w.scal, s));
+            rescaled = true;
+        }
+        act[i] = 1;
+    }
+    if (rescaled)
+        if (int e = read_all())
+            return e;
+    for (int64_t m = 0; m < batch; ++m) {
+        const size_t i = (size_t)m;
+        if (!act[i])
+            continue;
+        const double normf = std::sqrt(sc[8 * i]);
+        tol[i] = tol_in > 0.0 ? std::ldexp(tol_in, ks[i]) : 1e-15 * (double)n * normf;
+        thr[i] = tol[i] / (double)n;
+        CK(launch_eye<double>(ws[i].V64, g.npad, s));
+        CK(launch_off2_partial<double>(ws[i].B64, g.npad, ws[i].partial, s));
+    }
+    CK(hipMemcpyAsync(act_d, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(thr_d, thr.data(), thr.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    const Batch bact{batch, (int64_t)R, act_d, nullptr};
+    CK(launch_sum(w0.partial, OFF_BLOCKS, w0.scal + 1, s, bact));
+    if (int e = read_all())
+        return e;
+    std::vector<int> solved((size_t)batch, 0); // outputs to write (OK or NOCONV)
+    for (int64_t m = 0; m < batch; ++m) {
+        const size_t i = (size_t)m;
+        if (!act[i])
+            continue;
+        const double off = std::sqrt(sc[8 * i + 1]);
+        solved[i] = 1;
+        if (!std::isfinite(off)) {
+            st[i] = JACOBI_NONFINITE;
+            solved[i] = 0;
+            act[i] = 0;
+        } else if (!(off > tol[i])) {
+            act[i] = 0;
+        }
+    }
+    // the sweeps (run_sweeps with the shared launch, per matrix)
+    const size_t ustride = (size_t)g.npairs * g.M * g.M;
+    const int2 *vpend_pairs = nullptr;
+    const double *vpend_U = nullptr;
+    const int *vpend_prot = nullptr;
+    int64_t round = 0;
+    for (;;) {
+        bool any_fin = false;
+        for (int64_t m = 0; m < batch; ++m) {
+            const size_t i = (size_t)m;
+            if (act[i] && sweeps[i] >= o.max_sweeps) {
+                st[i] = JACOBI_NOCONV;
+                act[i] = 0;
+                fin[i] = 1;
+            }
+            any_fin = any_fin || fin[i];
+        }
+        if (any_fin && vpend_pairs) {
+            CK(hipMemcpyAsync(fin_d, fin.data(), fin.size() * sizeof(int),
+                              hipMemcpyHostToDevice, s));
+            const Batch bf{batch, (int64_t)R, fin_d, nullptr};
+            CK(launch_update_v<double>(w0.V64, g.npad, g.npad, g.b, g.npairs, vpend_pairs,
+                                       vpend_U, vpend_prot, s, nullptr, nullptr, bf));
+        }
+        if (std::find(act.begin(), act.end(), 1) == act.end())
+            break;
+        CK(hipMemcpyAsync(act_d, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        const Batch bt{batch, (int64_t)R, act_d, thr_d};
+        CK(launch_fill_batch_i32(w0.flags + 2, 1, 0, bt, s));
+        for (int r = 0; r < g.N - 1; ++r, ++round) {
+            const int j = (int)(round & 1);
+            double *Ub = w0.U64 + j * ustride;
+            int *pf = w0.prot + (size_t)j * g.npairs * PROT_STRIDE;
+            const int *pfc = o.pair_skip ? pf : nullptr;
+            const int2 *pr = w0.pairs + (size_t)r * g.npairs;
+            const int cross = o.schedule == 0 && r > 0;
+            const int2 *map = w0.psmap + (cross ? (size_t)g.b * (g.b + 1) / 2 : 0);
+            if (vpend_pairs) {
+                CK(launch_pair_solve_v<double>(w0.B64, g.npad, g.b, g.npairs, pr, map, Ub, U_D,
+                                               0.0, o.inner, 0, cross, w0.partial, w0.flags + 2,
+                                               pf, w0.V64, g.npad, g.npad, vpend_pairs, vpend_U,
+                                               vpend_prot, s, o.pair_v_split, nullptr, nullptr,
+                                               bt));
+            } else {
+                CK(launch_pair_solve<double>(w0.B64, g.npad, g.b, g.npairs, pr, map, Ub, U_D, 0.0,
+                                             o.inner, 0, cross, w0.partial, w0.flags + 2, pf, s,
+                                             nullptr, nullptr, bt));
+            }
+            CK(launch_update_b<double>(w0.B64, g.npad, g.b, g.npairs, pr, Ub,
+                                       w0.partial + (size_t)g.npairs * pair_solve_waves(g.M),
+                                       r == g.N - 2, 0, pfc, w0.flags + 3, s, nullptr, nullptr,
+                                       bt));
+            vpend_pairs = pr;
+            vpend_U = Ub;
+            vpend_prot = pfc;
+        }
+        CK(launch_sum(w0.partial,
+                      (int64_t)g.npairs * pair_solve_waves(g.M) + (int64_t)g.nbt * (g.M / 16),
+                      w0.scal + 1, s, bt));
+        if (int e = read_all())
+            return e;
+        // the host copies of act and fin are rewritten only after a stream
+        // synchronisation (their asynchronous uploads have then been made)
+        std::fill(fin.begin(), fin.end(), 0);
+        for (int64_t m = 0; m < batch; ++m) {
+            const size_t i = (size_t)m;
+            if (!act[i])
+                continue;
+            ++sweeps[i];
+            const double off = std::sqrt(sc[8 * i + 1]);
+            if (!std::isfinite(off)) {
+                st[i] = JACOBI_NONFINITE;
+                solved[i] = 0;
+                act[i] = 0;
+            } else if (!fl[8 * i + 2] || !(off > tol[i])) {
+                act[i] = 0; // no pair rotated, or off <= tol
+                fin[i] = 1;
+            }
+        }
+    }
+    // the output stage
+    for (int64_t m = 0; m < batch; ++m)
+        if (solved[(size_t)m])
+            if (int e = finalize_probe(g, n, ws[(size_t)m], ws[(size_t)m].B64, ws[(size_t)m].V64, s))
+                return e;
+    if (int e = read_all())
+        return e;
+    for (int64_t m = 0; m < batch; ++m) {
+        const size_t i = (size_t)m;
+        if (!solved[i])
+            continue;
+        const BlockWs &w = ws[i];
+        double est = 0.0;
+        int pol = 0;
+        if (int e = finalize_finish(g, n, w, sc[8 * i + 3], w.V64, w.B64, w.Vt, W + woff(m),
+                                    V + aoff(m), n, s, &est, &pol, ks[i] ? w.A0 : A + aoff(m),
+                                    ks[i] ? g.npad : n))
+            return e;
+        if (ks[i])
+            CK(launch_scale_pow2(W + woff(m), n, -ks[i], nullptr, s));
+    }
+    CK(hipStreamSynchronize(s));
+    return 0;
+}
+
 } // namespace
 
 // ======================================================================= ABI
@@ -1251,6 +1509,8 @@ size_t jacobi_workspace_bytes(int op, int64_t n_max, int64_t batch, const jacobi
     case 1:
         return ws_block(std::max<int64_t>(n_max, 1), o, true) + 256;
     case 2:
+        if (n_max > 128) // a batch of one order on the block path
+            return ws_block_batched(n_max, batch, o) + 256;
         return ws_small(std::max<int64_t>(batch, 1), std::max<int64_t>(n_max, 1), o.threads,
                         o.tune) +
                256;
@@ -1320,15 +1580,24 @@ int jacobi_eigh_batched(const double *A, const int64_t *n, const int64_t *a_off,
     if (batch > 0 && !n)
         return -2;
     int64_t n_max = 0;
+    bool uniform = true;
     for (int64_t i = 0; i < batch; ++i) {
-        if (n[i] < 1 || n[i] > 128)
+        if (n[i] < 1 || n[i] > (int64_t)1 << 20)
             return -2;
+        uniform = uniform && n[i] == n[0];
         n_max = std::max(n_max, n[i]);
         if (a_off && a_off[i] < 0)
             return -3;
         if (w_off && w_off[i] < 0)
             return -6;
     }
+    // orders above 128 (one workgroup's LDS) only as a batch of one order,
+    // which runs on the block path
+    const bool block = n_max > 128;
+    if (block && !uniform)
+        return -2;
+    if (block && batch > 65535)
+        return -4; // the matrix index is the launches' second grid dimension
     if (batch > 0 && !A)
         return -1;
     if (batch > 0 && !W)
@@ -1346,6 +1615,29 @@ int jacobi_eigh_batched(const double *A, const int64_t *n, const int64_t *a_off,
         return JACOBI_OK;
     hipStream_t s = (hipStream_t)stream;
     const size_t need = jacobi_workspace_bytes(2, n_max, batch, opts);
+    if (block) {
+        WsGuard bguard;
+        if (!work) {
+            CK(hipMalloc(&bguard.p, need));
+            bguard.s = s;
+            work = bguard.p;
+        } else if (work_bytes < need) {
+            return JACOBI_WORKSPACE;
+        }
+        std::vector<int32_t> st;
+        if (int e = eigh_block_batched(A, n_max, a_off, batch, W, w_off, V, tol, o,
+                                       (void *)(((uintptr_t)work + 255) & ~(uintptr_t)255), s, st))
+            return e;
+        if (status) {
+            CK(hipMemcpyAsync(status, st.data(), st.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
+            CK(hipStreamSynchronize(s));
+        }
+        int worst = 0;
+        for (int32_t v : st)
+            worst = std::max(worst, (int)v);
+        return worst;
+    }
     WsGuard guard;
     if (!work) {
         CK(hipMalloc(&guard.p, need));

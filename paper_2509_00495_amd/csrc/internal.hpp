@@ -62,11 +62,31 @@ inline void launch_timed(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStrea
 }
 
 // ---- block path (kernels_block.hip); T = double or float
+// A batch of equal-order solves in one launch per step (blockIdx.y = matrix):
+// every matrix's buffers sit at the same offsets of equally sized workspace
+// regions sW bytes apart, so each kernel moves its workspace pointers by
+// m sW; the pair tables are shared.  act (device, count ints, or null): a
+// matrix whose entry is 0 is left alone (its workgroups return at once);
+// thr (device, count doubles, or null): per-matrix absolute rotation
+// thresholds replacing the scalar one.
+struct Batch {
+    int64_t count = 1;
+    int64_t sW = 0;
+    const int *act = nullptr;
+    const double *thr = nullptr;
+};
+template <typename P>
+__device__ __forceinline__ P *bat(P *p, int64_t m, int64_t sW)
+{
+    return p ? reinterpret_cast<P *>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)(m * sW)) : p;
+}
+
 template <typename T>
 hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                              const int2 *psmap, T *U, double eps, double thr, int inner, int r16,
                              int cross, double *partial, int *rot_flag, int *prot,
-                             hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                             hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+                             const Batch &bt = Batch());
 // the same pair solves, plus the V update V[:, cols] <- V[:, cols] vU of the
 // previous round (pairs vpairs, rotations vU, rotation flags vprot or null)
 // on further workgroups of the same launch; vsplit: 16-row V tiles per pair
@@ -77,7 +97,8 @@ hipError_t launch_pair_solve_v(T *B, int64_t ldb, int b, int npairs, const int2 
                                int r16, int cross, double *partial, int *rot_flag, int *prot, T *V,
                                int64_t ldv, int64_t nrows, const int2 *vpairs, const T *vU,
                                const int *vprot, hipStream_t s, int vsplit = 0,
-                               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+                               const Batch &bt = Batch());
 // experiments: V workgroups of the shared launch (0 = default), a minimum
 // dynamic LDS per workgroup (larger keeps one workgroup per compute unit) and
 // the working wavefronts per V workgroup (0 = all)
@@ -96,7 +117,8 @@ void pair_solve_map(int M, int cross, int2 *out);
 template <typename T>
 hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pairs, const T *U,
                            double *partial, int want_off, int r16, const int *prot, int *skipped,
-                           hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                           hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+                           const Batch &bt = Batch());
 template <typename T>
 int update_b_blocks_per_cu(int b);
 // grid sizing of the V update: total resident wavefronts (0 = from occupancy)
@@ -108,8 +130,14 @@ void tune_update_v(int total_waves);
 template <typename T>
 hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
                            const int2 *pairs, const T *U, const int *prot, hipStream_t s,
-                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
-hipError_t launch_sum(const double *x, int64_t count, double *out, hipStream_t s);
+                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+                           const Batch &bt = Batch());
+// out[0] = sum of x[0 .. count) by one workgroup (per matrix of a batch)
+hipError_t launch_sum(const double *x, int64_t count, double *out, hipStream_t s,
+                      const Batch &bt = Batch());
+// p[0 .. count_per) = value in every matrix's region (p moved by m sW)
+hipError_t launch_fill_batch_i32(int *p, int64_t count_per, int value, const Batch &bt,
+                                 hipStream_t s);
 hipError_t launch_max(const double *x, int64_t count, double *out, hipStream_t s);
 // x <- 2^k x for count entries (exact), also written to copy when not null
 hipError_t launch_scale_pow2(double *x, int64_t count, int k, double *copy, hipStream_t s);

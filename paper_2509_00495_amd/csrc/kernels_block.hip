@@ -421,10 +421,17 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
                                                         T *__restrict__ U, double eps,
                                                         double thr, int inner,
                                                         double *__restrict__ partial,
-                                                        int *rot_flag, int *__restrict__ prot)
+                                                        int *rot_flag, int *__restrict__ prot,
+                                                        int64_t sW, const int *__restrict__ act,
+                                                        const double *__restrict__ thrb)
 {
-    pair_solve_body<T, M, NT, CROSS>(B, ldb, pairs, psmap, U, eps, thr, inner, R16 ? 1 : 0,
-                                     partial, rot_flag, prot, blockIdx.x);
+    const int64_t m = blockIdx.y; // matrix of a batch (0 for a single solve)
+    if (act && !act[m])
+        return;
+    pair_solve_body<T, M, NT, CROSS>(bat(B, m, sW), ldb, pairs, psmap, bat(U, m, sW), eps,
+                                     thrb ? thrb[m] : thr, inner, R16 ? 1 : 0,
+                                     bat(partial, m, sW), bat(rot_flag, m, sW), bat(prot, m, sW),
+                                     blockIdx.x);
 }
 
 // The pair solves of a round on workgroups 0 .. npairs-1 and, on the
@@ -440,10 +447,24 @@ __global__ __launch_bounds__(NT) void pair_solve_v_kernel(
     const int2 *__restrict__ psmap, T *__restrict__ U, double eps, double thr, int inner,
     double *__restrict__ partial, int *rot_flag, int *__restrict__ prot, int npairs,
     T *__restrict__ V, int64_t ldv, int64_t ntile, const int2 *__restrict__ vpairs,
-    const T *__restrict__ vU, const int *__restrict__ vprot, int vranges, int vwaves, int vx)
+    const T *__restrict__ vU, const int *__restrict__ vprot, int vranges, int vwaves, int vx,
+    int64_t sW, const int *__restrict__ act, const double *__restrict__ thrb)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *ufl = reinterpret_cast<T *>(smem_raw);
+    const int64_t m = blockIdx.y; // matrix of a batch (0 for a single solve)
+    if (act && !act[m])
+        return;
+    B = bat(B, m, sW);
+    U = bat(U, m, sW);
+    partial = bat(partial, m, sW);
+    rot_flag = bat(rot_flag, m, sW);
+    prot = bat(prot, m, sW);
+    V = bat(V, m, sW);
+    vU = bat(vU, m, sW);
+    vprot = bat(vprot, m, sW);
+    if (thrb)
+        thr = thrb[m];
     const int64_t split = ntile - vx;
     if ((int)blockIdx.x < npairs) {
         pair_solve_body<T, M, NT, CROSS>(B, ldb, pairs, psmap, U, eps, thr, inner, R16 ? 1 : 0,
@@ -465,7 +486,7 @@ static hipError_t launch_pair_solve_t(T *B, int64_t ldb, int npairs, const int2 
                                       const int2 *psmap, T *U, double eps, double thr,
                                       int inner, double *partial, int *rot_flag,
                                       int *prot, size_t smem, hipStream_t s, hipEvent_t e0,
-                                      hipEvent_t e1)
+                                      hipEvent_t e1, const Batch &bt)
 {
     auto k = pair_solve_kernel<T, M, NT, CROSS, R16>;
     static size_t smem_set = 0; // the attribute is set once per size (host-side cost)
@@ -476,8 +497,8 @@ static hipError_t launch_pair_solve_t(T *B, int64_t ldb, int npairs, const int2 
             return e;
         smem_set = smem;
     }
-    launch_timed(k, dim3(npairs), dim3(NT), (uint32_t)smem, s, e0, e1, B, ldb, pairs, psmap, U,
-                 eps, thr, inner, partial, rot_flag, prot);
+    launch_timed(k, dim3(npairs, (unsigned)bt.count), dim3(NT), (uint32_t)smem, s, e0, e1, B, ldb,
+                 pairs, psmap, U, eps, thr, inner, partial, rot_flag, prot, bt.sW, bt.act, bt.thr);
     return hipGetLastError();
 }
 
@@ -496,7 +517,8 @@ template <typename T, bool R16>
 static hipError_t launch_pair_solve_r(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                                       const int2 *psmap, T *U, double eps, double thr,
                                       int inner, int cross, double *partial, int *rot_flag,
-                                      int *prot, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+                                      int *prot, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                                      const Batch &bt)
 {
     const int M = 2 * b;
     const size_t smem = pair_solve_smem<T>(b);
@@ -509,19 +531,19 @@ static hipError_t launch_pair_solve_r(T *B, int64_t ldb, int b, int npairs, cons
         return cross ? launch_pair_solve_t<T, 64, NT64, true, R16>(B, ldb, npairs, pairs, psmap,
                                                                    U, eps, thr, inner, partial,
                                                                    rot_flag, prot, smem, s, e0,
-                                                                   e1)
+                                                                   e1, bt)
                      : launch_pair_solve_t<T, 64, NT64, false, R16>(B, ldb, npairs, pairs, psmap,
                                                                     U, eps, thr, inner, partial,
                                                                     rot_flag, prot, smem, s, e0,
-                                                                    e1);
+                                                                    e1, bt);
     if (M == 32)
         return cross ? launch_pair_solve_t<T, 32, 256, true, R16>(B, ldb, npairs, pairs, psmap, U,
                                                                   eps, thr, inner, partial,
-                                                                  rot_flag, prot, smem, s, e0, e1)
+                                                                  rot_flag, prot, smem, s, e0, e1, bt)
                      : launch_pair_solve_t<T, 32, 256, false, R16>(B, ldb, npairs, pairs, psmap,
                                                                    U, eps, thr, inner, partial,
                                                                    rot_flag, prot, smem, s, e0,
-                                                                   e1);
+                                                                   e1, bt);
     return hipErrorInvalidValue;
 }
 
@@ -529,14 +551,14 @@ template <typename T>
 hipError_t launch_pair_solve(T *B, int64_t ldb, int b, int npairs, const int2 *pairs,
                              const int2 *psmap, T *U, double eps, double thr, int inner, int r16,
                              int cross, double *partial, int *rot_flag, int *prot, hipStream_t s,
-                             hipEvent_t e0, hipEvent_t e1)
+                             hipEvent_t e0, hipEvent_t e1, const Batch &bt)
 {
     if (sizeof(T) == 4 && r16)
         return launch_pair_solve_r<T, sizeof(T) == 4>(B, ldb, b, npairs, pairs, psmap, U, eps,
                                                       thr, inner, cross, partial, rot_flag, prot,
-                                                      s, e0, e1);
+                                                      s, e0, e1, bt);
     return launch_pair_solve_r<T, false>(B, ldb, b, npairs, pairs, psmap, U, eps, thr, inner,
-                                         cross, partial, rot_flag, prot, s, e0, e1);
+                                         cross, partial, rot_flag, prot, s, e0, e1, bt);
 }
 
 int g_pair_v_wgs = 0;    // V workgroups of the shared launch; 0 = free compute units
@@ -555,7 +577,8 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
                                         int inner, double *partial, int *rot_flag,
                                         int *prot, size_t smem, T *V, int64_t ldv, int64_t nrows,
                                         const int2 *vpairs, const T *vU, const int *vprot,
-                                        hipStream_t s, int vsplit, hipEvent_t e0, hipEvent_t e1)
+                                        hipStream_t s, int vsplit, hipEvent_t e0, hipEvent_t e1,
+                                        const Batch &bt)
 {
     auto k = pair_solve_v_kernel<T, M, NT, CROSS, R16>;
     static size_t smem_set = 0;
@@ -570,9 +593,11 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
     const int64_t ntile = nrows / 16;
     // V workgroups: about one per compute unit the pair solves leave free (at
     // least a quarter of the units), a whole number of row ranges per pair
-    const int vwg = g_pair_v_wgs > 0 ? g_pair_v_wgs
-                                     : (cus - npairs > cus / 4 ? cus - npairs : cus / 4);
-    int64_t ranges = vwg / npairs;
+    // (over the whole batch: at least one range per pair of every matrix)
+    const int64_t spairs = (int64_t)npairs * bt.count;
+    const int64_t vwg = g_pair_v_wgs > 0 ? g_pair_v_wgs
+                                         : (cus - spairs > cus / 4 ? cus - spairs : cus / 4);
+    int64_t ranges = vwg / spairs;
     if (ranges < 1)
         ranges = 1;
     if (ranges > ntile)
@@ -613,9 +638,9 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
             return e;
         smem_set = lds;
     }
-    launch_timed(k, dim3(grid), dim3(NT), (uint32_t)lds, s, e0, e1, B, ldb, pairs, psmap, U, eps,
-                 thr, inner, partial, rot_flag, prot, npairs, V, ldv, ntile, vpairs, vU, vprot,
-                 (int)ranges, vwaves, vx);
+    launch_timed(k, dim3(grid, (unsigned)bt.count), dim3(NT), (uint32_t)lds, s, e0, e1, B, ldb,
+                 pairs, psmap, U, eps, thr, inner, partial, rot_flag, prot, npairs, V, ldv, ntile,
+                 vpairs, vU, vprot, (int)ranges, vwaves, vx, bt.sW, bt.act, bt.thr);
     return hipGetLastError();
 }
 
@@ -625,24 +650,25 @@ static hipError_t launch_pair_solve_v_r(T *B, int64_t ldb, int b, int npairs, co
                                         int inner, int cross, double *partial, int *rot_flag,
                                         int *prot, T *V, int64_t ldv, int64_t nrows,
                                         const int2 *vpairs, const T *vU, const int *vprot,
-                                        hipStream_t s, int vsplit, hipEvent_t e0, hipEvent_t e1)
+                                        hipStream_t s, int vsplit, hipEvent_t e0, hipEvent_t e1,
+                                        const Batch &bt)
 {
     const int M = 2 * b;
     const size_t smem = pair_solve_smem<T>(b);
     if (M == 64)
         return cross ? launch_pair_solve_v_t<T, 64, 1024, true, R16>(
                            B, ldb, npairs, pairs, psmap, U, eps, thr, inner, partial, rot_flag,
-                           prot, smem, V, ldv, nrows, vpairs, vU, vprot, s, vsplit, e0, e1)
+                           prot, smem, V, ldv, nrows, vpairs, vU, vprot, s, vsplit, e0, e1, bt)
                      : launch_pair_solve_v_t<T, 64, 1024, false, R16>(
                            B, ldb, npairs, pairs, psmap, U, eps, thr, inner, partial, rot_flag,
-                           prot, smem, V, ldv, nrows, vpairs, vU, vprot, s, vsplit, e0, e1);
+                           prot, smem, V, ldv, nrows, vpairs, vU, vprot, s, vsplit, e0, e1, bt);
     if (M == 32)
         return cross ? launch_pair_solve_v_t<T, 32, 256, true, R16>(
                            B, ldb, npairs, pairs, psmap, U, eps, thr, inner, partial, rot_flag,
-                           prot, smem, V, ldv, nrows, vpairs, vU, vprot, s, vsplit, e0, e1)
+                           prot, smem, V, ldv, nrows, vpairs, vU, vprot, s, vsplit, e0, e1, bt)
                      : launch_pair_solve_v_t<T, 32, 256, false, R16>(
                            B, ldb, npairs, pairs, psmap, U, eps, thr, inner, partial, rot_flag,
-                           prot, smem, V, ldv, nrows, vpairs, vU, vprot, s, vsplit, e0, e1);
+                           prot, smem, V, ldv, nrows, vpairs, vU, vprot, s, vsplit, e0, e1, bt);
     return hipErrorInvalidValue;
 }
 
@@ -652,7 +678,7 @@ hipError_t launch_pair_solve_v(T *B, int64_t ldb, int b, int npairs, const int2 
                                int r16, int cross, double *partial, int *rot_flag, int *prot, T *V,
                                int64_t ldv, int64_t nrows, const int2 *vpairs, const T *vU,
                                const int *vprot, hipStream_t s, int vsplit, hipEvent_t e0,
-                               hipEvent_t e1)
+                               hipEvent_t e1, const Batch &bt)
 {
     if (nrows % 16 != 0 || ldv % (16 / (int64_t)sizeof(T)) != 0 || ((uintptr_t)V % 16) != 0)
         return hipErrorInvalidValue;
@@ -660,17 +686,23 @@ hipError_t launch_pair_solve_v(T *B, int64_t ldb, int b, int npairs, const int2 
         return launch_pair_solve_v_r<T, sizeof(T) == 4>(B, ldb, b, npairs, pairs, psmap, U, eps,
                                                         thr, inner, cross, partial, rot_flag,
                                                         prot, V, ldv, nrows, vpairs, vU, vprot,
-                                                        s, vsplit, e0, e1);
+                                                        s, vsplit, e0, e1, bt);
     return launch_pair_solve_v_r<T, false>(B, ldb, b, npairs, pairs, psmap, U, eps, thr, inner,
                                            cross, partial, rot_flag, prot, V, ldv, nrows, vpairs,
-                                           vU, vprot, s, vsplit, e0, e1);
+                                           vU, vprot, s, vsplit, e0, e1, bt);
 }
 
 
 // ------------------------------------------------------- reductions, etc.
 __global__ __launch_bounds__(256) void sum_kernel(const double *__restrict__ x, int64_t count,
-                                                  double *out)
+                                                  double *out, int64_t sW,
+                                                  const int *__restrict__ act)
 {
+    const int64_t m = blockIdx.x; // matrix of a batch (0 for a single sum)
+    if (act && !act[m])
+        return;
+    x = bat(x, m, sW);
+    out = bat(out, m, sW);
     __shared__ double red[4];
     double acc = 0.0;
     for (int64_t i = threadIdx.x; i < count; i += 256)
@@ -683,9 +715,11 @@ __global__ __launch_bounds__(256) void sum_kernel(const double *__restrict__ x, 
         out[0] = red[0] + red[1] + red[2] + red[3];
 }
 
-hipError_t launch_sum(const double *x, int64_t count, double *out, hipStream_t s)
+hipError_t launch_sum(const double *x, int64_t count, double *out, hipStream_t s,
+                      const Batch &bt)
 {
-    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, s, x, count, out);
+    hipLaunchKernelGGL(sum_kernel, dim3((unsigned)bt.count), dim3(256), 0, s, x, count, out,
+                       bt.sW, bt.act);
     return hipGetLastError();
 }
 
@@ -863,6 +897,28 @@ hipError_t launch_fill_i32(int *p, int64_t count, int value, hipStream_t s)
     int grid = (int)((count + 255) / 256);
     grid = grid < 1 ? 1 : (grid > 1024 ? 1024 : grid);
     hipLaunchKernelGGL(fill_i32_kernel, dim3(grid), dim3(256), 0, s, p, count, value);
+    return hipGetLastError();
+}
+
+// the same count_per entries in every matrix's workspace region
+__global__ void fill_batch_i32_kernel(int *p, int64_t count_per, int value, int64_t sW,
+                                      const int *__restrict__ act)
+{
+    const int64_t m = blockIdx.y;
+    if (act && !act[m])
+        return;
+    p = bat(p, m, sW);
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < count_per; i += (int64_t)gridDim.x * 256)
+        p[i] = value;
+}
+
+hipError_t launch_fill_batch_i32(int *p, int64_t count_per, int value, const Batch &bt,
+                                 hipStream_t s)
+{
+    int grid = (int)((count_per + 255) / 256);
+    grid = grid < 1 ? 1 : (grid > 64 ? 64 : grid);
+    hipLaunchKernelGGL(fill_batch_i32_kernel, dim3(grid, (unsigned)bt.count), dim3(256), 0, s, p,
+                       count_per, value, bt.sW, bt.act);
     return hipGetLastError();
 }
 
@@ -1287,20 +1343,21 @@ template hipError_t launch_pair_solve_v<double>(double *, int64_t, int, int, con
                                                double *, int *, int *, double *, int64_t,
                                                int64_t, const int2 *, const double *,
                                                const int *, hipStream_t, int, hipEvent_t,
-                                               hipEvent_t);
+                                               hipEvent_t, const Batch &);
 template hipError_t launch_pair_solve_v<float>(float *, int64_t, int, int, const int2 *,
                                               const int2 *, float *, double, double, int, int, int,
                                               double *, int *, int *, float *, int64_t,
                                               int64_t, const int2 *, const float *, const int *,
-                                              hipStream_t, int, hipEvent_t, hipEvent_t);
+                                              hipStream_t, int, hipEvent_t, hipEvent_t,
+                                              const Batch &);
 template hipError_t launch_pair_solve<double>(double *, int64_t, int, int, const int2 *,
                                               const int2 *, double *, double, double, int, int, int,
                                               double *, int *, int *, hipStream_t, hipEvent_t,
-                                              hipEvent_t);
+                                              hipEvent_t, const Batch &);
 template hipError_t launch_pair_solve<float>(float *, int64_t, int, int, const int2 *,
                                              const int2 *, float *, double, double, int, int, int,
                                              double *, int *, int *, hipStream_t, hipEvent_t,
-                                             hipEvent_t);
+                                             hipEvent_t, const Batch &);
 
 // Thread -> 2x2 block map of the pair solve for M = 2b positions: entry t < M/2
 // is the block hosting pair t of the next round, then the M/2 diagonal blocks

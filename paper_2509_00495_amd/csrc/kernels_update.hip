@@ -19,9 +19,14 @@ template <typename T, int M>
 __global__ __launch_bounds__(256) void update_v_kernel(T *__restrict__ V, int64_t ldv,
                                                        int64_t ntile, const int2 *__restrict__ pairs,
                                                        int npairs, const T *__restrict__ U,
-                                                       const int *__restrict__ prot, int chunks)
+                                                       const int *__restrict__ prot, int chunks,
+                                                       int64_t sW, const int *__restrict__ act)
 {
-    vupd::v_update_wave<T, M>(V, ldv, ntile, pairs, npairs, U, prot, chunks,
+    const int64_t m = blockIdx.y; // matrix of a batch (0 for a single solve)
+    if (act && !act[m])
+        return;
+    vupd::v_update_wave<T, M>(bat(V, m, sW), ldv, ntile, pairs, npairs, bat(U, m, sW),
+                              bat(prot, m, sW), chunks,
                               blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE);
 }
 
@@ -50,15 +55,29 @@ __global__ __launch_bounds__(256) void update_v_kernel(T *__restrict__ V, int64_
 // costs the loop registers).
 // R16: Z rounded to binary16 on its way to B (the binary16 stage), a
 // template argument so that the FP32 stage's kernel carries no trace of it.
-template <typename T, int M, bool R16>
+template <typename T, int M, bool R16, bool BAT>
 __global__ __launch_bounds__(M * 4, sizeof(T) == 4 ? 4 : 2) void update_b_kernel(T *__restrict__ B, int64_t ldb,
                                                          const int2 *__restrict__ pairs_g,
                                                          int npairs, const T *__restrict__ U,
                                                          double *__restrict__ partial,
                                                          int want_off,
                                                          const int *__restrict__ prot,
-                                                         int *skipped)
+                                                         int *skipped, int64_t sW,
+                                                         const int *__restrict__ act)
 {
+    // BAT: a batch of equal-order solves, blockIdx.y is the matrix, whose
+    // buffers lie sW bytes after the previous one's (a template argument: the
+    // offsets cost the single-solve kernel registers)
+    if constexpr (BAT) {
+        const int64_t m = blockIdx.y;
+        if (act && !act[m])
+            return;
+        B = bat(B, m, sW);
+        U = bat(U, m, sW);
+        partial = bat(partial, m, sW);
+        prot = bat(prot, m, sW);
+        skipped = bat(skipped, m, sW);
+    }
     constexpr int r16 = R16 ? 1 : 0;
     constexpr int b = M / 2, NW = M / 16, NT = NW * WAVE;
     constexpr int VK = 16 / (int)sizeof(T);
@@ -349,7 +368,7 @@ int g_update_v_waves = 0; // total resident wavefronts to size the V-update grid
 template <typename T, int M>
 hipError_t launch_update_v_t(T *V, int64_t ldv, int64_t nrows, int npairs, const int2 *pairs,
                              const T *U, const int *prot, hipStream_t s, hipEvent_t e0,
-                             hipEvent_t e1)
+                             hipEvent_t e1, const Batch &bt)
 {
     static int occ_waves = 0;
     if (occ_waves == 0) {
@@ -363,15 +382,15 @@ hipError_t launch_update_v_t(T *V, int64_t ldv, int64_t nrows, int npairs, const
     }
     const int64_t ntile = nrows / 16;
     const int waves_total = g_update_v_waves > 0 ? g_update_v_waves : occ_waves;
-    int64_t chunks = waves_total / npairs;
+    int64_t chunks = waves_total / ((int64_t)npairs * bt.count);
     if (chunks < 1)
         chunks = 1;
     if (chunks > ntile)
         chunks = ntile;
     const int64_t waves = chunks * npairs;
     const unsigned grid = (unsigned)((waves + 3) / 4);
-    launch_timed(update_v_kernel<T, M>, dim3(grid), dim3(256), 0, s, e0, e1, V, ldv, ntile, pairs,
-                 npairs, U, prot, (int)chunks);
+    launch_timed(update_v_kernel<T, M>, dim3(grid, (unsigned)bt.count), dim3(256), 0, s, e0, e1,
+                 V, ldv, ntile, pairs, npairs, U, prot, (int)chunks, bt.sW, bt.act);
     return hipGetLastError();
 }
 
@@ -381,7 +400,7 @@ int update_b_blocks_per_cu_t()
     static int per = -1;
     if (per < 0) {
         int p = 0;
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, update_b_kernel<T, M, false>, M * 4, 0);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&p, update_b_kernel<T, M, false, false>, M * 4, 0);
         per = p > 0 ? p : 1;
     }
     return per;
@@ -400,7 +419,7 @@ void tune_update_v(int total_waves) { g_update_v_waves = total_waves; }
 template <typename T>
 hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pairs, const T *U,
                            double *partial, int want_off, int r16, const int *prot, int *skipped,
-                           hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+                           hipStream_t s, hipEvent_t e0, hipEvent_t e1, const Batch &bt)
 {
     if (prot && !skipped)
         return hipErrorInvalidValue;
@@ -417,17 +436,27 @@ hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pai
         if (cus <= 0)
             cus = 256;
     }
-    const int slots = cus * update_b_blocks_per_cu<T>(b);
-    const unsigned grid = (unsigned)(ntiles < slots ? ntiles : slots);
+    // resident workgroups, shared by the matrices of a batch
+    int64_t slots = (int64_t)cus * update_b_blocks_per_cu<T>(b) / bt.count;
+    if (slots < 1)
+        slots = 1;
+    const dim3 grid((unsigned)(ntiles < slots ? ntiles : slots), (unsigned)bt.count);
     const bool h = sizeof(T) == 4 && r16;
+    const bool batched = bt.count > 1 || bt.sW != 0 || bt.act != nullptr;
+    if (batched && h)
+        return hipErrorInvalidValue; // no batched binary16 stage
     if (b == 32)
-        launch_timed(h ? update_b_kernel<T, 64, sizeof(T) == 4> : update_b_kernel<T, 64, false>,
-                     dim3(grid), dim3(256), 0, s, e0, e1, B, ldb, pairs, npairs, U, partial,
-                     want_off, prot, skipped);
+        launch_timed(batched ? update_b_kernel<T, 64, false, true>
+                             : (h ? update_b_kernel<T, 64, sizeof(T) == 4, false>
+                                  : update_b_kernel<T, 64, false, false>),
+                     grid, dim3(256), 0, s, e0, e1, B, ldb, pairs, npairs, U, partial,
+                     want_off, prot, skipped, bt.sW, bt.act);
     else if (b == 16)
-        launch_timed(h ? update_b_kernel<T, 32, sizeof(T) == 4> : update_b_kernel<T, 32, false>,
-                     dim3(grid), dim3(128), 0, s, e0, e1, B, ldb, pairs, npairs, U, partial,
-                     want_off, prot, skipped);
+        launch_timed(batched ? update_b_kernel<T, 32, false, true>
+                             : (h ? update_b_kernel<T, 32, sizeof(T) == 4, false>
+                                  : update_b_kernel<T, 32, false, false>),
+                     grid, dim3(128), 0, s, e0, e1, B, ldb, pairs, npairs, U, partial,
+                     want_off, prot, skipped, bt.sW, bt.act);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -436,7 +465,7 @@ hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pai
 template <typename T>
 hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
                            const int2 *pairs, const T *U, const int *prot, hipStream_t s,
-                           hipEvent_t e0, hipEvent_t e1)
+                           hipEvent_t e0, hipEvent_t e1, const Batch &bt)
 {
     if (nrows % 16 != 0 || ldv % (16 / (int64_t)sizeof(T)) != 0 ||
         ((uintptr_t)V % 16) != 0)
@@ -444,9 +473,9 @@ hipError_t launch_update_v(T *V, int64_t ldv, int64_t nrows, int b, int npairs,
     if (nrows == 0 || npairs == 0)
         return record_pair(e0, e1, s);
     if (b == 32)
-        return launch_update_v_t<T, 64>(V, ldv, nrows, npairs, pairs, U, prot, s, e0, e1);
+        return launch_update_v_t<T, 64>(V, ldv, nrows, npairs, pairs, U, prot, s, e0, e1, bt);
     if (b == 16)
-        return launch_update_v_t<T, 32>(V, ldv, nrows, npairs, pairs, U, prot, s, e0, e1);
+        return launch_update_v_t<T, 32>(V, ldv, nrows, npairs, pairs, U, prot, s, e0, e1, bt);
     return hipErrorInvalidValue;
 }
 
@@ -454,15 +483,15 @@ template int update_b_blocks_per_cu<double>(int);
 template int update_b_blocks_per_cu<float>(int);
 template hipError_t launch_update_b<double>(double *, int64_t, int, int, const int2 *,
                                             const double *, double *, int, int, const int *, int *,
-                                            hipStream_t, hipEvent_t, hipEvent_t);
+                                            hipStream_t, hipEvent_t, hipEvent_t, const Batch &);
 template hipError_t launch_update_b<float>(float *, int64_t, int, int, const int2 *,
                                            const float *, double *, int, int, const int *, int *,
-                                           hipStream_t, hipEvent_t, hipEvent_t);
+                                           hipStream_t, hipEvent_t, hipEvent_t, const Batch &);
 template hipError_t launch_update_v<double>(double *, int64_t, int64_t, int, int, const int2 *,
                                             const double *, const int *, hipStream_t,
-                                            hipEvent_t, hipEvent_t);
+                                            hipEvent_t, hipEvent_t, const Batch &);
 template hipError_t launch_update_v<float>(float *, int64_t, int64_t, int, int, const int2 *,
                                            const float *, const int *, hipStream_t, hipEvent_t,
-                                           hipEvent_t);
+                                           hipEvent_t, const Batch &);
 
 } // namespace lj

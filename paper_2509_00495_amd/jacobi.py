@@ -355,17 +355,18 @@ def _autograd():
 
     class EighFn(torch.autograd.Function):
         """(W, V) = eigh(A) with the adjoint of jacobi_eigh_backward.  A is a
-        (batch x) n x n float64 GPU tensor; a plain batch of order <= 128 runs
-        in one jacobi_eigh_batched launch, larger orders (and mixed) per
-        matrix."""
+        (batch x) n x n float64 GPU tensor; a plain batch runs in one
+        jacobi_eigh_batched call (one persistent launch for order <= 128, the
+        block path with one launch per step for the whole batch above), a
+        mixed batch per matrix."""
 
         @staticmethod
         def forward(ctx, A, mixed=False, tol=None):
             fn = eigh_mixed if mixed else eigh
             if A.dim() == 2:
                 W, V = fn(A, tol)
-            elif not mixed and 1 <= A.shape[-1] <= 128:
-                # one persistent launch for the whole batch
+            elif not mixed and A.shape[-1] >= 1:
+                # one jacobi_eigh_batched call for the whole batch
                 b, n = A.shape[0], A.shape[-1]
                 Wp, Vp, _ = eigh_batched(A.contiguous().reshape(-1), [n] * b, tol)
                 W = Wp.reshape(b, n)
