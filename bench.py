@@ -12,8 +12,9 @@ same matrix.  The other workloads measure the other configurations:
                    4096-matrix batch of the same order through jacobi_eigh_batched
   clustered10000   10 000 matrices of order 8..128 (clustered spectra) in one
                    persistent jacobi_eigh_batched launch per step
-  gapped256x256    256 matrices of order 256: forward (per matrix) and the
-                   batched adjoint jacobi_eigh_backward per step
+  gapped256x256    256 matrices of order 256: forward (one batched call, and
+                   per matrix for comparison) and the batched adjoint
+                   jacobi_eigh_backward per step
 --orth householder|cholesky replaces Newton-Schulz in the mixed path (the
 comparators of Section 4.4); --compare-orth times all three on the workload.
 One JSON line is printed.
@@ -618,14 +619,24 @@ def bench_gapped(args, torch, pj):
     w = torch.tensor(ws_, device="cuda")
     C = torch.tensor(Cs, device="cuda")
     wsp = pj.Workspace()
-    # forward per matrix (order 256: block path)
+    b = A.shape[0]
+    # forward: the whole batch in one jacobi_eigh_batched call (order 256: the
+    # block path with one launch per step for every matrix still sweeping)
+    Ap = A.reshape(-1)
+    pj.eigh_batched(Ap, [n] * b, ws=wsp)  # warm-up
+    fsteps = max(args.steps, 3)
+    t_fwd, (Wp, Vp, st) = sync_time(torch, lambda: pj.eigh_batched(Ap, [n] * b, ws=wsp), fsteps)
+    t_fwd /= fsteps
+    W = Wp.reshape(b, n)
+    V = Vp.reshape(b, n, n)
+    fwd_err = float((W.cpu() - torch.tensor(lams)).abs().max() / np.abs(lams).max())
+    # the same forward one matrix at a time (16 matrices, scaled to the batch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    outs = [pj.eigh(A[k], ws=wsp) for k in range(A.shape[0])]
+    for k in range(16):
+        pj.eigh(A[k], ws=wsp)
     torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
-    W = torch.stack([o[0] for o in outs]).contiguous()
-    V = torch.stack([o[1] for o in outs]).contiguous()
+    t_single = (time.perf_counter() - t0) / 16 * b
     # loss = sum w lam + <C, V>: dW = w, dV = C
     for _ in range(max(args.warmup, 2)):
         pj.eigh_backward(W, V, w, C, ws=wsp)
@@ -649,7 +660,10 @@ def bench_gapped(args, torch, pj):
                    "path": "jacobi_eigh_backward (batched FP64 GEMMs)", "batch": 256, "n": n},
         "forward": {"ms_per_batch": round(1e3 * t_fwd, 2),
                     "value": round(256 / t_fwd, 2), "unit": "eigendecomps/s",
-                    "path": "jacobi_eigh per matrix (block path)"},
+                    "path": "jacobi_eigh_batched (block path, one launch per step for the batch)",
+                    "max_rel_eig_err_vs_constructed": fwd_err,
+                    "gate_passed": bool(fwd_err <= 1e-13),
+                    "ms_per_batch_one_call_per_matrix": round(1e3 * t_single, 1)},
         "accuracy": {"max_rel_err_vs_oracle_adjoint_sample": err,
                      "gate_passed": bool(err <= 1e-10)},
         "roofline": {"kernel": "jacobi_eigh_backward (three batched 128x128-tile FP64 GEMM "

@@ -1238,6 +1238,59 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
 // are bitwise those of jacobi_eigh on it; a matrix leaves the sweeps when its
 // own tests say so (act = 0 from then on, its pending V update applied by one
 // launch over the matrices leaving together).
+// Streams of a batch's per-matrix ingest and output stages: their kernels
+// are latency-bound (a few workgroups each), so the matrices' chains run on
+// NPOOL streams side by side, forked from and joined back into the caller's
+// stream by events.  Created once per device (non-blocking, default
+// priority) and kept until the process ends.
+constexpr int NPOOL = 8;
+struct StreamPool {
+    hipStream_t st[NPOOL] = {};
+    hipEvent_t fork = nullptr, join[NPOOL] = {};
+};
+
+int stream_pool(StreamPool *&out)
+{
+    static StreamPool pools[64];
+    static bool made[64] = {};
+    static std::mutex mu;
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64)
+        return JACOBI_DEVICE;
+    std::lock_guard<std::mutex> lk(mu);
+    StreamPool &p = pools[dev];
+    if (!made[dev]) {
+        CK(hipEventCreateWithFlags(&p.fork, hipEventDisableTiming));
+        for (int k = 0; k < NPOOL; ++k) {
+            CK(hipStreamCreateWithFlags(&p.st[k], hipStreamNonBlocking));
+            CK(hipEventCreateWithFlags(&p.join[k], hipEventDisableTiming));
+        }
+        made[dev] = true;
+    }
+    out = &p;
+    return 0;
+}
+
+// work on the pool streams after everything issued so far on s
+int pool_fork(StreamPool &p, hipStream_t s)
+{
+    CK(hipEventRecord(p.fork, s));
+    for (int k = 0; k < NPOOL; ++k)
+        CK(hipStreamWaitEvent(p.st[k], p.fork, 0));
+    return 0;
+}
+
+// s waits for everything issued on the pool streams
+int pool_join(StreamPool &p, hipStream_t s)
+{
+    for (int k = 0; k < NPOOL; ++k) {
+        CK(hipEventRecord(p.join[k], p.st[k]));
+        CK(hipStreamWaitEvent(s, p.join[k], 0));
+    }
+    return 0;
+}
+
 size_t block_region_bytes(int64_t n, const Opts &o)
 {
     Bump bp(nullptr);
@@ -1278,30 +1331,65 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
     const Batch all{batch, (int64_t)R, nullptr, nullptr};
     CK(launch_fill_batch_i32(w0.flags, 8, 0, all, s));
     CK(launch_fill_batch_i32(w0.prot, (int64_t)2 * g.npairs * PROT_STRIDE, 0, all, s));
-    // every region's scalars and flags back to the host at once
-    std::vector<double> sc((size_t)batch * 8);
-    std::vector<int> fl((size_t)batch * 8);
+    // Host side of the per-matrix transfers in pinned memory: every region's
+    // scalars and flags come back in two strided copies (one synchronisation
+    // per phase), the activity flags and thresholds go up from it.  (Strided
+    // and upload copies from pageable memory were measured to return stale
+    // data under a profiler that intercepts the runtime; pinned copies are
+    // plain DMA on the stream.)
+    struct Pinned {
+        void *p = nullptr;
+        ~Pinned()
+        {
+            if (p)
+                hipHostFree(p);
+        }
+    } pin;
+    CK(hipHostMalloc(&pin.p, (size_t)batch * (9 * sizeof(double) + 10 * sizeof(int)),
+                     hipHostMallocDefault));
+    double *sc = (double *)pin.p;            // 8 scalars per matrix
+    double *thr = sc + (size_t)batch * 8;    // rotation thresholds
+    int *fl = (int *)(thr + batch);          // 8 flags per matrix
+    int *act = fl + (size_t)batch * 8;       // in the sweeps
+    int *fin = act + batch;                  // leaving the sweeps together
     auto read_all = [&]() -> int {
-        CK(hipMemcpy2DAsync(sc.data(), 8 * sizeof(double), w0.scal, R, 8 * sizeof(double),
+        CK(hipMemcpy2DAsync(sc, 8 * sizeof(double), w0.scal, R, 8 * sizeof(double),
                             (size_t)batch, hipMemcpyDeviceToHost, s));
-        CK(hipMemcpy2DAsync(fl.data(), 8 * sizeof(int), w0.flags, R, 8 * sizeof(int),
-                            (size_t)batch, hipMemcpyDeviceToHost, s));
+        CK(hipMemcpy2DAsync(fl, 8 * sizeof(int), w0.flags, R, 8 * sizeof(int), (size_t)batch,
+                            hipMemcpyDeviceToHost, s));
         CK(hipStreamSynchronize(s));
         return 0;
     };
+    // host flags to the device; the stream is synchronised after the copy, so
+    // the host copy may be rewritten as soon as this returns
+    auto upload = [&](void *dst, const void *src, size_t bytes) -> int {
+        CK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+        CK(hipStreamSynchronize(s));
+        return 0;
+    };
+    StreamPool *pool = nullptr;
+    if (int e = stream_pool(pool))
+        return e;
+    auto ps = [&](int64_t m) { return pool->st[m % NPOOL]; };
     // ingest (ingest_norm per matrix)
+    if (int e = pool_fork(*pool, s))
+        return e;
     for (int64_t m = 0; m < batch; ++m) {
         const BlockWs &w = ws[(size_t)m];
         CK(launch_ingest<double>(A + aoff(m), n, n, w.B64, g.npad, w.partial, w.flags,
-                                 o.check_sym, s));
-        CK(launch_sum(w.partial, INGEST_BLOCKS, w.scal, s));
-        CK(launch_max(w.partial + INGEST_BLOCKS, INGEST_BLOCKS, w.scal + 4, s));
+                                 o.check_sym, ps(m)));
+        CK(launch_sum(w.partial, INGEST_BLOCKS, w.scal, ps(m)));
+        CK(launch_max(w.partial + INGEST_BLOCKS, INGEST_BLOCKS, w.scal + 4, ps(m)));
     }
+    if (int e = pool_join(*pool, s))
+        return e;
     if (int e = read_all())
         return e;
-    std::vector<int> ks((size_t)batch, 0), act((size_t)batch, 0), fin((size_t)batch, 0),
-        sweeps((size_t)batch, 0);
-    std::vector<double> tol((size_t)batch, 0.0), thr((size_t)batch, 0.0);
+    std::vector<int> ks((size_t)batch, 0), sweeps((size_t)batch, 0);
+    std::vector<double> tol((size_t)batch, 0.0);
+    std::fill(act, act + batch, 0);
+    std::fill(fin, fin + batch, 0);
+    std::fill(thr, thr + batch, 0.0);
     bool rescaled = false;
     for (int64_t m = 0; m < batch; ++m) {
         const size_t i = (size_t)m;
@@ -1326,6 +1414,8 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
     if (rescaled)
         if (int e = read_all())
             return e;
+    if (int e = pool_fork(*pool, s))
+        return e;
     for (int64_t m = 0; m < batch; ++m) {
         const size_t i = (size_t)m;
         if (!act[i])
@@ -1333,16 +1423,23 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
         const double normf = std::sqrt(sc[8 * i]);
         tol[i] = tol_in > 0.0 ? std::ldexp(tol_in, ks[i]) : 1e-15 * (double)n * normf;
         thr[i] = tol[i] / (double)n;
-        CK(launch_eye<double>(ws[i].V64, g.npad, s));
-        CK(launch_off2_partial<double>(ws[i].B64, g.npad, ws[i].partial, s));
+        CK(launch_eye<double>(ws[i].V64, g.npad, ps(m)));
+        CK(launch_off2_partial<double>(ws[i].B64, g.npad, ws[i].partial, ps(m)));
     }
-    CK(hipMemcpyAsync(act_d, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    CK(hipMemcpyAsync(thr_d, thr.data(), thr.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    if (int e = pool_join(*pool, s))
+        return e;
+    if (int e = upload(act_d, act, (size_t)batch * sizeof(int)))
+        return e;
+    if (int e = upload(thr_d, thr, (size_t)batch * sizeof(double)))
+        return e;
     const Batch bact{batch, (int64_t)R, act_d, nullptr};
     CK(launch_sum(w0.partial, OFF_BLOCKS, w0.scal + 1, s, bact));
     if (int e = read_all())
         return e;
     std::vector<int> solved((size_t)batch, 0); // outputs to write (OK or NOCONV)
+    if (trace_on())
+        std::fprintf(stderr, "jacobi: batch of %lld, n %lld: matrix 0 normf %.3e tol %.3e off %.3e\n",
+                     (long long)batch, (long long)n, std::sqrt(sc[0]), tol[0], std::sqrt(sc[1]));
     for (int64_t m = 0; m < batch; ++m) {
         const size_t i = (size_t)m;
         if (!act[i])
@@ -1375,15 +1472,17 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
             any_fin = any_fin || fin[i];
         }
         if (any_fin && vpend_pairs) {
-            CK(hipMemcpyAsync(fin_d, fin.data(), fin.size() * sizeof(int),
-                              hipMemcpyHostToDevice, s));
+            if (int e = upload(fin_d, fin, (size_t)batch * sizeof(int)))
+                return e;
             const Batch bf{batch, (int64_t)R, fin_d, nullptr};
             CK(launch_update_v<double>(w0.V64, g.npad, g.npad, g.b, g.npairs, vpend_pairs,
                                        vpend_U, vpend_prot, s, nullptr, nullptr, bf));
         }
-        if (std::find(act.begin(), act.end(), 1) == act.end())
+        std::fill(fin, fin + batch, 0);
+        if (std::find(act, act + batch, 1) == act + batch)
             break;
-        CK(hipMemcpyAsync(act_d, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        if (int e = upload(act_d, act, (size_t)batch * sizeof(int)))
+            return e;
         const Batch bt{batch, (int64_t)R, act_d, thr_d};
         CK(launch_fill_batch_i32(w0.flags + 2, 1, 0, bt, s));
         for (int r = 0; r < g.N - 1; ++r, ++round) {
@@ -1418,9 +1517,9 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
                       w0.scal + 1, s, bt));
         if (int e = read_all())
             return e;
-        // the host copies of act and fin are rewritten only after a stream
-        // synchronisation (their asynchronous uploads have then been made)
-        std::fill(fin.begin(), fin.end(), 0);
+        if (trace_on())
+            std::fprintf(stderr, "jacobi: batch sweep, %lld matrices active, matrix 0 off %.3e\n",
+                         (long long)std::count(act, act + batch, 1), std::sqrt(sc[1]));
         for (int64_t m = 0; m < batch; ++m) {
             const size_t i = (size_t)m;
             if (!act[i])
@@ -1438,11 +1537,18 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
         }
     }
     // the output stage
+    if (int e = pool_fork(*pool, s))
+        return e;
     for (int64_t m = 0; m < batch; ++m)
         if (solved[(size_t)m])
-            if (int e = finalize_probe(g, n, ws[(size_t)m], ws[(size_t)m].B64, ws[(size_t)m].V64, s))
+            if (int e = finalize_probe(g, n, ws[(size_t)m], ws[(size_t)m].B64,
+                                       ws[(size_t)m].V64, ps(m)))
                 return e;
+    if (int e = pool_join(*pool, s))
+        return e;
     if (int e = read_all())
+        return e;
+    if (int e = pool_fork(*pool, s))
         return e;
     for (int64_t m = 0; m < batch; ++m) {
         const size_t i = (size_t)m;
@@ -1452,12 +1558,14 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
         double est = 0.0;
         int pol = 0;
         if (int e = finalize_finish(g, n, w, sc[8 * i + 3], w.V64, w.B64, w.Vt, W + woff(m),
-                                    V + aoff(m), n, s, &est, &pol, ks[i] ? w.A0 : A + aoff(m),
-                                    ks[i] ? g.npad : n))
+                                    V + aoff(m), n, ps(m), &est, &pol,
+                                    ks[i] ? w.A0 : A + aoff(m), ks[i] ? g.npad : n))
             return e;
         if (ks[i])
-            CK(launch_scale_pow2(W + woff(m), n, -ks[i], nullptr, s));
+            CK(launch_scale_pow2(W + woff(m), n, -ks[i], nullptr, ps(m)));
     }
+    if (int e = pool_join(*pool, s))
+        return e;
     CK(hipStreamSynchronize(s));
     return 0;
 }

@@ -602,7 +602,6 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
         ranges = 1;
     if (ranges > ntile)
         ranges = ntile;
-    const unsigned grid = (unsigned)(npairs + ranges * npairs);
     // working wavefronts per V workgroup: one per SIMD in FP32, two in FP64
     // (long runs of tiles per wavefront; measured at n = 4096)
     const int vdef = (sizeof(T) == 4 ? 4 : 8) < NT / WAVE ? (sizeof(T) == 4 ? 4 : 8) : NT / WAVE;
@@ -630,6 +629,14 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
         if (x > 0.0)
             vx = (int)std::min<double>(x + 0.5, (double)ntile / (double)(ranges + 1));
     }
+    // a batch whose pair solves alone fill the compute units: no V
+    // workgroups, every pair-solve workgroup updates its pair's V columns
+    // after its solve (the same per-tile arithmetic as a V workgroup's)
+    if (bt.count > 1 && spairs >= cus && g_pair_v_wgs == 0 && vsplit == 0) {
+        ranges = 0;
+        vx = (int)ntile;
+    }
+    const unsigned grid_x = (unsigned)(npairs + ranges * npairs);
     const size_t lds = smem > g_pair_v_lds ? smem : g_pair_v_lds;
     if (lds != smem_set) {
         hipError_t e = hipFuncSetAttribute((const void *)k,
@@ -638,7 +645,7 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
             return e;
         smem_set = lds;
     }
-    launch_timed(k, dim3(grid, (unsigned)bt.count), dim3(NT), (uint32_t)lds, s, e0, e1, B, ldb,
+    launch_timed(k, dim3(grid_x, (unsigned)bt.count), dim3(NT), (uint32_t)lds, s, e0, e1, B, ldb,
                  pairs, psmap, U, eps, thr, inner, partial, rot_flag, prot, npairs, V, ldv, ntile,
                  vpairs, vU, vprot, (int)ranges, vwaves, vx, bt.sW, bt.act, bt.thr);
     return hipGetLastError();
