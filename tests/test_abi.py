@@ -96,6 +96,22 @@ def test_batched_argument_validation(lib):
     assert f(None, n, None, 0, None, None, None, 0.0, 0, None, None, 0, None, None) == 0
 
 
+def test_batched_block_path_validation(lib):
+    """Orders above 128 only as a batch of one order (the block path), at most
+    65535 matrices; the no-allocation variant keeps the limit of 128."""
+    f = lib.jacobi_eigh_batched
+    n = (ctypes.c_int64 * 2)(200, 201)
+    assert f(FAKE, n, None, 2, FAKE, None, FAKE, 0.0, 0, None, None, 0, None, None) == -2
+    n = (ctypes.c_int64 * 2)(200, 200)
+    assert f(None, n, None, 2, FAKE, None, FAKE, 0.0, 0, None, None, 0, None, None) == -1
+    assert f(FAKE, n, None, 2, FAKE, None, FAKE, 0.0, 1, None, None, 0, None, None) == -9
+    many = (ctypes.c_int64 * 65536)(*([200] * 65536))
+    assert f(FAKE, many, None, 65536, FAKE, None, FAKE, 0.0, 0, None, None, 0, None,
+             None) == -4
+    g = lib.jacobi_eigh_batched_noalloc
+    assert g(FAKE, n, None, 2, FAKE, None, FAKE, 0.0, 0, None, None, None) == -2
+
+
 def test_backward_argument_validation(lib):
     f = lib.jacobi_eigh_backward
     assert f(FAKE, FAKE, None, None, -1, 1, 1, FAKE, 0.0, None, 0, None) == -5
@@ -116,6 +132,8 @@ def test_workspace_query(pj):
     assert mixed >= 4 * 4096 * 4096 * 8 + 2 * 4096 * 4096 * 4
     assert pj.workspace_bytes(3, 256, 256) >= 2 * 256 * 256 * 256 * 8
     assert pj.workspace_bytes(9, 10) == 0
+    # a batch of one order above 128: one single-solve workspace per matrix
+    assert pj.workspace_bytes(2, 256, 10) >= 10 * (pj.workspace_bytes(0, 256) - 512)
     assert pj.workspace_bytes(0, 64, 1, pj.make_opts(block=48)) == 0
 
 
