@@ -218,6 +218,8 @@ int jacobi_eigh_mixed(const double *A, int64_t n, int64_t lda, double *W,
  * matrix, and each matrix's W, V and status are bitwise those of jacobi_eigh
  * on it with the same opts (opts.timing, serial_v, graph, tune and threads do
  * not apply there; the workspace holds one single-solve workspace per matrix).
+ * That path synchronises with the host between sweeps: on a stream being
+ * captured into a HIP graph it returns JACOBI_DEVICE before launching.
  *   A      [in]  matrix i is n_i x n_i row-major (ld = n_i) at offset a_off[i]
  *                doubles
  *   n      [in, HOST] batch orders, 1 <= n_i <= 128, or all equal (any order

@@ -1724,6 +1724,14 @@ int jacobi_eigh_batched(const double *A, const int64_t *n, const int64_t *a_off,
     hipStream_t s = (hipStream_t)stream;
     const size_t need = jacobi_workspace_bytes(2, n_max, batch, opts);
     if (block) {
+        // the block path synchronises with the host between sweeps, which a
+        // stream being captured into a graph does not allow
+        hipStreamCaptureStatus bcap = hipStreamCaptureStatusNone;
+        CK(hipStreamIsCapturing(s, &bcap));
+        if (bcap != hipStreamCaptureStatusNone) {
+            g_last_error = hipErrorStreamCaptureUnsupported;
+            return JACOBI_DEVICE;
+        }
         WsGuard bguard;
         if (!work) {
             CK(hipMalloc(&bguard.p, need));
