@@ -366,7 +366,7 @@ def bench_mixed(args, torch, pj):
     kern_ms["pair_solve_alone_f64"] = round(inf2["t_pair_ms"][0], 2)
     kern_ms["orthogonaliser"] = round(inf1["t_orth_ms"], 2)
     names = {"PV": "pair_solve_v_kernel<{t}, 64, 1024, true, false> (pair solves + previous V update)",
-             "B": "update_b_kernel<{t}, 64, false> (off-diagonal B tiles)",
+             "B": "update_b_kernel<{t}, 64, false, false> (off-diagonal B tiles)",
              "V": "update_v_kernel<{t}, 64> (V row tiles)"}
     dom = max(cands, key=lambda k: cands[k][0])
     t_ms, cnt, part, dtype = cands[dom]
