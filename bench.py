@@ -365,9 +365,9 @@ def bench_mixed(args, torch, pj):
     kern_ms["pair_solve_alone_f32"] = round(inf2["t_pair_ms"][1], 2)
     kern_ms["pair_solve_alone_f64"] = round(inf2["t_pair_ms"][0], 2)
     kern_ms["orthogonaliser"] = round(inf1["t_orth_ms"], 2)
-    names = {"PV": "pair_solve_v_kernel<{t}, 64, 1024, true, false> (pair solves + previous V update)",
+    names = {"PV": "pair_solve_v_kernel<{t}, 64, 1024, true, false, false> (pair solves + previous V update)",
              "B": "update_b_kernel<{t}, 64, false, false> (off-diagonal B tiles)",
-             "V": "update_v_kernel<{t}, 64> (V row tiles)"}
+             "V": "update_v_kernel<{t}, 64, false> (V row tiles)"}
     dom = max(cands, key=lambda k: cands[k][0])
     t_ms, cnt, part, dtype = cands[dom]
     elem = 4 if dtype == "f32" else 8
@@ -412,7 +412,7 @@ def bench_mixed(args, torch, pj):
             ps[dt_] = {"avg_launch_us": round(a_s * 1e6, 2), "flops_per_launch": fl,
                        "achieved": round(fl / a_s / 1e12, 3), "peak": PEAK[dt_],
                        "frac": round(fl / a_s / 1e12 / PEAK[dt_], 4)}
-    roofline_pair = {"kernel": "lj::pair_solve_kernel<T, 64, 1024, true, false> (alone)",
+    roofline_pair = {"kernel": "lj::pair_solve_kernel<T, 64, 1024, true, false, false> (alone)",
                      "bound": "alu", "unit": "TFLOP/s", "per_precision": ps}
 
     cpu = None

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -75,10 +76,17 @@ struct Batch {
     const int *act = nullptr;
     const double *thr = nullptr;
 };
+// (byte arithmetic on the pointer itself: an integer round trip would lose
+// its global address space and turn every access into a flat one)
 template <typename P>
 __device__ __forceinline__ P *bat(P *p, int64_t m, int64_t sW)
 {
-    return p ? reinterpret_cast<P *>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)(m * sW)) : p;
+    typedef typename std::conditional<std::is_const<P>::value, const char, char>::type C;
+    return p ? reinterpret_cast<P *>(reinterpret_cast<C *>(p) + m * sW) : p;
+}
+inline bool batched(const Batch &bt)
+{
+    return bt.count > 1 || bt.sW != 0 || bt.act != nullptr || bt.thr != nullptr;
 }
 
 template <typename T>

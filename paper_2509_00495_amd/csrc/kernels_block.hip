@@ -414,7 +414,11 @@ __device__ __forceinline__ void pair_solve_body(T *__restrict__ B, int64_t ldb,
 
 // R16 (template argument, so that the FP32 stage's kernels carry no trace of
 // it): every stored entry of the tile rounded to binary16 (the binary16 stage)
-template <typename T, int M, int NT, bool CROSS, bool R16>
+// BAT (template argument, so that a single solve's kernel carries none of
+// it): a batch of equal-order solves, blockIdx.y = matrix, whose workspace
+// buffers lie sW bytes after the previous matrix's; act (or null): matrices
+// whose entry is 0 are skipped; thrb (or null): per-matrix thresholds
+template <typename T, int M, int NT, bool CROSS, bool R16, bool BAT>
 __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64_t ldb,
                                                         const int2 *__restrict__ pairs,
                                                         const int2 *__restrict__ psmap,
@@ -425,13 +429,18 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
                                                         int64_t sW, const int *__restrict__ act,
                                                         const double *__restrict__ thrb)
 {
-    const int64_t m = blockIdx.y; // matrix of a batch (0 for a single solve)
-    if (act && !act[m])
-        return;
-    pair_solve_body<T, M, NT, CROSS>(bat(B, m, sW), ldb, pairs, psmap, bat(U, m, sW), eps,
-                                     thrb ? thrb[m] : thr, inner, R16 ? 1 : 0,
-                                     bat(partial, m, sW), bat(rot_flag, m, sW), bat(prot, m, sW),
-                                     blockIdx.x);
+    if constexpr (BAT) {
+        const int64_t m = blockIdx.y;
+        if (act && !act[m])
+            return;
+        pair_solve_body<T, M, NT, CROSS>(bat(B, m, sW), ldb, pairs, psmap, bat(U, m, sW), eps,
+                                         thrb ? thrb[m] : thr, inner, R16 ? 1 : 0,
+                                         bat(partial, m, sW), bat(rot_flag, m, sW),
+                                         bat(prot, m, sW), blockIdx.x);
+    } else {
+        pair_solve_body<T, M, NT, CROSS>(B, ldb, pairs, psmap, U, eps, thr, inner, R16 ? 1 : 0,
+                                         partial, rot_flag, prot, blockIdx.x);
+    }
 }
 
 // The pair solves of a round on workgroups 0 .. npairs-1 and, on the
@@ -441,7 +450,7 @@ __global__ __launch_bounds__(NT) void pair_solve_kernel(T *__restrict__ B, int64
 // split at ntile - vx: V workgroup (l, part) takes part `part` of vranges
 // equal ranges of [0, ntile - vx), and pair-solve workgroup l, once its solve
 // is done, takes [ntile - vx, ntile).
-template <typename T, int M, int NT, bool CROSS, bool R16>
+template <typename T, int M, int NT, bool CROSS, bool R16, bool BAT>
 __global__ __launch_bounds__(NT) void pair_solve_v_kernel(
     T *__restrict__ B, int64_t ldb, const int2 *__restrict__ pairs,
     const int2 *__restrict__ psmap, T *__restrict__ U, double eps, double thr, int inner,
@@ -452,19 +461,21 @@ __global__ __launch_bounds__(NT) void pair_solve_v_kernel(
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *ufl = reinterpret_cast<T *>(smem_raw);
-    const int64_t m = blockIdx.y; // matrix of a batch (0 for a single solve)
-    if (act && !act[m])
-        return;
-    B = bat(B, m, sW);
-    U = bat(U, m, sW);
-    partial = bat(partial, m, sW);
-    rot_flag = bat(rot_flag, m, sW);
-    prot = bat(prot, m, sW);
-    V = bat(V, m, sW);
-    vU = bat(vU, m, sW);
-    vprot = bat(vprot, m, sW);
-    if (thrb)
-        thr = thrb[m];
+    if constexpr (BAT) {
+        const int64_t m = blockIdx.y;
+        if (act && !act[m])
+            return;
+        B = bat(B, m, sW);
+        U = bat(U, m, sW);
+        partial = bat(partial, m, sW);
+        rot_flag = bat(rot_flag, m, sW);
+        prot = bat(prot, m, sW);
+        V = bat(V, m, sW);
+        vU = bat(vU, m, sW);
+        vprot = bat(vprot, m, sW);
+        if (thrb)
+            thr = thrb[m];
+    }
     const int64_t split = ntile - vx;
     if ((int)blockIdx.x < npairs) {
         pair_solve_body<T, M, NT, CROSS>(B, ldb, pairs, psmap, U, eps, thr, inner, R16 ? 1 : 0,
@@ -488,14 +499,20 @@ static hipError_t launch_pair_solve_t(T *B, int64_t ldb, int npairs, const int2 
                                       int *prot, size_t smem, hipStream_t s, hipEvent_t e0,
                                       hipEvent_t e1, const Batch &bt)
 {
-    auto k = pair_solve_kernel<T, M, NT, CROSS, R16>;
-    static size_t smem_set = 0; // the attribute is set once per size (host-side cost)
-    if (smem_set != smem) {
+    // the batched kernel exists for the FP64 sweeps only
+    constexpr bool CAN_BAT = sizeof(T) == 8 && !R16;
+    const bool bt_on = batched(bt);
+    if (bt_on && !CAN_BAT)
+        return hipErrorInvalidValue;
+    auto k = bt_on ? pair_solve_kernel<T, M, NT, CROSS, R16, CAN_BAT>
+                   : pair_solve_kernel<T, M, NT, CROSS, R16, false>;
+    static size_t smem_set[2] = {0, 0}; // the attribute is set once per size (host-side cost)
+    if (smem_set[bt_on] != smem) {
         hipError_t e = hipFuncSetAttribute((const void *)k,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess)
             return e;
-        smem_set = smem;
+        smem_set[bt_on] = smem;
     }
     launch_timed(k, dim3(npairs, (unsigned)bt.count), dim3(NT), (uint32_t)smem, s, e0, e1, B, ldb,
                  pairs, psmap, U, eps, thr, inner, partial, rot_flag, prot, bt.sW, bt.act, bt.thr);
@@ -580,8 +597,13 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
                                         hipStream_t s, int vsplit, hipEvent_t e0, hipEvent_t e1,
                                         const Batch &bt)
 {
-    auto k = pair_solve_v_kernel<T, M, NT, CROSS, R16>;
-    static size_t smem_set = 0;
+    constexpr bool CAN_BAT = sizeof(T) == 8 && !R16;
+    const bool bt_on = batched(bt);
+    if (bt_on && !CAN_BAT)
+        return hipErrorInvalidValue;
+    auto k = bt_on ? pair_solve_v_kernel<T, M, NT, CROSS, R16, CAN_BAT>
+                   : pair_solve_v_kernel<T, M, NT, CROSS, R16, false>;
+    static size_t smem_set[2] = {0, 0};
     static int cus = 0;
     if (cus == 0) {
         int dev = 0;
@@ -638,12 +660,12 @@ static hipError_t launch_pair_solve_v_t(T *B, int64_t ldb, int npairs, const int
     }
     const unsigned grid_x = (unsigned)(npairs + ranges * npairs);
     const size_t lds = smem > g_pair_v_lds ? smem : g_pair_v_lds;
-    if (lds != smem_set) {
+    if (lds != smem_set[bt_on]) {
         hipError_t e = hipFuncSetAttribute((const void *)k,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
             return e;
-        smem_set = lds;
+        smem_set[bt_on] = lds;
     }
     launch_timed(k, dim3(grid_x, (unsigned)bt.count), dim3(NT), (uint32_t)lds, s, e0, e1, B, ldb,
                  pairs, psmap, U, eps, thr, inner, partial, rot_flag, prot, npairs, V, ldv, ntile,

@@ -15,19 +15,27 @@ namespace {
 
 using namespace vupd;
 
-template <typename T, int M>
+template <typename T, int M, bool BAT>
 __global__ __launch_bounds__(256) void update_v_kernel(T *__restrict__ V, int64_t ldv,
                                                        int64_t ntile, const int2 *__restrict__ pairs,
                                                        int npairs, const T *__restrict__ U,
                                                        const int *__restrict__ prot, int chunks,
                                                        int64_t sW, const int *__restrict__ act)
 {
-    const int64_t m = blockIdx.y; // matrix of a batch (0 for a single solve)
-    if (act && !act[m])
-        return;
-    vupd::v_update_wave<T, M>(bat(V, m, sW), ldv, ntile, pairs, npairs, bat(U, m, sW),
-                              bat(prot, m, sW), chunks,
-                              blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE);
+    // BAT: a batch of equal-order solves (blockIdx.y = matrix, buffers sW
+    // bytes apart); a template argument so that a single solve's kernel
+    // carries none of it
+    if constexpr (BAT) {
+        const int64_t m = blockIdx.y;
+        if (act && !act[m])
+            return;
+        vupd::v_update_wave<T, M>(bat(V, m, sW), ldv, ntile, pairs, npairs, bat(U, m, sW),
+                                  bat(prot, m, sW), chunks,
+                                  blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE);
+    } else {
+        vupd::v_update_wave<T, M>(V, ldv, ntile, pairs, npairs, U, prot, chunks,
+                                  blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE);
+    }
 }
 
 // B update.  The kernel takes a list of T tiles (k, l), k < l (all of them,
@@ -389,8 +397,13 @@ hipError_t launch_update_v_t(T *V, int64_t ldv, int64_t nrows, int npairs, const
         chunks = ntile;
     const int64_t waves = chunks * npairs;
     const unsigned grid = (unsigned)((waves + 3) / 4);
-    launch_timed(update_v_kernel<T, M>, dim3(grid, (unsigned)bt.count), dim3(256), 0, s, e0, e1,
-                 V, ldv, ntile, pairs, npairs, U, prot, (int)chunks, bt.sW, bt.act);
+    constexpr bool CAN_BAT = sizeof(T) == 8; // the batched kernel: FP64 sweeps only
+    const bool bt_on = batched(bt);
+    if (bt_on && !CAN_BAT)
+        return hipErrorInvalidValue;
+    launch_timed(bt_on ? update_v_kernel<T, M, CAN_BAT> : update_v_kernel<T, M, false>,
+                 dim3(grid, (unsigned)bt.count), dim3(256), 0, s, e0, e1, V, ldv, ntile, pairs,
+                 npairs, U, prot, (int)chunks, bt.sW, bt.act);
     return hipGetLastError();
 }
 
@@ -442,17 +455,18 @@ hipError_t launch_update_b(T *B, int64_t ldb, int b, int npairs, const int2 *pai
         slots = 1;
     const dim3 grid((unsigned)(ntiles < slots ? ntiles : slots), (unsigned)bt.count);
     const bool h = sizeof(T) == 4 && r16;
-    const bool batched = bt.count > 1 || bt.sW != 0 || bt.act != nullptr;
-    if (batched && h)
-        return hipErrorInvalidValue; // no batched binary16 stage
+    const bool bt_on = batched(bt);
+    if (bt_on && sizeof(T) != 8)
+        return hipErrorInvalidValue; // the batched kernel: FP64 sweeps only
+    constexpr bool CAN_BAT = sizeof(T) == 8;
     if (b == 32)
-        launch_timed(batched ? update_b_kernel<T, 64, false, true>
+        launch_timed(bt_on ? update_b_kernel<T, 64, false, CAN_BAT>
                              : (h ? update_b_kernel<T, 64, sizeof(T) == 4, false>
                                   : update_b_kernel<T, 64, false, false>),
                      grid, dim3(256), 0, s, e0, e1, B, ldb, pairs, npairs, U, partial,
                      want_off, prot, skipped, bt.sW, bt.act);
     else if (b == 16)
-        launch_timed(batched ? update_b_kernel<T, 32, false, true>
+        launch_timed(bt_on ? update_b_kernel<T, 32, false, CAN_BAT>
                              : (h ? update_b_kernel<T, 32, sizeof(T) == 4, false>
                                   : update_b_kernel<T, 32, false, false>),
                      grid, dim3(128), 0, s, e0, e1, B, ldb, pairs, npairs, U, partial,
