@@ -1241,17 +1241,14 @@ int eigh_mixed_block(const double *A, int64_t n, int64_t lda, double *W, double 
 // Streams of a batch's per-matrix ingest and output stages: their kernels
 // are latency-bound (a few workgroups each), so the matrices' chains run on
 // NPOOL streams side by side, forked from and joined back into the caller's
-// stream by events.  Created once per device (non-blocking, default
-// priority) and kept until the process ends.
+// stream by events.  The streams are created once per device (non-blocking,
+// default priority) and kept until the process ends; the events belong to
+// one call, so calls from several host threads can share the streams (a
+// stream then also carries another call's work, which only adds waiting).
 constexpr int NPOOL = 8;
-struct StreamPool {
-    hipStream_t st[NPOOL] = {};
-    hipEvent_t fork = nullptr, join[NPOOL] = {};
-};
-
-int stream_pool(StreamPool *&out)
+int pool_streams(hipStream_t *&out)
 {
-    static StreamPool pools[64];
+    static hipStream_t pools[64][NPOOL] = {};
     static bool made[64] = {};
     static std::mutex mu;
     int dev = 0;
@@ -1259,18 +1256,36 @@ int stream_pool(StreamPool *&out)
     if (dev < 0 || dev >= 64)
         return JACOBI_DEVICE;
     std::lock_guard<std::mutex> lk(mu);
-    StreamPool &p = pools[dev];
     if (!made[dev]) {
-        CK(hipEventCreateWithFlags(&p.fork, hipEventDisableTiming));
-        for (int k = 0; k < NPOOL; ++k) {
-            CK(hipStreamCreateWithFlags(&p.st[k], hipStreamNonBlocking));
-            CK(hipEventCreateWithFlags(&p.join[k], hipEventDisableTiming));
-        }
+        for (int k = 0; k < NPOOL; ++k)
+            CK(hipStreamCreateWithFlags(&pools[dev][k], hipStreamNonBlocking));
         made[dev] = true;
     }
-    out = &p;
+    out = pools[dev];
     return 0;
 }
+
+struct StreamPool {
+    hipStream_t *st = nullptr;
+    hipEvent_t fork = nullptr, join[NPOOL] = {};
+    int init()
+    {
+        if (int e = pool_streams(st))
+            return e;
+        CK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        for (int k = 0; k < NPOOL; ++k)
+            CK(hipEventCreateWithFlags(&join[k], hipEventDisableTiming));
+        return 0;
+    }
+    ~StreamPool()
+    {
+        if (fork)
+            hipEventDestroy(fork);
+        for (int k = 0; k < NPOOL; ++k)
+            if (join[k])
+                hipEventDestroy(join[k]);
+    }
+};
 
 // work on the pool streams after everything issued so far on s
 int pool_fork(StreamPool &p, hipStream_t s)
@@ -1367,9 +1382,10 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
         CK(hipStreamSynchronize(s));
         return 0;
     };
-    StreamPool *pool = nullptr;
-    if (int e = stream_pool(pool))
+    StreamPool pool_obj;
+    if (int e = pool_obj.init())
         return e;
+    StreamPool *pool = &pool_obj;
     auto ps = [&](int64_t m) { return pool->st[m % NPOOL]; };
     // ingest (ingest_norm per matrix)
     if (int e = pool_fork(*pool, s))

@@ -135,3 +135,44 @@ def test_block_batch_full_differentiation_workload(pj):
         assert np.abs(Wk - lams[k]).max() <= 1e-13 * np.abs(lams[k]).max(), k
         assert np.linalg.norm(Ak @ Vk - Vk * Wk) / np.linalg.norm(Ak) <= 1e-13 * n, k
         assert np.linalg.norm(Vk.T @ Vk - np.eye(n)) <= 1e-14 * n, k
+
+
+def test_block_batch_two_host_threads(pj):
+    """Two host threads, each on its own stream and workspace, run block-path
+    batches at the same time (they share the library's pool streams): every
+    result is bitwise that of the same call made alone."""
+    import threading
+    n = 200
+    sets = [[wl.goe(n, 51 + k) for k in range(4)], [wl.goe(n, 61 + k) for k in range(4)]]
+    alone = []
+    for mats in sets:
+        W, V, st = pj.eigh_batched(_pack(mats), [n] * len(mats), ws=pj.Workspace())
+        torch.cuda.synchronize()
+        alone.append((W.cpu().numpy(), V.cpu().numpy(), st.cpu().numpy()))
+    out = [None, None]
+    errs = []
+
+    def work(i):
+        try:
+            stream = torch.cuda.Stream()
+            ws = pj.Workspace()
+            A = _pack(sets[i])
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                for _ in range(3):
+                    W, V, st = pj.eigh_batched(A, [n] * len(sets[i]), ws=ws)
+                stream.synchronize()
+            out[i] = (W.cpu().numpy(), V.cpu().numpy(), st.cpu().numpy())
+        except Exception as e:  # reported below
+            errs.append(e)
+
+    print("  -> two threads, block-path batches of 4 at n=200", flush=True)
+    th = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errs, errs
+    for i in range(2):
+        for a, b in zip(out[i], alone[i]):
+            assert np.array_equal(a, b), i
