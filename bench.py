@@ -260,6 +260,27 @@ def cpu_baseline_rows(name, A, budget_s=12.0):
     return out
 
 
+# The paper's own timing comparison (Section 5.2.3): the fraction of the
+# plain cyclic-by-row Jacobi time saved by the mixed method, MATLAB on the
+# paper's test machine, n = 100 .. 500.  Context only: its low-precision stage
+# is LAPACK's single-precision eig rather than Jacobi sweeps, and its plain
+# runs are interpreted cyclic-by-row Jacobi capped at 10 sweeps.
+_PAPER_N = [100, 200, 300, 400, 500]
+_PAPER_GEO = [0.7150, 0.7574, 0.7739, 0.7747, 0.7789]
+_PAPER_ARI = [0.7294, 0.7513, 0.7543, 0.7619, 0.7663]
+PAPER_CONTEXT = {
+    "source": "Section 5.2.3 (time with and without preconditioning)",
+    "hardware": "MATLAB R2022a, Intel Core i5-9600KF (the paper's test machine)",
+    "n": _PAPER_N,
+    "time_saved_geometric": _PAPER_GEO,
+    "time_saved_arithmetic": _PAPER_ARI,
+    "speedup_geometric": [round(1.0 / (1.0 - r), 2) for r in _PAPER_GEO],
+    "speedup_arithmetic": [round(1.0 / (1.0 - r), 2) for r in _PAPER_ARI],
+    "note": "context, not the target: the paper's first stage is LAPACK eig in single "
+            "precision, not Jacobi sweeps, and its plain runs stop at 10 sweeps",
+}
+
+
 def sync_time(torch, fn, steps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -454,6 +475,7 @@ def bench_mixed(args, torch, pj):
         "roofline": roofline,
         "roofline_pair_solve": roofline_pair,
         "cpu_baseline": cpu,
+        "paper_context": PAPER_CONTEXT,
     }
     if args.compare_orth:
         comp = {}
