@@ -3,6 +3,7 @@
 // kernels_*.hip; the host only launches, reads back one convergence scalar
 // per sweep and decides when to stop.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -1382,6 +1383,11 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
         CK(hipStreamSynchronize(s));
         return 0;
     };
+    const auto t_start = std::chrono::steady_clock::now();
+    auto ms_since = [](std::chrono::steady_clock::time_point t) {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t)
+            .count();
+    };
     StreamPool pool_obj;
     if (int e = pool_obj.init())
         return e;
@@ -1471,6 +1477,9 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
         }
     }
     // the sweeps (run_sweeps with the shared launch, per matrix)
+    const double t_ingest = ms_since(t_start);
+    const auto t_sweeps0 = std::chrono::steady_clock::now();
+    int nsweeps = 0;
     const size_t ustride = (size_t)g.npairs * g.M * g.M;
     const int2 *vpend_pairs = nullptr;
     const double *vpend_U = nullptr;
@@ -1533,6 +1542,7 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
                       w0.scal + 1, s, bt));
         if (int e = read_all())
             return e;
+        ++nsweeps;
         if (trace_on())
             std::fprintf(stderr, "jacobi: batch sweep, %lld matrices active, matrix 0 off %.3e\n",
                          (long long)std::count(act, act + batch, 1), std::sqrt(sc[1]));
@@ -1553,6 +1563,8 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
         }
     }
     // the output stage
+    const double t_sweeps = ms_since(t_sweeps0);
+    const auto t_out0 = std::chrono::steady_clock::now();
     if (int e = pool_fork(*pool, s))
         return e;
     for (int64_t m = 0; m < batch; ++m)
@@ -1583,6 +1595,11 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
     if (int e = pool_join(*pool, s))
         return e;
     CK(hipStreamSynchronize(s));
+    if (trace_on())
+        std::fprintf(stderr,
+                     "jacobi: batch of %lld, n %lld: ingest %.2f ms, %d sweeps %.2f ms, output "
+                     "%.2f ms\n",
+                     (long long)batch, (long long)n, t_ingest, nsweeps, t_sweeps, ms_since(t_out0));
     return 0;
 }
 
