@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -1307,6 +1308,46 @@ int pool_join(StreamPool &p, hipStream_t s)
     return 0;
 }
 
+// fn(m, stream) for every matrix m of a batch: matrix m's launches go to pool
+// stream m mod NPOOL and are issued by host thread m mod NPOOL, so the
+// per-matrix stages (many launches of a few microseconds of host time each)
+// are issued side by side instead of one after another.  Returns the first
+// failing matrix's code (its HIP error becomes this thread's last error).
+template <typename F>
+int pool_each(StreamPool &p, int64_t batch, F fn)
+{
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    const int nt = (int)std::min<int64_t>(NPOOL, batch);
+    std::vector<int> err((size_t)nt, 0);
+    std::vector<hipError_t> herr((size_t)nt, hipSuccess);
+    auto body = [&](int k) {
+        if (hipSetDevice(dev) != hipSuccess) {
+            err[(size_t)k] = JACOBI_DEVICE;
+            herr[(size_t)k] = hipErrorInvalidDevice;
+            return;
+        }
+        for (int64_t m = k; m < batch; m += NPOOL)
+            if (int e = fn(m, p.st[k])) {
+                err[(size_t)k] = e;
+                herr[(size_t)k] = g_last_error;
+                return;
+            }
+    };
+    std::vector<std::thread> th;
+    for (int k = 1; k < nt; ++k)
+        th.emplace_back(body, k);
+    body(0);
+    for (std::thread &t : th)
+        t.join();
+    for (int k = 0; k < nt; ++k)
+        if (err[(size_t)k]) {
+            g_last_error = herr[(size_t)k];
+            return err[(size_t)k];
+        }
+    return 0;
+}
+
 size_t block_region_bytes(int64_t n, const Opts &o)
 {
     Bump bp(nullptr);
@@ -1392,17 +1433,18 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
     if (int e = pool_obj.init())
         return e;
     StreamPool *pool = &pool_obj;
-    auto ps = [&](int64_t m) { return pool->st[m % NPOOL]; };
     // ingest (ingest_norm per matrix)
     if (int e = pool_fork(*pool, s))
         return e;
-    for (int64_t m = 0; m < batch; ++m) {
-        const BlockWs &w = ws[(size_t)m];
-        CK(launch_ingest<double>(A + aoff(m), n, n, w.B64, g.npad, w.partial, w.flags,
-                                 o.check_sym, ps(m)));
-        CK(launch_sum(w.partial, INGEST_BLOCKS, w.scal, ps(m)));
-        CK(launch_max(w.partial + INGEST_BLOCKS, INGEST_BLOCKS, w.scal + 4, ps(m)));
-    }
+    if (int e = pool_each(*pool, batch, [&](int64_t m, hipStream_t st) -> int {
+            const BlockWs &w = ws[(size_t)m];
+            CK(launch_ingest<double>(A + aoff(m), n, n, w.B64, g.npad, w.partial, w.flags,
+                                     o.check_sym, st));
+            CK(launch_sum(w.partial, INGEST_BLOCKS, w.scal, st));
+            CK(launch_max(w.partial + INGEST_BLOCKS, INGEST_BLOCKS, w.scal + 4, st));
+            return 0;
+        }))
+        return e;
     if (int e = pool_join(*pool, s))
         return e;
     if (int e = read_all())
@@ -1445,9 +1487,15 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
         const double normf = std::sqrt(sc[8 * i]);
         tol[i] = tol_in > 0.0 ? std::ldexp(tol_in, ks[i]) : 1e-15 * (double)n * normf;
         thr[i] = tol[i] / (double)n;
-        CK(launch_eye<double>(ws[i].V64, g.npad, ps(m)));
-        CK(launch_off2_partial<double>(ws[i].B64, g.npad, ws[i].partial, ps(m)));
     }
+    if (int e = pool_each(*pool, batch, [&](int64_t m, hipStream_t st) -> int {
+            if (!act[(size_t)m])
+                return 0;
+            CK(launch_eye<double>(ws[(size_t)m].V64, g.npad, st));
+            CK(launch_off2_partial<double>(ws[(size_t)m].B64, g.npad, ws[(size_t)m].partial, st));
+            return 0;
+        }))
+        return e;
     if (int e = pool_join(*pool, s))
         return e;
     if (int e = upload(act_d, act, (size_t)batch * sizeof(int)))
@@ -1567,31 +1615,34 @@ int eigh_block_batched(const double *A, int64_t n, const int64_t *a_off, int64_t
     const auto t_out0 = std::chrono::steady_clock::now();
     if (int e = pool_fork(*pool, s))
         return e;
-    for (int64_t m = 0; m < batch; ++m)
-        if (solved[(size_t)m])
-            if (int e = finalize_probe(g, n, ws[(size_t)m], ws[(size_t)m].B64,
-                                       ws[(size_t)m].V64, ps(m)))
-                return e;
+    if (int e = pool_each(*pool, batch, [&](int64_t m, hipStream_t st) -> int {
+            if (!solved[(size_t)m])
+                return 0;
+            return finalize_probe(g, n, ws[(size_t)m], ws[(size_t)m].B64, ws[(size_t)m].V64, st);
+        }))
+        return e;
     if (int e = pool_join(*pool, s))
         return e;
     if (int e = read_all())
         return e;
     if (int e = pool_fork(*pool, s))
         return e;
-    for (int64_t m = 0; m < batch; ++m) {
-        const size_t i = (size_t)m;
-        if (!solved[i])
-            continue;
-        const BlockWs &w = ws[i];
-        double est = 0.0;
-        int pol = 0;
-        if (int e = finalize_finish(g, n, w, sc[8 * i + 3], w.V64, w.B64, w.Vt, W + woff(m),
-                                    V + aoff(m), n, ps(m), &est, &pol,
-                                    ks[i] ? w.A0 : A + aoff(m), ks[i] ? g.npad : n))
-            return e;
-        if (ks[i])
-            CK(launch_scale_pow2(W + woff(m), n, -ks[i], nullptr, ps(m)));
-    }
+    if (int e = pool_each(*pool, batch, [&](int64_t m, hipStream_t st) -> int {
+            const size_t i = (size_t)m;
+            if (!solved[i])
+                return 0;
+            const BlockWs &w = ws[i];
+            double est = 0.0;
+            int pol = 0;
+            if (int e2 = finalize_finish(g, n, w, sc[8 * i + 3], w.V64, w.B64, w.Vt,
+                                         W + woff(m), V + aoff(m), n, st, &est, &pol,
+                                         ks[i] ? w.A0 : A + aoff(m), ks[i] ? g.npad : n))
+                return e2;
+            if (ks[i])
+                CK(launch_scale_pow2(W + woff(m), n, -ks[i], nullptr, st));
+            return 0;
+        }))
+        return e;
     if (int e = pool_join(*pool, s))
         return e;
     CK(hipStreamSynchronize(s));
