@@ -53,7 +53,14 @@ struct RoundItems {
     }
 };
 
-// S: m x m symmetric, row stride ld (LDS), m a multiple of 4.
+// entry (i, j) of a symmetric matrix kept as its upper triangle, row stride ld
+__device__ __forceinline__ int sym_idx(int i, int j, int ld)
+{
+    return i <= j ? i * ld + j : j * ld + i;
+}
+
+// S: m x m symmetric, row stride ld (LDS), m a multiple of 4; after the first
+// round only its upper triangle (i <= j) is kept current.
 // cs: LDS scratch of 3 * m/2 doubles (c, s, t of each pair).
 // Vt: V transposed, m rows of stride ldt (even, >= nv; LDS or global, 16-byte
 //    aligned rows), updated as Vt([p q], :) <- J^T Vt([p q], :), i.e.
@@ -62,8 +69,8 @@ struct RoundItems {
 // In round r the m/2 disjoint pairs (p, q) of the round-robin schedule are
 // rotated simultaneously: angles first (phase 1), then the two-sided update
 // B <- J^T B J restricted to the 2x2 blocks [p_k q_k] x [p_l q_l] (phase 2),
-// which touches every entry once.  Only blocks with k <= l are computed; the
-// mirror is written from the same values so S stays exactly symmetric.  The
+// which touches every entry once.  Only blocks with k <= l are computed, on
+// the upper triangle (the mirror would be a copy of the same values).  The
 // rotated pair itself gets the closed-form diagonal (a_pp - t a_pq,
 // a_qq + t a_pq) and an exact zero off the diagonal.
 // The index work of a thread comes from its lists `it` (built once per
@@ -112,24 +119,21 @@ __device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps, d
             S[pk * ld + pk] = (T)(app - tk * apq);
             S[qk * ld + qk] = (T)(aqq + tk * apq);
             S[pk * ld + qk] = (T)0;
-            S[qk * ld + pk] = (T)0;
             continue;
         }
         const T ck = (T)cs[k], skT = (T)sk, cl = (T)cs[l], slT = (T)sl;
-        const T x00 = S[pk * ld + pl], x01 = S[pk * ld + ql];
-        const T x10 = S[qk * ld + pl], x11 = S[qk * ld + ql];
+        const int a00 = sym_idx(pk, pl, ld), a01 = sym_idx(pk, ql, ld);
+        const int a10 = sym_idx(qk, pl, ld), a11 = sym_idx(qk, ql, ld);
+        const T x00 = S[a00], x01 = S[a01];
+        const T x10 = S[a10], x11 = S[a11];
         const T y00 = ck * x00 - skT * x10, y01 = ck * x01 - skT * x11;
         const T y10 = skT * x00 + ck * x10, y11 = skT * x01 + ck * x11;
         const T z00 = cl * y00 - slT * y01, z01 = slT * y00 + cl * y01;
         const T z10 = cl * y10 - slT * y11, z11 = slT * y10 + cl * y11;
-        S[pk * ld + pl] = z00;
-        S[pk * ld + ql] = z01;
-        S[qk * ld + pl] = z10;
-        S[qk * ld + ql] = z11;
-        S[pl * ld + pk] = z00;
-        S[ql * ld + pk] = z01;
-        S[pl * ld + qk] = z10;
-        S[ql * ld + qk] = z11;
+        S[a00] = z00;
+        S[a01] = z01;
+        S[a10] = z10;
+        S[a11] = z11;
     }
     if (Vt) {
         // items in groups of VB, all loads of a group before its stores
@@ -187,7 +191,7 @@ __device__ inline double lds_off2(const T *S, int ld, int m, double *red)
     for (int idx = threadIdx.x; idx < m * m; idx += NT) {
         int i = idx / m, j = idx - (idx / m) * m;
         if (i != j) {
-            double v = (double)S[i * ld + j];
+            double v = (double)S[sym_idx(i, j, ld)];
             acc += v * v;
         }
     }
