@@ -299,7 +299,9 @@ int small_pool(int64_t n_max, int lds_max)
     const size_t fixed = small_smem_bytes(m, 0);
     if (fixed >= (size_t)lds_max)
         return 0;
-    const int fit = (int)((lds_max - fixed) / sizeof(double));
+    // even, so that the scratch after the pool stays 16-byte aligned without
+    // growing the allocation
+    const int fit = (int)((lds_max - fixed) / sizeof(double)) & ~1;
     return fit >= s ? fit : 0;
 }
 

@@ -19,7 +19,7 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
     extern __shared__ __align__(16) double smem[];
     const int tid = threadIdx.x;
     double *S = smem;                                  // pool: S, then V if it fits
-    double *cs = smem + pool;                          // 3 * m_max / 2
+    double *cs = smem + ((pool + 1) & ~1);             // 3 * m_max / 2, 16-byte aligned
     double *wv = cs + 3 * (m_max / 2);                 // m_max
     double *sg = wv + m_max;                           // m_max
     double *red = sg + m_max;                          // 16
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(NT) void small_jacobi_kernel(
 
 size_t small_smem_bytes(int m_max, int pool)
 {
-    size_t d = (size_t)pool + 3 * (m_max / 2) + 2 * m_max + 16;
+    size_t d = (size_t)((pool + 1) & ~1) + 3 * (m_max / 2) + 2 * m_max + 16;
     return d * sizeof(double) + (size_t)(m_max + 1 + 16) * sizeof(int);
 }
 

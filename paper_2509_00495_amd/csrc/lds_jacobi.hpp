@@ -61,7 +61,8 @@ __device__ __forceinline__ int sym_idx(int i, int j, int ld)
 
 // S: m x m symmetric, row stride ld (LDS), m a multiple of 4; after the first
 // round only its upper triangle (i <= j) is kept current.
-// cs: LDS scratch of 3 * m/2 doubles (c, s, t of each pair).
+// cs: LDS scratch of 3 * m/2 doubles, 16-byte aligned: (c, s) of pair k at
+//    2k, 2k + 1 (one 16-byte read), t at m + k.
 // Vt: V transposed, m rows of stride ldt (even, >= nv; LDS or global, 16-byte
 //    aligned rows), updated as Vt([p q], :) <- J^T Vt([p q], :), i.e.
 //    V(:, [p q]) <- V(:, [p q]) J; may be null.  A pair's two rows are
@@ -95,8 +96,11 @@ __device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps, d
             jacobi_angle_fast(app, aqq, apq, c, s, t);
             rotated = 1;
         }
-        cs[k] = c;
-        cs[h + k] = s;
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        d2 cv;
+        cv.x = c;
+        cv.y = s;
+        reinterpret_cast<d2 *>(cs)[k] = cv;
         cs[2 * h + k] = t;
     }
     __syncthreads();
@@ -105,7 +109,9 @@ __device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps, d
         if (it.kl[u] < 0)
             continue;
         const int k = it.kl[u] >> 16, l = it.kl[u] & 0xffff;
-        const double sk = cs[h + k], sl = cs[h + l];
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2 csk = reinterpret_cast<const d2 *>(cs)[k], csl = reinterpret_cast<const d2 *>(cs)[l];
+        const double sk = csk.y, sl = csl.y;
         if (sk == 0.0 && sl == 0.0)
             continue;
         int pk, qk, pl, ql;
@@ -121,7 +127,7 @@ __device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps, d
             S[pk * ld + qk] = (T)0;
             continue;
         }
-        const T ck = (T)cs[k], skT = (T)sk, cl = (T)cs[l], slT = (T)sl;
+        const T ck = (T)csk.x, skT = (T)sk, cl = (T)csl.x, slT = (T)sl;
         const int a00 = sym_idx(pk, pl, ld), a01 = sym_idx(pk, ql, ld);
         const int a10 = sym_idx(qk, pl, ld), a11 = sym_idx(qk, ql, ld);
         const T x00 = S[a00], x01 = S[a01];
@@ -147,7 +153,7 @@ __device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps, d
             for (int u = 0; u < VB; ++u) {
                 ks[u] = -1;
                 if (k < h) {
-                    if (cs[h + k] != 0.0) {
+                    if (cs[2 * k + 1] != 0.0) {
                         ks[u] = k;
                         cc[u] = c;
                         rr_pair_r(k, r, m, pp[u], qq[u]);
@@ -165,7 +171,9 @@ __device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps, d
 #pragma unroll
             for (int u = 0; u < VB; ++u) {
                 if (ks[u] >= 0) {
-                    const T cv = (T)cs[ks[u]], sv = (T)cs[h + ks[u]];
+                    typedef double d2 __attribute__((ext_vector_type(2)));
+                    const d2 csu = reinterpret_cast<const d2 *>(cs)[ks[u]];
+                    const T cv = (T)csu.x, sv = (T)csu.y;
                     t2 x, y;
                     x.x = cv * a[u].x - sv * b[u].x;
                     x.y = cv * a[u].y - sv * b[u].y;
