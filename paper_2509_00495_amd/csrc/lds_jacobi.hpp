@@ -76,11 +76,11 @@ __device__ __forceinline__ int sym_idx(int i, int j, int ld)
 // a_qq + t a_pq) and an exact zero off the diagonal.
 // The index work of a thread comes from its lists `it` (built once per
 // matrix) and the angles from jacobi_angle_fast.
-// Returns (per thread) whether this thread computed a rotation in phase 1.
-template <typename T, int NT, int SI>
-__device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps, double thr,
-                                       T *Vt, int ldt, double *cs,
-                                       const RoundItems<NT, SI> &it)
+// Phase 1 of round r: the angles of the round's m/2 pairs into cs (pair k on
+// thread k mod NT).  Returns (per thread) whether it computed a rotation.
+template <typename T, int NT>
+__device__ inline int lds_round_angles(const T *S, int ld, int m, int r, double eps, double thr,
+                                       double *cs)
 {
     const int h = m / 2;
     const int tid = threadIdx.x;
@@ -103,7 +103,15 @@ __device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps, d
         reinterpret_cast<d2 *>(cs)[k] = cv;
         cs[2 * h + k] = t;
     }
-    __syncthreads();
+    return rotated;
+}
+
+// Phase 2 of round r on S with the round's angles in cs.
+template <typename T, int NT, int SI>
+__device__ inline void lds_round_update_s(T *S, int ld, int m, int r, const double *cs,
+                                          const RoundItems<NT, SI> &it)
+{
+    const int h = m / 2;
 #pragma unroll
     for (int u = 0; u < SI; ++u) {
         if (it.kl[u] < 0)
@@ -141,6 +149,14 @@ __device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps, d
         S[a10] = z10;
         S[a11] = z11;
     }
+}
+
+// The V update of round r with the round's angles in cs.
+template <typename T, int NT, int SI>
+__device__ inline void lds_round_update_v(T *Vt, int ldt, int m, int r, const double *cs,
+                                          const RoundItems<NT, SI> &it)
+{
+    const int h = m / 2;
     if (Vt) {
         // items in groups of VB, all loads of a group before its stores
         constexpr int VB = 2;
@@ -185,6 +201,19 @@ __device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps, d
             }
         }
     }
+}
+
+// One whole round: angles, barrier, S and V updates, barrier.  Returns (per
+// thread) whether this thread computed a rotation in phase 1.
+template <typename T, int NT, int SI>
+__device__ inline int lds_jacobi_round(T *S, int ld, int m, int r, double eps, double thr,
+                                       T *Vt, int ldt, double *cs,
+                                       const RoundItems<NT, SI> &it)
+{
+    const int rotated = lds_round_angles<T, NT>(S, ld, m, r, eps, thr, cs);
+    __syncthreads();
+    lds_round_update_s<T, NT, SI>(S, ld, m, r, cs, it);
+    lds_round_update_v<T, NT, SI>(Vt, ldt, m, r, cs, it);
     __syncthreads();
     return rotated;
 }
