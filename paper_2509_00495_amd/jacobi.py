@@ -242,13 +242,15 @@ def eigh_mixed(A, tol: float | None = None, opts: Opts | None = None,
 def eigh_batched(A_packed, ns, tol: float | None = None, opts: Opts | None = None,
                  ws: Workspace | None = None, check: bool = True, out=None, a_off=None,
                  w_off=None):
-    """Batch of uneven orders in one persistent launch.  A_packed: 1-D float64
-    GPU tensor holding the matrices (row-major, ld = n_i), back to back or at
-    the element offsets a_off (host ints); eigenvalues go back to back or to
-    w_off.  Returns (W, V, status): V has A_packed's layout, status is an
-    int32 GPU tensor of per-matrix codes.  `out` = (W, V, status) reuses
-    caller tensors (fixed addresses, which a graph replay with opts.graph
-    needs)."""
+    """jacobi_eigh_batched: a batch of uneven orders <= 128 in one persistent
+    launch, or a batch of one order above 128 on the block path (one launch
+    per step for the whole batch; each result bitwise that of eigh on the
+    matrix).  A_packed: 1-D float64 GPU tensor holding the matrices
+    (row-major, ld = n_i), back to back or at the element offsets a_off (host
+    ints); eigenvalues go back to back or to w_off.  Returns (W, V, status):
+    V has A_packed's layout, status is an int32 GPU tensor of per-matrix
+    codes.  `out` = (W, V, status) reuses caller tensors (fixed addresses,
+    which a graph replay with opts.graph needs)."""
     torch = _torch()
     ns = [int(x) for x in ns]
     batch = len(ns)
