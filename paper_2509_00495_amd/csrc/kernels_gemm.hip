@@ -586,11 +586,47 @@ __global__ __launch_bounds__(256) void adjoint_mid_kernel(double *__restrict__ M
         atomicOr(flag, 1);
 }
 
+// The same entries on a (column chunk, row, matrix) grid: no index divisions.
+__global__ __launch_bounds__(256) void adjoint_mid_grid_kernel(double *__restrict__ Mm,
+                                                               const double *__restrict__ W,
+                                                               const double *__restrict__ dW,
+                                                               int64_t n, double gap_tol,
+                                                               int has_dv, int *flag)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x, i = blockIdx.y, z = blockIdx.z;
+    int degen = 0;
+    if (j < n) {
+        const int64_t e = (z * n + i) * n + j;
+        double m;
+        if (i == j) {
+            m = dW ? dW[z * n + i] : 0.0;
+        } else {
+            double mv = has_dv ? Mm[e] : 0.0;
+            double gap = W[z * n + j] - W[z * n + i];
+            if (fabs(gap) < gap_tol) {
+                if (mv != 0.0)
+                    degen = 1;
+                m = 0.0;
+            } else {
+                m = mv / gap;
+            }
+        }
+        Mm[e] = m;
+    }
+    if (__any(degen) && threadIdx.x % WAVE == 0)
+        atomicOr(flag, 1);
+}
+
 hipError_t launch_adjoint_mid(double *M, const double *W, const double *dW, int64_t n,
                               int64_t batch, double gap_tol, int has_dv, int *flag, hipStream_t s)
 {
-    hipLaunchKernelGGL(adjoint_mid_kernel, dim3(2048), dim3(256), 0, s, M, W, dW, n, batch,
-                       gap_tol, has_dv, flag);
+    if (n <= 65535 && batch <= 65535)
+        hipLaunchKernelGGL(adjoint_mid_grid_kernel, dim3((unsigned)((n + 255) / 256),
+                                                         (unsigned)n, (unsigned)batch),
+                           dim3(256), 0, s, M, W, dW, n, gap_tol, has_dv, flag);
+    else
+        hipLaunchKernelGGL(adjoint_mid_kernel, dim3(2048), dim3(256), 0, s, M, W, dW, n, batch,
+                           gap_tol, has_dv, flag);
     return hipGetLastError();
 }
 
@@ -608,10 +644,52 @@ __global__ __launch_bounds__(256) void sym_out_kernel(const double *__restrict__
     }
 }
 
+// The same entries by 32 x 32 tiles: workgroup (I, J, matrix), I <= J, reads
+// the tiles G_IJ and G_JI once along their rows into LDS and writes dA_IJ and
+// dA_JI along their rows (the transposed reads come from LDS; the row stride
+// 33 keeps them free of bank conflicts).  Workgroups with I > J return.
+constexpr int SYM_T = 32;
+__global__ __launch_bounds__(256) void sym_out_tiled_kernel(const double *__restrict__ G,
+                                                            double *__restrict__ dA, int64_t n,
+                                                            int64_t ld)
+{
+    const int I = blockIdx.x, J = blockIdx.y;
+    if (I > J)
+        return;
+    __shared__ double a[SYM_T][SYM_T + 1], b[SYM_T][SYM_T + 1];
+    const int64_t z = blockIdx.z;
+    const double *Gz = G + z * n * n;
+    double *Dz = dA + z * n * ld;
+    const int tx = threadIdx.x % SYM_T, ty = threadIdx.x / SYM_T; // 8 rows per pass
+    const int64_t i0 = (int64_t)I * SYM_T, j0 = (int64_t)J * SYM_T;
+#pragma unroll
+    for (int rr = 0; rr < SYM_T; rr += 8) {
+        const int row = ty + rr;
+        a[row][tx] = (i0 + row < n && j0 + tx < n) ? Gz[(i0 + row) * n + j0 + tx] : 0.0;
+        b[row][tx] = (j0 + row < n && i0 + tx < n) ? Gz[(j0 + row) * n + i0 + tx] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < SYM_T; rr += 8) {
+        const int row = ty + rr;
+        // dA_IJ[row][tx] = (G_IJ[row][tx] + G_JI[tx][row]) / 2
+        if (i0 + row < n && j0 + tx < n)
+            Dz[(i0 + row) * ld + j0 + tx] = 0.5 * (a[row][tx] + b[tx][row]);
+        // dA_JI[row][tx] = (G_JI[row][tx] + G_IJ[tx][row]) / 2
+        if (I != J && j0 + row < n && i0 + tx < n)
+            Dz[(j0 + row) * ld + i0 + tx] = 0.5 * (b[row][tx] + a[tx][row]);
+    }
+}
+
 hipError_t launch_sym_out(const double *G, double *dA, int64_t n, int64_t ld, int64_t batch,
                           hipStream_t s)
 {
-    hipLaunchKernelGGL(sym_out_kernel, dim3(2048), dim3(256), 0, s, G, dA, n, ld, batch);
+    const int64_t nt = (n + SYM_T - 1) / SYM_T;
+    if (nt <= 65535 && batch <= 65535)
+        hipLaunchKernelGGL(sym_out_tiled_kernel, dim3((unsigned)nt, (unsigned)nt, (unsigned)batch),
+                           dim3(256), 0, s, G, dA, n, ld);
+    else
+        hipLaunchKernelGGL(sym_out_kernel, dim3(2048), dim3(256), 0, s, G, dA, n, ld, batch);
     return hipGetLastError();
 }
 
