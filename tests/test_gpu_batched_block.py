@@ -176,3 +176,42 @@ def test_block_batch_two_host_threads(pj):
     for i in range(2):
         for a, b in zip(out[i], alone[i]):
             assert np.array_equal(a, b), i
+
+
+def test_block_batch_offsets_and_workspace(pj):
+    """Matrices at explicit, non-packed offsets (gaps between them, eigenvalues
+    scattered), through the C ABI with a caller workspace: one byte short of
+    jacobi_workspace_bytes returns JACOBI_WORKSPACE before anything runs, the
+    exact size solves; every matrix bitwise its single solve."""
+    import ctypes
+    n, b = 160, 3
+    mats = [wl.goe(n, 71 + k) for k in range(b)]
+    a_off = [0, n * n + 37, 2 * n * n + 1000]
+    w_off = [500, 3, 250]
+    tot = a_off[-1] + n * n
+    A = torch.zeros(tot, dtype=torch.float64, device="cuda")
+    for k, M in enumerate(mats):
+        A[a_off[k]:a_off[k] + n * n] = torch.tensor(M.ravel(), device="cuda")
+    W = torch.full((700,), 7.0, dtype=torch.float64, device="cuda")
+    V = torch.zeros(tot, dtype=torch.float64, device="cuda")
+    st = torch.zeros(b, dtype=torch.int32, device="cuda")
+    lib = pj.jacobi._lib()
+    need = pj.workspace_bytes(2, n, b)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    i64 = ctypes.c_int64 * b
+    args = lambda nbytes: (A.data_ptr(), i64(*[n] * b), i64(*a_off), b, W.data_ptr(),
+                           i64(*w_off), V.data_ptr(), 0.0, 0, None, ws.data_ptr(), nbytes,
+                           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                           st.data_ptr())
+    print(f"  -> block batch n={n} at offsets {a_off}, workspace {need} bytes", flush=True)
+    assert lib.jacobi_eigh_batched(*args(need - 1)) == pj.WORKSPACE
+    assert lib.jacobi_eigh_batched(*args(need)) == 0
+    torch.cuda.synchronize()
+    Wh, Vh = W.cpu().numpy(), V.cpu().numpy()
+    assert (st.cpu().numpy() == 0).all()
+    for k, M in enumerate(mats):
+        Ws, Vs, ss = _single(pj, M, None, None)
+        assert np.array_equal(Wh[w_off[k]:w_off[k] + n], Ws), k
+        assert np.array_equal(Vh[a_off[k]:a_off[k] + n * n].reshape(n, n), Vs), k
+    # the gaps are untouched
+    assert (Vh[n * n:n * n + 37] == 0).all() and (Wh[163:250] == 7.0).all()
